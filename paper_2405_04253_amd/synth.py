@@ -1,0 +1,278 @@
+"""Seeded synthetic coherent-receiver workloads (the input generator).
+
+This module stands in for the paper's lab capture chain (Experimental
+verification section: 40 GBaud PDM-16QAM, RRC pulse shaping, 75 km SSMF,
+80 GSa/s sampling, matched filtering).  It produces the integer arrays that
+both the GPU path and the oracle consume:
+
+* ``samples``  int8  [n][4]   5-bit signed {XI, XQ, YI, YQ} at 2 samples/symbol
+* ``taps``     int8  [L][2]   6-bit signed (re, im) chromatic-dispersion inverse
+
+It contains none of the equaliser's arithmetic: no number-theoretic
+transform, no convolution of the quantised data, no tap update.  Floating
+point lives only here, before quantisation, so float rounding can never
+affect parity (both sides read the same int8 arrays).
+
+Channel recipe (all float, complex64 FFT based, circular over the stream):
+16QAM symbols uniform in {-3,-1,1,3}^2 per polarisation -> 2 sps ->
+Tx RRC -> chromatic dispersion (D=17 ps/nm/km, 1550 nm) -> Haar-random U(2)
+polarisation rotation -> AWGN (SNR = OSNR * 12.5 GHz / symbol rate) ->
+Rx RRC (matched filter) -> scale to per-component RMS 4 LSB -> round and clip
+to [-16, 15].
+"""
+from __future__ import annotations
+
+import hashlib
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+C_LIGHT = 299792458.0
+D_PS_NM_KM = 17.0
+LAMBDA_M = 1550e-9
+BAUD = 40e9
+SPS = 2
+ROLLOFF = 0.1
+SAMPLE_RMS = 4.0          # per real component, in LSBs of the 5-bit grid
+MAX_TAPS = 32
+BLOCK_SYMBOLS = 16        # one equaliser block = 16 symbols = 32 instants
+
+
+def seed_for(*parts) -> int:
+    """Stable 64-bit seed from any tuple of ints/strings (sha256)."""
+    h = hashlib.sha256(repr(parts).encode()).digest()
+    return int.from_bytes(h[:8], "little")
+
+
+def _fast_len(n: int) -> int:
+    try:
+        from scipy.fft import next_fast_len
+        return int(next_fast_len(n))
+    except Exception:  # pragma: no cover
+        return 1 << (n - 1).bit_length()
+
+
+def dispersion_beta(fibre_km: float) -> float:
+    """Phase coefficient k such that H_CD(f) = exp(-j k f^2), f in Hz."""
+    d = D_PS_NM_KM * 1e-6       # s/m^2
+    z = fibre_km * 1e3
+    return math.pi * d * LAMBDA_M ** 2 * z / C_LIGHT
+
+
+def cdc_tap_count(fibre_km: float) -> int:
+    """Taps for the CD inverse at 2 sps: 2*floor(D lambda^2 z / (2 c T^2)), clamped to [8, 32]."""
+    t = 1.0 / (BAUD * SPS)
+    d = D_PS_NM_KM * 1e-6
+    span = d * LAMBDA_M ** 2 * fibre_km * 1e3 / (2 * C_LIGHT * t * t)
+    return int(min(MAX_TAPS, max(8, 2 * math.floor(span))))
+
+
+def _rrc_response(nfft: int) -> np.ndarray:
+    """Root-raised-cosine magnitude on the FFT grid of a 2 sps stream."""
+    f = np.fft.fftfreq(nfft)                 # cycles/sample
+    nu = np.abs(f) * SPS                     # in units of the symbol rate
+    lo, hi = (1 - ROLLOFF) / 2, (1 + ROLLOFF) / 2
+    rc = np.where(nu <= lo, 1.0,
+                  np.where(nu <= hi, 0.5 * (1 + np.cos(np.pi / ROLLOFF * (nu - lo))), 0.0))
+    return np.sqrt(rc)
+
+
+def design_cdc_taps(fibre_km: float, ntaps: int | None = None):
+    """Weighted least-squares CD-inverse FIR, quantised to 6 bit.
+
+    The fit runs over the whole 2 sps Nyquist band with weight
+    sqrt(RC(f) + 0.01): tight inside the signal band, loose outside, which
+    keeps the short filter well conditioned.  Returns (taps int8[L][2],
+    requant_shift, in-band amplitude gain of the integer taps).  The filter is
+    centred on tap L/2, so its delay is L/2 samples = an integer number of
+    symbols.  The requantisation shift is log2 of the gain, rounded, so the
+    1 sample/symbol stream keeps about the input's 5-bit scale.
+    """
+    L = cdc_tap_count(fibre_km) if ntaps is None else int(ntaps)
+    k = dispersion_beta(fibre_km)
+    fs = BAUD * SPS
+    fgrid = np.linspace(-fs / 2, fs / 2, 4096, endpoint=False)
+    nu = np.abs(fgrid) / BAUD
+    lo, hi = (1 - ROLLOFF) / 2, (1 + ROLLOFF) / 2
+    rc = np.where(nu <= lo, 1.0,
+                  np.where(nu <= hi, 0.5 * (1 + np.cos(np.pi / ROLLOFF * (nu - lo))), 0.0))
+    w = np.sqrt(rc + 0.01)
+    target = np.exp(1j * k * fgrid ** 2)     # inverse of exp(-j k f^2)
+    n = np.arange(L) - L // 2
+    a = np.exp(-2j * np.pi * np.outer(fgrid, n) / fs)
+    h, *_ = np.linalg.lstsq(a * w[:, None], target * w, rcond=None)
+    scale = 31.0 / max(np.abs(h.real).max(), np.abs(h.imag).max())
+    hq = np.stack([np.round(h.real * scale), np.round(h.imag * scale)], axis=1)
+    hq = np.clip(hq, -32, 31).astype(np.int8)
+    # power gain of the integer filter over the signal band (RC-weighted)
+    hint = hq[:, 0].astype(np.float64) + 1j * hq[:, 1].astype(np.float64)
+    resp = a @ hint
+    gain = math.sqrt(float(np.sum(rc * np.abs(resp) ** 2) / np.sum(rc)))
+    shift = int(max(0, round(math.log2(max(gain, 1.0)))))
+    return hq, shift, gain
+
+
+def _haar_u2(rng: np.random.Generator) -> np.ndarray:
+    z = (rng.standard_normal((2, 2)) + 1j * rng.standard_normal((2, 2))) / math.sqrt(2)
+    q, r = np.linalg.qr(z)
+    d = np.diag(r)
+    return q * (d / np.abs(d))
+
+
+@dataclass
+class Channel:
+    """One synthetic dual-polarisation channel, ready for the receiver."""
+    samples: np.ndarray            # int8 [n][4]
+    taps: np.ndarray               # int8 [L][2]
+    requant_shift: int
+    fibre_km: float
+    osnr_db: float
+    symbols: np.ndarray = field(repr=False)   # int8 [nsym][4] transmitted levels (for BER sanity)
+    const_unit: int = 64                      # expected 16QAM unit at the equaliser output
+
+    @property
+    def ntaps(self) -> int:
+        return int(self.taps.shape[0])
+
+    @property
+    def n(self) -> int:
+        return int(self.samples.shape[0])
+
+
+def gen_channel(nsym: int, fibre_km: float = 75.0, osnr_db: float = 22.0,
+                seed: int = 0, ntaps: int | None = None) -> Channel:
+    """Generate ``nsym`` symbols per polarisation -> int8 [2*nsym][4] samples."""
+    rng = np.random.default_rng(seed)
+    nsym = int(nsym)
+    symbols = rng.integers(0, 4, size=(nsym, 4), dtype=np.int8) * 2 - 3
+    taps, shift, gain = design_cdc_taps(fibre_km, ntaps)
+    unit = const_unit_for(gain, shift)
+    if nsym == 0:
+        return Channel(np.zeros((0, 4), np.int8), taps, shift, fibre_km, osnr_db, symbols, unit)
+    ng = _fast_len(nsym)
+    sym = np.zeros((ng, 4), np.float32)
+    sym[:nsym] = symbols
+    nfft = SPS * ng
+    rrc = _rrc_response(nfft).astype(np.float32)
+    fhz = np.fft.fftfreq(nfft).astype(np.float64) * BAUD * SPS
+    cd = np.exp(-1j * dispersion_beta(fibre_km) * fhz ** 2).astype(np.complex64)
+    u = _haar_u2(rng).astype(np.complex64)
+    snr_lin = 10 ** (osnr_db / 10) * 12.5e9 / BAUD
+    spec = []
+    for p in range(2):
+        s = (sym[:, 2 * p] + 1j * sym[:, 2 * p + 1]).astype(np.complex64)
+        sf = np.fft.fft(s)
+        spec.append(np.tile(sf, SPS) * (rrc * cd))   # zero-stuffed upsample = tiled spectrum
+    rot = [u[0, 0] * spec[0] + u[0, 1] * spec[1], u[1, 0] * spec[0] + u[1, 1] * spec[1]]
+    del spec
+    out = np.empty((nfft, 4), np.float32)
+    for p in range(2):
+        sig = rot[p] * rrc
+        p_sig = float(np.mean(np.abs(sig) ** 2)) / nfft        # mean time-domain power
+        p_rrc = float(np.mean(rrc.astype(np.float64) ** 2))
+        sigma2 = p_sig / snr_lin / max(p_rrc, 1e-12)
+        noise = (rng.standard_normal(nfft, dtype=np.float32)
+                 + 1j * rng.standard_normal(nfft, dtype=np.float32)).astype(np.complex64)
+        noise *= np.float32(math.sqrt(sigma2 * nfft / 2))
+        y = np.fft.ifft(sig + noise * rrc)
+        out[:, 2 * p] = y.real
+        out[:, 2 * p + 1] = y.imag
+    del rot
+    out = out[: SPS * nsym]
+    rms = float(np.sqrt(np.mean(out.astype(np.float64) ** 2)))
+    q = np.clip(np.rint(out * (SAMPLE_RMS / max(rms, 1e-30))), -16, 15).astype(np.int8)
+    return Channel(np.ascontiguousarray(q), taps, shift, fibre_km, osnr_db, symbols, unit)
+
+
+# ---------------------------------------------------------------------------
+# Equaliser defaults: integer constants of the tap update (inputs, not arithmetic)
+# ---------------------------------------------------------------------------
+AEQ_DEFAULTS = dict(out_shift=7, err_shift=16, mu_shift=3, const_unit=64, update_enable=1)
+AEQ_UNITY = 4096          # 1.0 in the 14-bit tap format
+
+
+def const_unit_for(cdc_gain: float, requant_shift: int, out_shift: int = 7) -> int:
+    """Expected 16QAM unit amplitude at the equaliser output for a channel.
+
+    The 5-bit input has per-component RMS SAMPLE_RMS; the CD inverse scales it
+    by ``cdc_gain`` and the requantisation divides by 2^requant_shift; 16QAM
+    with levels +-1, +-3 has per-component RMS sqrt(5) units; a unity tap is
+    AEQ_UNITY and the output drops ``out_shift`` bits.
+    """
+    unit_in = SAMPLE_RMS * cdc_gain / (1 << requant_shift) / math.sqrt(5)
+    return int(max(1, round(AEQ_UNITY / (1 << out_shift) * unit_in)))
+
+
+def aeq_params_for(ch: "Channel") -> dict:
+    d = dict(AEQ_DEFAULTS)
+    d["const_unit"] = ch.const_unit
+    return d
+
+
+def centre_spike_taps(unity: int = AEQ_UNITY, centre: int = 8) -> np.ndarray:
+    """int16 [4 S1][4 S2][16]: identity MIMO with a centre spike on each diagonal filter."""
+    w = np.zeros((4, 4, 16), np.int16)
+    for s in range(4):
+        w[s, s, centre] = unity
+    return w
+
+
+# ---------------------------------------------------------------------------
+# Workload definitions (sizes and distributions of the paper's setting)
+# ---------------------------------------------------------------------------
+def single_channel(nsym: int, base_seed: int = 0, tag: str = "single") -> Channel:
+    """75 km, OSNR 22 dB, 32 taps (the paper's transmission case)."""
+    return gen_channel(nsym, 75.0, 22.0, seed_for(base_seed, tag, 0))
+
+
+@dataclass
+class ChannelSpec:
+    channel_id: int
+    nsym: int
+    fibre_km: float
+    osnr_db: float
+    seed: int
+
+
+def batched_specs(nch: int, log2_min: int, log2_max: int, base_seed: int = 0,
+                  tag: str = "batched", multiple: int = 1) -> list[ChannelSpec]:
+    """Per-channel lengths log-uniform in [2^log2_min, 2^log2_max] symbols/pol,
+    fibre U(10, 80) km, OSNR U(18, 26) dB; one independent seed per channel."""
+    specs = []
+    for c in range(nch):
+        s = seed_for(base_seed, tag, c)
+        r = np.random.default_rng(s ^ 0x5EED)
+        nsym = int(round(2 ** r.uniform(log2_min, log2_max)))
+        nsym = max(multiple, (nsym // multiple) * multiple)
+        specs.append(ChannelSpec(c, nsym, float(r.uniform(10, 80)), float(r.uniform(18, 26)), s))
+    return specs
+
+
+def gen_spec(spec: ChannelSpec) -> Channel:
+    return gen_channel(spec.nsym, spec.fibre_km, spec.osnr_db, spec.seed)
+
+
+def gen_many(specs, workers: int = 8) -> list[Channel]:
+    """Generate many channels in parallel threads (numpy FFTs release the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+    if workers <= 1 or len(specs) <= 1:
+        return [gen_spec(s) for s in specs]
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(gen_spec, specs))
+
+
+def random_samples(n: int, seed: int) -> np.ndarray:
+    """Uniform 5-bit samples over the whole legal range (edge-case stress input)."""
+    r = np.random.default_rng(seed)
+    return r.integers(-16, 16, size=(n, 4), dtype=np.int8)
+
+
+def random_taps(ntaps: int, seed: int) -> np.ndarray:
+    r = np.random.default_rng(seed)
+    return r.integers(-32, 32, size=(ntaps, 2), dtype=np.int8)
+
+
+def random_aeq_taps(seed: int, lo: int = -8192, hi: int = 8191) -> np.ndarray:
+    r = np.random.default_rng(seed)
+    return r.integers(lo, hi + 1, size=(4, 4, 16), dtype=np.int16)

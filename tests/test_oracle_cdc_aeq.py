@@ -1,0 +1,232 @@
+"""Pins for the oracle's CDC, resampling/requantisation and AEQ definitions.
+
+CDC is pinned to numpy's convolution (library routine) and to the FNT block
+model of Eqs. (7)-(8); requantisation to hand-worked rounding values and the
+round-to-nearest property; the AEQ filter bank to numpy's convolution, and the
+RDE update (Eq. (6)) to a hand-worked two-block example and to invariants.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import fnt_ref as R
+from paper_2405_04253_amd import synth
+
+
+def np_cdc(x, h):
+    """Exact complex causal convolution by numpy (int64), both polarisations."""
+    x = x.astype(np.int64)
+    hr, hi = h[:, 0].astype(np.int64), h[:, 1].astype(np.int64)
+    n = x.shape[0]
+    z = np.zeros((n, 4), np.int64)
+    if n == 0:
+        return z
+    for p in range(2):
+        xr, xi = x[:, 2 * p], x[:, 2 * p + 1]
+        z[:, 2 * p] = (np.convolve(xr, hr) - np.convolve(xi, hi))[:n]
+        z[:, 2 * p + 1] = (np.convolve(xi, hr) + np.convolve(xr, hi))[:n]
+    return z
+
+
+def test_rounding_hand_values():
+    # rs(v, s): round half up then drop s bits; sat_b: clamp to b-bit two's complement.
+    cases = [(3, 1, 2), (-3, 1, -1), (5, 2, 1), (6, 2, 2), (-5, 2, -1), (-6, 2, -1),
+             (-7, 2, -2), (7, 0, 7), (-1, 1, 0), (1, 1, 1), (-32768, 15, -1), (32767, 15, 1)]
+    for v, s, want in cases:
+        assert O.rs(v, s) == want, (v, s)
+    assert O.sat(100, 5) == 15 and O.sat(-100, 5) == -16 and O.sat(15, 5) == 15
+    assert O.sat(40000, 16) == 32767 and O.sat(-9000, 14) == -8192 and O.sat(8191, 14) == 8191
+
+
+def _check_requant(z, a, shift):
+    """Round-to-nearest property (ties up), with saturation to 5 bit."""
+    z = z.astype(np.int64)
+    a = a.astype(np.int64)
+    sat_hi = a == 15
+    sat_lo = a == -16
+    mid = ~(sat_hi | sat_lo)
+    if shift == 0:
+        assert np.array_equal(a[mid], z[mid])
+    else:
+        d = z - a * (1 << shift)           # remainder after rounding
+        half = 1 << (shift - 1)
+        assert np.all((d[mid] >= -half) & (d[mid] < half))
+    assert np.all(z[sat_hi] >= 15 * (1 << shift) - (1 << shift) // 2)
+    assert np.all(z[sat_lo] < -16 * (1 << shift) + (1 << shift) // 2)
+
+
+@pytest.mark.parametrize("n,L,shift,phase", [(0, 32, 7, 0), (1, 5, 0, 0), (2, 32, 7, 1),
+                                             (97, 17, 6, 0), (1000, 32, 7, 1), (333, 8, 3, 1)])
+def test_cdc_matches_numpy_convolve(n, L, shift, phase):
+    x = synth.random_samples(n, seed=n + L)
+    h = synth.random_taps(L, seed=L)
+    z, a = O.cdc(x, h, shift, phase)
+    assert np.array_equal(z.astype(np.int64), np_cdc(x, h))
+    assert a.shape[0] == O.n_symbols(n, phase) == len(range(phase, n, 2))
+    _check_requant(z[phase::2], a, shift)
+
+
+def test_cdc_generated_channel_and_bound():
+    ch = synth.single_channel(1 << 12)
+    z, a = O.cdc(ch.samples, ch.taps, ch.requant_shift)
+    assert np.array_equal(z.astype(np.int64), np_cdc(ch.samples, ch.taps))
+    assert np.abs(z).max() <= 32768          # Eq. (5) holds for 5-bit data, 32 taps of 6 bit
+    _check_requant(z[0::2], a, ch.requant_shift)
+
+
+def test_cdc_matches_eq78_block_model():
+    # Two independent formulations of the oracle side agree: direct convolution and
+    # the overlap-save FNT block with the complex packing (64-point window, 32 new).
+    ch = synth.single_channel(256)
+    z, _ = O.cdc(ch.samples, ch.taps, ch.requant_shift)
+    L = ch.ntaps
+    hr = [int(v) for v in ch.taps[:, 0]] + [0] * (64 - L)
+    hi = [int(v) for v in ch.taps[:, 1]] + [0] * (64 - L)
+    x = np.concatenate([np.zeros((32, 4), np.int8), ch.samples])
+    for b in (0, 3, 7):
+        for p in range(2):
+            win = x[32 * b: 32 * b + 64]
+            zr, zi = R.cdc_block_eq78([int(v) for v in win[:, 2 * p]],
+                                      [int(v) for v in win[:, 2 * p + 1]], hr, hi)
+            assert zr[32:] == [int(v) for v in z[32 * b: 32 * b + 32, 2 * p]]
+            assert zi[32:] == [int(v) for v in z[32 * b: 32 * b + 32, 2 * p + 1]]
+
+
+def test_cdc_history_streaming():
+    x = synth.random_samples(640, seed=5)
+    h = synth.random_taps(32, seed=6)
+    z, a = O.cdc(x, h, 7)
+    k = 320
+    z2, a2 = O.cdc(x[k:], h, 7, hist=x[k - 32:k])
+    assert np.array_equal(z2, z[k:])
+    assert np.array_equal(a2, a[k // 2:])
+
+
+def np_fir_bank(a, w):
+    a = a.astype(np.int64)
+    M = a.shape[0]
+    y = np.zeros((M, 4), np.int64)
+    if M == 0:
+        return y
+    for s2 in range(4):
+        for s1 in range(4):
+            y[:, s2] += np.convolve(a[:, s1], w[s1, s2].astype(np.int64))[:M]
+    return y
+
+
+def test_aeq_fixed_bank_matches_numpy(aeq_defaults):
+    rng = np.random.default_rng(9)
+    for M in (0, 1, 15, 16, 17, 100):
+        a = rng.integers(-16, 16, (M, 4)).astype(np.int8)
+        w = synth.random_aeq_taps(seed=M)
+        prm = O.params(**dict(aeq_defaults, update_enable=0))
+        out, wf = O.aeq(a, w, prm)
+        assert np.array_equal(wf, w)
+        y = np_fir_bank(a, w)
+        s = aeq_defaults["out_shift"]
+        half = 1 << (s - 1)
+        yh = out.astype(np.int64)
+        d = y - yh * (1 << s)
+        ok = (yh == 32767) | (yh == -32768) | ((d >= -half) & (d < half))
+        assert ok.all()
+
+
+def test_aeq_hand_worked_two_blocks():
+    # Block 0: a[0].XI = 8, w[XI][XI][0] = w[XQ][XQ][0] = 4096, s_o = 7, c_y = 64
+    # (c^2 = 4096: thresholds 6c^2 = 24576, 14c^2 = 57344), s_e = 16, s_mu = 0.
+    #   y_XI[0] = 4096*8 = 32768 -> yhat = rs(32768, 7) = 256, all other yhat = 0.
+    #   r2 = 65536 >= 57344 -> R2 = 18c^2 = 73728, e = 8192,
+    #   eps_XI[0] = rs(8192*256, 16) = 32; all other eps are 0 (yhat = 0).
+    #   G[XI][XI][0] = 32 * a[0].XI = 256, every other G entry is 0
+    #   -> w[XI][XI][0] = 4096 + 256 = 4352.
+    # Block 1: a[16].XQ = -4.
+    #   y_XQ[16] = w[XQ][XQ][0] * -4 = -16384 -> yhat = -128; pol X r2 = 16384 < 24576
+    #   -> R2 = 2c^2 = 8192, e = -8192, eps_XQ[16] = rs(-8192*-128, 16) = 16.
+    #   G[XQ][XQ][0] = 16 * -4 = -64 -> w[XQ][XQ][0] = 4032.  a[0] is 16 symbols back,
+    #   outside the 16 taps, so nothing else moves.
+    a = np.zeros((32, 4), np.int8)
+    a[0, 0] = 8
+    a[16, 1] = -4
+    w = np.zeros((4, 4, 16), np.int16)
+    w[0, 0, 0] = 4096
+    w[1, 1, 0] = 4096
+    prm = O.params(out_shift=7, err_shift=16, mu_shift=0, const_unit=64, update_enable=1)
+    out, wf = O.aeq(a, w, prm)
+    want_out = np.zeros((32, 4), np.int16)
+    want_out[0, 0] = 256
+    want_out[16, 1] = -128
+    assert np.array_equal(out, want_out)
+    want_w = w.copy()
+    want_w[0, 0, 0] = 4352
+    want_w[1, 1, 0] = 4032
+    assert np.array_equal(wf, want_w)
+
+
+def test_aeq_update_invariants(aeq_defaults):
+    ch = synth.single_channel(1 << 10)
+    _, a = O.cdc(ch.samples, ch.taps, ch.requant_shift)
+    w0 = synth.centre_spike_taps()
+    # a step size too small to move any tap leaves the filter fixed
+    out1, wf1 = O.aeq(a, w0, O.params(**dict(aeq_defaults, mu_shift=40)))
+    out0, wf0 = O.aeq(a, w0, O.params(**dict(aeq_defaults, update_enable=0)))
+    assert np.array_equal(wf1, w0) and np.array_equal(out1, out0)
+    # zero error terms (err_shift huge) leave the taps fixed too
+    _, wf2 = O.aeq(a, w0, O.params(**dict(aeq_defaults, err_shift=60)))
+    assert np.array_equal(wf2, w0)
+    # with the default step the taps move and stay within 14 bit
+    _, wf3 = O.aeq(a, w0, O.params(**aeq_defaults))
+    assert not np.array_equal(wf3, w0)
+    assert wf3.min() >= -8192 and wf3.max() <= 8191
+
+
+def test_aeq_history_streaming(aeq_defaults):
+    rng = np.random.default_rng(11)
+    a = rng.integers(-16, 16, (160, 4)).astype(np.int8)
+    w0 = synth.centre_spike_taps()
+    prm = O.params(**aeq_defaults)
+    out, wf = O.aeq(a, w0, prm)
+    k = 64
+    o1, w1 = O.aeq(a[:k], w0, prm)
+    o2, w2 = O.aeq(a[k:], w1, prm, hist=a[k - 16:k])
+    assert np.array_equal(np.concatenate([o1, o2]), out)
+    assert np.array_equal(w2, wf)
+
+
+def test_rde_reduces_radius_error():
+    # Sanity of the chosen constants (not parity): on the 75 km channel the RDE
+    # pulls the outputs onto the 16QAM rings as the taps adapt.
+    ch = synth.single_channel(1 << 14)
+    prm = synth.aeq_params_for(ch)
+    out, wf, a = O.cdc_aeq(ch.samples, ch.taps, ch.requant_shift, synth.centre_spike_taps(),
+                           O.params(**prm))
+    c2 = prm["const_unit"] ** 2
+    y = out.astype(np.float64)
+
+    def ring_err(seg):
+        errs = []
+        for p in range(2):
+            r2 = seg[:, 2 * p] ** 2 + seg[:, 2 * p + 1] ** 2
+            R2 = np.where(r2 < 6 * c2, 2 * c2, np.where(r2 < 14 * c2, 10 * c2, 18 * c2))
+            errs.append(np.mean(np.abs(R2 - r2)) / c2)
+        return float(np.mean(errs))
+
+    early, late = ring_err(y[16:1024]), ring_err(y[-4096:])
+    assert late < 0.7 * early, (early, late)
+
+
+def test_chain_equals_parts_and_batch(aeq_defaults):
+    prm = O.params(**aeq_defaults)
+    chs = [synth.gen_channel(n, km, 20.0, seed=s) for n, km, s in ((300, 75, 1), (17, 12, 2), (0, 40, 3))]
+    ref = []
+    for ch in chs:
+        _, a = O.cdc(ch.samples, ch.taps, ch.requant_shift)
+        out, wf = O.aeq(a, synth.centre_spike_taps(), prm)
+        o2, w2, a2 = O.cdc_aeq(ch.samples, ch.taps, ch.requant_shift, synth.centre_spike_taps(), prm)
+        assert np.array_equal(out, o2) and np.array_equal(wf, w2) and np.array_equal(a, a2)
+        ref.append((out, wf))
+    outs, finals, used = O.batch([dict(samples=c.samples, taps=c.taps, shift=c.requant_shift,
+                                       w=synth.centre_spike_taps(), params=prm) for c in chs],
+                                 threads=2)
+    assert used >= 1
+    for (o, w), o2, w2 in zip(ref, outs, finals):
+        assert np.array_equal(o, o2) and np.array_equal(w, w2)
