@@ -1,0 +1,283 @@
+/*
+ * libfnt -- Fermat-number-transform chromatic-dispersion compensation (FNT-CDC)
+ * and adaptive equalisation (FNT-AEQ) on AMD MI355X (gfx950).
+ *
+ * Method: "Fermat Number Transform Based Chromatic Dispersion Compensation and
+ * Adaptive Equalization Algorithm" (arXiv 2405.04253).
+ *
+ * Conventions for every entry point
+ *  - Return value: FNT_OK (0) or one of the FNT_E_* codes below.  No exception,
+ *    abort or longjmp crosses this interface.  fnt_last_error() gives text for the
+ *    last failure on the calling thread.
+ *  - Buffers are caller-owned DEVICE pointers unless a name starts with host_.
+ *    The library never frees caller memory.  int8 sample/symbol buffers must be
+ *    4-byte aligned, int16/int32 buffers 8-byte aligned.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Calls
+ *    that take a stream only enqueue work on it and return; results are valid
+ *    once the stream has reached that point.
+ *  - Values that must lie in a declared bit width and live in device memory are
+ *    checked by the kernels; a violation is latched in a per-device flag and
+ *    reported as FNT_E_RANGE by fnt_check().  Outputs of such a call are then
+ *    unspecified (but every access stays in bounds).
+ *
+ * Data layouts
+ *  - instant   : one 2-samples/symbol dual-polarisation sample, int8[4] =
+ *                {XI, XQ, YI, YQ}, each 5-bit two's complement in [-16, 15].
+ *  - symbol    : one 1-sample/symbol dual-polarisation value, int8[4] (AEQ
+ *                input, 5 bit) or int16[4] (AEQ output).
+ *  - AEQ taps  : int16[4 S1][4 S2][16], 14-bit two's complement in
+ *                [-8192, 8191]; S1 = input stream, S2 = output stream, both
+ *                ordered XI, XQ, YI, YQ (4x4 real-valued MIMO).
+ */
+#ifndef FNT_H
+#define FNT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    FNT_OK = 0,
+    FNT_E_INVAL = 1,   /* bad shape, parameter, alignment or NULL pointer */
+    FNT_E_RANGE = 2,   /* an input value outside its declared bit width / >= F */
+    FNT_E_NOMEM = 3,   /* device or host allocation failed */
+    FNT_E_DEVICE = 4,  /* a HIP call failed (text in fnt_last_error) */
+    FNT_E_BUSY = 5,    /* admission refused: the request does not fit right now */
+    FNT_E_STATE = 6    /* unknown channel / ticket, or an object in the wrong state */
+};
+
+enum { FNT_ALPHA_2 = 0, FNT_ALPHA_SQRT2 = 1 };
+
+#define FNT_MAX_CDC_TAPS 32
+#define FNT_AEQ_TAPS 16
+#define FNT_AEQ_BLOCK 16       /* symbols per AEQ block (one tap update per block) */
+#define FNT_CDC_HOP 32         /* new instants per CDC overlap-save block */
+
+/* Text of the last error on this thread ("" if none).  The pointer stays valid
+ * until the next failing call on the same thread. */
+const char *fnt_last_error(void);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int fnt_version(void);
+
+/* Synchronise `stream`, then report and clear the per-device range flag of the
+ * current device: FNT_E_RANGE if any kernel launched since the previous check
+ * saw an out-of-range input, else FNT_OK. */
+int fnt_check(void *stream);
+
+/* ------------------------------------------------------------------------
+ * Transforms -- Eq. (1) (forward) and Eq. (2) (inverse, including N^-1) over
+ * Z_F with F = 2^(2^t) + 1 (FNT section).  Supported (t, N, alpha):
+ *   (2,  8, 2)      the 8-point, radix-2, modulus-17 example of Fig. 1
+ *   (4, 32, 2)      the FNT-AEQ transform (Proposed structure, AEQ part)
+ *   (4, 64, sqrt 2) the FNT-CDC transform (Proposed structure, CDC part),
+ *                   alpha = 2^12 - 2^4 = 4080, the square root of 2 whose
+ *                   powers are sums of two powers of two.
+ * x, X : uint32[batch][N], natural order, canonical residues in [0, F).  In-place
+ * (x == X) is allowed.  Inputs >= F are a range error (flagged, see fnt_check).
+ * log2n must equal log2 of N above; other combinations return FNT_E_INVAL.
+ * ------------------------------------------------------------------------ */
+int fnt_forward(const uint32_t *x, uint32_t *X, size_t batch, int t, int log2n,
+                int alpha_kind, void *stream);
+int fnt_inverse(const uint32_t *X, uint32_t *x, size_t batch, int t, int log2n,
+                int alpha_kind, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Parameters (host structs, copied at call time)
+ * ------------------------------------------------------------------------ */
+
+/* CDC (Proposed structure: F = 65537, alpha = sqrt 2, N = 64, 5-bit signal,
+ * 6-bit taps; complex product by Eqs. (7)-(8)).
+ *   taps[k] = (re, im), 6-bit in [-32, 31], k < ntaps; entries >= ntaps ignored.
+ *   ntaps in [1, 32]: with 32 new instants per 64-point block the circular
+ *   convolution equals the linear one (the zero-padding remark after Eq. (5)),
+ *   and Eq. (5) holds: 32 taps * 1024 <= (F - 1) / 2.
+ *   requant_shift s_c in [0, 16]: the 1-sample/symbol output is
+ *   a[m] = sat5(rs(z[2m + decim_phase], s_c)), rs(v, s) = floor((v + 2^(s-1)) / 2^s).
+ *   decim_phase in {0, 1}: which 2-sps instant of each symbol is kept. */
+typedef struct fnt_cdc_params {
+    int8_t taps[FNT_MAX_CDC_TAPS][2];
+    int32_t ntaps;
+    int32_t requant_shift;
+    int32_t decim_phase;
+} fnt_cdc_params;
+
+/* AEQ (4x4 real-valued MIMO with the RDE update of Eq. (6); 14-bit taps split
+ * into two 7-bit groups convolved separately through F = 65537, alpha = 2,
+ * N = 32 transforms).  Per block of 16 symbols, with the block's taps w:
+ *   y_S2[m]  = sum_S1 sum_k w[S1][S2][k] * a_S1[m - k]           (exact)
+ *   yhat     = sat16(rs(y, out_shift))                              -> output
+ *   r2_P     = yhat_PI^2 + yhat_PQ^2,  R2 = c^2 * {2 if r2 < 6c^2, 10 if r2 < 14c^2, else 18}
+ *   eps_S2   = sat8(rs((R2 - r2_pol(S2)) * yhat_S2, err_shift))
+ *   w       <- sat14(w + rs(sum_m eps_S2[m] * a_S1[m - k], mu_shift))   if update_enable
+ *   out_shift in [0, 24], err_shift in [0, 62], mu_shift in [0, 40],
+ *   const_unit c in [1, 4096], update_enable in {0, 1}. */
+typedef struct fnt_aeq_params {
+    int32_t out_shift;
+    int32_t err_shift;
+    int32_t mu_shift;
+    int32_t const_unit;
+    int32_t update_enable;
+} fnt_aeq_params;
+
+/* ------------------------------------------------------------------------
+ * Single-stream calls (zero history before the first sample).
+ * ------------------------------------------------------------------------ */
+
+/* FNT-CDC of n instants (Fig. 2 structure, Eqs. (5), (7), (8)).
+ *   in        int8[n][4] device
+ *   out_exact int32[n][4] device or NULL: exact z = {Re zX, Im zX, Re zY, Im zY}
+ *   out_1sps  int8[M][4] device or NULL, M = (n + 1 - decim_phase) / 2:
+ *             resampled to 1 sample/symbol and requantised to 5 bit. */
+int fnt_cdc(const int8_t *in, uint64_t n, const fnt_cdc_params *p, int32_t *out_exact,
+            int8_t *out_1sps, void *stream);
+
+/* FNT-AEQ of m symbols (Fig. 3 structure, Eq. (6)).
+ *   in_1sps int8[m][4] device (5-bit values)
+ *   taps    int16[4][4][16] device, read at the start, overwritten with the state
+ *           after the last block's update
+ *   out     int16[m][4] device.
+ * The final partial block (m not a multiple of 16) updates from its valid
+ * symbols only. */
+int fnt_aeq(const int8_t *in_1sps, uint64_t m, int16_t *taps, const fnt_aeq_params *p,
+            int16_t *out, void *stream);
+
+/* The receiver chain on one channel: fnt_cdc (to 1 sample/symbol) then fnt_aeq.
+ * out int16[M][4] with M = (n + 1 - decim_phase) / 2.  The 1-sample/symbol
+ * stream lives in a stream-ordered scratch of M*4 bytes (hipMallocAsync and
+ * hipFreeAsync on `stream`). */
+int fnt_cdc_aeq(const int8_t *in, uint64_t n, const fnt_cdc_params *cp, int16_t *taps,
+                const fnt_aeq_params *ap, int16_t *out, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batched plans: many independent channels in one launch sequence.
+ * ------------------------------------------------------------------------ */
+
+typedef struct fnt_channel_desc {
+    const int8_t *in;      /* device int8[n][4] */
+    int16_t *out;          /* device int16[M][4], M = (n + 1 - cdc.decim_phase) / 2 */
+    int16_t *taps;         /* device int16[4][4][16], in/out as for fnt_aeq */
+    uint64_t n;            /* instants */
+    fnt_cdc_params cdc;
+    fnt_aeq_params aeq;
+} fnt_channel_desc;
+
+typedef struct fnt_plan_config {
+    int32_t device;        /* HIP device ordinal the buffers live on */
+    int32_t autotune;      /* 1: time the candidate schedules at create and keep the fastest */
+    int32_t use_graph;     /* 1: capture the launch sequence in a hipGraph, replay it in run */
+    int32_t reserved;
+    const char *tune_cache;/* optional JSON file remembering autotune results (NULL: none) */
+} fnt_plan_config;
+
+typedef struct fnt_plan_info {
+    uint64_t channels;
+    uint64_t instants;     /* total instants over all channels */
+    uint64_t symbols;      /* total output symbols */
+    uint64_t cdc_blocks;   /* total 32-instant CDC blocks */
+    uint64_t aeq_blocks_max;  /* longest per-channel AEQ chain, in 16-symbol blocks */
+    int32_t cdc_waves_per_group;  /* chosen schedule */
+    int32_t cdc_blocks_per_wave;
+    int32_t aeq_variant;   /* 0 = Fermat-domain filtering (the method), 1 = direct comparator */
+    int32_t graph;         /* 1 if a hipGraph is replayed */
+    double tune_ms;        /* time of the chosen schedule during autotune (0 if none) */
+} fnt_plan_info;
+
+typedef struct fnt_plan fnt_plan;
+
+/* Build a plan for `nch` channels (copied; the device buffers must stay valid
+ * while the plan is used).  Allocates the plan's device tables and scratch.
+ * With autotune, times the candidate CDC schedules on `stream` (the CDC stage
+ * only writes plan scratch; taps and outputs are not touched). */
+int fnt_plan_create(fnt_plan **plan, const fnt_channel_desc *host_channels, size_t nch,
+                    const fnt_plan_config *cfg, void *stream);
+/* Run every channel once (CDC + resample + AEQ), enqueued on `stream`. */
+int fnt_plan_run(fnt_plan *plan, void *stream);
+int fnt_plan_get_info(const fnt_plan *plan, fnt_plan_info *info);
+int fnt_plan_destroy(fnt_plan *plan);
+
+/* Direct-convolution comparator of the same chain (bit-identical results; no
+ * Fermat-domain arithmetic): aeq_variant = 1 selects it in a plan. */
+int fnt_plan_set_aeq_variant(fnt_plan *plan, int variant);
+
+/* ------------------------------------------------------------------------
+ * Serving sessions: continuing per-channel streams with device-resident state.
+ * ------------------------------------------------------------------------ */
+
+typedef struct fnt_session_config {
+    int32_t device;
+    uint32_t max_channels;     /* channel ids are 0 .. max_channels-1 */
+    uint64_t hbm_budget_bytes; /* staging pool for FNT_SUBMIT_HOST requests + scratch */
+    uint32_t chunk_blocks;     /* AEQ blocks advanced per request per tick (0: 64) */
+    uint32_t max_active;       /* requests advanced per tick (0: max_channels) */
+} fnt_session_config;
+
+typedef struct fnt_session_stats {
+    uint64_t submitted, completed, cancelled, rejected;
+    uint64_t instants_done;    /* instants of completed requests */
+    uint64_t ticks;            /* launch ticks issued */
+    double p50_us, p99_us, mean_us, max_us;  /* completion - arrival, completed requests */
+    double first_arrival_s, last_completion_s;  /* session clock, seconds */
+    double gsamples_per_s;     /* instants_done / (last_completion - first_arrival) / 1e9 */
+} fnt_session_stats;
+
+typedef struct fnt_session fnt_session;
+
+#define FNT_SUBMIT_HOST 1u     /* in/out are host pointers, staged through the HBM pool */
+
+/* Session state of one channel, as exported by fnt_session_get_state. */
+#define FNT_STATE_BYTES 768
+
+uint64_t fnt_now_ns(void);     /* the session clock (monotonic, ns) */
+
+int fnt_session_create(fnt_session **s, const fnt_session_config *cfg);
+/* Register channel `ch` with its CDC and AEQ parameters and initial taps
+ * (host int16[4][4][16]; NULL = centre spike 4096 at tap 8 on each S1 == S2). */
+int fnt_session_add_channel(fnt_session *s, uint32_t ch, const fnt_cdc_params *cp,
+                            const fnt_aeq_params *ap, const int16_t *host_init_taps);
+/* Queue `n` instants (a multiple of 32) of channel `ch`'s continuing stream.
+ * Output: n/2 symbols int16[n/2][4] (decim_phase 0) at `out`.  `in`/`out` are
+ * device pointers unless flags has FNT_SUBMIT_HOST.  Requests of one channel run
+ * in submission order; a channel's output depends only on its own stream.
+ * arrival_ns (session clock, 0 = now) is the time latency is measured from.
+ * FNT_E_BUSY: a host-buffer request larger than the whole HBM budget. */
+int fnt_session_submit(fnt_session *s, uint32_t ch, const int8_t *in, uint64_t n,
+                       int16_t *out, uint32_t flags, uint64_t arrival_ns, uint64_t *ticket);
+int fnt_session_poll(fnt_session *s, uint64_t ticket, int *done);
+int fnt_session_wait(fnt_session *s, uint64_t ticket);
+/* Wait until every submitted request has completed. */
+int fnt_session_drain(fnt_session *s);
+/* Cancel a request that has not started; FNT_E_STATE if it already runs or ended. */
+int fnt_session_cancel(fnt_session *s, uint64_t ticket);
+/* Export / import one channel's resident state (taps, overlap tails, stream
+ * position) to/from host memory of FNT_STATE_BYTES.  The channel must be idle. */
+int fnt_session_get_state(fnt_session *s, uint32_t ch, void *host_buf, size_t *size);
+int fnt_session_set_state(fnt_session *s, uint32_t ch, const void *host_buf, size_t size);
+int fnt_session_get_stats(fnt_session *s, fnt_session_stats *st);
+
+/* One request of a replayed arrival trace: submitted at start + at_ns. */
+typedef struct fnt_request {
+    uint32_t ch;
+    uint32_t flags;
+    const int8_t *in;
+    int16_t *out;
+    uint64_t n;
+    uint64_t at_ns;
+} fnt_request;
+
+/* Submit `nreq` requests at their scheduled times (offsets from the call, in
+ * ascending order), from the calling thread, with arrival stamped as the
+ * scheduled time.  Returns after the last submission; tickets[i] (optional)
+ * receive the tickets.  Use fnt_session_drain to wait for completion. */
+int fnt_session_replay(fnt_session *s, const fnt_request *reqs, size_t nreq, uint64_t *tickets);
+/* Drains outstanding work, then frees everything. */
+int fnt_session_destroy(fnt_session *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FNT_H */

@@ -1,0 +1,568 @@
+// C ABI of libfnt: errors, parameter validation, single-stream calls and
+// batched plans (device tables, hipGraph capture, schedule autotuning).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "fnt_common.hpp"
+#include "fnt_internal.hpp"
+
+using namespace fnti;
+
+namespace fnti {
+
+static thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(FNT_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+struct DeviceCtx {
+    int *d_err = nullptr;
+};
+
+static std::mutex g_ctx_mu;
+static std::map<int, DeviceCtx> g_ctx;
+
+int device_err_flag(int **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> g(g_ctx_mu);
+    DeviceCtx &c = g_ctx[dev];
+    if (!c.d_err) {
+        e = hipMalloc(&c.d_err, sizeof(int));
+        if (e != hipSuccess) return fail(FNT_E_NOMEM, "hipMalloc(range flag): %s", hipGetErrorString(e));
+        e = hipMemset(c.d_err, 0, sizeof(int));
+        if (e != hipSuccess) return hip_fail(e, "hipMemset(range flag)");
+    }
+    *out = c.d_err;
+    return FNT_OK;
+}
+
+int validate_cdc(const fnt_cdc_params *p) {
+    if (!p) return fail(FNT_E_INVAL, "cdc params: NULL");
+    if (p->ntaps < 1 || p->ntaps > FNT_MAX_CDC_TAPS)
+        return fail(FNT_E_INVAL, "cdc params: ntaps %d outside [1, 32]", p->ntaps);
+    if (p->requant_shift < 0 || p->requant_shift > 16)
+        return fail(FNT_E_INVAL, "cdc params: requant_shift %d outside [0, 16]", p->requant_shift);
+    if (p->decim_phase != 0 && p->decim_phase != 1)
+        return fail(FNT_E_INVAL, "cdc params: decim_phase %d not 0 or 1", p->decim_phase);
+    for (int k = 0; k < p->ntaps; ++k)
+        for (int c = 0; c < 2; ++c)
+            if (p->taps[k][c] < -32 || p->taps[k][c] > 31)
+                return fail(FNT_E_RANGE, "cdc params: tap %d component %d = %d outside 6 bit", k, c,
+                            p->taps[k][c]);
+    return FNT_OK;
+}
+
+int validate_aeq(const fnt_aeq_params *p) {
+    if (!p) return fail(FNT_E_INVAL, "aeq params: NULL");
+    if (p->out_shift < 0 || p->out_shift > 24)
+        return fail(FNT_E_INVAL, "aeq params: out_shift %d outside [0, 24]", p->out_shift);
+    if (p->err_shift < 0 || p->err_shift > 62)
+        return fail(FNT_E_INVAL, "aeq params: err_shift %d outside [0, 62]", p->err_shift);
+    if (p->mu_shift < 0 || p->mu_shift > 40)
+        return fail(FNT_E_INVAL, "aeq params: mu_shift %d outside [0, 40]", p->mu_shift);
+    if (p->const_unit < 1 || p->const_unit > 4096)
+        return fail(FNT_E_INVAL, "aeq params: const_unit %d outside [1, 4096]", p->const_unit);
+    if (p->update_enable != 0 && p->update_enable != 1)
+        return fail(FNT_E_INVAL, "aeq params: update_enable %d not 0 or 1", p->update_enable);
+    return FNT_OK;
+}
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+void fill_cdc_item(CdcItem &it, const int8_t *in, uint64_t n, const fnt_cdc_params *p) {
+    std::memset(&it, 0, sizeof it);
+    it.in = in;
+    it.n = n;
+    std::memcpy(it.taps, p->taps, sizeof it.taps);
+    for (int k = p->ntaps; k < FNT_MAX_CDC_TAPS; ++k) it.taps[k][0] = it.taps[k][1] = 0;
+    it.ntaps = p->ntaps;
+    it.shift = p->requant_shift;
+    it.phase = p->decim_phase;
+}
+
+void fill_aeq_item(AeqItem &it, const int8_t *a, uint64_t m, int16_t *taps, const fnt_aeq_params *p,
+                   int16_t *out) {
+    std::memset(&it, 0, sizeof it);
+    it.a = a;
+    it.m = m;
+    it.taps = taps;
+    it.out = out;
+    it.out_shift = p->out_shift;
+    it.err_shift = p->err_shift;
+    it.mu_shift = p->mu_shift;
+    it.const_unit = p->const_unit;
+    it.update_enable = p->update_enable;
+}
+
+// Default CDC schedule: enough waves to fill 256 CUs several times over.
+void default_cdc_schedule(uint64_t total_blocks, int *wpg, int *bpw) {
+    *wpg = 4;
+    uint64_t b = total_blocks / (256ull * 4 * 16);
+    *bpw = (int)std::max<uint64_t>(1, std::min<uint64_t>(64, b));
+}
+
+}  // namespace fnti
+
+// ------------------------------------------------------------------ C ABI --
+
+extern "C" {
+
+const char *fnt_last_error(void) { return fnti::g_last_error.c_str(); }
+
+int fnt_version(void) { return 10000; }
+
+int fnt_check(void *stream) {
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    int *d = nullptr;
+    int rc = device_err_flag(&d);
+    if (rc) return rc;
+    int h = 0;
+    e = hipMemcpy(&h, d, sizeof h, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(range flag)");
+    if (h) {
+        e = hipMemset(d, 0, sizeof(int));
+        if (e != hipSuccess) return hip_fail(e, "hipMemset(range flag)");
+        return fail(FNT_E_RANGE, "input value outside its declared width (flags 0x%x)", h);
+    }
+    return FNT_OK;
+}
+
+static int transform_common(const uint32_t *x, uint32_t *X, size_t batch, int t, int log2n,
+                            int alpha_kind, bool inv, void *stream) {
+    bool legal = (t == 2 && log2n == 3 && alpha_kind == FNT_ALPHA_2) ||
+                 (t == 4 && log2n == 5 && alpha_kind == FNT_ALPHA_2) ||
+                 (t == 4 && log2n == 6 && alpha_kind == FNT_ALPHA_SQRT2);
+    if (!legal)
+        return fail(FNT_E_INVAL, "unsupported transform (t=%d, log2n=%d, alpha=%d)", t, log2n,
+                    alpha_kind);
+    if (batch == 0) return FNT_OK;
+    if (!x || !X) return fail(FNT_E_INVAL, "transform: NULL buffer");
+    if (!aligned(x, 4) || !aligned(X, 4)) return fail(FNT_E_INVAL, "transform: misaligned buffer");
+    int *err = nullptr;
+    int rc = device_err_flag(&err);
+    if (rc) return rc;
+    hipError_t e = launch_transform(x, X, batch, t, log2n, alpha_kind, inv, err, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "transform launch");
+    return FNT_OK;
+}
+
+int fnt_forward(const uint32_t *x, uint32_t *X, size_t batch, int t, int log2n, int alpha_kind,
+                void *stream) {
+    return transform_common(x, X, batch, t, log2n, alpha_kind, false, stream);
+}
+
+int fnt_inverse(const uint32_t *X, uint32_t *x, size_t batch, int t, int log2n, int alpha_kind,
+                void *stream) {
+    return transform_common(X, x, batch, t, log2n, alpha_kind, true, stream);
+}
+
+int fnt_cdc(const int8_t *in, uint64_t n, const fnt_cdc_params *p, int32_t *out_exact,
+            int8_t *out_1sps, void *stream) {
+    int rc = validate_cdc(p);
+    if (rc) return rc;
+    if (n == 0) return FNT_OK;
+    if (!in) return fail(FNT_E_INVAL, "fnt_cdc: NULL input");
+    if (!aligned(in, 4) || (out_exact && !aligned(out_exact, 16)) || (out_1sps && !aligned(out_1sps, 4)))
+        return fail(FNT_E_INVAL, "fnt_cdc: misaligned buffer");
+    int *err = nullptr;
+    if ((rc = device_err_flag(&err))) return rc;
+    CdcItem it;
+    fill_cdc_item(it, in, n, p);
+    it.z_out = out_exact;
+    it.a_out = out_1sps;
+    int wpg, bpw;
+    default_cdc_schedule(cdc_blocks(n), &wpg, &bpw);
+    hipError_t e = launch_cdc(nullptr, 0, it, cdc_blocks(n), wpg, bpw, out_exact != nullptr, err,
+                              (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "fnt_cdc launch");
+    return FNT_OK;
+}
+
+int fnt_aeq(const int8_t *in_1sps, uint64_t m, int16_t *taps, const fnt_aeq_params *p, int16_t *out,
+            void *stream) {
+    int rc = validate_aeq(p);
+    if (rc) return rc;
+    if (!taps) return fail(FNT_E_INVAL, "fnt_aeq: NULL taps");
+    if (m > 0 && (!in_1sps || !out)) return fail(FNT_E_INVAL, "fnt_aeq: NULL buffer");
+    if (!aligned(in_1sps, 4) || !aligned(out, 8) || !aligned(taps, 2))
+        return fail(FNT_E_INVAL, "fnt_aeq: misaligned buffer");
+    int *err = nullptr;
+    if ((rc = device_err_flag(&err))) return rc;
+    AeqItem it;
+    fill_aeq_item(it, in_1sps, m, taps, p, out);
+    hipError_t e = launch_aeq(nullptr, 0, it, 0, err, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "fnt_aeq launch");
+    return FNT_OK;
+}
+
+int fnt_cdc_aeq(const int8_t *in, uint64_t n, const fnt_cdc_params *cp, int16_t *taps,
+                const fnt_aeq_params *ap, int16_t *out, void *stream) {
+    int rc = validate_cdc(cp);
+    if (rc) return rc;
+    if ((rc = validate_aeq(ap))) return rc;
+    if (!taps) return fail(FNT_E_INVAL, "fnt_cdc_aeq: NULL taps");
+    const uint64_t M = n_symbols(n, cp->decim_phase);
+    if (n > 0 && (!in || !out)) return fail(FNT_E_INVAL, "fnt_cdc_aeq: NULL buffer");
+    if (!aligned(in, 4) || !aligned(out, 8) || !aligned(taps, 2))
+        return fail(FNT_E_INVAL, "fnt_cdc_aeq: misaligned buffer");
+    int *err = nullptr;
+    if ((rc = device_err_flag(&err))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    int8_t *abuf = nullptr;
+    if (M > 0) {
+        hipError_t e = hipMallocAsync((void **)&abuf, M * 4, s);
+        if (e != hipSuccess) return fail(FNT_E_NOMEM, "hipMallocAsync(%llu): %s",
+                                         (unsigned long long)(M * 4), hipGetErrorString(e));
+        CdcItem ci;
+        fill_cdc_item(ci, in, n, cp);
+        ci.a_out = abuf;
+        int wpg, bpw;
+        default_cdc_schedule(cdc_blocks(n), &wpg, &bpw);
+        e = launch_cdc(nullptr, 0, ci, cdc_blocks(n), wpg, bpw, false, err, s);
+        if (e != hipSuccess) {
+            (void)hipFreeAsync(abuf, s);
+            return hip_fail(e, "fnt_cdc_aeq: cdc launch");
+        }
+    }
+    AeqItem ai;
+    fill_aeq_item(ai, abuf, M, taps, ap, out);
+    hipError_t e = launch_aeq(nullptr, 0, ai, 0, err, s);
+    if (abuf) (void)hipFreeAsync(abuf, s);
+    if (e != hipSuccess) return hip_fail(e, "fnt_cdc_aeq: aeq launch");
+    return FNT_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ plans --
+
+struct fnt_plan {
+    int device = 0;
+    std::vector<CdcItem> cdc_host;
+    std::vector<AeqItem> aeq_host;
+    CdcItem *cdc_dev = nullptr;
+    AeqItem *aeq_dev = nullptr;
+    int8_t *abuf = nullptr;
+    int *err = nullptr;
+    uint64_t total_blocks = 0;
+    fnt_plan_info info{};
+    int wpg = 4, bpw = 1, variant = 0;
+    bool use_graph = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+static int plan_launch(fnt_plan *p, hipStream_t s) {
+    hipError_t e = launch_cdc(p->cdc_dev, (int)p->cdc_host.size(), CdcItem{}, p->total_blocks, p->wpg,
+                              p->bpw, false, p->err, s);
+    if (e != hipSuccess) return hip_fail(e, "plan: cdc launch");
+    e = launch_aeq(p->aeq_dev, (int)p->aeq_host.size(), AeqItem{}, p->variant, p->err, s);
+    if (e != hipSuccess) return hip_fail(e, "plan: aeq launch");
+    return FNT_OK;
+}
+
+static void plan_drop_graph(fnt_plan *p) {
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+}
+
+static int plan_capture(fnt_plan *p, hipStream_t s) {
+    plan_drop_graph(p);
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "plan: capture stream");
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return hip_fail(e, "plan: begin capture");
+    }
+    int rc = plan_launch(p, cs);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cs, &g);
+    (void)hipStreamDestroy(cs);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "plan: end capture");
+    e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(e, "plan: graph instantiate");
+    }
+    p->graph = g;
+    (void)s;
+    return FNT_OK;
+}
+
+static std::string tune_key(const fnt_plan *p) {
+    // length histogram (log2 buckets of instants) + channel count + variant
+    int hist[48] = {0};
+    for (const CdcItem &c : p->cdc_host) {
+        int b = 0;
+        while (b < 47 && (1ull << (b + 1)) <= c.n) ++b;
+        hist[b]++;
+    }
+    std::ostringstream k;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) k << prop.gcnArchName;
+    k << "|v" << p->variant << "|ch" << p->cdc_host.size() << "|";
+    for (int i = 0; i < 48; ++i)
+        if (hist[i]) k << i << ":" << hist[i] << ",";
+    return k.str();
+}
+
+static bool tune_cache_lookup(const char *path, const std::string &key, int *wpg, int *bpw) {
+    if (!path) return false;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        // one JSON object per line: {"key": "...", "wpg": W, "bpw": B}
+        size_t a = line.find("\"key\": \"");
+        if (a == std::string::npos) continue;
+        size_t b = line.find('"', a + 8);
+        if (b == std::string::npos || line.substr(a + 8, b - a - 8) != key) continue;
+        int w = 0, bb = 0;
+        size_t pw = line.find("\"wpg\": "), pb = line.find("\"bpw\": ");
+        if (pw == std::string::npos || pb == std::string::npos) continue;
+        w = std::atoi(line.c_str() + pw + 7);
+        bb = std::atoi(line.c_str() + pb + 7);
+        if (w >= 1 && w <= 4 && bb >= 1) {
+            *wpg = w;
+            *bpw = bb;
+            return true;
+        }
+    }
+    return false;
+}
+
+static void tune_cache_store(const char *path, const std::string &key, int wpg, int bpw, double ms) {
+    if (!path) return;
+    std::ofstream f(path, std::ios::app);
+    f << "{\"key\": \"" << key << "\", \"wpg\": " << wpg << ", \"bpw\": " << bpw << ", \"ms\": " << ms
+      << "}\n";
+}
+
+static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
+    std::string key = tune_key(p);
+    int w, b;
+    if (tune_cache_lookup(cache, key, &w, &b)) {
+        p->wpg = w;
+        p->bpw = b;
+        return FNT_OK;
+    }
+    // candidate CDC schedules; the AEQ schedule is one wave per channel
+    std::vector<std::pair<int, int>> cand;
+    for (int wpg : {1, 2, 4})
+        for (int bpw : {1, 2, 4, 8, 16, 32, 64})
+            if ((uint64_t)bpw <= std::max<uint64_t>(1, p->total_blocks)) cand.push_back({wpg, bpw});
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    double best = 1e30;
+    int bw = p->wpg, bb = p->bpw;
+    for (auto &c : cand) {
+        // time the CDC stage alone: it is the stage whose schedule varies
+        float ms = 0;
+        hipError_t e = hipSuccess;
+        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+            (void)hipEventRecord(e0, s);
+            e = launch_cdc(p->cdc_dev, (int)p->cdc_host.size(), CdcItem{}, p->total_blocks, c.first,
+                           c.second, false, p->err, s);
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            (void)hipEventElapsedTime(&ms, e0, e1);
+        }
+        if (e != hipSuccess) continue;
+        if (ms < best) {
+            best = ms;
+            bw = c.first;
+            bb = c.second;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p->wpg = bw;
+    p->bpw = bb;
+    p->info.tune_ms = best;
+    tune_cache_store(cache, key, bw, bb, best);
+    return FNT_OK;
+}
+
+extern "C" {
+
+int fnt_plan_create(fnt_plan **out, const fnt_channel_desc *ch, size_t nch, const fnt_plan_config *cfg,
+                    void *stream) {
+    if (!out) return fail(FNT_E_INVAL, "plan: NULL out");
+    *out = nullptr;
+    if (nch > 0 && !ch) return fail(FNT_E_INVAL, "plan: NULL channel table");
+    if (nch > (size_t)0x7FFFFFFF) return fail(FNT_E_INVAL, "plan: too many channels");
+    fnt_plan_config c{};
+    if (cfg) c = *cfg;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (cfg && c.device != dev) {
+        hipError_t e = hipSetDevice(c.device);
+        if (e != hipSuccess) return hip_fail(e, "plan: hipSetDevice");
+        dev = c.device;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    fnt_plan *p = new fnt_plan();
+    p->device = dev;
+    int rc = device_err_flag(&p->err);
+    if (rc) {
+        delete p;
+        return rc;
+    }
+    uint64_t sym_total = 0, blocks = 0, inst = 0, chain_max = 0;
+    std::vector<uint64_t> aoff(nch);
+    for (size_t i = 0; i < nch; ++i) {
+        const fnt_channel_desc &d = ch[i];
+        if ((rc = validate_cdc(&d.cdc)) || (rc = validate_aeq(&d.aeq))) {
+            delete p;
+            return fail(rc, "plan: channel %zu: %s", i, fnt_last_error());
+        }
+        if (!d.taps || (d.n > 0 && (!d.in || !d.out)) || !aligned(d.in, 4) || !aligned(d.out, 8) ||
+            !aligned(d.taps, 2)) {
+            delete p;
+            return fail(FNT_E_INVAL, "plan: channel %zu: NULL or misaligned buffer", i);
+        }
+        uint64_t M = n_symbols(d.n, d.cdc.decim_phase);
+        aoff[i] = sym_total;
+        sym_total += (M + 3) & ~3ull;   // keep each channel's scratch 16-byte aligned
+        inst += d.n;
+        chain_max = std::max(chain_max, (M + 15) / 16);
+    }
+    if (sym_total > 0) {
+        hipError_t e = hipMalloc(&p->abuf, sym_total * 4);
+        if (e != hipSuccess) {
+            delete p;
+            return fail(FNT_E_NOMEM, "plan: scratch of %llu bytes: %s", (unsigned long long)(sym_total * 4),
+                        hipGetErrorString(e));
+        }
+    }
+    p->cdc_host.resize(nch);
+    p->aeq_host.resize(nch);
+    for (size_t i = 0; i < nch; ++i) {
+        const fnt_channel_desc &d = ch[i];
+        CdcItem &ci = p->cdc_host[i];
+        fill_cdc_item(ci, d.in, d.n, &d.cdc);
+        ci.a_out = p->abuf + aoff[i] * 4;
+        ci.block0 = blocks;
+        blocks += cdc_blocks(d.n);
+        AeqItem &ai = p->aeq_host[i];
+        fill_aeq_item(ai, ci.a_out, n_symbols(d.n, d.cdc.decim_phase), d.taps, &d.aeq, d.out);
+    }
+    // longest AEQ chains first: they bound the makespan
+    std::stable_sort(p->aeq_host.begin(), p->aeq_host.end(),
+                     [](const AeqItem &a, const AeqItem &b) { return a.m > b.m; });
+    p->total_blocks = blocks;
+    hipError_t e = hipSuccess;
+    if (nch > 0) {
+        e = hipMalloc(&p->cdc_dev, nch * sizeof(CdcItem));
+        if (e == hipSuccess) e = hipMalloc(&p->aeq_dev, nch * sizeof(AeqItem));
+        if (e != hipSuccess) {
+            fnt_plan_destroy(p);
+            return fail(FNT_E_NOMEM, "plan: tables: %s", hipGetErrorString(e));
+        }
+        e = hipMemcpyAsync(p->cdc_dev, p->cdc_host.data(), nch * sizeof(CdcItem), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(p->aeq_dev, p->aeq_host.data(), nch * sizeof(AeqItem), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            fnt_plan_destroy(p);
+            return hip_fail(e, "plan: upload tables");
+        }
+    }
+    default_cdc_schedule(blocks, &p->wpg, &p->bpw);
+    if (c.autotune && blocks > 0) {
+        if ((rc = plan_autotune(p, s, c.tune_cache))) {
+            fnt_plan_destroy(p);
+            return rc;
+        }
+    }
+    p->use_graph = c.use_graph != 0;
+    if (p->use_graph && nch > 0) {
+        if ((rc = plan_capture(p, s))) {
+            fnt_plan_destroy(p);
+            return rc;
+        }
+    }
+    p->info.channels = nch;
+    p->info.instants = inst;
+    p->info.symbols = 0;
+    for (auto &a : p->aeq_host) p->info.symbols += a.m;
+    p->info.cdc_blocks = blocks;
+    p->info.aeq_blocks_max = chain_max;
+    *out = p;
+    return FNT_OK;
+}
+
+int fnt_plan_run(fnt_plan *p, void *stream) {
+    if (!p) return fail(FNT_E_INVAL, "plan: NULL");
+    if (p->cdc_host.empty()) return FNT_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (p->exec) {
+        hipError_t e = hipGraphLaunch(p->exec, s);
+        if (e != hipSuccess) return hip_fail(e, "plan: graph launch");
+        return FNT_OK;
+    }
+    return plan_launch(p, s);
+}
+
+int fnt_plan_get_info(const fnt_plan *p, fnt_plan_info *info) {
+    if (!p || !info) return fail(FNT_E_INVAL, "plan info: NULL");
+    *info = p->info;
+    info->cdc_waves_per_group = p->wpg;
+    info->cdc_blocks_per_wave = p->bpw;
+    info->aeq_variant = p->variant;
+    info->graph = p->exec ? 1 : 0;
+    return FNT_OK;
+}
+
+int fnt_plan_set_aeq_variant(fnt_plan *p, int variant) {
+    if (!p) return fail(FNT_E_INVAL, "plan: NULL");
+    if (variant != 0 && variant != 1) return fail(FNT_E_INVAL, "plan: variant %d", variant);
+    p->variant = variant;
+    if (p->exec) return plan_capture(p, nullptr);
+    return FNT_OK;
+}
+
+int fnt_plan_destroy(fnt_plan *p) {
+    if (!p) return FNT_OK;
+    plan_drop_graph(p);
+    if (p->cdc_dev) (void)hipFree(p->cdc_dev);
+    if (p->aeq_dev) (void)hipFree(p->aeq_dev);
+    if (p->abuf) (void)hipFree(p->abuf);
+    delete p;
+    return FNT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,163 @@
+// Device-side arithmetic in Z_F, F = 2^Q + 1 (a Fermat number, FNT section of
+// the paper), and the cross-lane radix-2 transforms used by every kernel.
+//
+// Residues are uint32 in canonical form [0, F).  For Q = 16 (F = 65537) all
+// reductions use 2^16 = -1 (mod F): a 32-bit value h*2^16 + l reduces to l - h.
+// Multiplication by a power of the radix is a shift (alpha = 2) or a shift plus
+// one multiply by 2^12 - 2^4 (alpha = sqrt 2), never a general product.
+//
+// Transforms run "across lanes": a group of N consecutive lanes of a wave64
+// holds one length-N vector, one element per lane.  The forward transform is
+// decimation in frequency (natural order in, bit-reversed order out); the
+// inverse is decimation in time (bit-reversed order in, natural order out,
+// unnormalised).  Each radix-2 stage exchanges partners with a lane xor.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fntd {
+
+template <int Q>
+struct Field {
+    static constexpr uint32_t F = (1u << Q) + 1u;
+
+    // Reduce any uint32 to [0, F).
+    static __device__ __forceinline__ uint32_t red(uint32_t x) {
+        if constexpr (Q == 16) {
+            int32_t r = (int32_t)(x & 0xFFFFu) - (int32_t)(x >> 16);
+            return r < 0 ? (uint32_t)(r + (int32_t)F) : (uint32_t)r;
+        } else {
+            return x % F;
+        }
+    }
+    // Signed integer with |v| < 2^31 - F to [0, F).
+    static __device__ __forceinline__ uint32_t from_int(int32_t v) {
+        if constexpr (Q == 16) {
+            // v = h*2^16 + l with l in [0, 65535], h signed: v == l - h (mod F)
+            int32_t r = (int32_t)((uint32_t)v & 0xFFFFu) - (v >> 16);  // in [-32767, 98303]
+            r = r < 0 ? r + (int32_t)F : r;
+            return r >= (int32_t)F ? (uint32_t)(r - (int32_t)F) : (uint32_t)r;
+        } else {
+            int32_t r = v % (int32_t)F;
+            return (uint32_t)(r < 0 ? r + (int32_t)F : r);
+        }
+    }
+    static __device__ __forceinline__ uint32_t add(uint32_t a, uint32_t b) {
+        uint32_t s = a + b;
+        return s >= F ? s - F : s;
+    }
+    static __device__ __forceinline__ uint32_t sub(uint32_t a, uint32_t b) {
+        return a >= b ? a - b : a + F - b;
+    }
+    static __device__ __forceinline__ uint32_t neg(uint32_t a) { return a ? F - a : 0u; }
+    // a * b for canonical a, b.
+    static __device__ __forceinline__ uint32_t mul(uint32_t a, uint32_t b) {
+        if constexpr (Q == 16) {
+            uint64_t p = (uint64_t)a * b;             // <= 2^32
+            uint32_t lo = (uint32_t)p, hi = (uint32_t)(p >> 32);
+            uint32_t r = red(lo) + hi;                 // 2^32 == 1 (mod F)
+            return r >= F ? r - F : r;
+        } else {
+            return (a * b) % F;
+        }
+    }
+    // a * 2^e for canonical a, 0 <= e < 2Q (2^Q == -1).
+    static __device__ __forceinline__ uint32_t mulpow2(uint32_t a, int e) {
+        bool negate = e >= Q;
+        int s = negate ? e - Q : e;
+        uint32_t r;
+        if constexpr (Q == 16) {
+            r = red(a << s);                           // a <= 2^16, s <= 15: fits 32 bits
+        } else {
+            r = (a << s) % F;
+        }
+        return negate ? neg(r) : r;
+    }
+    // a * 2^(Q/4) * (2^(Q/2) - 1), the square root of 2 (Q >= 4).
+    static __device__ __forceinline__ uint32_t mulsqrt2(uint32_t a) {
+        constexpr uint32_t R = (1u << (3 * Q / 4)) - (1u << (Q / 4));
+        if constexpr (Q == 16) {
+            return red(a * R);                         // a * 4080 < 2^28
+        } else {
+            return (a * R) % F;
+        }
+    }
+    // a * alpha^e, alpha = 2 (SQRT2 = false, 0 <= e < 2Q) or sqrt 2 (0 <= e < 4Q).
+    template <bool SQRT2>
+    static __device__ __forceinline__ uint32_t mul_radix_pow(uint32_t a, int e) {
+        if constexpr (SQRT2) {
+            uint32_t r = mulpow2(a, e >> 1);
+            return (e & 1) ? mulsqrt2(r) : r;
+        } else {
+            return mulpow2(a, e);
+        }
+    }
+    // Centred lift of a canonical residue to [-(F-1)/2, (F-1)/2].
+    static __device__ __forceinline__ int32_t lift(uint32_t r) {
+        return r > (F - 1) / 2 ? (int32_t)r - (int32_t)F : (int32_t)r;
+    }
+};
+
+// Forward transform (Eq. (1)) across N = 2^LOGN lanes, decimation in frequency.
+// Lane with position pos = lane & (N-1) holds x[pos]; on return it holds
+// X[bitrev(pos)].  All lanes of the wave must call it (shuffles).
+template <int Q, int LOGN, bool SQRT2>
+__device__ __forceinline__ uint32_t fwd_xlane(uint32_t x, int lane) {
+    using FF = Field<Q>;
+    constexpr int N = 1 << LOGN;
+    const int pos = lane & (N - 1);
+#pragma unroll
+    for (int h = N / 2; h >= 1; h >>= 1) {
+        uint32_t p = (uint32_t)__shfl_xor((int)x, h);
+        bool upper = (pos & h) != 0;
+        int e = (N / (2 * h)) * (pos & (h - 1));
+        uint32_t s = FF::add(x, p);
+        uint32_t d = FF::template mul_radix_pow<SQRT2>(FF::sub(p, x), e);
+        x = upper ? d : s;
+    }
+    return x;
+}
+
+// Inverse transform (Eq. (2) without the N^-1 factor) across N lanes,
+// decimation in time.  Lane pos holds X[bitrev(pos)]; on return it holds
+// N * x[pos].
+template <int Q, int LOGN, bool SQRT2>
+__device__ __forceinline__ uint32_t inv_xlane(uint32_t x, int lane) {
+    using FF = Field<Q>;
+    constexpr int N = 1 << LOGN;
+    const int pos = lane & (N - 1);
+#pragma unroll
+    for (int h = 1; h < N; h <<= 1) {
+        bool upper = (pos & h) != 0;
+        int e = (N / (2 * h)) * (pos & (h - 1));
+        // alpha^-e = alpha^(N - e); upper lanes twiddle their own value first
+        uint32_t t = upper ? FF::template mul_radix_pow<SQRT2>(x, e ? N - e : 0) : x;
+        uint32_t p = (uint32_t)__shfl_xor((int)t, h);
+        x = upper ? FF::sub(p, t) : FF::add(x, p);
+    }
+    return x;
+}
+
+__device__ __forceinline__ int bitrev(int v, int bits) {
+    return (int)(__brev((uint32_t)v) >> (32 - bits));
+}
+
+// Round half up then drop s bits (s >= 0), on 64-bit signed values.
+__device__ __forceinline__ int64_t rs64(int64_t v, int s) {
+    return s > 0 ? ((v + ((int64_t)1 << (s - 1))) >> s) : v;
+}
+__device__ __forceinline__ int32_t rs32(int32_t v, int s) {
+    return s > 0 ? (int32_t)(((int64_t)v + ((int64_t)1 << (s - 1))) >> s) : v;
+}
+__device__ __forceinline__ int64_t clamp64(int64_t v, int64_t lo, int64_t hi) {
+    return v < lo ? lo : (v > hi ? hi : v);
+}
+__device__ __forceinline__ int32_t clamp32(int32_t v, int32_t lo, int32_t hi) {
+    return v < lo ? lo : (v > hi ? hi : v);
+}
+
+// Range-violation bits latched into the per-device flag.
+enum : int { RANGE_SAMPLE = 1, RANGE_TAP = 2, RANGE_RESIDUE = 4, RANGE_SYMBOL = 8 };
+
+}  // namespace fntd

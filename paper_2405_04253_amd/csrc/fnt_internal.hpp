@@ -1,0 +1,61 @@
+// Internal interfaces between the C-ABI layer and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/fnt.h"
+
+namespace fnti {
+
+// One channel's CDC work: 32 new instants per overlap-save block.
+struct CdcItem {
+    const int8_t *in;      // [n][4]
+    const int8_t *hist;    // [32][4] instants preceding in[0], or nullptr (zeros)
+    int32_t *z_out;        // [n][4] or nullptr
+    int8_t *a_out;         // [M][4] or nullptr, M = (n + 1 - phase) / 2
+    uint64_t n;
+    uint64_t block0;       // first global block index of this item (prefix sum)
+    int8_t taps[32][2];
+    int32_t ntaps;
+    int32_t shift;
+    int32_t phase;
+    int32_t pad_;
+};
+
+// One channel's AEQ run over m symbols (serial chain of 16-symbol blocks).
+struct AeqItem {
+    const int8_t *a;       // [m][4]
+    int16_t *out;          // [m][4]
+    int16_t *taps;         // [4][4][16] in/out
+    const int8_t *hist_in; // [16][4] symbols preceding a[0], or nullptr (zeros)
+    int8_t *hist_out;      // [16][4] receives the last 16 symbols, or nullptr
+    const int8_t *cdc_in;  // CDC input of this run, for the CDC tail update
+    int8_t *cdc_tail;      // [32][4] CDC history (in/out), or nullptr: no update
+    uint64_t cdc_n;        // instants in cdc_in
+    uint64_t m;
+    int32_t out_shift;
+    int32_t err_shift;
+    int32_t mu_shift;
+    int32_t const_unit;
+    int32_t update_enable;
+    int32_t pad_;
+};
+
+__host__ __device__ inline uint64_t cdc_blocks(uint64_t n) { return (n + 31) / 32; }
+__host__ __device__ inline uint64_t n_symbols(uint64_t n, int phase) {
+    return n + 1 > (uint64_t)phase ? (n + 1 - (uint64_t)phase) / 2 : 0;
+}
+
+// Launchers (fnt_kernels.hip).  `items` is a device table or nullptr, in which
+// case `single` is used (passed by value in the kernel arguments).
+hipError_t launch_transform(const uint32_t *x, uint32_t *X, size_t batch, int t, int log2n,
+                            int alpha_kind, bool inverse, int *err, hipStream_t s);
+hipError_t launch_cdc(const CdcItem *items, int nitems, const CdcItem &single,
+                      uint64_t total_blocks, int waves_per_group, int blocks_per_wave,
+                      bool with_z, int *err, hipStream_t s);
+hipError_t launch_aeq(const AeqItem *items, int nitems, const AeqItem &single, int variant,
+                      int *err, hipStream_t s);
+
+}  // namespace fnti

@@ -1,0 +1,497 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, bit-exact.
+
+Every result of the path is integer, so the tolerance is zero everywhere.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import fnt_ref as R
+from paper_2405_04253_amd import fnt, synth
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    fnt.lib()
+    fnt.fnt_check()
+    return torch, torch.device("cuda:0")
+
+
+def note(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def to_dev(torch, dev, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+# ---------------------------------------------------------------- transforms --
+TRANSFORMS = [(2, 3, fnt.FNT_ALPHA_2, 17, 2), (4, 5, fnt.FNT_ALPHA_2, 65537, 2),
+              (4, 6, fnt.FNT_ALPHA_SQRT2, 65537, 4080)]
+
+
+def test_transform_fig1_golden(torch_dev):
+    torch, dev = torch_dev
+    rows = []
+    for line in open(os.path.join(GOLDEN, "fig1_fnt8_mod17.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        x, X = line.split("|")
+        rows.append(([int(v) for v in x.split()], [int(v) for v in X.split()]))
+    xs = to_dev(torch, dev, np.array([r[0] for r in rows], np.int32))
+    note("fnt_forward t=2 N=8 golden")
+    got = fnt.fnt_forward(xs, 2, 3, fnt.FNT_ALPHA_2).cpu().numpy()
+    assert got.tolist() == [r[1] for r in rows]
+    back = fnt.fnt_inverse(to_dev(torch, dev, got), 2, 3, fnt.FNT_ALPHA_2).cpu().numpy()
+    assert back.tolist() == [r[0] for r in rows]
+    fnt.fnt_check()
+
+
+@pytest.mark.parametrize("t,log2n,kind,F,alpha", TRANSFORMS)
+def test_transform_random_vs_definition(torch_dev, t, log2n, kind, F, alpha):
+    torch, dev = torch_dev
+    N = 1 << log2n
+    rng = np.random.default_rng(N + t)
+    batch = 37
+    x = rng.integers(0, F, (batch, N)).astype(np.int64)
+    x[0, :] = F - 1
+    x[1, :] = 0
+    x[2, :] = np.arange(N) % F
+    xd = to_dev(torch, dev, x.astype(np.int32))
+    note(f"fnt_forward t={t} N={N} batch={batch}")
+    X = fnt.fnt_forward(xd, t, log2n, kind).cpu().numpy().astype(np.int64)
+    for b in range(batch):
+        assert X[b].tolist() == R.fnt(x[b].tolist(), alpha, F), b
+    note(f"fnt_inverse t={t} N={N}")
+    xi = fnt.fnt_inverse(to_dev(torch, dev, X.astype(np.int32)), t, log2n, kind).cpu().numpy()
+    assert np.array_equal(xi.astype(np.int64), x)
+    y = fnt.fnt_inverse(xd, t, log2n, kind).cpu().numpy().astype(np.int64)
+    for b in range(3, 6):
+        assert y[b].tolist() == R.ifnt(x[b].tolist(), alpha, F)
+    # in place
+    fnt.fnt_forward(xd, t, log2n, kind, out=xd)
+    assert np.array_equal(xd.cpu().numpy().astype(np.int64), X)
+    fnt.fnt_check()
+
+
+def test_transform_range_and_shape_errors(torch_dev):
+    torch, dev = torch_dev
+    x = torch.zeros((2, 64), dtype=torch.int32, device=dev)
+    x[1, 5] = 65537
+    note("fnt_forward out-of-range residue")
+    fnt.fnt_forward(x, 4, 6, fnt.FNT_ALPHA_SQRT2)
+    with pytest.raises(fnt.FntError) as e:
+        fnt.fnt_check()
+    assert e.value.code == fnt.FNT_E_RANGE
+    fnt.fnt_check()  # cleared
+    with pytest.raises(fnt.FntError) as e:
+        fnt.fnt_forward(torch.zeros((2, 64), dtype=torch.int32, device=dev), 4, 6, fnt.FNT_ALPHA_2)
+    assert e.value.code == fnt.FNT_E_INVAL
+
+
+# ----------------------------------------------------------------------- CDC --
+CDC_CASES = [(1, 1, 0, 0), (31, 8, 3, 0), (32, 32, 7, 1), (33, 17, 6, 0), (64, 32, 7, 0),
+             (95, 5, 2, 1), (1000, 32, 7, 1), (4099, 24, 5, 0), (5000, 32, 0, 1), (12345, 32, 8, 0)]
+
+
+@pytest.mark.parametrize("n,L,shift,phase", CDC_CASES)
+def test_cdc_random_vs_oracle(torch_dev, n, L, shift, phase):
+    torch, dev = torch_dev
+    x = synth.random_samples(n, seed=1000 + n)
+    h = synth.random_taps(L, seed=L + n)
+    zr, ar = O.cdc(x, h, shift, phase)
+    note(f"fnt_cdc n={n} L={L} shift={shift} phase={phase}")
+    z, a = fnt.fnt_cdc(to_dev(torch, dev, x), fnt.cdc_params(h, shift, phase))
+    assert np.array_equal(z.cpu().numpy(), zr)
+    assert np.array_equal(a.cpu().numpy(), ar)
+    fnt.fnt_check()
+
+
+def test_cdc_eq5_worst_case(torch_dev):
+    torch, dev = torch_dev
+    n = 256
+    for xv, hv in (((-16, -16), (-32, -32)), ((-16, -16), (-32, 31)), ((15, -16), (31, -32))):
+        x = np.tile(np.array([xv[0], xv[1], xv[1], xv[0]], np.int8), (n, 1))
+        h = np.tile(np.array(hv, np.int8), (32, 1))
+        zr, ar = O.cdc(x, h, 11)
+        note(f"fnt_cdc worst case x={xv} h={hv}")
+        z, a = fnt.fnt_cdc(to_dev(torch, dev, x), fnt.cdc_params(h, 11))
+        assert np.array_equal(z.cpu().numpy(), zr)
+        assert np.array_equal(a.cpu().numpy(), ar)
+    assert np.abs(zr).max() <= 32768
+    fnt.fnt_check()
+
+
+def test_cdc_generated_channel(torch_dev):
+    torch, dev = torch_dev
+    ch = synth.single_channel(1 << 14)
+    zr, ar = O.cdc(ch.samples, ch.taps, ch.requant_shift)
+    note("fnt_cdc 75 km channel 2^14 symbols")
+    z, a = fnt.fnt_cdc(to_dev(torch, dev, ch.samples), fnt.cdc_params(ch.taps, ch.requant_shift))
+    assert np.array_equal(z.cpu().numpy(), zr)
+    assert np.array_equal(a.cpu().numpy(), ar)
+    fnt.fnt_check()
+
+
+def test_cdc_range_flag(torch_dev):
+    torch, dev = torch_dev
+    x = synth.random_samples(100, seed=3)
+    x[57, 2] = 16
+    note("fnt_cdc out-of-range sample")
+    fnt.fnt_cdc(to_dev(torch, dev, x), fnt.cdc_params(synth.random_taps(8, 1), 4))
+    with pytest.raises(fnt.FntError) as e:
+        fnt.fnt_check()
+    assert e.value.code == fnt.FNT_E_RANGE
+    bad = synth.random_taps(8, 1)
+    bad[3, 0] = -33
+    with pytest.raises(fnt.FntError) as e:
+        fnt.fnt_cdc(to_dev(torch, dev, x), fnt.cdc_params(bad, 4))
+    assert e.value.code == fnt.FNT_E_RANGE
+
+
+# ----------------------------------------------------------------------- AEQ --
+AEQ_PARAMS = [dict(out_shift=7, err_shift=16, mu_shift=3, const_unit=52, update_enable=1),
+              dict(out_shift=7, err_shift=16, mu_shift=3, const_unit=52, update_enable=0),
+              dict(out_shift=0, err_shift=10, mu_shift=0, const_unit=4096, update_enable=1),
+              dict(out_shift=12, err_shift=30, mu_shift=9, const_unit=1, update_enable=1)]
+
+
+@pytest.mark.parametrize("M", [0, 1, 15, 16, 17, 100, 1000])
+@pytest.mark.parametrize("pi", range(len(AEQ_PARAMS)))
+def test_aeq_random_vs_oracle(torch_dev, M, pi):
+    torch, dev = torch_dev
+    prm = AEQ_PARAMS[pi]
+    rng = np.random.default_rng(M * 7 + pi)
+    a = rng.integers(-16, 16, (M, 4)).astype(np.int8)
+    w = synth.random_aeq_taps(seed=M + pi) if pi != 0 else synth.centre_spike_taps()
+    if pi == 3:
+        w[0, :, :] = -8192
+        w[1, :, :] = 8191
+    outr, wr = O.aeq(a, w, O.params(**prm))
+    taps = to_dev(torch, dev, w)
+    note(f"fnt_aeq M={M} params={prm}")
+    out = fnt.fnt_aeq(to_dev(torch, dev, a), taps, fnt.aeq_params(**prm))
+    assert np.array_equal(out.cpu().numpy(), outr)
+    assert np.array_equal(taps.cpu().numpy(), wr)
+    fnt.fnt_check()
+
+
+def test_aeq_extreme_inputs(torch_dev):
+    torch, dev = torch_dev
+    M = 160
+    a = np.full((M, 4), -16, np.int8)
+    a[::3] = 15
+    for tap in (-8192, 8191, -8128, 8127, -64):
+        w = np.full((4, 4, 16), tap, np.int16)
+        prm = dict(out_shift=9, err_shift=20, mu_shift=2, const_unit=300, update_enable=1)
+        outr, wr = O.aeq(a, w, O.params(**prm))
+        taps = to_dev(torch, dev, w)
+        note(f"fnt_aeq extreme tap={tap}")
+        out = fnt.fnt_aeq(to_dev(torch, dev, a), taps, fnt.aeq_params(**prm))
+        assert np.array_equal(out.cpu().numpy(), outr)
+        assert np.array_equal(taps.cpu().numpy(), wr)
+    fnt.fnt_check()
+
+
+def test_cdc_aeq_chain_c0(torch_dev):
+    torch, dev = torch_dev
+    ch = synth.single_channel(1 << 14)
+    prm = synth.aeq_params_for(ch)
+    outr, wr, _ = O.cdc_aeq(ch.samples, ch.taps, ch.requant_shift, synth.centre_spike_taps(), O.params(**prm))
+    taps = to_dev(torch, dev, synth.centre_spike_taps())
+    note("fnt_cdc_aeq 75 km 2^14 symbols")
+    out = fnt.fnt_cdc_aeq(to_dev(torch, dev, ch.samples), fnt.cdc_params(ch.taps, ch.requant_shift), taps,
+                          fnt.aeq_params(**prm))
+    assert np.array_equal(out.cpu().numpy(), outr)
+    assert np.array_equal(taps.cpu().numpy(), wr)
+    fnt.fnt_check()
+
+
+# --------------------------------------------------------------------- plans --
+def _batch(nch, lo, hi, seed):
+    specs = synth.batched_specs(nch, lo, hi, base_seed=seed, tag="plan-test")
+    chans = synth.gen_many(specs, workers=4)
+    return chans
+
+
+def _plan_channels(torch, dev, chans, rng):
+    out = []
+    for i, ch in enumerate(chans):
+        w0 = synth.centre_spike_taps() if i % 3 else synth.random_aeq_taps(seed=i, lo=-300, hi=300)
+        prm = synth.aeq_params_for(ch)
+        M = O.n_symbols(ch.n, 0)
+        out.append(dict(ch=ch, w0=w0, prm=prm,
+                        x=to_dev(torch, dev, ch.samples),
+                        out=torch.full((M, 4), 12345, dtype=torch.int16, device=dev),
+                        taps=to_dev(torch, dev, w0)))
+    return out
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_plan_batched_vs_oracle(torch_dev, variant):
+    torch, dev = torch_dev
+    chans = _batch(40, 6, 11, seed=variant)
+    chans.append(synth.gen_channel(3, 30.0, 20.0, seed=5))      # ragged, tiny
+    chans.append(synth.gen_channel(0, 30.0, 20.0, seed=6))      # empty
+    rng = np.random.default_rng(0)
+    pc = _plan_channels(torch, dev, chans, rng)
+    refs = [O.cdc_aeq(c["ch"].samples, c["ch"].taps, c["ch"].requant_shift, c["w0"], O.params(**c["prm"]))
+            for c in pc]
+    plan = fnt.Plan([(c["x"], c["out"], c["taps"], fnt.cdc_params(c["ch"].taps, c["ch"].requant_shift),
+                      fnt.aeq_params(**c["prm"])) for c in pc], autotune=False, use_graph=True)
+    plan.set_aeq_variant(variant)
+    for rep in range(3):
+        for c in pc:        # eager work between replays: reset the tap state
+            c["taps"].copy_(to_dev(torch, dev, c["w0"]))
+            c["out"].fill_(-1)
+        note(f"plan run variant={variant} replay={rep}")
+        plan.run()
+        torch.cuda.synchronize()
+        for c, (outr, wr, _) in zip(pc, refs):
+            assert np.array_equal(c["out"].cpu().numpy(), outr), (rep, c["ch"].n)
+            assert np.array_equal(c["taps"].cpu().numpy(), wr), (rep, c["ch"].n)
+    info = plan.info()
+    assert info["channels"] == len(pc) and info["graph"] == 1 and info["aeq_variant"] == variant
+    plan.close()
+    fnt.fnt_check()
+
+
+def test_plan_autotune_and_eager(torch_dev, tmp_path):
+    torch, dev = torch_dev
+    chans = _batch(12, 8, 12, seed=9)
+    pc = _plan_channels(torch, dev, chans, None)
+    cache = str(tmp_path / "tune.jsonl")
+    note("plan autotune")
+    plan = fnt.Plan([(c["x"], c["out"], c["taps"], fnt.cdc_params(c["ch"].taps, c["ch"].requant_shift),
+                      fnt.aeq_params(**c["prm"])) for c in pc], autotune=True, use_graph=False,
+                    tune_cache=cache)
+    plan.run()
+    torch.cuda.synchronize()
+    for c in pc:
+        outr, wr, _ = O.cdc_aeq(c["ch"].samples, c["ch"].taps, c["ch"].requant_shift, c["w0"],
+                                O.params(**c["prm"]))
+        assert np.array_equal(c["out"].cpu().numpy(), outr)
+        assert np.array_equal(c["taps"].cpu().numpy(), wr)
+    assert os.path.exists(cache) and "wpg" in open(cache).read()
+    info = plan.info()
+    assert info["graph"] == 0 and info["cdc_blocks_per_wave"] >= 1
+    plan.close()
+    fnt.fnt_check()
+
+
+# ------------------------------------------------------------------ sessions --
+def _session_channels(nch, seg_blocks, seed):
+    """Per channel: a continuing stream cut into segments (multiples of 32 instants)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for c in range(nch):
+        segs = [int(b) * 32 for b in rng.integers(1, seg_blocks, size=int(rng.integers(2, 5)))]
+        ch = synth.gen_channel(sum(segs) // 2, float(rng.uniform(10, 80)), float(rng.uniform(18, 26)),
+                               seed=synth.seed_for(seed, "session", c))
+        out.append((ch, segs))
+    return out
+
+
+def _oracle_stream(ch, w0=None):
+    prm = synth.aeq_params_for(ch)
+    outr, wr, _ = O.cdc_aeq(ch.samples, ch.taps, ch.requant_shift,
+                            synth.centre_spike_taps() if w0 is None else w0, O.params(**prm))
+    return outr, wr
+
+
+def test_session_streams_vs_oracle(torch_dev):
+    torch, dev = torch_dev
+    chans = _session_channels(6, 40, seed=1)
+    s = fnt.Session(max_channels=8, hbm_budget_bytes=64 << 20, chunk_blocks=8)
+    outs = []
+    for c, (ch, segs) in enumerate(chans):
+        s.add_channel(c, fnt.cdc_params(ch.taps, ch.requant_shift), fnt.aeq_params(**synth.aeq_params_for(ch)))
+        outs.append(torch.zeros((ch.n // 2, 4), dtype=torch.int16, device=dev))
+    xs = [to_dev(torch, dev, ch.samples) for ch, _ in chans]
+    # interleave the segments of all channels
+    order = []
+    for c, (ch, segs) in enumerate(chans):
+        off = 0
+        for k, n in enumerate(segs):
+            order.append((k, c, off, n))
+            off += n
+    order.sort()
+    note("session submit interleaved segments")
+    tickets = [s.submit(c, xs[c][off:off + n], outs[c][off // 2:(off + n) // 2]) for _, c, off, n in order]
+    s.drain()
+    assert all(s.poll(t) for t in tickets)
+    for c, (ch, segs) in enumerate(chans):
+        outr, _ = _oracle_stream(ch)
+        assert np.array_equal(outs[c].cpu().numpy(), outr), c
+    st = s.stats()
+    assert st["completed"] == len(tickets) and st["p99_us"] >= st["p50_us"] > 0
+    s.close()
+    fnt.fnt_check()
+
+
+def test_session_state_export_import(torch_dev):
+    torch, dev = torch_dev
+    ch = synth.gen_channel(1536, 75.0, 22.0, seed=77)
+    x = to_dev(torch, dev, ch.samples)
+    out = torch.zeros((ch.n // 2, 4), dtype=torch.int16, device=dev)
+    cp, ap = fnt.cdc_params(ch.taps, ch.requant_shift), fnt.aeq_params(**synth.aeq_params_for(ch))
+    k = 1024                     # split point (instants, multiple of 32)
+    s1 = fnt.Session(max_channels=2, hbm_budget_bytes=16 << 20, chunk_blocks=4)
+    s1.add_channel(1, cp, ap)
+    note("session export after first segment")
+    s1.wait(s1.submit(1, x[:k], out[:k // 2]))
+    state = s1.get_state(1)
+    assert len(state) == fnt.FNT_STATE_BYTES
+    s1.close()
+    s2 = fnt.Session(max_channels=4, hbm_budget_bytes=16 << 20, chunk_blocks=16)
+    s2.add_channel(3, cp, ap)
+    s2.set_state(3, state)
+    note("session import and continue")
+    s2.wait(s2.submit(3, x[k:], out[k // 2:]))
+    outr, wr = _oracle_stream(ch)
+    assert np.array_equal(out.cpu().numpy(), outr)
+    st2 = s2.get_state(3)
+    assert np.array_equal(np.frombuffer(st2[:512], np.int16).reshape(4, 4, 16), wr)
+    s2.close()
+    fnt.fnt_check()
+
+
+def test_session_alone_equals_in_mix(torch_dev):
+    torch, dev = torch_dev
+    chans = _session_channels(12, 60, seed=5)
+    target = 4
+
+    def run(which):
+        s = fnt.Session(max_channels=16, hbm_budget_bytes=64 << 20, chunk_blocks=3, max_active=5)
+        outs = {}
+        for c in which:
+            ch, segs = chans[c]
+            s.add_channel(c, fnt.cdc_params(ch.taps, ch.requant_shift), fnt.aeq_params(**synth.aeq_params_for(ch)))
+            outs[c] = torch.zeros((ch.n // 2, 4), dtype=torch.int16, device=dev)
+        xs = {c: to_dev(torch, dev, chans[c][0].samples) for c in which}
+        for c in which:
+            off = 0
+            for n in chans[c][1]:
+                s.submit(c, xs[c][off:off + n], outs[c][off // 2:(off + n) // 2])
+                off += n
+        s.drain()
+        s.close()
+        return outs[target].cpu().numpy()
+
+    note("session alone")
+    alone = run([target])
+    note("session in mix")
+    mixed = run(list(range(12)))
+    assert np.array_equal(alone, mixed)
+    assert np.array_equal(alone, _oracle_stream(chans[target][0])[0])
+    fnt.fnt_check()
+
+
+def test_session_host_buffers_admission_and_errors(torch_dev):
+    torch, dev = torch_dev
+    chans = _session_channels(3, 30, seed=8)
+    fixed = 3 * 2 * 8 * 64 + 4 * fnt.FNT_STATE_BYTES
+    biggest = max(sum(segs) for _, segs in chans)
+    # staging pool that holds roughly one request at a time
+    s = fnt.Session(max_channels=4, hbm_budget_bytes=fixed + 8 * biggest + 4096, chunk_blocks=8, max_active=2)
+    host_out = {}
+    keep = []
+    for c, (ch, segs) in enumerate(chans):
+        s.add_channel(c, fnt.cdc_params(ch.taps, ch.requant_shift), fnt.aeq_params(**synth.aeq_params_for(ch)))
+        host_out[c] = np.zeros((ch.n // 2, 4), np.int16)
+        off = 0
+        for n in segs:
+            xin = np.ascontiguousarray(ch.samples[off:off + n])
+            o = host_out[c][off // 2:(off + n) // 2]
+            keep.append(xin)
+            note(f"session host submit ch={c} n={n}")
+            s.submit(c, xin, o, host=True)
+            off += n
+    s.drain()
+    for c, (ch, _) in enumerate(chans):
+        assert np.array_equal(host_out[c], _oracle_stream(ch)[0]), c
+    # a request larger than the whole pool is refused
+    big = np.zeros((64 * biggest, 4), np.int8)
+    with pytest.raises(fnt.FntError) as e:
+        s.submit(0, big, np.zeros((32 * biggest, 4), np.int16), host=True)
+    assert e.value.code == fnt.FNT_E_BUSY
+    with pytest.raises(fnt.FntError) as e:
+        s.submit(0, np.zeros((33, 4), np.int8), np.zeros((16, 4), np.int16), host=True)
+    assert e.value.code == fnt.FNT_E_INVAL
+    with pytest.raises(fnt.FntError) as e:
+        s.submit(3, np.zeros((32, 4), np.int8), np.zeros((16, 4), np.int16), host=True)
+    assert e.value.code == fnt.FNT_E_STATE
+    s.close()
+    fnt.fnt_check()
+
+
+def test_session_replay_poisson(torch_dev):
+    torch, dev = torch_dev
+    rng = np.random.default_rng(4)
+    nch = 16
+    chans = []
+    for c in range(nch):
+        ch = synth.gen_channel(16 * int(rng.integers(20, 200)), float(rng.uniform(10, 80)), 22.0, seed=c + 500)
+        chans.append(ch)
+    s = fnt.Session(max_channels=nch, hbm_budget_bytes=64 << 20, chunk_blocks=16)
+    outs, xs, reqs = [], [], []
+    t = 0
+    for c, ch in enumerate(chans):
+        s.add_channel(c, fnt.cdc_params(ch.taps, ch.requant_shift), fnt.aeq_params(**synth.aeq_params_for(ch)))
+        xs.append(to_dev(torch, dev, ch.samples))
+        outs.append(torch.zeros((ch.n // 2, 4), dtype=torch.int16, device=dev))
+    # two requests per channel, Poisson arrivals at 20k/s
+    half = [ch.n // 64 * 32 for ch in chans]
+    for rep in range(2):
+        for c in range(nch):
+            t += int(rng.exponential(50_000))
+            lo = 0 if rep == 0 else half[c]
+            hi = half[c] if rep == 0 else chans[c].n
+            reqs.append((c, xs[c][lo:hi], outs[c][lo // 2:hi // 2], t))
+    note("session replay")
+    s.replay(reqs)
+    s.drain()
+    for c, ch in enumerate(chans):
+        assert np.array_equal(outs[c].cpu().numpy(), _oracle_stream(ch)[0]), c
+    st = s.stats()
+    assert st["completed"] == len(reqs)
+    s.close()
+    fnt.fnt_check()
+
+
+# ------------------------------------------------------------------ full size --
+def test_full_size_single_stream(torch_dev):
+    """2^24 symbols per polarisation, 75 km: the benchmark's workload and launch path."""
+    torch, dev = torch_dev
+    note("generate 2^24-symbol channel")
+    ch = synth.single_channel(1 << 24, tag="bench")
+    prm = synth.aeq_params_for(ch)
+    x = to_dev(torch, dev, ch.samples)
+    taps = to_dev(torch, dev, synth.centre_spike_taps())
+    note("fnt_cdc_aeq 2^24 symbols")
+    out = fnt.fnt_cdc_aeq(x, fnt.cdc_params(ch.taps, ch.requant_shift), taps, fnt.aeq_params(**prm))
+    torch.cuda.synchronize()
+    fnt.fnt_check()
+    note("oracle 2^24 symbols")
+    outr, wr, ar = O.cdc_aeq(ch.samples, ch.taps, ch.requant_shift, synth.centre_spike_taps(), O.params(**prm))
+    assert np.array_equal(out.cpu().numpy(), outr)
+    assert np.array_equal(taps.cpu().numpy(), wr)
+    # exact CDC at sampled windows (the oracle with the preceding 32 instants as history)
+    z, a = fnt.fnt_cdc(x, fnt.cdc_params(ch.taps, ch.requant_shift))
+    zc = z.cpu().numpy()
+    assert np.array_equal(a.cpu().numpy(), ar)
+    rng = np.random.default_rng(0)
+    for start in rng.integers(32, ch.n - 4096, size=8):
+        seg = ch.samples[start:start + 4096]
+        zr, _ = O.cdc(seg, ch.taps, ch.requant_shift, hist=ch.samples[start - 32:start])
+        assert np.array_equal(zc[start:start + 4096], zr)
