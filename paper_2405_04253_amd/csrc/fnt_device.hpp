@@ -157,6 +157,43 @@ __device__ __forceinline__ int32_t clamp32(int32_t v, int32_t lo, int32_t hi) {
     return v < lo ? lo : (v > hi ? hi : v);
 }
 
+// ---------------------------------------------------------------------------
+// Lazy arithmetic modulo F4 = 65537 on signed int32 ("loose residues").
+//
+// A loose residue is any int32 congruent to the value; callers keep the bounds
+// stated at each use.  The only reduction is inside mulmod: for |v|, |c| < 2^23
+// the 48-bit product v*c = hi*2^32 + lo (lo unsigned) is congruent to
+// hi + lo[15:0] - lo[31:16] because 2^32 == 1 and 2^16 == -1 (mod 65537); the
+// result has magnitude < 2^16 + 2^14.  The sign-extension idiom makes the
+// compiler emit v_mul_i32_i24 / v_mul_hi_i32_i24 and SDWA word selects.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int32_t sext24(int32_t v) { return (v << 8) >> 8; }
+
+__device__ __forceinline__ int32_t mulmod(int32_t v, int32_t c) {
+    int64_t p = (int64_t)sext24(v) * (int64_t)sext24(c);
+    uint32_t lo = (uint32_t)p;
+    int32_t hi = (int32_t)(p >> 32);
+    return hi + (int32_t)(lo & 0xFFFFu) - (int32_t)(lo >> 16);
+}
+
+// Centred representative in [-32768, 32768] of a loose residue with |r| < 2^30.
+__device__ __forceinline__ int32_t lift_loose(int32_t r) {
+    int32_t f = (int32_t)((uint32_t)r & 0xFFFFu) - (r >> 16);   // in [-2^14, 2^16 + 2^14)
+    f = f > 32768 ? f - 65537 : f;
+    return f < -32768 ? f + 65537 : f;
+}
+
+// Lane exchange with lane ^ X inside a wave64 (DPP where one exists, else
+// ds_swizzle inside 32-lane groups, else ds_bpermute).
+template <int X>
+__device__ __forceinline__ int32_t xor_lane(int32_t v) {
+    if constexpr (X == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+    else if constexpr (X == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);  // quad_perm 2,3,0,1
+    else if constexpr (X == 8) return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false); // row_ror:8
+    else if constexpr (X == 4 || X == 16) return __builtin_amdgcn_ds_swizzle(v, (X << 10) | 0x1F);
+    else return __shfl_xor(v, X);
+}
+
 // Range-violation bits latched into the per-device flag.
 enum : int { RANGE_SAMPLE = 1, RANGE_TAP = 2, RANGE_RESIDUE = 4, RANGE_SYMBOL = 8 };
 

@@ -226,24 +226,170 @@ __device__ __forceinline__ void aeq_finish(const AeqItem &it, int lane, const in
     }
 }
 
+// Twiddle constants of the N = 32, alpha = 2 transform in the layout where
+// lane t (0/1) register j holds position n = t + 2j.  For the radix-2 stage
+// with half-size h (h = 16, 8, 4, 2) and the pair starting at register j
+// (j' = j mod h/2), the exponent is e = (16/h) t + (32/h) j' < 16.
+template <int H, int JP>
+__device__ __forceinline__ int32_t tw_fwd(int t) {
+    constexpr int e0 = (32 / H) * JP;
+    constexpr int e1 = e0 + 16 / H;
+    return t ? (1 << e1) : (1 << e0);               // 2^e
+}
+template <int H, int JP>
+__device__ __forceinline__ int32_t tw_inv(int t) {
+    constexpr int e0 = (32 / H) * JP;
+    constexpr int e1 = e0 + 16 / H;
+    // 2^-e = 2^(32 - e) = -2^(16 - e) for 0 < e < 16 (2^16 == -1)
+    constexpr int c0 = e0 ? -(1 << (16 - e0)) : 1;
+    constexpr int c1 = -(1 << (16 - e1));
+    return t ? c1 : c0;
+}
+
+// DIF forward transform of 16 tap-digit positions (positions >= 16 are the
+// zero padding), two lanes per transform.  In: |x| <= 2^17.  Out: |X| <= 2^21,
+// lane t register j holds bin bitrev5(t + 2j).
+__device__ __forceinline__ void tap_fnt32(int32_t (&x)[16], int t) {
+    // h = 16: the partner positions are zero -> x[j + 8] = x[j] * 2^e
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        int32_t c;
+        switch (j) {
+            case 0: c = tw_fwd<16, 0>(t); break;
+            case 1: c = tw_fwd<16, 1>(t); break;
+            case 2: c = tw_fwd<16, 2>(t); break;
+            case 3: c = tw_fwd<16, 3>(t); break;
+            case 4: c = tw_fwd<16, 4>(t); break;
+            case 5: c = tw_fwd<16, 5>(t); break;
+            case 6: c = tw_fwd<16, 6>(t); break;
+            default: c = tw_fwd<16, 7>(t); break;
+        }
+        x[j + 8] = mulmod(x[j], c);
+    }
+    // h = 8, 4, 2: in-register butterflies; sums grow one bit per stage
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        if (j & 4) continue;
+        int32_t a = x[j], b = x[j + 4];
+        int32_t c;
+        switch (j & 3) {
+            case 0: c = tw_fwd<8, 0>(t); break;
+            case 1: c = tw_fwd<8, 1>(t); break;
+            case 2: c = tw_fwd<8, 2>(t); break;
+            default: c = tw_fwd<8, 3>(t); break;
+        }
+        x[j] = a + b;
+        x[j + 4] = mulmod(a - b, c);
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        if (j & 2) continue;
+        int32_t a = x[j], b = x[j + 2];
+        int32_t c = (j & 1) ? tw_fwd<4, 1>(t) : tw_fwd<4, 0>(t);
+        x[j] = a + b;
+        x[j + 2] = mulmod(a - b, c);
+    }
+#pragma unroll
+    for (int j = 0; j < 16; j += 2) {
+        int32_t a = x[j], b = x[j + 1];
+        x[j] = a + b;
+        x[j + 1] = mulmod(a - b, tw_fwd<2, 0>(t));
+    }
+    // h = 1: across the lane pair, no twiddle
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        int32_t p = xor_lane<1>(x[j]);
+        x[j] = t ? p - x[j] : x[j] + p;
+    }
+}
+
+// DIT inverse (unnormalised) of 32 bins in the same layout, keeping only the
+// outputs at positions 16..31 (registers 8..15).  In: |x| < 2^19.
+// Out: |x| < 2^21.
+__device__ __forceinline__ void ifnt32_upper(int32_t (&x)[16], int t) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {                  // h = 1: across the lane pair
+        int32_t p = xor_lane<1>(x[j]);
+        x[j] = t ? p - x[j] : x[j] + p;
+    }
+#pragma unroll
+    for (int j = 0; j < 16; j += 2) {               // h = 2
+        int32_t tt = mulmod(x[j + 1], tw_inv<2, 0>(t));
+        int32_t a = x[j];
+        x[j] = a + tt;
+        x[j + 1] = a - tt;
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {                  // h = 4
+        if (j & 2) continue;
+        int32_t c = (j & 1) ? tw_inv<4, 1>(t) : tw_inv<4, 0>(t);
+        int32_t tt = mulmod(x[j + 2], c);
+        int32_t a = x[j];
+        x[j] = a + tt;
+        x[j + 2] = a - tt;
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {                  // h = 8
+        if (j & 4) continue;
+        int32_t c;
+        switch (j & 3) {
+            case 0: c = tw_inv<8, 0>(t); break;
+            case 1: c = tw_inv<8, 1>(t); break;
+            case 2: c = tw_inv<8, 2>(t); break;
+            default: c = tw_inv<8, 3>(t); break;
+        }
+        int32_t tt = mulmod(x[j + 4], c);
+        int32_t a = x[j];
+        x[j] = a + tt;
+        x[j + 4] = a - tt;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {                   // h = 16: upper outputs only
+        int32_t c;
+        switch (j) {
+            case 0: c = tw_inv<16, 0>(t); break;
+            case 1: c = tw_inv<16, 1>(t); break;
+            case 2: c = tw_inv<16, 2>(t); break;
+            case 3: c = tw_inv<16, 3>(t); break;
+            case 4: c = tw_inv<16, 4>(t); break;
+            case 5: c = tw_inv<16, 5>(t); break;
+            case 6: c = tw_inv<16, 6>(t); break;
+            default: c = tw_inv<16, 7>(t); break;
+        }
+        x[j + 8] = x[j] - mulmod(x[j + 8], c);
+    }
+}
+
+// FNT-AEQ, one wave64 per channel.  Lane roles:
+//  * transform lanes: t = bit 0, s = bit 1, d = bit 2, S2 = bits 3-4, g = bit 5;
+//    the lane pair (t = 0, 1) holds the 32 bins of filter (S1 = 2g + s, S2),
+//    tap digit d (0 = high, 1 = low), 16 bins per lane.
+//  * input-spectrum lanes: S1 = lane / 16, 2 of the 32 window positions each.
+//  * output / error lanes: symbol m = lane / 4, stream S2 = lane % 4.
+//  * gradient / tap-state lanes: S1 = lane / 16, tap k = lane % 16, all 4 S2.
 __global__ __launch_bounds__(64) void aeq_fnt_kernel(const AeqItem *items, AeqItem single,
                                                      int *err) {
-    using FF = Field<16>;
     const AeqItem it = items ? items[blockIdx.x] : single;
     const int lane = threadIdx.x;
-    const int pos = lane & 31, half = lane >> 5;   // half 0: high digit, half 1: low digit
-    const int s1 = lane >> 4, kk = lane & 15;       // gradient / tap-state ownership
+    const int pos = lane & 31;
+    const int t = lane & 1, s = (lane >> 1) & 1, d = (lane >> 2) & 1;
+    const int tS2 = (lane >> 3) & 3, g = lane >> 5;
+    const int tS1 = 2 * g + s;
+    const int s1 = lane >> 4, kk = lane & 15;        // gradient / A-spectrum / tap-state role
+    const int om = lane >> 2, oS2 = lane & 3;         // output / error role
 
-    __shared__ int16_t tapl[256];                   // [S1][S2][k]
-    __shared__ uint32_t epsw[16];                   // bytes [S2][j], eps of the block
-    __shared__ uint32_t winw[36];                   // bytes [S1][32] window + zero pad
+    __shared__ int16_t tapl[256];                     // [S1][S2][k]
+    __shared__ int32_t aspec[4][32];                  // input spectra by position
+    __shared__ int32_t part[4][64];                   // [g*2+d][m*4+S2] lifted partial outputs
+    __shared__ uint32_t epsw[16];                     // bytes [S2][m]
+    __shared__ uint32_t winw[36];                     // bytes [S1][32] window + zero pad
 
     int32_t w[4];
 #pragma unroll
-    for (int s2 = 0; s2 < 4; ++s2) {
-        int32_t v = it.taps[(s1 * 4 + s2) * 16 + kk];
+    for (int q = 0; q < 4; ++q) {
+        int32_t v = it.taps[(s1 * 4 + q) * 16 + kk];
         if (v < -8192 || v > 8191) flag(err, RANGE_TAP);
-        w[s2] = clamp32(v, -8192, 8191);
+        w[q] = clamp32(v, -8192, 8191);
     }
     const uint64_t M = it.m;
     if (M == 0) {
@@ -252,119 +398,109 @@ __global__ __launch_bounds__(64) void aeq_fnt_kernel(const AeqItem *items, AeqIt
     }
     if (lane < 4) winw[32 + lane] = 0u;
 
-    // tap-digit spectra: W[f] = FNT32(digit_half(w_f) * 32^-1) at bin bitrev(pos)
-    uint32_t W[16];
+    // tap-digit spectra of filter (tS1, tS2), digit d, with N^-1 = -2048 folded in
+    int32_t W[16];
     auto transform_taps = [&]() {
 #pragma unroll
-        for (int s2 = 0; s2 < 4; ++s2) tapl[(s1 * 4 + s2) * 16 + kk] = (int16_t)w[s2];
+        for (int q = 0; q < 4; ++q) tapl[(s1 * 4 + q) * 16 + kk] = (int16_t)w[q];
         __syncthreads();
+        const int base = (tS1 * 4 + tS2) * 16 + t;
 #pragma unroll
-        for (int f = 0; f < 16; ++f) {
-            int32_t tv = (int32_t)tapl[f * 16 + (pos & 15)];
-            tv = pos < 16 ? tv : 0;                 // zero padding 16 -> 32
-            W[f] = fwd_xlane<16, 5, false>(tap_digit(tv, half), lane);
+        for (int j = 0; j < 8; ++j) {
+            int32_t v = tapl[base + 2 * j];
+            int32_t lo = ((v + 64) & 127) - 64;
+            int32_t hi = (v - lo) >> 7;
+            W[j] = (d ? lo : hi) * -2048;             // |.| <= 64 * 2048 = 2^17
         }
+        tap_fnt32(W, t);
         __syncthreads();
     };
     transform_taps();
 
     const int64_t nblocks = (int64_t)((M + 15) / 16);
     const int c2 = it.const_unit * it.const_unit;
-    // lane pos holds window symbol 16 b - 16 + pos (both halves alike)
-    uint32_t win = aeq_load(it, -16 + pos, err);
+    uint32_t win = aeq_load(it, -16 + pos, err);      // lane pos: symbol 16 b - 16 + pos
 
     for (int64_t b = 0; b < nblocks; ++b) {
-        // prefetch the next block's 16 new symbols
         uint32_t nxt = pos >= 16 ? aeq_load(it, 16 * b + pos, err) : 0u;
-
-        // input spectra: lanes 0-31 stream 0 / 2, lanes 32-63 stream 1 / 3
-        int r01 = half ? sbyte(win, 1) : sbyte(win, 0);
-        int r23 = half ? sbyte(win, 3) : sbyte(win, 2);
-        uint32_t A01 = fwd_xlane<16, 5, false>(FF::from_int(r01), lane);
-        uint32_t A23 = fwd_xlane<16, 5, false>(FF::from_int(r23), lane);
-        uint32_t A01x = (uint32_t)__shfl_xor((int)A01, 32);
-        uint32_t A23x = (uint32_t)__shfl_xor((int)A23, 32);
-        uint32_t A[4];
-        A[0] = half ? A01x : A01;
-        A[1] = half ? A01 : A01x;
-        A[2] = half ? A23x : A23;
-        A[3] = half ? A23 : A23x;
-
-        // Fermat-domain 4x4 MIMO: per output stream and polarisation pair, the
-        // two input streams are summed before one inverse transform (Eq. (5)
-        // holds for the pair: 2 * 16 taps * 64 * 16 = 32768 = (F - 1) / 2)
-        int32_t t[4];
+        if (lane < 32) {
+            uint8_t *wb = reinterpret_cast<uint8_t *>(winw);
 #pragma unroll
-        for (int s2 = 0; s2 < 4; ++s2) {
-            uint32_t yx = FF::add(FF::mul(A[0], W[0 * 4 + s2]), FF::mul(A[1], W[1 * 4 + s2]));
-            uint32_t yy = FF::add(FF::mul(A[2], W[2 * 4 + s2]), FF::mul(A[3], W[3 * 4 + s2]));
-            yx = inv_xlane<16, 5, false>(yx, lane);
-            yy = inv_xlane<16, 5, false>(yy, lane);
-            t[s2] = FF::lift(yx) + FF::lift(yy);
+            for (int c = 0; c < 4; ++c) wb[c * 32 + pos] = (uint8_t)(win >> (8 * c));
         }
-        // recombine the digit groups: y = 2^7 * (high-digit conv) + (low-digit conv)
-        int32_t yh[4];
+        __syncthreads();
+        // input spectra: lane (s1, kk) holds positions kk and kk + 16 of stream s1
+        {
+            const int8_t *wb = reinterpret_cast<const int8_t *>(winw) + s1 * 32;
+            int32_t x0 = wb[kk], x1 = wb[kk + 16];
+            int32_t u0 = x0 + x1;
+            int32_t u1 = mulmod(x0 - x1, 1 << kk);    // h = 16, e = kk
 #pragma unroll
-        for (int s2 = 0; s2 < 4; ++s2) {
-            int32_t lo = __shfl_xor(t[s2], 32);
-            int32_t y = 128 * t[s2] + lo;
-            yh[s2] = (int32_t)clamp64(rs64((int64_t)y, it.out_shift), -32768, 32767);
+            for (int h = 8; h >= 1; h >>= 1) {
+                const bool up = (kk & h) != 0;
+                const int32_t c = 1 << ((16 / h) * (kk & (h - 1)));
+                int32_t p0 = h == 8 ? xor_lane<8>(u0) : h == 4 ? xor_lane<4>(u0)
+                           : h == 2 ? xor_lane<2>(u0) : xor_lane<1>(u0);
+                int32_t p1 = h == 8 ? xor_lane<8>(u1) : h == 4 ? xor_lane<4>(u1)
+                           : h == 2 ? xor_lane<2>(u1) : xor_lane<1>(u1);
+                u0 = up ? mulmod(p0 - u0, c) : u0 + p0;
+                u1 = up ? mulmod(p1 - u1, c) : u1 + p1;
+            }
+            aspec[s1][kk] = u0;                        // |.| <= 2^21
+            aspec[s1][kk + 16] = u1;
         }
-        const int64_t m = 16 * b + (pos - 16);
-        const bool outlane = half == 0 && pos >= 16;
-        const bool valid = outlane && (uint64_t)m < M;
-        if (valid) {
-            uint2 o;
-            o.x = ((uint32_t)yh[0] & 0xFFFFu) | ((uint32_t)yh[1] << 16);
-            o.y = ((uint32_t)yh[2] & 0xFFFFu) | ((uint32_t)yh[3] << 16);
-            reinterpret_cast<uint2 *>(it.out)[m] = o;
+        __syncthreads();
+        // Fermat-domain 4x4 MIMO: product with the tap-digit spectra; the two
+        // streams of a polarisation are summed before one inverse transform
+        // (Eq. (5): 2 streams * 16 taps * 64 * 16 = 32768 = (F - 1) / 2)
+        int32_t Y[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            int32_t P = mulmod(aspec[tS1][t + 2 * j], W[j]);
+            Y[j] = P + xor_lane<2>(P);                 // |.| < 2^18
         }
+        ifnt32_upper(Y, t);
+        if (s == 0) {
+#pragma unroll
+            for (int j = 8; j < 16; ++j)
+                part[g * 2 + d][(t + 2 * (j - 8)) * 4 + tS2] = lift_loose(Y[j]);
+        }
+        __syncthreads();
+        // recombine the digit groups and the polarisation pairs: one (m, S2) per lane
+        const int32_t y = 128 * (part[0][lane] + part[2][lane]) + part[1][lane] + part[3][lane];
+        const int32_t yh = (int32_t)clamp64(rs64((int64_t)y, it.out_shift), -32768, 32767);
+        const int64_t m = 16 * b + om;
+        const bool valid = (uint64_t)m < M;
+        if (valid) it.out[m * 4 + oS2] = (int16_t)yh;
         if (it.update_enable) {
-            // RDE error per polarisation and the 8-bit error terms eps_S2
-            uint32_t epack = 0;
-#pragma unroll
-            for (int p = 0; p < 2; ++p) {
-                int64_t yi = yh[2 * p], yq = yh[2 * p + 1];
-                int64_t r2 = yi * yi + yq * yq;
-                int64_t R2 = r2 < 6LL * c2 ? 2LL * c2 : (r2 < 14LL * c2 ? 10LL * c2 : 18LL * c2);
-                int64_t e = R2 - r2;
-                int32_t ei = (int32_t)clamp64(rs64(e * yi, it.err_shift), -128, 127);
-                int32_t eq = (int32_t)clamp64(rs64(e * yq, it.err_shift), -128, 127);
-                epack |= ((uint32_t)ei & 0xFFu) << (16 * p);
-                epack |= ((uint32_t)eq & 0xFFu) << (16 * p + 8);
-            }
-            if (!valid) epack = 0u;
-            // stage eps (stream-major bytes) and the window (stream-major bytes)
-            if (outlane) {
-                uint8_t *eb = reinterpret_cast<uint8_t *>(epsw);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) eb[c * 16 + (pos - 16)] = (uint8_t)(epack >> (8 * c));
-            }
-            if (half == 0) {
-                uint8_t *wb = reinterpret_cast<uint8_t *>(winw);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) wb[c * 32 + pos] = (uint8_t)(win >> (8 * c));
-            }
+            // RDE error of this symbol's polarisation and the 8-bit error term
+            const int32_t yp = xor_lane<1>(yh);
+            const int64_t r2 = (int64_t)yh * yh + (int64_t)yp * yp;
+            const int64_t R2 = r2 < 6LL * c2 ? 2LL * c2 : (r2 < 14LL * c2 ? 10LL * c2 : 18LL * c2);
+            int32_t eps = (int32_t)clamp64(rs64((R2 - r2) * yh, it.err_shift), -128, 127);
+            if (!valid) eps = 0;
+            reinterpret_cast<int8_t *>(epsw)[oS2 * 16 + om] = (int8_t)eps;
             __syncthreads();
-            // G[S1][S2][k] = sum_j eps_S2[j] * a_S1[16 b + j - k], as 4-byte dot products
-            const int off = s1 * 32 + 16 - kk;          // byte offset of a_S1[16 b - k]
-            uint32_t d[5];
+            // G[S1][S2][k] = sum_j eps_S2[j] * a_S1[16 b + j - k] as 4-byte dot products
+            const int off = s1 * 32 + 16 - kk;
+            uint32_t dd[5];
 #pragma unroll
-            for (int r = 0; r < 5; ++r) d[r] = winw[(off >> 2) + r];
+            for (int r = 0; r < 5; ++r) dd[r] = winw[(off >> 2) + r];
             uint32_t xs[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) xs[q] = __builtin_amdgcn_alignbyte(d[q + 1], d[q], off & 3);
+            for (int q = 0; q < 4; ++q) xs[q] = __builtin_amdgcn_alignbyte(dd[q + 1], dd[q], off & 3);
 #pragma unroll
-            for (int s2 = 0; s2 < 4; ++s2) {
-                int32_t g = 0;
+            for (int q2 = 0; q2 < 4; ++q2) {
+                int32_t gsum = 0;
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    g = __builtin_amdgcn_sdot4((int)epsw[s2 * 4 + q], (int)xs[q], g, false);
-                w[s2] = clamp32(w[s2] + (int32_t)rs64((int64_t)g, it.mu_shift), -8192, 8191);
+                    gsum = __builtin_amdgcn_sdot4((int)epsw[q2 * 4 + q], (int)xs[q], gsum, false);
+                w[q2] = clamp32(w[q2] + (int32_t)rs64((int64_t)gsum, it.mu_shift), -8192, 8191);
             }
             transform_taps();
+        } else {
+            __syncthreads();
         }
-        // slide the window by 16 symbols
         uint32_t slid = (uint32_t)__shfl((int)win, (lane & 32) | ((pos + 16) & 31));
         win = pos < 16 ? slid : nxt;
     }
