@@ -181,8 +181,11 @@ typedef struct fnt_plan_info {
     uint64_t aeq_blocks_max;  /* longest per-channel AEQ chain, in 16-symbol blocks */
     int32_t cdc_waves_per_group;  /* chosen schedule */
     int32_t cdc_blocks_per_wave;
-    int32_t aeq_variant;   /* 0 = Fermat-domain filtering (the method), 1 = direct comparator */
+    int32_t aeq_variant;   /* 0 = Fermat-domain filtering (the method), 1 = direct comparator,
+                              2 = Fermat-domain, one wave per channel */
+    int32_t aeq_waves_per_pol;  /* variant 0: waves per polarisation half (1, 2 or 4) */
     int32_t graph;         /* 1 if a hipGraph is replayed */
+    int32_t reserved;
     double tune_ms;        /* time of the chosen schedule during autotune (0 if none) */
 } fnt_plan_info;
 
@@ -190,8 +193,10 @@ typedef struct fnt_plan fnt_plan;
 
 /* Build a plan for `nch` channels (copied; the device buffers must stay valid
  * while the plan is used).  Allocates the plan's device tables and scratch.
- * With autotune, times the candidate CDC schedules on `stream` (the CDC stage
- * only writes plan scratch; taps and outputs are not touched). */
+ * With autotune, times the candidate CDC schedules and AEQ waves-per-half on
+ * `stream`: the CDC runs write plan scratch, the AEQ runs work on scratch copies
+ * of the taps and write `out` (which a real run overwrites); the caller's taps
+ * are not touched. */
 int fnt_plan_create(fnt_plan **plan, const fnt_channel_desc *host_channels, size_t nch,
                     const fnt_plan_config *cfg, void *stream);
 /* Run every channel once (CDC + resample + AEQ), enqueued on `stream`. */
@@ -199,9 +204,15 @@ int fnt_plan_run(fnt_plan *plan, void *stream);
 int fnt_plan_get_info(const fnt_plan *plan, fnt_plan_info *info);
 int fnt_plan_destroy(fnt_plan *plan);
 
-/* Direct-convolution comparator of the same chain (bit-identical results; no
- * Fermat-domain arithmetic): aeq_variant = 1 selects it in a plan. */
+/* Select the AEQ kernel of a plan: 0 = Fermat-domain filtering split by output
+ * polarisation (default, the method), 1 = direct time-domain comparator with
+ * bit-identical results and no Fermat-domain arithmetic, 2 = Fermat-domain
+ * filtering with one wave per channel. */
 int fnt_plan_set_aeq_variant(fnt_plan *plan, int variant);
+/* Waves per polarisation half for AEQ variant 0: 1, 2 or 4 (more waves shorten
+ * each channel's serial chain; fewer use the chip more efficiently when there
+ * are many channels).  Overrides the default / autotuned choice. */
+int fnt_plan_set_aeq_waves(fnt_plan *plan, int waves_per_pol);
 
 /* ------------------------------------------------------------------------
  * Serving sessions: continuing per-channel streams with device-resident state.

@@ -215,7 +215,7 @@ int fnt_aeq(const int8_t *in_1sps, uint64_t m, int16_t *taps, const fnt_aeq_para
     if ((rc = device_err_flag(&err))) return rc;
     AeqItem it;
     fill_aeq_item(it, in_1sps, m, taps, p, out);
-    hipError_t e = launch_aeq(nullptr, 0, it, 0, err, (hipStream_t)stream);
+    hipError_t e = launch_aeq(nullptr, 0, it, 0, 4, err, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "fnt_aeq launch");
     return FNT_OK;
 }
@@ -251,7 +251,7 @@ int fnt_cdc_aeq(const int8_t *in, uint64_t n, const fnt_cdc_params *cp, int16_t 
     }
     AeqItem ai;
     fill_aeq_item(ai, abuf, M, taps, ap, out);
-    hipError_t e = launch_aeq(nullptr, 0, ai, 0, err, s);
+    hipError_t e = launch_aeq(nullptr, 0, ai, 0, 4, err, s);
     if (abuf) (void)hipFreeAsync(abuf, s);
     if (e != hipSuccess) return hip_fail(e, "fnt_cdc_aeq: aeq launch");
     return FNT_OK;
@@ -271,7 +271,7 @@ struct fnt_plan {
     int *err = nullptr;
     uint64_t total_blocks = 0;
     fnt_plan_info info{};
-    int wpg = 4, bpw = 1, variant = 0;
+    int wpg = 4, bpw = 1, variant = 0, wpp = 1;
     bool use_graph = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -281,7 +281,7 @@ static int plan_launch(fnt_plan *p, hipStream_t s) {
     hipError_t e = launch_cdc(p->cdc_dev, (int)p->cdc_host.size(), CdcItem{}, p->total_blocks, p->wpg,
                               p->bpw, false, p->err, s);
     if (e != hipSuccess) return hip_fail(e, "plan: cdc launch");
-    e = launch_aeq(p->aeq_dev, (int)p->aeq_host.size(), AeqItem{}, p->variant, p->err, s);
+    e = launch_aeq(p->aeq_dev, (int)p->aeq_host.size(), AeqItem{}, p->variant, p->wpp, p->err, s);
     if (e != hipSuccess) return hip_fail(e, "plan: aeq launch");
     return FNT_OK;
 }
@@ -339,7 +339,7 @@ static std::string tune_key(const fnt_plan *p) {
     return k.str();
 }
 
-static bool tune_cache_lookup(const char *path, const std::string &key, int *wpg, int *bpw) {
+static bool tune_cache_lookup(const char *path, const std::string &key, int *wpg, int *bpw, int *wpp) {
     if (!path) return false;
     std::ifstream f(path);
     std::string line;
@@ -349,70 +349,113 @@ static bool tune_cache_lookup(const char *path, const std::string &key, int *wpg
         if (a == std::string::npos) continue;
         size_t b = line.find('"', a + 8);
         if (b == std::string::npos || line.substr(a + 8, b - a - 8) != key) continue;
-        int w = 0, bb = 0;
-        size_t pw = line.find("\"wpg\": "), pb = line.find("\"bpw\": ");
-        if (pw == std::string::npos || pb == std::string::npos) continue;
+        int w = 0, bb = 0, pp = 0;
+        size_t pw = line.find("\"wpg\": "), pb = line.find("\"bpw\": "), pq = line.find("\"wpp\": ");
+        if (pw == std::string::npos || pb == std::string::npos || pq == std::string::npos) continue;
         w = std::atoi(line.c_str() + pw + 7);
         bb = std::atoi(line.c_str() + pb + 7);
-        if (w >= 1 && w <= 4 && bb >= 1) {
+        pp = std::atoi(line.c_str() + pq + 7);
+        if (w >= 1 && w <= 4 && bb >= 1 && (pp == 1 || pp == 2 || pp == 4)) {
             *wpg = w;
             *bpw = bb;
+            *wpp = pp;
             return true;
         }
     }
     return false;
 }
 
-static void tune_cache_store(const char *path, const std::string &key, int wpg, int bpw, double ms) {
+static void tune_cache_store(const char *path, const std::string &key, int wpg, int bpw, int wpp,
+                             double ms) {
     if (!path) return;
     std::ofstream f(path, std::ios::app);
-    f << "{\"key\": \"" << key << "\", \"wpg\": " << wpg << ", \"bpw\": " << bpw << ", \"ms\": " << ms
-      << "}\n";
+    f << "{\"key\": \"" << key << "\", \"wpg\": " << wpg << ", \"bpw\": " << bpw << ", \"wpp\": " << wpp
+      << ", \"ms\": " << ms << "}\n";
 }
+
+// Default AEQ schedule: with few channels the chip is idle, so spread each
+// polarisation half over more waves to shorten the serial chain.
+static int default_wpp(size_t nch) { return nch >= 512 ? 1 : (nch >= 128 ? 2 : 4); }
 
 static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
     std::string key = tune_key(p);
-    int w, b;
-    if (tune_cache_lookup(cache, key, &w, &b)) {
+    int w, b, q;
+    if (tune_cache_lookup(cache, key, &w, &b, &q)) {
         p->wpg = w;
         p->bpw = b;
+        p->wpp = q;
         return FNT_OK;
     }
-    // candidate CDC schedules; the AEQ schedule is one wave per channel
-    std::vector<std::pair<int, int>> cand;
-    for (int wpg : {1, 2, 4})
-        for (int bpw : {1, 2, 4, 8, 16, 32, 64})
-            if ((uint64_t)bpw <= std::max<uint64_t>(1, p->total_blocks)) cand.push_back({wpg, bpw});
     hipEvent_t e0, e1;
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
-    double best = 1e30;
-    int bw = p->wpg, bb = p->bpw;
-    for (auto &c : cand) {
-        // time the CDC stage alone: it is the stage whose schedule varies
-        float ms = 0;
-        hipError_t e = hipSuccess;
-        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(FNT_E_DEVICE, "plan: autotune events");
+    auto time_it = [&](auto &&launch) -> double {
+        float ms = 0, best = 1e30f;
+        for (int rep = 0; rep < 2; ++rep) {
             (void)hipEventRecord(e0, s);
-            e = launch_cdc(p->cdc_dev, (int)p->cdc_host.size(), CdcItem{}, p->total_blocks, c.first,
-                           c.second, false, p->err, s);
+            if (launch() != hipSuccess) return 1e30;
             (void)hipEventRecord(e1, s);
             (void)hipEventSynchronize(e1);
             (void)hipEventElapsedTime(&ms, e0, e1);
+            best = std::min(best, ms);
         }
-        if (e != hipSuccess) continue;
-        if (ms < best) {
-            best = ms;
-            bw = c.first;
-            bb = c.second;
+        return best;
+    };
+    // CDC schedules
+    double best_cdc = 1e30;
+    int bw = p->wpg, bb = p->bpw;
+    for (int wpg : {1, 2, 4})
+        for (int bpw : {1, 2, 4, 8, 16, 32, 64}) {
+            if ((uint64_t)bpw > std::max<uint64_t>(1, p->total_blocks)) continue;
+            double ms = time_it([&] {
+                return launch_cdc(p->cdc_dev, (int)p->cdc_host.size(), CdcItem{}, p->total_blocks, wpg, bpw,
+                                  false, p->err, s);
+            });
+            if (ms < best_cdc) {
+                best_cdc = ms;
+                bw = wpg;
+                bb = bpw;
+            }
+        }
+    // AEQ waves per polarisation half, on scratch copies of the tap state
+    const size_t nch = p->aeq_host.size();
+    int16_t *tscratch = nullptr;
+    AeqItem *tdev = nullptr;
+    double best_aeq = 1e30;
+    int bq = p->wpp;
+    if (p->variant == 0 && hipMalloc(&tscratch, nch * 256 * sizeof(int16_t)) == hipSuccess &&
+        hipMalloc(&tdev, nch * sizeof(AeqItem)) == hipSuccess) {
+        std::vector<AeqItem> tab = p->aeq_host;
+        hipError_t e = hipSuccess;
+        for (size_t i = 0; i < nch && e == hipSuccess; ++i) {
+            e = hipMemcpyAsync(tscratch + i * 256, tab[i].taps, 256 * sizeof(int16_t),
+                               hipMemcpyDeviceToDevice, s);
+            tab[i].taps = tscratch + i * 256;
+        }
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(tdev, tab.data(), nch * sizeof(AeqItem), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e == hipSuccess) {
+            for (int wpp : {1, 2, 4}) {
+                double ms = time_it([&] {
+                    return launch_aeq(tdev, (int)nch, AeqItem{}, 0, wpp, p->err, s);
+                });
+                if (ms < best_aeq) {
+                    best_aeq = ms;
+                    bq = wpp;
+                }
+            }
         }
     }
+    if (tscratch) (void)hipFree(tscratch);
+    if (tdev) (void)hipFree(tdev);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     p->wpg = bw;
     p->bpw = bb;
-    p->info.tune_ms = best;
-    tune_cache_store(cache, key, bw, bb, best);
+    p->wpp = bq;
+    p->info.tune_ms = best_cdc + (best_aeq < 1e29 ? best_aeq : 0.0);
+    tune_cache_store(cache, key, bw, bb, bq, p->info.tune_ms);
     return FNT_OK;
 }
 
@@ -502,6 +545,7 @@ int fnt_plan_create(fnt_plan **out, const fnt_channel_desc *ch, size_t nch, cons
         }
     }
     default_cdc_schedule(blocks, &p->wpg, &p->bpw);
+    p->wpp = default_wpp(nch);
     if (c.autotune && blocks > 0) {
         if ((rc = plan_autotune(p, s, c.tune_cache))) {
             fnt_plan_destroy(p);
@@ -543,14 +587,23 @@ int fnt_plan_get_info(const fnt_plan *p, fnt_plan_info *info) {
     info->cdc_waves_per_group = p->wpg;
     info->cdc_blocks_per_wave = p->bpw;
     info->aeq_variant = p->variant;
+    info->aeq_waves_per_pol = p->wpp;
     info->graph = p->exec ? 1 : 0;
     return FNT_OK;
 }
 
 int fnt_plan_set_aeq_variant(fnt_plan *p, int variant) {
     if (!p) return fail(FNT_E_INVAL, "plan: NULL");
-    if (variant != 0 && variant != 1) return fail(FNT_E_INVAL, "plan: variant %d", variant);
+    if (variant < 0 || variant > 2) return fail(FNT_E_INVAL, "plan: variant %d", variant);
     p->variant = variant;
+    if (p->exec) return plan_capture(p, nullptr);
+    return FNT_OK;
+}
+
+int fnt_plan_set_aeq_waves(fnt_plan *p, int wpp) {
+    if (!p) return fail(FNT_E_INVAL, "plan: NULL");
+    if (wpp != 1 && wpp != 2 && wpp != 4) return fail(FNT_E_INVAL, "plan: waves per half %d", wpp);
+    p->wpp = wpp;
     if (p->exec) return plan_capture(p, nullptr);
     return FNT_OK;
 }

@@ -55,7 +55,9 @@ hipError_t launch_transform(const uint32_t *x, uint32_t *X, size_t batch, int t,
 hipError_t launch_cdc(const CdcItem *items, int nitems, const CdcItem &single,
                       uint64_t total_blocks, int waves_per_group, int blocks_per_wave,
                       bool with_z, int *err, hipStream_t s);
+// variant 0: Fermat-domain AEQ split by output polarisation, waves_per_pol in
+// {1, 2, 4}; 1: direct time-domain comparator; 2: Fermat-domain, one wave per channel.
 hipError_t launch_aeq(const AeqItem *items, int nitems, const AeqItem &single, int variant,
-                      int *err, hipStream_t s);
+                      int waves_per_pol, int *err, hipStream_t s);
 
 }  // namespace fnti

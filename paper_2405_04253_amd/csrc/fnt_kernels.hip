@@ -367,6 +367,35 @@ __device__ __forceinline__ void ifnt32_upper(int32_t (&x)[16], int t) {
 //  * input-spectrum lanes: S1 = lane / 16, 2 of the 32 window positions each.
 //  * output / error lanes: symbol m = lane / 4, stream S2 = lane % 4.
 //  * gradient / tap-state lanes: S1 = lane / 16, tap k = lane % 16, all 4 S2.
+// Final state of one polarisation half.  Taps: written by the waves that own
+// them (lane (S1, k) holds S2 = 2 pol + s2l0 .. + NWT - 1).  Symbol and CDC
+// histories: written once, by wave 0 of the polarisation-0 workgroup.
+template <int NWT>
+__device__ __forceinline__ void aeq_finish_pol(const AeqItem &it, int lane, int pol, bool tap_owner,
+                                               bool hist_owner, int s1, int s2l0,
+                                               const int32_t (&w)[NWT], int *err) {
+    const int kk = lane & 15;
+    if (tap_owner) {
+#pragma unroll
+        for (int q = 0; q < NWT; ++q) it.taps[(s1 * 4 + 2 * pol + s2l0 + q) * 16 + kk] = (int16_t)w[q];
+    }
+    if (hist_owner) {
+        if (it.hist_out) {
+            uint32_t h = (lane < 16) ? aeq_load(it, (int64_t)it.m - 16 + lane, err) : 0u;
+            if (lane < 16) reinterpret_cast<uint32_t *>(it.hist_out)[lane] = h;
+        }
+        if (it.cdc_tail) {
+            uint32_t tl = 0;
+            if (lane < 32) {
+                int64_t j = (int64_t)it.cdc_n - 32 + lane;
+                tl = j >= 0 ? reinterpret_cast<const uint32_t *>(it.cdc_in)[j]
+                            : reinterpret_cast<const uint32_t *>(it.cdc_tail)[32 + j];
+            }
+            if (lane < 32) reinterpret_cast<uint32_t *>(it.cdc_tail)[lane] = tl;
+        }
+    }
+}
+
 __global__ __launch_bounds__(64) void aeq_fnt_kernel(const AeqItem *items, AeqItem single,
                                                      int *err) {
     const AeqItem it = items ? items[blockIdx.x] : single;
@@ -505,6 +534,258 @@ __global__ __launch_bounds__(64) void aeq_fnt_kernel(const AeqItem *items, AeqIt
         win = pos < 16 ? slid : nxt;
     }
     aeq_finish(it, lane, w, err);
+}
+
+// ------------------------------------------------------------------------
+// FNT-AEQ split by output polarisation.
+//
+// The outputs of polarisation P (streams S2 = 2P, 2P+1) depend only on the 8
+// filters (S1 = 0..3) -> S2, and the RDE error of Eq. (6) for those filters
+// only on the same two outputs, so the 4x4 equaliser separates exactly into
+// two independent 4x2 halves.  One workgroup runs one half of one channel,
+// with WPP = LPT / 4 waves:
+//   * 16 tap-digit transforms per half (4 S1 x 2 S2 x 2 digits) over 64*WPP
+//     lanes: LPT lanes per transform, PPL = 32 / LPT bins per lane, lane t of a
+//     group holding positions n = t + LPT*j (stages with h >= LPT stay in
+//     registers, the rest exchange lanes t ^ h);
+//   * WPP = 2 splits the two tap digits over the waves, WPP = 4 also the two
+//     stream pairs (XI,XQ) / (YI,YQ); the waves then meet once per block to sum
+//     their partial outputs.
+// ------------------------------------------------------------------------
+template <int LPT>
+__device__ __forceinline__ int32_t xor_lpt_lane(int32_t v) { return xor_lane<LPT>(v); }
+
+template <int H>
+__device__ __forceinline__ int32_t xor_h(int32_t v) { return xor_lane<H>(v); }
+
+// In-register and cross-lane DIF of 16 tap-digit positions zero-padded to 32.
+// In: |x| <= 2^17; out: |X| <= 2^21; register j of lane t holds bin bitrev5(t + LPT j).
+template <int LPT>
+__device__ __forceinline__ void tap_fnt_lpt(int32_t (&x)[32 / LPT], int t) {
+    constexpr int PPL = 32 / LPT;
+#pragma unroll
+    for (int h = 16; h >= LPT; h >>= 1) {
+        const int jd = h / LPT;
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+            if (j & jd) continue;
+            const int e = (16 / h) * t + (16 * LPT / h) * (j & (jd - 1));   // < 16
+            if (h == 16) {
+                x[j + jd] = mulmod(x[j], 1 << e);     // the partner is zero padding
+            } else {
+                int32_t a = x[j], b = x[j + jd];
+                x[j] = a + b;
+                x[j + jd] = mulmod(a - b, 1 << e);
+            }
+        }
+    }
+#pragma unroll
+    for (int h = LPT / 2; h >= 1; h >>= 1) {
+        const bool up = (t & h) != 0;
+        const int32_t c = 1 << ((16 / h) * (t & (h - 1)));
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+            int32_t p = h == 8 ? xor_h<8>(x[j]) : h == 4 ? xor_h<4>(x[j])
+                      : h == 2 ? xor_h<2>(x[j]) : xor_h<1>(x[j]);
+            x[j] = up ? mulmod(p - x[j], c) : x[j] + p;
+        }
+    }
+}
+
+// 2^-e (mod 65537) as a small signed constant, 0 <= e < 16.
+__device__ __forceinline__ int32_t inv_pow2(int e) { return e ? -(1 << (16 - e)) : 1; }
+
+// DIT inverse (unnormalised) keeping positions 16..31 (registers PPL/2..PPL-1).
+// In: |x| < 2^18; out: |x| < 2^21.
+template <int LPT>
+__device__ __forceinline__ void ifnt_upper_lpt(int32_t (&x)[32 / LPT], int t) {
+    constexpr int PPL = 32 / LPT;
+#pragma unroll
+    for (int h = 1; h < LPT; h <<= 1) {
+        const bool up = (t & h) != 0;
+        const int32_t c = inv_pow2((16 / h) * (t & (h - 1)));
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+            int32_t tt = up ? mulmod(x[j], c) : x[j];
+            int32_t p = h == 8 ? xor_h<8>(tt) : h == 4 ? xor_h<4>(tt)
+                      : h == 2 ? xor_h<2>(tt) : xor_h<1>(tt);
+            x[j] = up ? p - tt : x[j] + p;
+        }
+    }
+#pragma unroll
+    for (int h = LPT; h <= 16; h <<= 1) {
+        const int jd = h / LPT;
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+            if (j & jd) continue;
+            const int e = (16 / h) * t + (16 * LPT / h) * (j & (jd - 1));
+            int32_t tt = mulmod(x[j + jd], inv_pow2(e));
+            if (h == 16) {
+                x[j + jd] = x[j] - tt;                // only the upper half is kept
+            } else {
+                int32_t a = x[j];
+                x[j] = a + tt;
+                x[j + jd] = a - tt;
+            }
+        }
+    }
+}
+
+template <int LPT>
+__global__ __launch_bounds__(64 * (LPT / 4)) void aeq_pol_kernel(const AeqItem *items, AeqItem single,
+                                                                 int *err) {
+    constexpr int WPP = LPT / 4;                       // waves per polarisation half
+    constexpr int PPL = 32 / LPT;                      // bins per lane
+    const AeqItem it = items ? items[blockIdx.x >> 1] : single;
+    const int pol = blockIdx.x & 1;
+    const int tid = threadIdx.x;
+    const int v = tid >> 6, lane = tid & 63;
+    const int pos = lane & 31;
+    // transform role
+    const int tr = lane / LPT, t = lane % LPT;
+    const int ts = tr & 1, tS2l = (tr >> 1) & 1;
+    const int td = WPP == 1 ? (tr >> 2) & 1 : (v & 1);
+    const int tg = WPP == 1 ? (tr >> 3) : WPP == 2 ? (tr >> 2) & 1 : (v >> 1);
+    const int tS1 = 2 * tg + ts;
+    // gradient / tap-state role: WPP <= 2: (S1, k) with both S2 of the half;
+    // WPP == 4: (S1 of this wave's stream pair, S2, k)
+    const int kk = lane & 15;
+    const int gS1 = WPP == 4 ? 2 * (v >> 1) + ((lane >> 4) & 1) : (lane >> 4);
+    constexpr int NW = WPP == 4 ? 1 : 2;             // taps per lane
+    const int gS2l0 = WPP == 4 ? (lane >> 5) : 0;
+    // output / error role (lanes 0..31): symbol m = lane / 2, stream S2l = lane % 2
+    const int om = (lane >> 1) & 15, oS2l = lane & 1;
+
+    __shared__ int16_t tapl_s[WPP][128];               // per wave: [S1][S2l][k]
+    __shared__ int32_t aspec_s[WPP][4][32];            // per wave: input spectra by position
+    __shared__ int32_t part_s[4][32];                  // [g*2+d][m*2+S2l], shared by the waves
+    __shared__ uint32_t epsw_s[WPP][8];                // per wave: bytes [S2l][m]
+    __shared__ uint32_t winw_s[WPP][36];               // per wave: bytes [S1][32] + pad
+    int16_t *tapl = tapl_s[v];
+    int32_t(*aspec)[32] = aspec_s[v];
+    uint32_t *epsw = epsw_s[v];
+    uint32_t *winw = winw_s[v];
+
+    int32_t w[NW];
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+        const int S2 = 2 * pol + gS2l0 + q;
+        int32_t val = it.taps[(gS1 * 4 + S2) * 16 + kk];
+        if (val < -8192 || val > 8191) flag(err, RANGE_TAP);
+        w[q] = clamp32(val, -8192, 8191);
+    }
+    const uint64_t M = it.m;
+    const bool writer = v == 0;                        // the wave that stores the outputs
+    const bool tap_owner = WPP == 4 ? (v & 1) == 0 : v == 0;
+    const bool hist_owner = pol == 0 && v == 0;
+    if (M == 0) {
+        aeq_finish_pol(it, lane, pol, tap_owner, hist_owner, gS1, gS2l0, w, err);
+        return;
+    }
+    if (lane < 4) winw[32 + lane] = 0u;
+
+    int32_t W[PPL];
+    auto transform_taps = [&]() {
+#pragma unroll
+        for (int q = 0; q < NW; ++q) tapl[(gS1 * 2 + gS2l0 + q) * 16 + kk] = (int16_t)w[q];
+        __syncthreads();
+        const int base = (tS1 * 2 + tS2l) * 16 + t;
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+            if (j < PPL / 2) {
+                int32_t val = tapl[base + LPT * j];
+                int32_t lo = ((val + 64) & 127) - 64;
+                int32_t hi = (val - lo) >> 7;
+                W[j] = (td ? lo : hi) * -2048;        // digit * 32^-1, |.| <= 2^17
+            } else {
+                W[j] = 0;
+            }
+        }
+        tap_fnt_lpt<LPT>(W, t);
+    };
+    transform_taps();
+
+    const uint32_t nblocks = (uint32_t)((M + 15) / 16);
+    const int c2 = it.const_unit * it.const_unit;
+    uint32_t win = aeq_load(it, -16 + pos, err);
+    int16_t *outp = it.out;
+
+    for (uint32_t b = 0; b < nblocks; ++b) {
+        uint32_t nxt = pos >= 16 ? aeq_load(it, (int64_t)16 * b + pos, err) : 0u;
+        if (lane < 32) {
+            uint8_t *wb = reinterpret_cast<uint8_t *>(winw);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) wb[c * 32 + pos] = (uint8_t)(win >> (8 * c));
+        }
+        __syncthreads();
+        {   // input spectra of the 4 streams: lane (S1 = lane / 16, k) holds positions k, k + 16
+            const int8_t *wb = reinterpret_cast<const int8_t *>(winw) + (lane >> 4) * 32;
+            int32_t x0 = wb[kk], x1 = wb[kk + 16];
+            int32_t u0 = x0 + x1;
+            int32_t u1 = mulmod(x0 - x1, 1 << kk);
+#pragma unroll
+            for (int h = 8; h >= 1; h >>= 1) {
+                const bool up = (kk & h) != 0;
+                const int32_t c = 1 << ((16 / h) * (kk & (h - 1)));
+                int32_t p0 = h == 8 ? xor_h<8>(u0) : h == 4 ? xor_h<4>(u0) : h == 2 ? xor_h<2>(u0) : xor_h<1>(u0);
+                int32_t p1 = h == 8 ? xor_h<8>(u1) : h == 4 ? xor_h<4>(u1) : h == 2 ? xor_h<2>(u1) : xor_h<1>(u1);
+                u0 = up ? mulmod(p0 - u0, c) : u0 + p0;
+                u1 = up ? mulmod(p1 - u1, c) : u1 + p1;
+            }
+            aspec[lane >> 4][kk] = u0;                  // |.| <= 2^21
+            aspec[lane >> 4][kk + 16] = u1;
+        }
+        __syncthreads();
+        int32_t Y[PPL];
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+            int32_t P = mulmod(aspec[tS1][t + LPT * j], W[j]);
+            Y[j] = P + xor_lpt_lane<LPT>(P);            // pair sum over S1 = 2g, 2g+1
+        }
+        ifnt_upper_lpt<LPT>(Y, t);
+        if (ts == 0) {
+#pragma unroll
+            for (int j = PPL / 2; j < PPL; ++j)
+                part_s[tg * 2 + td][(t + LPT * (j - PPL / 2)) * 2 + tS2l] = lift_loose(Y[j]);
+        }
+        __syncthreads();
+        // symbol om, stream 2 pol + oS2l: y = 2^7 (high-digit sums) + (low-digit sums)
+        const int pi = lane & 31;
+        const int32_t y = 128 * (part_s[0][pi] + part_s[2][pi]) + part_s[1][pi] + part_s[3][pi];
+        const int32_t yh = clamp32(rs32(y, it.out_shift), -32768, 32767);
+        const uint64_t m = (uint64_t)16 * b + om;
+        const bool valid = lane < 32 && m < M;
+        if (writer && valid) outp[m * 4 + 2 * pol + oS2l] = (int16_t)yh;
+        if (it.update_enable) {
+            const int32_t yp = xor_h<1>(yh);
+            const int64_t r2 = (int64_t)yh * yh + (int64_t)yp * yp;
+            const int64_t R2 = r2 < 6LL * c2 ? 2LL * c2 : (r2 < 14LL * c2 ? 10LL * c2 : 18LL * c2);
+            int32_t eps = (int32_t)clamp64(rs64((R2 - r2) * yh, it.err_shift), -128, 127);
+            if (!valid) eps = 0;
+            if (lane < 32) reinterpret_cast<int8_t *>(epsw)[oS2l * 16 + om] = (int8_t)eps;
+            __syncthreads();
+            const int off = gS1 * 32 + 16 - kk;
+            uint32_t dd[5];
+#pragma unroll
+            for (int r = 0; r < 5; ++r) dd[r] = winw[(off >> 2) + r];
+            uint32_t xs[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) xs[q] = __builtin_amdgcn_alignbyte(dd[q + 1], dd[q], off & 3);
+#pragma unroll
+            for (int q2 = 0; q2 < NW; ++q2) {
+                const int S2l = gS2l0 + q2;
+                int32_t gsum = 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    gsum = __builtin_amdgcn_sdot4((int)epsw[S2l * 4 + q], (int)xs[q], gsum, false);
+                w[q2] = clamp32(w[q2] + (int32_t)rs64((int64_t)gsum, it.mu_shift), -8192, 8191);
+            }
+            transform_taps();
+        }
+        uint32_t slid = (uint32_t)__shfl((int)win, (lane & 32) | ((pos + 16) & 31));
+        win = pos < 16 ? slid : nxt;
+    }
+    aeq_finish_pol(it, lane, pol, tap_owner, hist_owner, gS1, gS2l0, w, err);
 }
 
 // Direct comparator: y by integer dot products in the time domain, same RDE.
@@ -656,13 +937,25 @@ hipError_t launch_cdc(const CdcItem *items, int nitems, const CdcItem &single,
 }
 
 hipError_t launch_aeq(const AeqItem *items, int nitems, const AeqItem &single, int variant,
-                      int *err, hipStream_t s) {
-    const int grid = items ? nitems : 1;
-    if (grid <= 0) return hipSuccess;
-    if (variant == 0)
-        aeq_fnt_kernel<<<grid, 64, 0, s>>>(items, single, err);
-    else
-        aeq_direct_kernel<<<grid, 64, 0, s>>>(items, single, err);
+                      int waves_per_pol, int *err, hipStream_t s) {
+    const int n = items ? nitems : 1;
+    if (n <= 0) return hipSuccess;
+    if (variant == 0) {
+        if (waves_per_pol == 1)
+            aeq_pol_kernel<4><<<2 * n, 64, 0, s>>>(items, single, err);
+        else if (waves_per_pol == 2)
+            aeq_pol_kernel<8><<<2 * n, 128, 0, s>>>(items, single, err);
+        else if (waves_per_pol == 4)
+            aeq_pol_kernel<16><<<2 * n, 256, 0, s>>>(items, single, err);
+        else
+            return hipErrorInvalidValue;
+    } else if (variant == 1) {
+        aeq_direct_kernel<<<n, 64, 0, s>>>(items, single, err);
+    } else if (variant == 2) {
+        aeq_fnt_kernel<<<n, 64, 0, s>>>(items, single, err);
+    } else {
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

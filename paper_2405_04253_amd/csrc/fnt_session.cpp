@@ -296,7 +296,7 @@ void scheduler_main(fnt_session *s) {
             default_cdc_schedule(total_blocks, &wpg, &bpw);
             e = launch_cdc(slot.cdc_dev, nitems, CdcItem{}, total_blocks, wpg, bpw, false, s->err, st);
         }
-        if (e == hipSuccess) e = launch_aeq(slot.aeq_dev, nitems, AeqItem{}, 0, s->err, st);
+        if (e == hipSuccess) e = launch_aeq(slot.aeq_dev, nitems, AeqItem{}, 0, nitems >= 512 ? 1 : 2, s->err, st);
         for (auto &c : d2h)
             if (e == hipSuccess)
                 e = hipMemcpyAsync(c.first, c.second.first, c.second.second, hipMemcpyDeviceToHost, st);

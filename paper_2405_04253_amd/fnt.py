@@ -60,7 +60,8 @@ class PlanInfo(ctypes.Structure):
                 ("symbols", ctypes.c_uint64), ("cdc_blocks", ctypes.c_uint64),
                 ("aeq_blocks_max", ctypes.c_uint64), ("cdc_waves_per_group", ctypes.c_int32),
                 ("cdc_blocks_per_wave", ctypes.c_int32), ("aeq_variant", ctypes.c_int32),
-                ("graph", ctypes.c_int32), ("tune_ms", ctypes.c_double)]
+                ("aeq_waves_per_pol", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("tune_ms", ctypes.c_double)]
 
 
 class SessionConfig(ctypes.Structure):
@@ -100,6 +101,7 @@ SIGNATURES = {
     "fnt_plan_run": (_i32, [_vp, _vp]),
     "fnt_plan_get_info": (_i32, [_vp, ctypes.POINTER(PlanInfo)]),
     "fnt_plan_set_aeq_variant": (_i32, [_vp, _i32]),
+    "fnt_plan_set_aeq_waves": (_i32, [_vp, _i32]),
     "fnt_plan_destroy": (_i32, [_vp]),
     "fnt_now_ns": (_u64, []),
     "fnt_session_create": (_i32, [ctypes.POINTER(_vp), ctypes.POINTER(SessionConfig)]),
@@ -281,6 +283,9 @@ class Plan:
 
     def set_aeq_variant(self, variant: int):
         _ok(lib().fnt_plan_set_aeq_variant(self._h, int(variant)))
+
+    def set_aeq_waves(self, waves_per_pol: int):
+        _ok(lib().fnt_plan_set_aeq_waves(self._h, int(waves_per_pol)))
 
     def close(self):
         if getattr(self, "_h", None):

@@ -237,8 +237,8 @@ def _plan_channels(torch, dev, chans, rng):
     return out
 
 
-@pytest.mark.parametrize("variant", [0, 1])
-def test_plan_batched_vs_oracle(torch_dev, variant):
+@pytest.mark.parametrize("variant,wpp", [(0, 1), (0, 2), (0, 4), (1, 1), (2, 1)])
+def test_plan_batched_vs_oracle(torch_dev, variant, wpp):
     torch, dev = torch_dev
     chans = _batch(40, 6, 11, seed=variant)
     chans.append(synth.gen_channel(3, 30.0, 20.0, seed=5))      # ragged, tiny
@@ -250,11 +250,12 @@ def test_plan_batched_vs_oracle(torch_dev, variant):
     plan = fnt.Plan([(c["x"], c["out"], c["taps"], fnt.cdc_params(c["ch"].taps, c["ch"].requant_shift),
                       fnt.aeq_params(**c["prm"])) for c in pc], autotune=False, use_graph=True)
     plan.set_aeq_variant(variant)
+    plan.set_aeq_waves(wpp)
     for rep in range(3):
         for c in pc:        # eager work between replays: reset the tap state
             c["taps"].copy_(to_dev(torch, dev, c["w0"]))
             c["out"].fill_(-1)
-        note(f"plan run variant={variant} replay={rep}")
+        note(f"plan run variant={variant} wpp={wpp} replay={rep}")
         plan.run()
         torch.cuda.synchronize()
         for c, (outr, wr, _) in zip(pc, refs):
@@ -262,6 +263,7 @@ def test_plan_batched_vs_oracle(torch_dev, variant):
             assert np.array_equal(c["taps"].cpu().numpy(), wr), (rep, c["ch"].n)
     info = plan.info()
     assert info["channels"] == len(pc) and info["graph"] == 1 and info["aeq_variant"] == variant
+    assert info["aeq_waves_per_pol"] == wpp
     plan.close()
     fnt.fnt_check()
 
