@@ -127,10 +127,12 @@ def bench_single(args, torch, dev):
         if ev is not None:
             ev[2].record(stream)
 
+    progress(f"single: generated {n} instants in {gen_s:.1f} s; warmup")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     fnt.fnt_check()
+    progress(f"single: timing {args.steps} steps")
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -156,9 +158,9 @@ def bench_single(args, torch, dev):
                 "us_per_block": round(aeq_ms * 1e3 / blocks_aeq, 4)},
     }
     achieved = aeq_ops / (aeq_ms / 1e3) / 1e9
-    roof = {"kernel": "aeq_fnt_kernel", "bound": "alu", "achieved": round(achieved, 3),
+    roof = {"kernel": "aeq_pol_kernel<16>", "bound": "alu", "achieved": round(achieved, 3),
             "peak": PEAK_ALU_GOPS, "unit": "Gops/s", "frac": round(achieved / PEAK_ALU_GOPS, 6),
-            "traffic": load_traffic("aeq_fnt_kernel", "single"),
+            "traffic": load_traffic("aeq_pol_kernel", "single"),
             "algorithmic_ops_per_launch": aeq_ops}
     res = {
         "metric": "bit-exact Gsamples/s, batched/served vs plain FNT-CDC+AEQ; p50/p99 latency",
@@ -174,8 +176,189 @@ def bench_single(args, torch, dev):
         "gen_s": round(gen_s, 1),
     }
     if not args.no_cpu_baseline:
+        progress("single: oracle CPU baseline")
         res["cpu_baseline"] = cpu_baseline_single(ch, prm, args.cpu_budget)
     return res
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _time_events(torch, fn, reps, stream):
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in evs:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return float(np.mean([a.elapsed_time(b) for a, b in evs]))
+
+
+def bench_batched(args, torch, dev, single_gsps):
+    """Many channels of log-uniform length in one plan (hipGraph replay, autotuned)."""
+    import oracle as O
+    from paper_2405_04253_amd import fnt, synth
+    t0 = time.perf_counter()
+    specs = synth.batched_specs(args.nch, args.log2_min, args.log2_max, tag="bench-batched")
+    chans = []
+    for k, sp in enumerate(specs):
+        q, taps, sh, unit = synth.gen_channel_torch(sp.nsym, sp.fibre_km, sp.osnr_db, sp.seed, dev)
+        chans.append((sp, q, taps, sh, unit))
+        if k % 256 == 0:
+            torch.cuda.synchronize()
+            progress(f"batched: generated {k + 1}/{len(specs)} channels ({time.perf_counter() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    progress(f"batched: generation done in {gen_s:.1f} s")
+    w0 = torch.from_numpy(synth.centre_spike_taps()).to(dev)
+    taps_all = w0.unsqueeze(0).repeat(len(chans), 1, 1, 1).contiguous()
+    entries, prms = [], []
+    inst = 0
+    for i, (sp, q, taps, sh, unit) in enumerate(chans):
+        prm = dict(synth.AEQ_DEFAULTS, const_unit=unit)
+        prms.append(prm)
+        out = torch.empty((q.shape[0] // 2, 4), dtype=torch.int16, device=dev)
+        entries.append((q, out, taps_all[i], fnt.cdc_params(taps, sh), fnt.aeq_params(**prm)))
+        inst += q.shape[0]
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    progress(f"batched: plan create + autotune over {len(entries)} channels")
+    plan = fnt.Plan(entries, autotune=True, use_graph=True, stream=stream)
+    torch.cuda.synchronize()
+    tune_s = time.perf_counter() - t0
+    progress(f"batched: plan ready in {tune_s:.1f} s: {plan.info()}")
+    for _ in range(max(1, args.warmup)):
+        plan.run(stream)
+    torch.cuda.synchronize()
+    fnt.fnt_check()
+    reps = max(1, args.batched_steps)
+    progress(f"batched: timing {reps} runs")
+    ms = _time_events(torch, lambda: plan.run(stream), reps, stream)
+    fnt.fnt_check()
+    progress(f"batched: {ms:.1f} ms per run; checking parity")
+    info = plan.info()
+    # parity on sampled channels: reset the taps, run once more, compare with the oracle
+    taps_all.copy_(w0.unsqueeze(0).expand_as(taps_all))
+    plan.run(stream)
+    torch.cuda.synchronize()
+    order = sorted(range(len(chans)), key=lambda i: chans[i][1].shape[0])
+    pick = sorted(set([order[0], order[len(order) // 2], order[-1]]))
+    for i in pick:
+        sp, q, taps, sh, unit = chans[i]
+        outr, wr, _ = O.cdc_aeq(q.cpu().numpy(), taps, sh, synth.centre_spike_taps(), O.params(**prms[i]))
+        if not (np.array_equal(entries[i][1].cpu().numpy(), outr) and np.array_equal(taps_all[i].cpu().numpy(), wr)):
+            raise SystemExit(f"batched parity failure on channel {i}")
+    # plain comparator: the single-stream call (fnt_cdc_aeq) channel after channel, on
+    # a random sample of channels; its rate over the sample stands for the loop
+    rng = np.random.default_rng(7)
+    sample = [int(i) for i in rng.choice(len(chans), size=min(32, len(chans)), replace=False)]
+    tmp_taps = w0.clone()
+    s_inst = sum(chans[i][1].shape[0] for i in sample)
+    progress(f"batched: plain per-channel loop over {len(sample)} sampled channels")
+
+    def plain_loop():
+        for i in sample:
+            tmp_taps.copy_(w0)
+            fnt.fnt_cdc_aeq(chans[i][1], entries[i][3], tmp_taps, entries[i][4], out=entries[i][1], stream=stream)
+
+    plain_ms = _time_events(torch, plain_loop, 1, stream)
+    plain_gsps = s_inst / (plain_ms / 1e3) / 1e9
+    value = inst / (ms / 1e3) / 1e9
+    blocks = sum((e[0].shape[0] // 2 + 15) // 16 for e in entries)
+    aeq_ops = AEQ_OPS_PER_BLOCK * blocks
+    cdc_ops = CDC_OPS_PER_BLOCK * sum((e[0].shape[0] + 31) // 32 for e in entries)
+    achieved = (aeq_ops + cdc_ops) / (ms / 1e3) / 1e9
+    plan.close()
+    return {"value": round(value, 4), "unit": "Gsamples/s", "ms_per_run": round(ms, 3),
+            "vs_plain": round(value / plain_gsps, 2),
+            "plain_loop_gsamples_per_s": round(plain_gsps, 5),
+            "plain_loop_sample": f"{len(sample)} random channels, fnt_cdc_aeq one after another",
+            "vs_single_stream": round(value / single_gsps, 2) if single_gsps else None,
+            "workload": f"{len(chans)} channels, log-uniform 2^{args.log2_min}..2^{args.log2_max} "
+                        f"symbols/pol, fibre U(10,80) km, 8-32 taps, OSNR U(18,26) dB",
+            "channels": len(chans), "instants": inst, "longest_aeq_chain_blocks": info["aeq_blocks_max"],
+            "plan": {k: info[k] for k in ("cdc_waves_per_group", "cdc_blocks_per_wave", "aeq_variant",
+                                          "aeq_waves_per_pol", "graph")},
+            "roofline_whole_path": {"bound": "alu", "achieved": round(achieved, 1), "peak": PEAK_ALU_GOPS,
+                                    "unit": "Gops/s", "frac": round(achieved / PEAK_ALU_GOPS, 5)},
+            "parity": f"bit-exact vs oracle on channels {pick}", "gen_s": round(gen_s, 1),
+            "autotune_s": round(tune_s, 1)}
+
+
+def bench_served(args, torch, dev):
+    """Poisson arrivals of stream segments into a session; p50/p99 latency."""
+    import oracle as O
+    from paper_2405_04253_amd import fnt, synth
+    rng = np.random.default_rng(12345)
+    nch = args.served_channels
+    # arrivals over the window, each to a uniformly random channel
+    times, t = [], 0.0
+    while True:
+        t += rng.exponential(1.0 / args.rate)
+        if t > args.window:
+            break
+        times.append(t)
+    seg_sym = [16 * max(1, int(2 ** rng.uniform(13, 18)) // 16) for _ in times]
+    owner = rng.integers(0, nch, size=len(times))
+    per_ch = [[] for _ in range(nch)]
+    for i, c in enumerate(owner):
+        per_ch[c].append(i)
+    t0 = time.perf_counter()
+    streams, params = {}, {}
+    sess = fnt.Session(max_channels=nch, hbm_budget_bytes=1 << 30, chunk_blocks=args.chunk,
+                       max_active=nch)
+    progress(f"served: {len(times)} requests over {nch} channels; generating streams")
+    for c in range(nch):
+        if c % 128 == 0:
+            torch.cuda.synchronize()
+            progress(f"served: generated {c}/{nch} channel streams ({time.perf_counter() - t0:.1f} s)")
+        nsym = sum(seg_sym[i] for i in per_ch[c])
+        r = np.random.default_rng(synth.seed_for(0, "served", c))
+        km, osnr = float(r.uniform(10, 80)), float(r.uniform(18, 26))
+        q, taps, sh, unit = synth.gen_channel_torch(max(nsym, 16), km, osnr, synth.seed_for(1, "served", c), dev)
+        streams[c] = q
+        prm = dict(synth.AEQ_DEFAULTS, const_unit=unit)
+        params[c] = (taps, sh, prm)
+        sess.add_channel(c, fnt.cdc_params(taps, sh), fnt.aeq_params(**prm))
+    outs = {c: torch.zeros((streams[c].shape[0] // 2, 4), dtype=torch.int16, device=dev) for c in range(nch)}
+    reqs, offs = [], [0] * nch
+    for i in range(len(times)):
+        c = int(owner[i])
+        n = 2 * seg_sym[i]
+        o = offs[c]
+        reqs.append((c, streams[c][o:o + n], outs[c][o // 2:(o + n) // 2], int(times[i] * 1e9)))
+        offs[c] += n
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    progress(f"served: replaying {len(reqs)} arrivals over {args.window} s")
+    sess.replay(reqs)
+    t_end = time.perf_counter()
+    while sess.stats()["completed"] < len(reqs):
+        time.sleep(1.0)
+        progress(f"served: {sess.stats()['completed']}/{len(reqs)} done "
+                 f"({time.perf_counter() - t_end:.1f} s after the last arrival)")
+    sess.drain()
+    st = sess.stats()
+    sess.close()
+    fnt.fnt_check()
+    # parity: the two busiest channels against the oracle on their concatenated streams
+    busiest = sorted(range(nch), key=lambda c: -offs[c])[:2]
+    for c in busiest:
+        taps, sh, prm = params[c]
+        n = offs[c]
+        outr, _, _ = O.cdc_aeq(streams[c][:n].cpu().numpy(), taps, sh, synth.centre_spike_taps(), O.params(**prm))
+        if not np.array_equal(outs[c][: n // 2].cpu().numpy(), outr):
+            raise SystemExit(f"served parity failure on channel {c}")
+    inst = sum(2 * x for x in seg_sym)
+    return {"value": round(st["gsamples_per_s"], 4), "unit": "Gsamples/s",
+            "p50_us": round(st["p50_us"], 1), "p99_us": round(st["p99_us"], 1),
+            "mean_us": round(st["mean_us"], 1), "max_us": round(st["max_us"], 1),
+            "requests": int(st["completed"]), "ticks": int(st["ticks"]),
+            "offered_gsamples_per_s": round(inst / args.window / 1e9, 3),
+            "workload": f"{nch} channels, Poisson {args.rate:.0f} req/s for {args.window} s, segments "
+                        f"log-uniform 2^13..2^18 symbols, chunk {args.chunk} blocks/tick",
+            "parity": f"bit-exact vs oracle on channels {busiest} (whole streams)", "gen_s": round(gen_s, 1)}
 
 
 def main():
@@ -183,10 +366,22 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="single", choices=["single"])
     ap.add_argument("--log2-symbols", type=int, default=24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--skip-batched", action="store_true")
+    ap.add_argument("--skip-served", action="store_true")
+    ap.add_argument("--skip-single", action="store_true")
+    ap.add_argument("--nch", type=int, default=4096)
+    ap.add_argument("--log2-min", type=int, default=12)
+    ap.add_argument("--log2-max", type=int, default=20)
+    ap.add_argument("--batched-steps", type=int, default=3)
+    ap.add_argument("--served-channels", type=int, default=1024)
+    ap.add_argument("--rate", type=float, default=20000.0)
+    ap.add_argument("--window", type=float, default=0.5)
+    ap.add_argument("--chunk", type=int, default=64)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run 5 plain 256 MiB device-to-device copies (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -198,7 +393,23 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
-    res = bench_single(args, torch, dev)
+    if args.copy_probe:
+        x = torch.randint(-16, 16, (256 << 20,), dtype=torch.int8, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": x.numel(), "copies": 5}), flush=True)
+        return
+    progress("single stream")
+    res = bench_single(args, torch, dev) if not args.skip_single else {}
+    progress(f"single done: {res.get('value')}")
+    if not args.skip_batched:
+        res["batched"] = bench_batched(args, torch, dev, res.get("value"))
+        print(f"[bench] batched done: {res['batched']['value']}", file=sys.stderr, flush=True)
+    if not args.skip_served:
+        res["served"] = bench_served(args, torch, dev)
+        print(f"[bench] served done: {res['served']['value']}", file=sys.stderr, flush=True)
     print(json.dumps(res), flush=True)
 
 

@@ -185,18 +185,19 @@ typedef struct fnt_plan_info {
                               2 = Fermat-domain, one wave per channel */
     int32_t aeq_waves_per_pol;  /* variant 0: waves per polarisation half (1, 2 or 4) */
     int32_t graph;         /* 1 if a hipGraph is replayed */
-    int32_t reserved;
-    double tune_ms;        /* time of the chosen schedule during autotune (0 if none) */
+    int32_t aeq_waves_long;     /* waves per half for the long chains (see fnt_plan_set_aeq_split) */
+    double tune_ms;        /* AEQ time of the chosen schedule during autotune, ms (0 if none) */
+    uint64_t aeq_long_channels; /* longest channels run in their own concurrent launch */
 } fnt_plan_info;
 
 typedef struct fnt_plan fnt_plan;
 
 /* Build a plan for `nch` channels (copied; the device buffers must stay valid
  * while the plan is used).  Allocates the plan's device tables and scratch.
- * With autotune, times the candidate CDC schedules and AEQ waves-per-half on
- * `stream`: the CDC runs write plan scratch, the AEQ runs work on scratch copies
- * of the taps and write `out` (which a real run overwrites); the caller's taps
- * are not touched. */
+ * With autotune, times the candidate CDC schedules and AEQ schedules (waves per
+ * half, split of the longest chains) on `stream`: the CDC runs write plan
+ * scratch, the AEQ runs work on scratch copies of the taps and write `out`
+ * (which a real run overwrites); the caller's taps are not touched. */
 int fnt_plan_create(fnt_plan **plan, const fnt_channel_desc *host_channels, size_t nch,
                     const fnt_plan_config *cfg, void *stream);
 /* Run every channel once (CDC + resample + AEQ), enqueued on `stream`. */
@@ -213,6 +214,14 @@ int fnt_plan_set_aeq_variant(fnt_plan *plan, int variant);
  * each channel's serial chain; fewer use the chip more efficiently when there
  * are many channels).  Overrides the default / autotuned choice. */
 int fnt_plan_set_aeq_waves(fnt_plan *plan, int waves_per_pol);
+/* Split the AEQ of a plan: the `long_channels` channels with the longest chains
+ * run with `wpp_long` waves per polarisation half (short serial latency) in a
+ * launch concurrent with the rest, which run with `wpp` waves per half
+ * (fewer waves, higher throughput).  long_channels = 0 disables the split. */
+int fnt_plan_set_aeq_split(fnt_plan *plan, uint64_t long_channels, int wpp_long, int wpp);
+/* CDC launch schedule: waves per workgroup (1, 2 or 4) and consecutive 32-instant
+ * blocks per wave (1 .. 1024).  Results do not depend on it. */
+int fnt_plan_set_cdc_schedule(fnt_plan *plan, int waves_per_group, int blocks_per_wave);
 
 /* ------------------------------------------------------------------------
  * Serving sessions: continuing per-channel streams with device-resident state.

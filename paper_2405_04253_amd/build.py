@@ -29,27 +29,28 @@ def _run(cmd):
             sys.stderr.write(line + "\n")
 
 
-def build(force: bool = True, jobs: int = 3) -> str:
+def build(force: bool = True, jobs: int = 3, out: str | None = None, defines=()) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     deps = srcs + [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".hpp")]
     deps.append(os.path.join(HERE, "..", "include", "fnt.h"))
-    if not force and os.path.exists(LIB) and all(os.path.getmtime(LIB) >= os.path.getmtime(d) for d in deps):
-        return LIB
-    objdir = os.path.join(HERE, "_build")
+    lib = out or LIB
+    if not force and os.path.exists(lib) and all(os.path.getmtime(lib) >= os.path.getmtime(d) for d in deps):
+        return lib
+    objdir = os.path.join(HERE, "_build" if not defines else "_build_" + "_".join(d.replace("=", "") for d in defines))
     os.makedirs(objdir, exist_ok=True)
     objs, procs = [], []
     for s in srcs:
         o = os.path.join(objdir, os.path.basename(s) + ".o")
         objs.append(o)
         lang = ["-x", "hip"]
-        procs.append(["hipcc", *lang, *HIP_FLAGS, "-c", s, "-o", o])
+        procs.append(["hipcc", *lang, *HIP_FLAGS, *["-D" + d for d in defines], "-c", s, "-o", o])
     from concurrent.futures import ThreadPoolExecutor
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         list(ex.map(_run, procs))
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"])
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -272,16 +272,38 @@ struct fnt_plan {
     uint64_t total_blocks = 0;
     fnt_plan_info info{};
     int wpg = 4, bpw = 1, variant = 0, wpp = 1;
+    // AEQ split: the n_long longest chains (table prefix) run with wpp_long waves
+    // per half in a launch concurrent with the rest
+    int wpp_long = 4;
+    size_t n_long = 0;
+    hipStream_t side = nullptr;        // second stream for the concurrent AEQ launch
+    hipEvent_t fork = nullptr, join = nullptr;
     bool use_graph = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
 
-static int plan_launch(fnt_plan *p, hipStream_t s) {
+// Launch sequence of a plan on stream s: CDC over all blocks, then the AEQ of
+// the long chains on s concurrently with the AEQ of the others on a side stream
+// (fork / join by events, which a graph capture turns into parallel branches).
+static int plan_launch(fnt_plan *p, hipStream_t s, hipStream_t side) {
+    const int n = (int)p->aeq_host.size();
     hipError_t e = launch_cdc(p->cdc_dev, (int)p->cdc_host.size(), CdcItem{}, p->total_blocks, p->wpg,
                               p->bpw, false, p->err, s);
     if (e != hipSuccess) return hip_fail(e, "plan: cdc launch");
-    e = launch_aeq(p->aeq_dev, (int)p->aeq_host.size(), AeqItem{}, p->variant, p->wpp, p->err, s);
+    const int nl = (int)std::min<size_t>(p->n_long, (size_t)n);
+    if (nl == 0 || nl == n || p->variant != 0) {
+        const int w = (p->variant == 0 && nl == n) ? p->wpp_long : p->wpp;
+        e = launch_aeq(p->aeq_dev, n, AeqItem{}, p->variant, w, p->err, s);
+        if (e != hipSuccess) return hip_fail(e, "plan: aeq launch");
+        return FNT_OK;
+    }
+    e = hipEventRecord(p->fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side, p->fork, 0);
+    if (e == hipSuccess) e = launch_aeq(p->aeq_dev, nl, AeqItem{}, 0, p->wpp_long, p->err, s);
+    if (e == hipSuccess) e = launch_aeq(p->aeq_dev + nl, n - nl, AeqItem{}, 0, p->wpp, p->err, side);
+    if (e == hipSuccess) e = hipEventRecord(p->join, side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, p->join, 0);
     if (e != hipSuccess) return hip_fail(e, "plan: aeq launch");
     return FNT_OK;
 }
@@ -295,18 +317,24 @@ static void plan_drop_graph(fnt_plan *p) {
 
 static int plan_capture(fnt_plan *p, hipStream_t s) {
     plan_drop_graph(p);
-    hipStream_t cs = nullptr;
+    hipStream_t cs = nullptr, cs2 = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-    if (e != hipSuccess) return hip_fail(e, "plan: capture stream");
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs2, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        if (cs) (void)hipStreamDestroy(cs);
+        return hip_fail(e, "plan: capture streams");
+    }
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) {
         (void)hipStreamDestroy(cs);
+        (void)hipStreamDestroy(cs2);
         return hip_fail(e, "plan: begin capture");
     }
-    int rc = plan_launch(p, cs);
+    int rc = plan_launch(p, cs, cs2);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(cs, &g);
     (void)hipStreamDestroy(cs);
+    (void)hipStreamDestroy(cs2);
     if (rc) {
         if (g) (void)hipGraphDestroy(g);
         return rc;
@@ -339,7 +367,8 @@ static std::string tune_key(const fnt_plan *p) {
     return k.str();
 }
 
-static bool tune_cache_lookup(const char *path, const std::string &key, int *wpg, int *bpw, int *wpp) {
+static bool tune_cache_lookup(const char *path, const std::string &key, int *wpg, int *bpw, int *wpp,
+                              int *wpp_long, long long *n_long) {
     if (!path) return false;
     std::ifstream f(path);
     std::string line;
@@ -355,10 +384,17 @@ static bool tune_cache_lookup(const char *path, const std::string &key, int *wpg
         w = std::atoi(line.c_str() + pw + 7);
         bb = std::atoi(line.c_str() + pb + 7);
         pp = std::atoi(line.c_str() + pq + 7);
-        if (w >= 1 && w <= 4 && bb >= 1 && (pp == 1 || pp == 2 || pp == 4)) {
+        size_t pl = line.find("\"wpp_long\": "), pn = line.find("\"n_long\": ");
+        if (pl == std::string::npos || pn == std::string::npos) continue;
+        int ql = std::atoi(line.c_str() + pl + 12);
+        long long nl = std::atoll(line.c_str() + pn + 10);
+        if (w >= 1 && w <= 4 && bb >= 1 && (pp == 1 || pp == 2 || pp == 4) &&
+            (ql == 1 || ql == 2 || ql == 4) && nl >= 0) {
             *wpg = w;
             *bpw = bb;
             *wpp = pp;
+            *wpp_long = ql;
+            *n_long = nl;
             return true;
         }
     }
@@ -366,11 +402,11 @@ static bool tune_cache_lookup(const char *path, const std::string &key, int *wpg
 }
 
 static void tune_cache_store(const char *path, const std::string &key, int wpg, int bpw, int wpp,
-                             double ms) {
+                             int wpp_long, long long n_long, double ms) {
     if (!path) return;
     std::ofstream f(path, std::ios::app);
     f << "{\"key\": \"" << key << "\", \"wpg\": " << wpg << ", \"bpw\": " << bpw << ", \"wpp\": " << wpp
-      << ", \"ms\": " << ms << "}\n";
+      << ", \"wpp_long\": " << wpp_long << ", \"n_long\": " << n_long << ", \"ms\": " << ms << "}\n";
 }
 
 // Default AEQ schedule: with few channels the chip is idle, so spread each
@@ -379,11 +415,14 @@ static int default_wpp(size_t nch) { return nch >= 512 ? 1 : (nch >= 128 ? 2 : 4
 
 static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
     std::string key = tune_key(p);
-    int w, b, q;
-    if (tune_cache_lookup(cache, key, &w, &b, &q)) {
+    int w, b, q, ql;
+    long long nl;
+    if (tune_cache_lookup(cache, key, &w, &b, &q, &ql, &nl)) {
         p->wpg = w;
         p->bpw = b;
         p->wpp = q;
+        p->wpp_long = ql;
+        p->n_long = (size_t)nl;
         return FNT_OK;
     }
     hipEvent_t e0, e1;
@@ -417,12 +456,14 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
                 bb = bpw;
             }
         }
-    // AEQ waves per polarisation half, on scratch copies of the tap state
+    // AEQ schedule (waves per half for the long chains and for the rest, and
+    // where the longest-first table splits), on scratch copies of the tap state
     const size_t nch = p->aeq_host.size();
     int16_t *tscratch = nullptr;
     AeqItem *tdev = nullptr;
     double best_aeq = 1e30;
-    int bq = p->wpp;
+    int bq = p->wpp, bql = p->wpp_long;
+    size_t bnl = p->n_long;
     if (p->variant == 0 && hipMalloc(&tscratch, nch * 256 * sizeof(int16_t)) == hipSuccess &&
         hipMalloc(&tdev, nch * sizeof(AeqItem)) == hipSuccess) {
         std::vector<AeqItem> tab = p->aeq_host;
@@ -436,15 +477,37 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
             e = hipMemcpyAsync(tdev, tab.data(), nch * sizeof(AeqItem), hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e == hipSuccess) {
-            for (int wpp : {1, 2, 4}) {
-                double ms = time_it([&] {
-                    return launch_aeq(tdev, (int)nch, AeqItem{}, 0, wpp, p->err, s);
-                });
-                if (ms < best_aeq) {
-                    best_aeq = ms;
-                    bq = wpp;
-                }
+            // split points: channels whose chain is at least 1/2, 1/4, ... of the longest
+            std::vector<size_t> splits = {0};
+            const uint64_t longest = (p->aeq_host[0].m + 15) / 16;
+            for (int d = 2; d <= 64; d *= 2) {
+                size_t k = 0;
+                while (k < nch && (p->aeq_host[k].m + 15) / 16 * d >= longest) ++k;
+                if (k > 0 && k < nch && k != splits.back()) splits.push_back(k);
             }
+            AeqItem *saved = p->aeq_dev;
+            p->aeq_dev = tdev;
+            for (size_t nl : splits)
+                for (int q : {1, 2, 4}) {
+                    const int ql = 4;                           // long chains: shortest latency
+                    if (nl > 0 && q == 4) continue;             // a split only pays with fewer waves
+                    {
+                        p->n_long = nl;
+                        p->wpp_long = ql;
+                        p->wpp = q;
+                        double ms = time_it([&] {
+                            int rc = plan_launch(p, s, p->side);
+                            return rc ? hipErrorUnknown : hipSuccess;
+                        });
+                        if (ms < best_aeq) {
+                            best_aeq = ms;
+                            bq = q;
+                            bql = ql;
+                            bnl = nl;
+                        }
+                    }
+                }
+            p->aeq_dev = saved;
         }
     }
     if (tscratch) (void)hipFree(tscratch);
@@ -454,8 +517,10 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
     p->wpg = bw;
     p->bpw = bb;
     p->wpp = bq;
-    p->info.tune_ms = best_cdc + (best_aeq < 1e29 ? best_aeq : 0.0);
-    tune_cache_store(cache, key, bw, bb, bq, p->info.tune_ms);
+    p->wpp_long = bql;
+    p->n_long = bnl;
+    p->info.tune_ms = best_aeq < 1e29 ? best_aeq : best_cdc;
+    tune_cache_store(cache, key, bw, bb, bq, bql, (long long)bnl, p->info.tune_ms);
     return FNT_OK;
 }
 
@@ -546,6 +611,17 @@ int fnt_plan_create(fnt_plan **out, const fnt_channel_desc *ch, size_t nch, cons
     }
     default_cdc_schedule(blocks, &p->wpg, &p->bpw);
     p->wpp = default_wpp(nch);
+    p->wpp_long = 4;
+    p->n_long = 0;
+    {
+        hipError_t ee = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
+        if (ee == hipSuccess) ee = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
+        if (ee == hipSuccess) ee = hipEventCreateWithFlags(&p->join, hipEventDisableTiming);
+        if (ee != hipSuccess) {
+            fnt_plan_destroy(p);
+            return hip_fail(ee, "plan: side stream");
+        }
+    }
     if (c.autotune && blocks > 0) {
         if ((rc = plan_autotune(p, s, c.tune_cache))) {
             fnt_plan_destroy(p);
@@ -578,7 +654,7 @@ int fnt_plan_run(fnt_plan *p, void *stream) {
         if (e != hipSuccess) return hip_fail(e, "plan: graph launch");
         return FNT_OK;
     }
-    return plan_launch(p, s);
+    return plan_launch(p, s, p->side);
 }
 
 int fnt_plan_get_info(const fnt_plan *p, fnt_plan_info *info) {
@@ -588,6 +664,8 @@ int fnt_plan_get_info(const fnt_plan *p, fnt_plan_info *info) {
     info->cdc_blocks_per_wave = p->bpw;
     info->aeq_variant = p->variant;
     info->aeq_waves_per_pol = p->wpp;
+    info->aeq_waves_long = p->wpp_long;
+    info->aeq_long_channels = p->variant == 0 ? std::min(p->n_long, p->aeq_host.size()) : 0;
     info->graph = p->exec ? 1 : 0;
     return FNT_OK;
 }
@@ -604,6 +682,28 @@ int fnt_plan_set_aeq_waves(fnt_plan *p, int wpp) {
     if (!p) return fail(FNT_E_INVAL, "plan: NULL");
     if (wpp != 1 && wpp != 2 && wpp != 4) return fail(FNT_E_INVAL, "plan: waves per half %d", wpp);
     p->wpp = wpp;
+    p->n_long = 0;
+    if (p->exec) return plan_capture(p, nullptr);
+    return FNT_OK;
+}
+
+int fnt_plan_set_aeq_split(fnt_plan *p, uint64_t long_channels, int wpp_long, int wpp) {
+    if (!p) return fail(FNT_E_INVAL, "plan: NULL");
+    if ((wpp_long != 1 && wpp_long != 2 && wpp_long != 4) || (wpp != 1 && wpp != 2 && wpp != 4))
+        return fail(FNT_E_INVAL, "plan: waves per half %d / %d", wpp_long, wpp);
+    p->n_long = (size_t)std::min<uint64_t>(long_channels, p->aeq_host.size());
+    p->wpp_long = wpp_long;
+    p->wpp = wpp;
+    if (p->exec) return plan_capture(p, nullptr);
+    return FNT_OK;
+}
+
+int fnt_plan_set_cdc_schedule(fnt_plan *p, int wpg, int bpw) {
+    if (!p) return fail(FNT_E_INVAL, "plan: NULL");
+    if (wpg != 1 && wpg != 2 && wpg != 4) return fail(FNT_E_INVAL, "plan: waves per group %d", wpg);
+    if (bpw < 1 || bpw > 1024) return fail(FNT_E_INVAL, "plan: blocks per wave %d", bpw);
+    p->wpg = wpg;
+    p->bpw = bpw;
     if (p->exec) return plan_capture(p, nullptr);
     return FNT_OK;
 }
@@ -611,6 +711,9 @@ int fnt_plan_set_aeq_waves(fnt_plan *p, int wpp) {
 int fnt_plan_destroy(fnt_plan *p) {
     if (!p) return FNT_OK;
     plan_drop_graph(p);
+    if (p->side) (void)hipStreamDestroy(p->side);
+    if (p->fork) (void)hipEventDestroy(p->fork);
+    if (p->join) (void)hipEventDestroy(p->join);
     if (p->cdc_dev) (void)hipFree(p->cdc_dev);
     if (p->aeq_dev) (void)hipFree(p->aeq_dev);
     if (p->abuf) (void)hipFree(p->abuf);

@@ -69,6 +69,16 @@ __global__ __launch_bounds__(256) void fnt_transform_kernel(const uint32_t *x, u
 
 // ----------------------------------------------------------------------- CDC --
 
+// LDS hand-off between lanes of one wave: LDS instructions of a wave are
+// processed in issue order, so only the compiler must not move memory
+// operations across this point.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+
 // All bytes of w in [-16, 15]: the top four bits of each byte are equal.
 __device__ __forceinline__ bool bytes_5bit(uint32_t w) {
     return ((w ^ (w << 1)) & 0xE0E0E0E0u) == 0u;
@@ -83,34 +93,141 @@ __device__ __forceinline__ uint32_t cdc_load(const CdcItem &it, int64_t i) {
     return (uint64_t)i < it.n ? reinterpret_cast<const uint32_t *>(it.in)[i] : 0u;
 }
 
-// Tap spectra H+ = FNT64(h_r + 256 h_i), H- = FNT64(h_r - 256 h_i) in lane order
-// (lane l holds bin bitrev(l)), the per-channel factors of Eqs. (7)-(8).
-// `taps` points at the item's int8[32][2] taps (device table or kernel argument).
-__device__ __forceinline__ void cdc_spectra(const int8_t *taps, int ntaps, int lane, uint32_t &hp,
-                                            uint32_t &hm) {
-    using FF = Field<16>;
-    int hr = 0, hi = 0;
-    if (lane < ntaps) {
-        hr = taps[2 * lane];
-        hi = taps[2 * lane + 1];
+// Powers of the CDC radix alpha = sqrt 2 = 4080 modulo 65537, alpha^e for e < 64.
+struct AlphaPow {
+    int32_t v[64];
+};
+constexpr AlphaPow make_alpha_pow() {
+    AlphaPow a{};
+    uint64_t x = 1;
+    for (int e = 0; e < 64; ++e) {
+        a.v[e] = (int32_t)x;
+        x = x * 4080u % 65537u;
     }
-    hp = fwd_xlane<16, 6, true>(FF::from_int(hr + 256 * hi), lane);
-    hm = fwd_xlane<16, 6, true>(FF::from_int(hr - 256 * hi), lane);
+    return a;
+}
+__constant__ AlphaPow kAlphaPow = make_alpha_pow();
+
+// 64-point transforms of the CDC, 16 lanes per transform, 4 points per lane:
+// lane t of a group holds positions n = t + 16 j (j < 4).  Twiddle constants
+// of this lane for the forward (alpha^e) and inverse (alpha^-e) transforms.
+struct CdcTw {
+    int32_t f32[2], f16, fx[4];    // forward: h = 32 (j = 0, 1), h = 16, h = 8, 4, 2, 1
+    int32_t i32[2], i16, ix[4];    // inverse: the same exponents negated
+};
+__device__ __forceinline__ CdcTw cdc_twiddles(int t) {
+    CdcTw w;
+    const int32_t *ap = kAlphaPow.v;
+    w.f32[0] = ap[t];
+    w.f32[1] = ap[t + 16];
+    w.f16 = ap[2 * t];
+    w.i32[0] = ap[(64 - t) & 63];
+    w.i32[1] = ap[(64 - t - 16) & 63];
+    w.i16 = ap[(64 - 2 * t) & 63];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int h = 8 >> q;
+        const int e = (32 / h) * (t & (h - 1));
+        w.fx[q] = ap[e];
+        w.ix[q] = ap[(64 - e) & 63];
+    }
+    return w;
 }
 
+// DIF forward, in: |x| < 2^15; out: |X| < 2^22, register j holds bin bitrev6(t + 16 j).
+__device__ __forceinline__ void cdc_fnt64(int32_t (&x)[4], int t, const CdcTw &w) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {                       // h = 32
+        int32_t a = x[j], b = x[j + 2];
+        x[j] = a + b;
+        x[j + 2] = mulmod(a - b, w.f32[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j += 2) {                    // h = 16
+        int32_t a = x[j], b = x[j + 1];
+        x[j] = a + b;
+        x[j + 1] = mulmod(a - b, w.f16);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {                       // h = 8, 4, 2, 1 across lanes
+        const int h = 8 >> q;
+        const bool up = (t & h) != 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            int32_t p = h == 8 ? xor_pos<8>(x[j]) : h == 4 ? xor_pos<4>(x[j])
+                      : h == 2 ? xor_pos<2>(x[j]) : xor_pos<1>(x[j]);
+            x[j] = blend(up, mulmod(p - x[j], w.fx[q]), x[j] + p);
+        }
+    }
+}
+
+// DIT inverse (unnormalised) keeping positions 32..63 (registers 2, 3).
+// In: |x| < 2^18; out: |x| < 2^20.
+__device__ __forceinline__ void cdc_ifnt64_upper(int32_t (&x)[4], int t, const CdcTw &w) {
+#pragma unroll
+    for (int q = 3; q >= 0; --q) {                      // h = 1, 2, 4, 8 across lanes
+        const int h = 8 >> q;
+        const bool up = (t & h) != 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            int32_t tt = blend(up, mulmod(x[j], w.ix[q]), x[j]);
+            int32_t p = h == 8 ? xor_pos<8>(tt) : h == 4 ? xor_pos<4>(tt)
+                      : h == 2 ? xor_pos<2>(tt) : xor_pos<1>(tt);
+            x[j] = blend(up, p - tt, x[j] + p);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j += 2) {                    // h = 16
+        int32_t tt = mulmod(x[j + 1], w.i16);
+        int32_t a = x[j];
+        x[j] = a + tt;
+        x[j + 1] = a - tt;
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j)                         // h = 32: upper half only
+        x[j + 2] = x[j] - mulmod(x[j + 2], w.i32[j]);
+}
+
+// Tap spectra of this lane's group: g = 2 pol + uv, uv = 0: H+ = FNT64(h_r + 2^8 h_i),
+// uv = 1: H- = FNT64(h_r - 2^8 h_i) (the per-channel factors of Eqs. (7)-(8)).
+__device__ __forceinline__ void cdc_tap_spectra(const int8_t *taps, int ntaps, int uv, int t,
+                                                const CdcTw &w, int32_t (&H)[4]) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int k = t + 16 * j;
+        int32_t hr = 0, hi = 0;
+        if (k < ntaps) {
+            hr = taps[2 * k];
+            hi = taps[2 * k + 1];
+        }
+        H[j] = uv ? hr - 256 * hi : hr + 256 * hi;
+    }
+    cdc_fnt64(H, t, w);
+}
+
+// Overlap-save FNT-CDC.  One wave per 32-instant block (contiguous ranges of
+// blocks per wave); the 64-instant window is transformed as four 64-point
+// sequences u_X, v_X, u_Y, v_Y (u = x_r + 2^8 x_i, v = x_r - 2^8 x_i, Eqs. (7)-(8)
+// by linearity), one per 16-lane group.
 template <bool WITH_Z>
 __global__ __launch_bounds__(256) void cdc_kernel(const CdcItem *items, int nitems,
                                                   CdcItem single, uint64_t total_blocks,
                                                   int blocks_per_wave, int *err) {
-    using FF = Field<16>;
     const int lane = threadIdx.x & 63;
-    const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int wv = threadIdx.x >> 6;
+    const int g = lane >> 4, t = lane_pos(lane & 15);   // t: position index of the lane
+    const int pol = g >> 1, uv = g & 1;
+    __shared__ uint32_t winw_s[4][64];                 // per wave: the 64-instant window
+    __shared__ uint32_t outw_s[4][32];                 // per wave: requantised bytes [instant][comp]
+    uint32_t *winw = winw_s[wv];
+    uint32_t *outw = outw_s[wv];
+
+    const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wv;
     const uint64_t b_begin = wave * (uint64_t)blocks_per_wave;
     if (b_begin >= total_blocks) return;
     uint64_t b_end = b_begin + (uint64_t)blocks_per_wave;
     if (b_end > total_blocks) b_end = total_blocks;
 
-    // item holding global block b_begin: the last one with block0 <= b_begin
     int idx = 0;
     if (items) {
         int lo = 0, hi = nitems - 1;
@@ -122,64 +239,70 @@ __global__ __launch_bounds__(256) void cdc_kernel(const CdcItem *items, int nite
     }
     CdcItem it = items ? items[idx] : single;
     uint64_t it_end = it.block0 + fnti::cdc_blocks(it.n);
-    uint32_t hp, hm;
-    cdc_spectra(items ? &items[idx].taps[0][0] : &single.taps[0][0], it.ntaps, lane, hp, hm);
+    const CdcTw tw = cdc_twiddles(t);
+    int32_t H[4];
+    cdc_tap_spectra(items ? &items[idx].taps[0][0] : &single.taps[0][0], it.ntaps, uv, t, tw, H);
+    // Eq. (7): z = -2^15 * 64^-1 * IFNT' = -512 IFNT'; Eq. (8): z^ = -2^7 * 64^-1 * IFNT' = -2 IFNT'
+    const int32_t scale = uv ? -2 : -512;
     bool have_prev = false;
     uint32_t prev = 0;
 
     for (uint64_t b = b_begin; b < b_end; ++b) {
-        while (b >= it_end) {  // next item (skips items with n == 0)
-            ++idx;
-            it = items[idx];
-            it_end = it.block0 + fnti::cdc_blocks(it.n);
+        if (b >= it_end) {
+            // next item holding block b (skips items with n == 0); a table whose
+            // prefix sums do not cover total_blocks ends the wave instead of
+            // reading past its last entry
+            while (b >= it_end && items && idx + 1 < nitems) {
+                ++idx;
+                it = items[idx];
+                it_end = it.block0 + fnti::cdc_blocks(it.n);
+            }
+            if (b >= it_end || b < it.block0) return;
             have_prev = false;
-            cdc_spectra(&items[idx].taps[0][0], it.ntaps, lane, hp, hm);
+            cdc_tap_spectra(&items[idx].taps[0][0], it.ntaps, uv, t, tw, H);
         }
         const int64_t lb = (int64_t)(b - it.block0);
-        // window: instants [32 lb - 32, 32 lb + 32); lanes 0..31 reuse the
+        // window word of instant 32 lb - 32 + lane; lanes 0..31 reuse the
         // previous block's new half when this wave just processed it
-        const int64_t inst = 32 * lb - 32 + lane;
         uint32_t carried = (uint32_t)__shfl((int)prev, (lane + 32) & 63);
-        uint32_t w = (have_prev && lane < 32) ? carried : cdc_load(it, inst);
-        if (!bytes_5bit(w)) flag(err, RANGE_SAMPLE);
-        prev = w;
+        uint32_t wd = (have_prev && lane < 32) ? carried : cdc_load(it, 32 * lb - 32 + lane);
+        if (!bytes_5bit(wd)) flag(err, RANGE_SAMPLE);
+        prev = wd;
         have_prev = true;
-
-        uint32_t u[2], v[2];
+        winw[lane] = wd;
+        wave_lds_sync();
+        int32_t x[4];
 #pragma unroll
-        for (int p = 0; p < 2; ++p) {
-            int xr = sbyte(w, 2 * p), xi = sbyte(w, 2 * p + 1);
-            u[p] = fwd_xlane<16, 6, true>(FF::from_int(xr + 256 * xi), lane);
-            v[p] = fwd_xlane<16, 6, true>(FF::from_int(xr - 256 * xi), lane);
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t u = winw[t + 16 * j];
+            const int32_t xr = sbyte(u, 2 * pol), xi = sbyte(u, 2 * pol + 1);
+            x[j] = uv ? xr - 256 * xi : xr + 256 * xi;  // |.| <= 4112
         }
-        int32_t z[4];
+        cdc_fnt64(x, t, tw);
+        // P = U H+ (uv = 0 groups), Q = V H- (uv = 1 groups); S = P + Q, D = P - Q
 #pragma unroll
-        for (int p = 0; p < 2; ++p) {
-            uint32_t P = FF::mul(u[p], hp), Qv = FF::mul(v[p], hm);
-            uint32_t S = inv_xlane<16, 6, true>(FF::add(P, Qv), lane);
-            uint32_t D = inv_xlane<16, 6, true>(FF::sub(P, Qv), lane);
-            // Eq. (7): z = -2^15 * 64^-1 * S' = -512 S'; Eq. (8): z^ = -2^7 * 64^-1 * D' = -2 D'
-            z[2 * p] = FF::lift(FF::neg(FF::mulpow2(S, 9)));
-            z[2 * p + 1] = FF::lift(FF::neg(FF::mulpow2(D, 1)));
+        for (int j = 0; j < 4; ++j) {
+            int32_t pq = mulmod(x[j], H[j]);
+            int32_t o = xor_lane<16>(pq);
+            x[j] = uv ? o - pq : pq + o;                 // |.| < 2^18
         }
-        if (lane >= 32) {
-            const int64_t i = 32 * lb + (lane - 32);
-            if ((uint64_t)i < it.n) {
-                if (WITH_Z && it.z_out) {
-                    int4 zz = make_int4(z[0], z[1], z[2], z[3]);
-                    reinterpret_cast<int4 *>(it.z_out)[i] = zz;
-                }
-                if (it.a_out && i >= it.phase && ((i - it.phase) & 1) == 0) {
-                    uint32_t packed = 0;
+        cdc_ifnt64_upper(x, t, tw);
+        const int64_t i0 = 32 * lb;
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        int32_t q = clamp32(rs32(z[c], it.shift), -16, 15);
-                        packed |= ((uint32_t)q & 0xFFu) << (8 * c);
-                    }
-                    reinterpret_cast<uint32_t *>(it.a_out)[(i - it.phase) >> 1] = packed;
-                }
-            }
+        for (int j = 2; j < 4; ++j) {
+            const int32_t z = lift_loose(mulmod(x[j], scale));
+            const int il = t + 16 * (j - 2);             // instant within the block
+            if (WITH_Z && it.z_out && (uint64_t)(i0 + il) < it.n) it.z_out[(i0 + il) * 4 + g] = z;
+            reinterpret_cast<int8_t *>(outw)[il * 4 + g] = (int8_t)clamp32(rs32(z, it.shift), -16, 15);
         }
+        wave_lds_sync();
+        if (it.a_out && lane < 16) {
+            // symbol instants 2 m + phase inside this block
+            const int il = 2 * lane + it.phase;
+            const int64_t i = i0 + il;
+            if ((uint64_t)i < it.n) reinterpret_cast<uint32_t *>(it.a_out)[(i - it.phase) >> 1] = outw[il];
+        }
+        wave_lds_sync();
     }
 }
 
@@ -367,35 +490,6 @@ __device__ __forceinline__ void ifnt32_upper(int32_t (&x)[16], int t) {
 //  * input-spectrum lanes: S1 = lane / 16, 2 of the 32 window positions each.
 //  * output / error lanes: symbol m = lane / 4, stream S2 = lane % 4.
 //  * gradient / tap-state lanes: S1 = lane / 16, tap k = lane % 16, all 4 S2.
-// Final state of one polarisation half.  Taps: written by the waves that own
-// them (lane (S1, k) holds S2 = 2 pol + s2l0 .. + NWT - 1).  Symbol and CDC
-// histories: written once, by wave 0 of the polarisation-0 workgroup.
-template <int NWT>
-__device__ __forceinline__ void aeq_finish_pol(const AeqItem &it, int lane, int pol, bool tap_owner,
-                                               bool hist_owner, int s1, int s2l0,
-                                               const int32_t (&w)[NWT], int *err) {
-    const int kk = lane & 15;
-    if (tap_owner) {
-#pragma unroll
-        for (int q = 0; q < NWT; ++q) it.taps[(s1 * 4 + 2 * pol + s2l0 + q) * 16 + kk] = (int16_t)w[q];
-    }
-    if (hist_owner) {
-        if (it.hist_out) {
-            uint32_t h = (lane < 16) ? aeq_load(it, (int64_t)it.m - 16 + lane, err) : 0u;
-            if (lane < 16) reinterpret_cast<uint32_t *>(it.hist_out)[lane] = h;
-        }
-        if (it.cdc_tail) {
-            uint32_t tl = 0;
-            if (lane < 32) {
-                int64_t j = (int64_t)it.cdc_n - 32 + lane;
-                tl = j >= 0 ? reinterpret_cast<const uint32_t *>(it.cdc_in)[j]
-                            : reinterpret_cast<const uint32_t *>(it.cdc_tail)[32 + j];
-            }
-            if (lane < 32) reinterpret_cast<uint32_t *>(it.cdc_tail)[lane] = tl;
-        }
-    }
-}
-
 __global__ __launch_bounds__(64) void aeq_fnt_kernel(const AeqItem *items, AeqItem single,
                                                      int *err) {
     const AeqItem it = items ? items[blockIdx.x] : single;
@@ -472,8 +566,8 @@ __global__ __launch_bounds__(64) void aeq_fnt_kernel(const AeqItem *items, AeqIt
                            : h == 2 ? xor_lane<2>(u0) : xor_lane<1>(u0);
                 int32_t p1 = h == 8 ? xor_lane<8>(u1) : h == 4 ? xor_lane<4>(u1)
                            : h == 2 ? xor_lane<2>(u1) : xor_lane<1>(u1);
-                u0 = up ? mulmod(p0 - u0, c) : u0 + p0;
-                u1 = up ? mulmod(p1 - u1, c) : u1 + p1;
+                u0 = blend(up, mulmod(p0 - u0, c), u0 + p0);
+                u1 = blend(up, mulmod(p1 - u1, c), u1 + p1);
             }
             aspec[s1][kk] = u0;                        // |.| <= 2^21
             aspec[s1][kk + 16] = u1;
@@ -571,23 +665,24 @@ __device__ __forceinline__ void tap_fnt_lpt(int32_t (&x)[32 / LPT], int t) {
             if (j & jd) continue;
             const int e = (16 / h) * t + (16 * LPT / h) * (j & (jd - 1));   // < 16
             if (h == 16) {
-                x[j + jd] = mulmod(x[j], 1 << e);     // the partner is zero padding
+                x[j + jd] = mulmod(x[j], opq(1 << e));   // the partner is zero padding
             } else {
                 int32_t a = x[j], b = x[j + jd];
                 x[j] = a + b;
-                x[j + jd] = mulmod(a - b, 1 << e);
+                x[j + jd] = mulmod(a - b, opq(1 << e));
             }
         }
     }
+    // across lanes: lower lane x + p, upper lane (p - x) * 2^e
 #pragma unroll
     for (int h = LPT / 2; h >= 1; h >>= 1) {
         const bool up = (t & h) != 0;
-        const int32_t c = 1 << ((16 / h) * (t & (h - 1)));
+        const int32_t c = opq(1 << ((16 / h) * (t & (h - 1))));
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
-            int32_t p = h == 8 ? xor_h<8>(x[j]) : h == 4 ? xor_h<4>(x[j])
-                      : h == 2 ? xor_h<2>(x[j]) : xor_h<1>(x[j]);
-            x[j] = up ? mulmod(p - x[j], c) : x[j] + p;
+            int32_t p = h == 8 ? xor_pos<8>(x[j]) : h == 4 ? xor_pos<4>(x[j])
+                      : h == 2 ? xor_pos<2>(x[j]) : xor_pos<1>(x[j]);
+            x[j] = blend(up, mulmod(p - x[j], c), x[j] + p);
         }
     }
 }
@@ -600,16 +695,18 @@ __device__ __forceinline__ int32_t inv_pow2(int e) { return e ? -(1 << (16 - e))
 template <int LPT>
 __device__ __forceinline__ void ifnt_upper_lpt(int32_t (&x)[32 / LPT], int t) {
     constexpr int PPL = 32 / LPT;
+    // across lanes: the upper lane twiddles its value first, then
+    // lower = own + partner, upper = partner - own
 #pragma unroll
     for (int h = 1; h < LPT; h <<= 1) {
         const bool up = (t & h) != 0;
-        const int32_t c = inv_pow2((16 / h) * (t & (h - 1)));
+        const int32_t c = opq(inv_pow2((16 / h) * (t & (h - 1))));
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
-            int32_t tt = up ? mulmod(x[j], c) : x[j];
-            int32_t p = h == 8 ? xor_h<8>(tt) : h == 4 ? xor_h<4>(tt)
-                      : h == 2 ? xor_h<2>(tt) : xor_h<1>(tt);
-            x[j] = up ? p - tt : x[j] + p;
+            int32_t tt = blend(up, mulmod(x[j], c), x[j]);
+            int32_t p = h == 8 ? xor_pos<8>(tt) : h == 4 ? xor_pos<4>(tt)
+                      : h == 2 ? xor_pos<2>(tt) : xor_pos<1>(tt);
+            x[j] = blend(up, p - tt, x[j] + p);
         }
     }
 #pragma unroll
@@ -619,7 +716,7 @@ __device__ __forceinline__ void ifnt_upper_lpt(int32_t (&x)[32 / LPT], int t) {
         for (int j = 0; j < PPL; ++j) {
             if (j & jd) continue;
             const int e = (16 / h) * t + (16 * LPT / h) * (j & (jd - 1));
-            int32_t tt = mulmod(x[j + jd], inv_pow2(e));
+            int32_t tt = mulmod(x[j + jd], opq(inv_pow2(e)));
             if (h == 16) {
                 x[j + jd] = x[j] - tt;                // only the upper half is kept
             } else {
@@ -631,74 +728,101 @@ __device__ __forceinline__ void ifnt_upper_lpt(int32_t (&x)[32 / LPT], int t) {
     }
 }
 
+// Symbol i of the AEQ input (history before 0, zeros past m), as one dword.
+__device__ __forceinline__ uint32_t aeq_sym(const AeqItem &it, int64_t i) {
+    uint32_t v = 0u;
+    if (i < 0) {
+        if (it.hist_in != nullptr && i >= -16) v = reinterpret_cast<const uint32_t *>(it.hist_in)[16 + i];
+    } else if ((uint64_t)i < it.m) {
+        v = reinterpret_cast<const uint32_t *>(it.a)[i];
+    }
+    return v;
+}
+
 template <int LPT>
 __global__ __launch_bounds__(64 * (LPT / 4)) void aeq_pol_kernel(const AeqItem *items, AeqItem single,
                                                                  int *err) {
     constexpr int WPP = LPT / 4;                       // waves per polarisation half
     constexpr int PPL = 32 / LPT;                      // bins per lane
+    constexpr int NT = 16 / LPT;                       // taps owned per lane (= PPL / 2)
     const AeqItem it = items ? items[blockIdx.x >> 1] : single;
     const int pol = blockIdx.x & 1;
     const int tid = threadIdx.x;
     const int v = tid >> 6, lane = tid & 63;
     const int pos = lane & 31;
-    // transform role
-    const int tr = lane / LPT, t = lane % LPT;
+    // transform role: filter (tS1 -> 2 pol + tS2l), digit td, lane t of LPT; the
+    // lane also owns the taps k = t + LPT i (i < NT) of that filter
+    const int tr = lane / LPT, t = lane_pos(lane % LPT);
     const int ts = tr & 1, tS2l = (tr >> 1) & 1;
     const int td = WPP == 1 ? (tr >> 2) & 1 : (v & 1);
     const int tg = WPP == 1 ? (tr >> 3) : WPP == 2 ? (tr >> 2) & 1 : (v >> 1);
     const int tS1 = 2 * tg + ts;
-    // gradient / tap-state role: WPP <= 2: (S1, k) with both S2 of the half;
-    // WPP == 4: (S1 of this wave's stream pair, S2, k)
-    const int kk = lane & 15;
-    const int gS1 = WPP == 4 ? 2 * (v >> 1) + ((lane >> 4) & 1) : (lane >> 4);
-    constexpr int NW = WPP == 4 ? 1 : 2;             // taps per lane
-    const int gS2l0 = WPP == 4 ? (lane >> 5) : 0;
-    // output / error role (lanes 0..31): symbol m = lane / 2, stream S2l = lane % 2
+    const int tS2 = 2 * pol + tS2l;
+    // output / error role (lanes 0..31 of every wave): symbol om, stream 2 pol + oS2l
     const int om = (lane >> 1) & 15, oS2l = lane & 1;
+    const int kk = lane & 15;
 
-    __shared__ int16_t tapl_s[WPP][128];               // per wave: [S1][S2l][k]
     __shared__ int32_t aspec_s[WPP][4][32];            // per wave: input spectra by position
-    __shared__ int32_t part_s[4][32];                  // [g*2+d][m*2+S2l], shared by the waves
+    // [block parity][g*2+d][m*2+S2l], shared by the waves; double-buffered so a
+    // wave that runs ahead (one barrier per block) never overwrites partials
+    // another wave is still reading
+    __shared__ int32_t part_s[2][4][32];
     __shared__ uint32_t epsw_s[WPP][8];                // per wave: bytes [S2l][m]
     __shared__ uint32_t winw_s[WPP][36];               // per wave: bytes [S1][32] + pad
-    int16_t *tapl = tapl_s[v];
     int32_t(*aspec)[32] = aspec_s[v];
     uint32_t *epsw = epsw_s[v];
     uint32_t *winw = winw_s[v];
 
-    int32_t w[NW];
+    int16_t *const wrow = it.taps + (tS1 * 4 + tS2) * 16;
+    int32_t w[NT];
 #pragma unroll
-    for (int q = 0; q < NW; ++q) {
-        const int S2 = 2 * pol + gS2l0 + q;
-        int32_t val = it.taps[(gS1 * 4 + S2) * 16 + kk];
+    for (int i = 0; i < NT; ++i) {
+        int32_t val = wrow[t + LPT * i];
         if (val < -8192 || val > 8191) flag(err, RANGE_TAP);
-        w[q] = clamp32(val, -8192, 8191);
+        w[i] = clamp32(val, -8192, 8191);
     }
     const uint64_t M = it.m;
-    const bool writer = v == 0;                        // the wave that stores the outputs
-    const bool tap_owner = WPP == 4 ? (v & 1) == 0 : v == 0;
+    const bool writer = v == 0;                        // stores the outputs
+    const bool tap_owner = td == 0;                    // one of the two digit copies stores taps
     const bool hist_owner = pol == 0 && v == 0;
+    auto finish = [&]() {
+        if (tap_owner) {
+#pragma unroll
+            for (int i = 0; i < NT; ++i) wrow[t + LPT * i] = (int16_t)w[i];
+        }
+        if (hist_owner) {
+            if (it.hist_out) {
+                uint32_t h = (lane < 16) ? aeq_sym(it, (int64_t)M - 16 + lane) : 0u;
+                if (lane < 16) reinterpret_cast<uint32_t *>(it.hist_out)[lane] = h;
+            }
+            if (it.cdc_tail) {
+                uint32_t tl = 0;
+                if (lane < 32) {
+                    int64_t j = (int64_t)it.cdc_n - 32 + lane;
+                    tl = j >= 0 ? reinterpret_cast<const uint32_t *>(it.cdc_in)[j]
+                                : reinterpret_cast<const uint32_t *>(it.cdc_tail)[32 + j];
+                }
+                if (lane < 32) reinterpret_cast<uint32_t *>(it.cdc_tail)[lane] = tl;
+            }
+        }
+    };
     if (M == 0) {
-        aeq_finish_pol(it, lane, pol, tap_owner, hist_owner, gS1, gS2l0, w, err);
+        finish();
         return;
     }
     if (lane < 4) winw[32 + lane] = 0u;
 
+    // tap-digit spectra of this lane's filter and digit, N^-1 = -2048 folded in
     int32_t W[PPL];
     auto transform_taps = [&]() {
 #pragma unroll
-        for (int q = 0; q < NW; ++q) tapl[(gS1 * 2 + gS2l0 + q) * 16 + kk] = (int16_t)w[q];
-        __syncthreads();
-        const int base = (tS1 * 2 + tS2l) * 16 + t;
-#pragma unroll
         for (int j = 0; j < PPL; ++j) {
-            if (j < PPL / 2) {
-                int32_t val = tapl[base + LPT * j];
-                int32_t lo = ((val + 64) & 127) - 64;
-                int32_t hi = (val - lo) >> 7;
-                W[j] = (td ? lo : hi) * -2048;        // digit * 32^-1, |.| <= 2^17
+            if (j < NT) {
+                int32_t lo = ((w[j] + 64) & 127) - 64;
+                int32_t hi = (w[j] - lo) >> 7;
+                W[j] = (td ? lo : hi) * -2048;        // |.| <= 2^17
             } else {
-                W[j] = 0;
+                W[j] = 0;                             // zero padding 16 -> 32
             }
         }
         tap_fnt_lpt<LPT>(W, t);
@@ -707,35 +831,42 @@ __global__ __launch_bounds__(64 * (LPT / 4)) void aeq_pol_kernel(const AeqItem *
 
     const uint32_t nblocks = (uint32_t)((M + 15) / 16);
     const int c2 = it.const_unit * it.const_unit;
-    uint32_t win = aeq_load(it, -16 + pos, err);
-    int16_t *outp = it.out;
+    bool bad = false;                                  // range violations, flagged once at the end
+    uint32_t win = aeq_sym(it, -16 + pos);
+    bad |= !bytes_5bit(win);
+    // running pointers: next window symbols and this block's outputs
+    const uint32_t *asym = reinterpret_cast<const uint32_t *>(it.a) + pos;
+    int16_t *outp = it.out + 4 * om + 2 * pol + oS2l;
+    int64_t left = (int64_t)M;                         // symbols from 16 b on
 
-    for (uint32_t b = 0; b < nblocks; ++b) {
-        uint32_t nxt = pos >= 16 ? aeq_load(it, (int64_t)16 * b + pos, err) : 0u;
+    for (uint32_t b = 0; b < nblocks; ++b, asym += 16, outp += 64, left -= 16) {
+        uint32_t nxt = pos < left ? *asym : 0u;        // used by lanes pos >= 16
+        bad |= !bytes_5bit(nxt);
         if (lane < 32) {
             uint8_t *wb = reinterpret_cast<uint8_t *>(winw);
 #pragma unroll
             for (int c = 0; c < 4; ++c) wb[c * 32 + pos] = (uint8_t)(win >> (8 * c));
         }
-        __syncthreads();
+        wave_lds_sync();
         {   // input spectra of the 4 streams: lane (S1 = lane / 16, k) holds positions k, k + 16
+            const int kp = lane_pos(kk);                 // position index of this lane
             const int8_t *wb = reinterpret_cast<const int8_t *>(winw) + (lane >> 4) * 32;
-            int32_t x0 = wb[kk], x1 = wb[kk + 16];
+            int32_t x0 = wb[kp], x1 = wb[kp + 16];
             int32_t u0 = x0 + x1;
-            int32_t u1 = mulmod(x0 - x1, 1 << kk);
+            int32_t u1 = mulmod(x0 - x1, opq(1 << kp));
 #pragma unroll
             for (int h = 8; h >= 1; h >>= 1) {
-                const bool up = (kk & h) != 0;
-                const int32_t c = 1 << ((16 / h) * (kk & (h - 1)));
-                int32_t p0 = h == 8 ? xor_h<8>(u0) : h == 4 ? xor_h<4>(u0) : h == 2 ? xor_h<2>(u0) : xor_h<1>(u0);
-                int32_t p1 = h == 8 ? xor_h<8>(u1) : h == 4 ? xor_h<4>(u1) : h == 2 ? xor_h<2>(u1) : xor_h<1>(u1);
-                u0 = up ? mulmod(p0 - u0, c) : u0 + p0;
-                u1 = up ? mulmod(p1 - u1, c) : u1 + p1;
+                const bool up = (kp & h) != 0;
+                const int32_t c = opq(1 << ((16 / h) * (kp & (h - 1))));
+                int32_t p0 = h == 8 ? xor_pos<8>(u0) : h == 4 ? xor_pos<4>(u0) : h == 2 ? xor_pos<2>(u0) : xor_pos<1>(u0);
+                int32_t p1 = h == 8 ? xor_pos<8>(u1) : h == 4 ? xor_pos<4>(u1) : h == 2 ? xor_pos<2>(u1) : xor_pos<1>(u1);
+                u0 = blend(up, mulmod(p0 - u0, c), u0 + p0);
+                u1 = blend(up, mulmod(p1 - u1, c), u1 + p1);
             }
-            aspec[lane >> 4][kk] = u0;                  // |.| <= 2^21
-            aspec[lane >> 4][kk + 16] = u1;
+            aspec[lane >> 4][kp] = u0;                  // |.| <= 2^21
+            aspec[lane >> 4][kp + 16] = u1;
         }
-        __syncthreads();
+        wave_lds_sync();
         int32_t Y[PPL];
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
@@ -746,16 +877,16 @@ __global__ __launch_bounds__(64 * (LPT / 4)) void aeq_pol_kernel(const AeqItem *
         if (ts == 0) {
 #pragma unroll
             for (int j = PPL / 2; j < PPL; ++j)
-                part_s[tg * 2 + td][(t + LPT * (j - PPL / 2)) * 2 + tS2l] = lift_loose(Y[j]);
+                part_s[b & 1][tg * 2 + td][(t + LPT * (j - PPL / 2)) * 2 + tS2l] = lift_loose(Y[j]);
         }
-        __syncthreads();
+        if (WPP > 1) __syncthreads(); else wave_lds_sync();
         // symbol om, stream 2 pol + oS2l: y = 2^7 (high-digit sums) + (low-digit sums)
         const int pi = lane & 31;
-        const int32_t y = 128 * (part_s[0][pi] + part_s[2][pi]) + part_s[1][pi] + part_s[3][pi];
+        const int32_t(*part)[32] = part_s[b & 1];
+        const int32_t y = 128 * (part[0][pi] + part[2][pi]) + part[1][pi] + part[3][pi];
         const int32_t yh = clamp32(rs32(y, it.out_shift), -32768, 32767);
-        const uint64_t m = (uint64_t)16 * b + om;
-        const bool valid = lane < 32 && m < M;
-        if (writer && valid) outp[m * 4 + 2 * pol + oS2l] = (int16_t)yh;
+        const bool valid = lane < 32 && om < left;
+        if (writer && valid) *outp = (int16_t)yh;
         if (it.update_enable) {
             const int32_t yp = xor_h<1>(yh);
             const int64_t r2 = (int64_t)yh * yh + (int64_t)yp * yp;
@@ -763,29 +894,35 @@ __global__ __launch_bounds__(64 * (LPT / 4)) void aeq_pol_kernel(const AeqItem *
             int32_t eps = (int32_t)clamp64(rs64((R2 - r2) * yh, it.err_shift), -128, 127);
             if (!valid) eps = 0;
             if (lane < 32) reinterpret_cast<int8_t *>(epsw)[oS2l * 16 + om] = (int8_t)eps;
-            __syncthreads();
-            const int off = gS1 * 32 + 16 - kk;
-            uint32_t dd[5];
+            wave_lds_sync();
+            // G[S1][S2][k] = sum_j eps_S2[j] * a_S1[16 b + j - k] for the lane's taps
+            uint32_t e4[4];
 #pragma unroll
-            for (int r = 0; r < 5; ++r) dd[r] = winw[(off >> 2) + r];
-            uint32_t xs[4];
+            for (int q = 0; q < 4; ++q) e4[q] = epsw[tS2l * 4 + q];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) xs[q] = __builtin_amdgcn_alignbyte(dd[q + 1], dd[q], off & 3);
+            for (int i = 0; i < NT; ++i) {
+                const int off = tS1 * 32 + 16 - (t + LPT * i);   // byte of a_S1[16 b - k]
+                uint32_t dd[5];
 #pragma unroll
-            for (int q2 = 0; q2 < NW; ++q2) {
-                const int S2l = gS2l0 + q2;
+                for (int r = 0; r < 5; ++r) dd[r] = winw[(off >> 2) + r];
                 int32_t gsum = 0;
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    gsum = __builtin_amdgcn_sdot4((int)epsw[S2l * 4 + q], (int)xs[q], gsum, false);
-                w[q2] = clamp32(w[q2] + (int32_t)rs64((int64_t)gsum, it.mu_shift), -8192, 8191);
+                    gsum = __builtin_amdgcn_sdot4((int)e4[q],
+                                                  (int)__builtin_amdgcn_alignbyte(dd[q + 1], dd[q], off & 3),
+                                                  gsum, false);
+                w[i] = clamp32(w[i] + (int32_t)rs64((int64_t)gsum, it.mu_shift), -8192, 8191);
             }
             transform_taps();
         }
+        // the next block reuses this wave's window and error bytes: keep the LDS
+        // reads above in front of the writes that follow
+        wave_lds_sync();
         uint32_t slid = (uint32_t)__shfl((int)win, (lane & 32) | ((pos + 16) & 31));
         win = pos < 16 ? slid : nxt;
     }
-    aeq_finish_pol(it, lane, pol, tap_owner, hist_owner, gS1, gS2l0, w, err);
+    if (bad) flag(err, RANGE_SYMBOL);
+    finish();
 }
 
 // Direct comparator: y by integer dot products in the time domain, same RDE.

@@ -61,7 +61,8 @@ class PlanInfo(ctypes.Structure):
                 ("aeq_blocks_max", ctypes.c_uint64), ("cdc_waves_per_group", ctypes.c_int32),
                 ("cdc_blocks_per_wave", ctypes.c_int32), ("aeq_variant", ctypes.c_int32),
                 ("aeq_waves_per_pol", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("tune_ms", ctypes.c_double)]
+                ("aeq_waves_long", ctypes.c_int32), ("tune_ms", ctypes.c_double),
+                ("aeq_long_channels", ctypes.c_uint64)]
 
 
 class SessionConfig(ctypes.Structure):
@@ -102,6 +103,8 @@ SIGNATURES = {
     "fnt_plan_get_info": (_i32, [_vp, ctypes.POINTER(PlanInfo)]),
     "fnt_plan_set_aeq_variant": (_i32, [_vp, _i32]),
     "fnt_plan_set_aeq_waves": (_i32, [_vp, _i32]),
+    "fnt_plan_set_cdc_schedule": (_i32, [_vp, _i32, _i32]),
+    "fnt_plan_set_aeq_split": (_i32, [_vp, _u64, _i32, _i32]),
     "fnt_plan_destroy": (_i32, [_vp]),
     "fnt_now_ns": (_u64, []),
     "fnt_session_create": (_i32, [ctypes.POINTER(_vp), ctypes.POINTER(SessionConfig)]),
@@ -286,6 +289,12 @@ class Plan:
 
     def set_aeq_waves(self, waves_per_pol: int):
         _ok(lib().fnt_plan_set_aeq_waves(self._h, int(waves_per_pol)))
+
+    def set_aeq_split(self, long_channels: int, waves_long: int, waves: int):
+        _ok(lib().fnt_plan_set_aeq_split(self._h, int(long_channels), int(waves_long), int(waves)))
+
+    def set_cdc_schedule(self, waves_per_group: int, blocks_per_wave: int):
+        _ok(lib().fnt_plan_set_cdc_schedule(self._h, int(waves_per_group), int(blocks_per_wave)))
 
     def close(self):
         if getattr(self, "_h", None):

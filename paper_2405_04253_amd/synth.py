@@ -92,7 +92,7 @@ def design_cdc_taps(fibre_km: float, ntaps: int | None = None):
     L = cdc_tap_count(fibre_km) if ntaps is None else int(ntaps)
     k = dispersion_beta(fibre_km)
     fs = BAUD * SPS
-    fgrid = np.linspace(-fs / 2, fs / 2, 4096, endpoint=False)
+    fgrid = np.linspace(-fs / 2, fs / 2, 1024, endpoint=False)
     nu = np.abs(fgrid) / BAUD
     lo, hi = (1 - ROLLOFF) / 2, (1 + ROLLOFF) / 2
     rc = np.where(nu <= lo, 1.0,
@@ -276,3 +276,59 @@ def random_taps(ntaps: int, seed: int) -> np.ndarray:
 def random_aeq_taps(seed: int, lo: int = -8192, hi: int = 8191) -> np.ndarray:
     r = np.random.default_rng(seed)
     return r.integers(lo, hi + 1, size=(4, 4, 16), dtype=np.int16)
+
+
+# ---------------------------------------------------------------------------
+# Same recipe on a torch device (large workloads: 10^9 symbols in seconds).
+# ---------------------------------------------------------------------------
+def gen_channel_torch(nsym: int, fibre_km: float, osnr_db: float, seed: int, device,
+                      ntaps: int | None = None):
+    """gen_channel's recipe with torch FFTs on `device`.  Returns (samples int8
+    tensor [2*nsym][4] on device, taps int8 [L][2] numpy, requant_shift, const_unit).
+    Float rounding differs from the numpy generator, so the two give close but
+    not identical samples; each workload is generated once and then read by both
+    the GPU path and the oracle."""
+    import torch
+    taps, shift, gain = design_cdc_taps(fibre_km, ntaps)
+    unit = const_unit_for(gain, shift)
+    nsym = int(nsym)
+    if nsym == 0:
+        return torch.zeros((0, 4), dtype=torch.int8, device=device), taps, shift, unit
+    rng = np.random.default_rng(seed)
+    u = _haar_u2(rng)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed) & 0x7FFFFFFFFFFFFFFF)
+    ng = 1 << (nsym - 1).bit_length()          # power-of-two FFTs: few distinct plan sizes
+    sym = torch.zeros((ng, 4), dtype=torch.float32, device=device)
+    sym[:nsym] = (torch.randint(0, 4, (nsym, 4), generator=g, device=device) * 2 - 3).float()
+    nfft = SPS * ng
+    rrc = torch.from_numpy(_rrc_response(nfft).astype(np.float32)).to(device)
+    fhz = torch.fft.fftfreq(nfft, device=device, dtype=torch.float64) * (BAUD * SPS)
+    ph = (-dispersion_beta(fibre_km) * fhz * fhz)
+    cd = torch.polar(torch.ones_like(ph), ph).to(torch.complex64)
+    snr_lin = 10 ** (osnr_db / 10) * 12.5e9 / BAUD
+    spec = []
+    for p in range(2):
+        sf = torch.fft.fft(torch.complex(sym[:, 2 * p], sym[:, 2 * p + 1]))
+        spec.append(sf.repeat(SPS) * (rrc * cd))
+    del sym
+    uc = torch.tensor(u, dtype=torch.complex64, device=device)
+    rot = [uc[0, 0] * spec[0] + uc[0, 1] * spec[1], uc[1, 0] * spec[0] + uc[1, 1] * spec[1]]
+    del spec
+    out = torch.empty((nfft, 4), dtype=torch.float32, device=device)
+    p_rrc = float(np.mean(_rrc_response(nfft) ** 2))
+    for p in range(2):
+        sig = rot[p] * rrc
+        p_sig = float(torch.mean(sig.real ** 2 + sig.imag ** 2)) / nfft
+        sigma2 = p_sig / snr_lin / max(p_rrc, 1e-12)
+        noise = torch.complex(torch.randn(nfft, generator=g, device=device),
+                              torch.randn(nfft, generator=g, device=device))
+        noise = noise * math.sqrt(sigma2 * nfft / 2)
+        y = torch.fft.ifft(sig + noise * rrc)
+        out[:, 2 * p] = y.real
+        out[:, 2 * p + 1] = y.imag
+    del rot
+    out = out[: SPS * nsym]
+    rms = float(torch.sqrt(torch.mean(out.double() ** 2)))
+    q = torch.clamp(torch.round(out * (SAMPLE_RMS / max(rms, 1e-30))), -16, 15).to(torch.int8).contiguous()
+    return q, taps, shift, unit

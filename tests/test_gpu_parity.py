@@ -268,6 +268,52 @@ def test_plan_batched_vs_oracle(torch_dev, variant, wpp):
     fnt.fnt_check()
 
 
+def test_plan_determinism_across_schedules(torch_dev):
+    """Race check: identical outputs for every launch schedule and wave split."""
+    torch, dev = torch_dev
+    chans = _batch(24, 7, 11, seed=21)
+    pc = _plan_channels(torch, dev, chans, None)
+    plan = fnt.Plan([(c["x"], c["out"], c["taps"], fnt.cdc_params(c["ch"].taps, c["ch"].requant_shift),
+                      fnt.aeq_params(**c["prm"])) for c in pc], autotune=False, use_graph=True)
+    ref = None
+    for wpg, bpw, wpp, variant in [(4, 1, 1, 0), (1, 1, 2, 0), (2, 3, 4, 0), (4, 64, 1, 0), (1, 7, 2, 0),
+                                   (2, 2, 1, 1), (4, 5, 1, 2)]:
+        plan.set_cdc_schedule(wpg, bpw)
+        plan.set_aeq_waves(wpp)
+        plan.set_aeq_variant(variant)
+        for rep in range(2):
+            for c in pc:
+                c["taps"].copy_(to_dev(torch, dev, c["w0"]))
+            note(f"plan schedule wpg={wpg} bpw={bpw} wpp={wpp} variant={variant} rep={rep}")
+            plan.run()
+            torch.cuda.synchronize()
+            got = [(c["out"].cpu().numpy().copy(), c["taps"].cpu().numpy().copy()) for c in pc]
+            if ref is None:
+                ref = got
+                for c, (o, w) in zip(pc, got):
+                    outr, wr, _ = O.cdc_aeq(c["ch"].samples, c["ch"].taps, c["ch"].requant_shift, c["w0"],
+                                            O.params(**c["prm"]))
+                    assert np.array_equal(o, outr) and np.array_equal(w, wr)
+            else:
+                for (o, w), (o2, w2) in zip(ref, got):
+                    assert np.array_equal(o, o2) and np.array_equal(w, w2)
+    # longest chains in their own concurrent launch
+    plan.set_aeq_variant(0)
+    for nl, wl, ws in [(5, 4, 1), (12, 2, 1), (1, 4, 2), (24, 4, 1)]:
+        plan.set_aeq_split(nl, wl, ws)
+        for c in pc:
+            c["taps"].copy_(to_dev(torch, dev, c["w0"]))
+        note(f"plan split long={nl} wl={wl} ws={ws}")
+        plan.run()
+        torch.cuda.synchronize()
+        info = plan.info()
+        assert info["aeq_long_channels"] == min(nl, len(pc)) and info["aeq_waves_long"] == wl
+        for c, (o, w) in zip(pc, ref):
+            assert np.array_equal(c["out"].cpu().numpy(), o) and np.array_equal(c["taps"].cpu().numpy(), w)
+    plan.close()
+    fnt.fnt_check()
+
+
 def test_plan_autotune_and_eager(torch_dev, tmp_path):
     torch, dev = torch_dev
     chans = _batch(12, 8, 12, seed=9)
