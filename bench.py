@@ -1,14 +1,18 @@
 #!/usr/bin/env python3
 """Throughput of the FNT-CDC + FNT-AEQ receiver path on one MI355X.
 
-Default workload ("single"): one channel, 2^24 PDM-16QAM symbols per
-polarisation at 2 samples/symbol (2^25 instants), 75 km SSMF, 5-bit samples,
-32 six-bit CD-inverse taps, N = 64 FNT mod 65537 with alpha = sqrt 2, then the
-N = 32 FNT-AEQ with the RDE update.  A step is one pass of the whole path over
-the stream (CDC + resample/requantise + AEQ), inputs resident in HBM.
+Headline workload ("batched"): 4096 independent channels in one plan, lengths
+log-uniform 2^12..2^20 PDM-16QAM symbols per polarisation at 2 samples/symbol,
+fibre U(10, 80) km (8-32 six-bit CD-inverse taps), OSNR U(18, 26) dB, 5-bit
+samples, N = 64 FNT mod 65537 with alpha = sqrt 2 for the CDC, then resample,
+requantise and the N = 32 FNT-AEQ with the RDE update.  A step is one pass of
+the whole path over every channel, inputs resident in HBM; the taps restart
+from the centre spike at each step.
 
-Other workloads: "batched" (many channels of log-uniform length in one plan,
-hipGraph replay) and "served" (Poisson arrivals into a session; p50/p99).
+Reported beside it: the plain single-stream path (one channel of 2^24 symbols,
+75 km: the comparator the batched figure is set against), the plain
+per-channel launch loop on a sample of the same channels, and a served
+workload (Poisson arrivals into a session; p50/p99 latency).
 
 Prints one JSON line.  Gsamples/s counts instants (one dual-polarisation
 2-samples/symbol sample = 4 int8).
@@ -53,6 +57,7 @@ AEQ_OPS_PER_BLOCK = (4 * FNT32_OPS         # input spectra
                      + 16 * 2 * 12         # RDE error terms
                      + 4096 * 2            # gradient MACs
                      + 256 * 3)            # tap update
+METRIC = "bit-exact Gsamples/s, batched/served vs plain FNT-CDC+AEQ; p50/p99 latency"
 CDC_BYTES_PER_INSTANT = 4 + 2              # int8[4] in, int8[4] per symbol out
 AEQ_BYTES_PER_SYMBOL = 4 + 8               # int8[4] in, int16[4] out
 
@@ -128,22 +133,23 @@ def bench_single(args, torch, dev):
             ev[2].record(stream)
 
     progress(f"single: generated {n} instants in {gen_s:.1f} s; warmup")
-    for _ in range(args.warmup):
+    for _ in range(1):
         step()
     torch.cuda.synchronize()
     fnt.fnt_check()
-    progress(f"single: timing {args.steps} steps")
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    steps = max(1, args.single_steps)
+    progress(f"single: timing {steps} steps")
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(steps):
         step(evs[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     fnt.fnt_check()
     cdc_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
     aeq_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
-    ms = wall / args.steps * 1e3
+    ms = wall / steps * 1e3
     blocks_cdc = (n + 31) // 32
     blocks_aeq = (M + 15) // 16
     aeq_ops = AEQ_OPS_PER_BLOCK * blocks_aeq
@@ -160,22 +166,16 @@ def bench_single(args, torch, dev):
     achieved = aeq_ops / (aeq_ms / 1e3) / 1e9
     roof = {"kernel": "aeq_pol_kernel<16>", "bound": "alu", "achieved": round(achieved, 3),
             "peak": PEAK_ALU_GOPS, "unit": "Gops/s", "frac": round(achieved / PEAK_ALU_GOPS, 6),
-            "traffic": load_traffic("aeq_pol_kernel", "single"),
+            "traffic": load_traffic("aeq_pol_kernel<16>", "single"),
             "algorithmic_ops_per_launch": aeq_ops}
     res = {
-        "metric": "bit-exact Gsamples/s, batched/served vs plain FNT-CDC+AEQ; p50/p99 latency",
-        "value": round(n / (ms / 1e3) / 1e9, 6), "unit": "Gsamples/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
-        "data": "synthetic",
-        "config": {"workload": "single-stream plain FNT-CDC+AEQ, 1 channel x 2^%d symbols/pol, "
-                               "75 km, 32 taps, N=64 FNT mod 65537 alpha=sqrt2, AEQ N=32" % args.log2_symbols,
-                   "instants": n, "symbols": M, "aeq_variant": "fnt"},
-        "roofline": roof,
-        "kernels": kernels,
-        "gen_s": round(gen_s, 1),
+        "value": round(n / (ms / 1e3) / 1e9, 6), "unit": "Gsamples/s",
+        "steps": steps, "ms_per_step": round(ms, 3),
+        "workload": "plain single-stream FNT-CDC+AEQ (fnt_cdc then fnt_aeq), 1 channel x 2^%d "
+                    "symbols/pol, 75 km, 32 taps" % args.log2_symbols,
+        "instants": n, "roofline": roof, "kernels": kernels, "gen_s": round(gen_s, 1),
     }
-    if not args.no_cpu_baseline:
+    if args.single_cpu_baseline:
         progress("single: oracle CPU baseline")
         res["cpu_baseline"] = cpu_baseline_single(ch, prm, args.cpu_budget)
     return res
@@ -195,8 +195,54 @@ def _time_events(torch, fn, reps, stream):
     return float(np.mean([a.elapsed_time(b) for a, b in evs]))
 
 
-def bench_batched(args, torch, dev, single_gsps):
-    """Many channels of log-uniform length in one plan (hipGraph replay, autotuned)."""
+def aeq_kernel_name(info) -> str:
+    lpt = {1: 4, 2: 8, 4: 16}
+    if info["aeq_variant"] == 1:
+        return "aeq_direct_kernel"
+    if info["aeq_variant"] == 2:
+        return "aeq_fnt_kernel"
+    k = "aeq_pol_kernel<%d>" % lpt[info["aeq_waves_per_pol"]]
+    if info["aeq_long_channels"]:
+        k = "aeq_pol_kernel<%d>+" % lpt[info["aeq_waves_long"]] + k
+    return k
+
+
+def cpu_baseline_batched(chans, prms, budget_s: float):
+    """The oracle with OpenMP over channels on the host cores, on a random sample
+    of the workload's channels sized to about `budget_s` of CPU time."""
+    import oracle as O
+    from paper_2405_04253_amd import synth
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    rng = np.random.default_rng(11)
+    order = [int(i) for i in rng.permutation(len(chans))]
+    # single-thread rate from a short probe on the smallest sampled channel
+    probe = min(order[:8], key=lambda i: chans[i][1].shape[0])
+    q = chans[probe][1].cpu().numpy()
+    t0 = time.perf_counter()
+    O.cdc_aeq(q, chans[probe][2], chans[probe][3], synth.centre_spike_taps(), O.params(**prms[probe]))
+    rate1 = q.shape[0] / max(time.perf_counter() - t0, 1e-6)
+    want = rate1 * threads * budget_s
+    pick, tot = [], 0
+    for i in order:
+        n = chans[i][1].shape[0]
+        if tot + n > want and pick:
+            continue
+        pick.append(i)
+        tot += n
+        if tot >= 0.9 * want:
+            break
+    jobs = [dict(samples=chans[i][1].cpu().numpy(), taps=chans[i][2], shift=chans[i][3], phase=0,
+                 w=synth.centre_spike_taps(), params=O.params(**prms[i])) for i in pick]
+    t0 = time.perf_counter()
+    _, _, used = O.batch(jobs, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": round(tot / dt / 1e9, 6), "unit": "Gsamples/s", "cores": used, "kind": "oracle",
+            "sample": f"{len(pick)} random channels of the workload ({tot} instants), CDC+AEQ, "
+                      f"OpenMP over channels, {dt:.1f} s"}
+
+
+def bench_batched(args, torch, dev):
+    """Many channels of log-uniform length in one plan (autotuned; hipGraph for plan.run)."""
     import oracle as O
     from paper_2405_04253_amd import fnt, synth
     t0 = time.perf_counter()
@@ -205,7 +251,7 @@ def bench_batched(args, torch, dev, single_gsps):
     for k, sp in enumerate(specs):
         q, taps, sh, unit = synth.gen_channel_torch(sp.nsym, sp.fibre_km, sp.osnr_db, sp.seed, dev)
         chans.append((sp, q, taps, sh, unit))
-        if k % 256 == 0:
+        if k % 512 == 0:
             torch.cuda.synchronize()
             progress(f"batched: generated {k + 1}/{len(specs)} channels ({time.perf_counter() - t0:.1f} s)")
     torch.cuda.synchronize()
@@ -227,23 +273,49 @@ def bench_batched(args, torch, dev, single_gsps):
     plan = fnt.Plan(entries, autotune=True, use_graph=True, stream=stream)
     torch.cuda.synchronize()
     tune_s = time.perf_counter() - t0
-    progress(f"batched: plan ready in {tune_s:.1f} s: {plan.info()}")
-    for _ in range(max(1, args.warmup)):
-        plan.run(stream)
+    info = plan.info()
+    progress(f"batched: plan ready in {tune_s:.1f} s: {info}")
+    w_all = w0.unsqueeze(0).expand_as(taps_all)
+
+    def step(ev=None):
+        taps_all.copy_(w_all)               # fresh adaptive state every step
+        if ev is not None:
+            ev[0].record(stream)
+        plan.run_stage(fnt.FNT_STAGE_CDC, stream)
+        if ev is not None:
+            ev[1].record(stream)
+        plan.run_stage(fnt.FNT_STAGE_AEQ, stream)
+        if ev is not None:
+            ev[2].record(stream)
+
+    for _ in range(args.warmup):
+        step()
     torch.cuda.synchronize()
     fnt.fnt_check()
-    reps = max(1, args.batched_steps)
-    progress(f"batched: timing {reps} runs")
-    ms = _time_events(torch, lambda: plan.run(stream), reps, stream)
+    progress(f"batched: timing {args.steps} steps")
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
     fnt.fnt_check()
-    progress(f"batched: {ms:.1f} ms per run; checking parity")
-    info = plan.info()
+    cdc_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    aeq_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    ms = wall / max(args.steps, 1) * 1e3
+    progress(f"batched: {ms:.1f} ms per step (cdc {cdc_ms:.1f} ms, aeq {aeq_ms:.1f} ms)")
+    # the captured graph of the same plan, for comparison
+    taps_all.copy_(w_all)
+    graph_ms = _time_events(torch, plan.run, 2, stream)
     # parity on sampled channels: reset the taps, run once more, compare with the oracle
-    taps_all.copy_(w0.unsqueeze(0).expand_as(taps_all))
+    taps_all.copy_(w_all)
     plan.run(stream)
     torch.cuda.synchronize()
+    fnt.fnt_check()
     order = sorted(range(len(chans)), key=lambda i: chans[i][1].shape[0])
     pick = sorted(set([order[0], order[len(order) // 2], order[-1]]))
+    progress(f"batched: parity on channels {pick}")
     for i in pick:
         sp, q, taps, sh, unit = chans[i]
         outr, wr, _ = O.cdc_aeq(q.cpu().numpy(), taps, sh, synth.centre_spike_taps(), O.params(**prms[i]))
@@ -265,25 +337,54 @@ def bench_batched(args, torch, dev, single_gsps):
     plain_ms = _time_events(torch, plain_loop, 1, stream)
     plain_gsps = s_inst / (plain_ms / 1e3) / 1e9
     value = inst / (ms / 1e3) / 1e9
-    blocks = sum((e[0].shape[0] // 2 + 15) // 16 for e in entries)
-    aeq_ops = AEQ_OPS_PER_BLOCK * blocks
-    cdc_ops = CDC_OPS_PER_BLOCK * sum((e[0].shape[0] + 31) // 32 for e in entries)
-    achieved = (aeq_ops + cdc_ops) / (ms / 1e3) / 1e9
+    aeq_blocks = sum((e[0].shape[0] // 2 + 15) // 16 for e in entries)
+    cdc_blocks = sum((e[0].shape[0] + 31) // 32 for e in entries)
+    aeq_ops = AEQ_OPS_PER_BLOCK * aeq_blocks
+    cdc_ops = CDC_OPS_PER_BLOCK * cdc_blocks
+    achieved = aeq_ops / (aeq_ms / 1e3) / 1e9
+    kname = aeq_kernel_name(info)
+    roof = {"kernel": kname, "bound": "alu", "achieved": round(achieved, 1), "peak": PEAK_ALU_GOPS,
+            "unit": "Gops/s", "frac": round(achieved / PEAK_ALU_GOPS, 5),
+            "traffic": load_traffic(kname, "batched"),
+            "algorithmic_ops_per_launch": aeq_ops,
+            "hbm_algorithmic_gbs": round(aeq_blocks * 16 * AEQ_BYTES_PER_SYMBOL / aeq_ms / 1e6, 1),
+            "hbm_frac": round(aeq_blocks * 16 * AEQ_BYTES_PER_SYMBOL / aeq_ms / 1e6 / PEAK_HBM_GBS, 5)}
+    kernels = {
+        "cdc": {"kernel": "cdc_kernel<0>", "ms": round(cdc_ms, 3),
+                "gops": round(cdc_ops / cdc_ms / 1e6, 1), "frac_alu": round(cdc_ops / cdc_ms / 1e6 / PEAK_ALU_GOPS, 5),
+                "gbs": round(inst * CDC_BYTES_PER_INSTANT / cdc_ms / 1e6, 1)},
+        "aeq": {"kernel": kname, "ms": round(aeq_ms, 3), "gops": round(achieved, 1),
+                "us_per_block_per_channel_longest": round(aeq_ms * 1e3 / max(info["aeq_blocks_max"], 1), 4)},
+    }
+    res = {
+        "metric": METRIC,
+        "value": round(value, 4), "unit": "Gsamples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"batched FNT-CDC+AEQ, {len(chans)} channels, log-uniform "
+                               f"2^{args.log2_min}..2^{args.log2_max} symbols/pol, fibre U(10,80) km, "
+                               f"8-32 taps, OSNR U(18,26) dB, N=64 FNT mod 65537 alpha=sqrt2, AEQ N=32",
+                   "channels": len(chans), "instants": inst, "longest_aeq_chain_blocks": info["aeq_blocks_max"]},
+        "vs_plain": round(value / plain_gsps, 2),
+        "plain_loop": {"value": round(plain_gsps, 5), "unit": "Gsamples/s",
+                       "sample": f"{len(sample)} random channels, fnt_cdc_aeq one after another"},
+        "roofline": roof,
+        "kernels": kernels,
+        "graph_ms_per_run": round(graph_ms, 3),
+        "roofline_whole_path": {"bound": "alu", "achieved": round((aeq_ops + cdc_ops) / (ms / 1e3) / 1e9, 1),
+                                "peak": PEAK_ALU_GOPS, "unit": "Gops/s",
+                                "frac": round((aeq_ops + cdc_ops) / (ms / 1e3) / 1e9 / PEAK_ALU_GOPS, 5)},
+        "plan": {k: info[k] for k in ("cdc_waves_per_group", "cdc_blocks_per_wave", "aeq_variant",
+                                      "aeq_waves_per_pol", "aeq_waves_long", "aeq_long_channels", "graph")},
+        "parity": f"bit-exact vs oracle on channels {pick}", "gen_s": round(gen_s, 1),
+        "autotune_s": round(tune_s, 1),
+    }
+    if not args.no_cpu_baseline:
+        progress("batched: oracle CPU baseline")
+        res["cpu_baseline"] = cpu_baseline_batched(chans, prms, args.cpu_budget)
     plan.close()
-    return {"value": round(value, 4), "unit": "Gsamples/s", "ms_per_run": round(ms, 3),
-            "vs_plain": round(value / plain_gsps, 2),
-            "plain_loop_gsamples_per_s": round(plain_gsps, 5),
-            "plain_loop_sample": f"{len(sample)} random channels, fnt_cdc_aeq one after another",
-            "vs_single_stream": round(value / single_gsps, 2) if single_gsps else None,
-            "workload": f"{len(chans)} channels, log-uniform 2^{args.log2_min}..2^{args.log2_max} "
-                        f"symbols/pol, fibre U(10,80) km, 8-32 taps, OSNR U(18,26) dB",
-            "channels": len(chans), "instants": inst, "longest_aeq_chain_blocks": info["aeq_blocks_max"],
-            "plan": {k: info[k] for k in ("cdc_waves_per_group", "cdc_blocks_per_wave", "aeq_variant",
-                                          "aeq_waves_per_pol", "graph")},
-            "roofline_whole_path": {"bound": "alu", "achieved": round(achieved, 1), "peak": PEAK_ALU_GOPS,
-                                    "unit": "Gops/s", "frac": round(achieved / PEAK_ALU_GOPS, 5)},
-            "parity": f"bit-exact vs oracle on channels {pick}", "gen_s": round(gen_s, 1),
-            "autotune_s": round(tune_s, 1)}
+    return res
 
 
 def bench_served(args, torch, dev):
@@ -368,6 +469,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--log2-symbols", type=int, default=24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--single-cpu-baseline", action="store_true",
+                    help="also time the single-threaded oracle on a prefix of the single stream")
+    ap.add_argument("--single-steps", type=int, default=3)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-served", action="store_true")
@@ -375,13 +479,12 @@ def main():
     ap.add_argument("--nch", type=int, default=4096)
     ap.add_argument("--log2-min", type=int, default=12)
     ap.add_argument("--log2-max", type=int, default=20)
-    ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--served-channels", type=int, default=1024)
     ap.add_argument("--rate", type=float, default=20000.0)
     ap.add_argument("--window", type=float, default=0.5)
     ap.add_argument("--chunk", type=int, default=64)
     ap.add_argument("--copy-probe", action="store_true",
-                    help="only run 5 plain 256 MiB device-to-device copies (counter calibration)")
+                    help="only run 5 plain 256 MiB elementwise copies (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -396,20 +499,27 @@ def main():
     if args.copy_probe:
         x = torch.randint(-16, 16, (256 << 20,), dtype=torch.int8, device=dev)
         y = torch.empty_like(x)
+        torch.cuda.synchronize()
         for _ in range(5):
-            y.copy_(x)
+            torch.neg(x, out=y)             # a plain elementwise kernel: reads 256 MiB, writes 256 MiB
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": x.numel(), "copies": 5}), flush=True)
         return
-    progress("single stream")
-    res = bench_single(args, torch, dev) if not args.skip_single else {}
-    progress(f"single done: {res.get('value')}")
+    res = {}
     if not args.skip_batched:
-        res["batched"] = bench_batched(args, torch, dev, res.get("value"))
-        print(f"[bench] batched done: {res['batched']['value']}", file=sys.stderr, flush=True)
+        progress("batched")
+        res = bench_batched(args, torch, dev)
+        progress(f"batched done: {res['value']}")
+    if not args.skip_single:
+        progress("plain single stream")
+        res["plain_single_stream"] = bench_single(args, torch, dev)
+        progress(f"single done: {res['plain_single_stream']['value']}")
+        if "value" in res:
+            res["vs_single_stream"] = round(res["value"] / res["plain_single_stream"]["value"], 1)
     if not args.skip_served:
+        progress("served")
         res["served"] = bench_served(args, torch, dev)
-        print(f"[bench] served done: {res['served']['value']}", file=sys.stderr, flush=True)
+        progress(f"served done: {res['served']['value']}")
     print(json.dumps(res), flush=True)
 
 

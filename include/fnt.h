@@ -202,6 +202,17 @@ int fnt_plan_create(fnt_plan **plan, const fnt_channel_desc *host_channels, size
                     const fnt_plan_config *cfg, void *stream);
 /* Run every channel once (CDC + resample + AEQ), enqueued on `stream`. */
 int fnt_plan_run(fnt_plan *plan, void *stream);
+
+#define FNT_STAGE_CDC 1   /* CDC + resample + requantise of every channel (writes plan scratch) */
+#define FNT_STAGE_AEQ 2   /* AEQ of every channel (reads plan scratch, updates taps, writes out) */
+#define FNT_STAGE_ALL 3
+/* Launch the stages in `stages` (a mask of FNT_STAGE_*) directly on `stream`,
+ * outside the plan's graph, so that a caller can bracket each with its own
+ * events.  FNT_STAGE_CDC then FNT_STAGE_AEQ is exactly one fnt_plan_run; the
+ * AEQ stage alone recomputes the AEQ from whatever the last CDC stage left in
+ * the scratch (taps continue from their current state).  FNT_E_INVAL for a
+ * mask outside FNT_STAGE_ALL. */
+int fnt_plan_run_stage(fnt_plan *plan, int stages, void *stream);
 int fnt_plan_get_info(const fnt_plan *plan, fnt_plan_info *info);
 int fnt_plan_destroy(fnt_plan *plan);
 

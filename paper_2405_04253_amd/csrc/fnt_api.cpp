@@ -286,12 +286,17 @@ struct fnt_plan {
 // Launch sequence of a plan on stream s: CDC over all blocks, then the AEQ of
 // the long chains on s concurrently with the AEQ of the others on a side stream
 // (fork / join by events, which a graph capture turns into parallel branches).
-static int plan_launch(fnt_plan *p, hipStream_t s, hipStream_t side) {
-    const int n = (int)p->aeq_host.size();
+static int plan_launch_cdc(fnt_plan *p, hipStream_t s) {
     hipError_t e = launch_cdc(p->cdc_dev, (int)p->cdc_host.size(), CdcItem{}, p->total_blocks, p->wpg,
                               p->bpw, false, p->err, s);
     if (e != hipSuccess) return hip_fail(e, "plan: cdc launch");
+    return FNT_OK;
+}
+
+static int plan_launch_aeq(fnt_plan *p, hipStream_t s, hipStream_t side) {
+    const int n = (int)p->aeq_host.size();
     const int nl = (int)std::min<size_t>(p->n_long, (size_t)n);
+    hipError_t e;
     if (nl == 0 || nl == n || p->variant != 0) {
         const int w = (p->variant == 0 && nl == n) ? p->wpp_long : p->wpp;
         e = launch_aeq(p->aeq_dev, n, AeqItem{}, p->variant, w, p->err, s);
@@ -306,6 +311,14 @@ static int plan_launch(fnt_plan *p, hipStream_t s, hipStream_t side) {
     if (e == hipSuccess) e = hipStreamWaitEvent(s, p->join, 0);
     if (e != hipSuccess) return hip_fail(e, "plan: aeq launch");
     return FNT_OK;
+}
+
+// Launch sequence of a plan on stream s: CDC over all blocks, then the AEQ of
+// the long chains on s concurrently with the AEQ of the others on a side stream
+// (fork / join by events, which a graph capture turns into parallel branches).
+static int plan_launch(fnt_plan *p, hipStream_t s, hipStream_t side) {
+    int rc = plan_launch_cdc(p, s);
+    return rc ? rc : plan_launch_aeq(p, s, side);
 }
 
 static void plan_drop_graph(fnt_plan *p) {
@@ -655,6 +668,17 @@ int fnt_plan_run(fnt_plan *p, void *stream) {
         return FNT_OK;
     }
     return plan_launch(p, s, p->side);
+}
+
+int fnt_plan_run_stage(fnt_plan *p, int stages, void *stream) {
+    if (!p) return fail(FNT_E_INVAL, "plan: NULL");
+    if (stages & ~FNT_STAGE_ALL) return fail(FNT_E_INVAL, "plan: stage mask 0x%x", stages);
+    if (p->cdc_host.empty()) return FNT_OK;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = FNT_OK;
+    if (stages & FNT_STAGE_CDC) rc = plan_launch_cdc(p, s);
+    if (!rc && (stages & FNT_STAGE_AEQ)) rc = plan_launch_aeq(p, s, p->side);
+    return rc;
 }
 
 int fnt_plan_get_info(const fnt_plan *p, fnt_plan_info *info) {

@@ -23,6 +23,7 @@ FNT_OK, FNT_E_INVAL, FNT_E_RANGE, FNT_E_NOMEM, FNT_E_DEVICE, FNT_E_BUSY, FNT_E_S
 FNT_ALPHA_2, FNT_ALPHA_SQRT2 = 0, 1
 FNT_SUBMIT_HOST = 1
 FNT_STATE_BYTES = 768
+FNT_STAGE_CDC, FNT_STAGE_AEQ, FNT_STAGE_ALL = 1, 2, 3
 _ERR_NAMES = {1: "FNT_E_INVAL", 2: "FNT_E_RANGE", 3: "FNT_E_NOMEM", 4: "FNT_E_DEVICE",
               5: "FNT_E_BUSY", 6: "FNT_E_STATE"}
 
@@ -100,6 +101,7 @@ SIGNATURES = {
     "fnt_plan_create": (_i32, [ctypes.POINTER(_vp), ctypes.POINTER(ChannelDesc), _sz,
                                ctypes.POINTER(PlanConfig), _vp]),
     "fnt_plan_run": (_i32, [_vp, _vp]),
+    "fnt_plan_run_stage": (_i32, [_vp, _i32, _vp]),
     "fnt_plan_get_info": (_i32, [_vp, ctypes.POINTER(PlanInfo)]),
     "fnt_plan_set_aeq_variant": (_i32, [_vp, _i32]),
     "fnt_plan_set_aeq_waves": (_i32, [_vp, _i32]),
@@ -278,6 +280,10 @@ class Plan:
 
     def run(self, stream=None):
         _ok(lib().fnt_plan_run(self._h, _stream(stream)))
+
+    def run_stage(self, stages: int, stream=None):
+        """Launch FNT_STAGE_CDC and/or FNT_STAGE_AEQ directly (outside the graph)."""
+        _ok(lib().fnt_plan_run_stage(self._h, int(stages), _stream(stream)))
 
     def info(self) -> dict:
         inf = PlanInfo()

@@ -23,6 +23,7 @@ to [-16, 15].
 from __future__ import annotations
 
 import hashlib
+import functools
 import math
 from dataclasses import dataclass, field
 
@@ -281,6 +282,15 @@ def random_aeq_taps(seed: int, lo: int = -8192, hi: int = 8191) -> np.ndarray:
 # ---------------------------------------------------------------------------
 # Same recipe on a torch device (large workloads: 10^9 symbols in seconds).
 # ---------------------------------------------------------------------------
+@functools.lru_cache(maxsize=32)
+def _rrc_on_device(nfft: int, device: str):
+    """RRC frequency response of length nfft as a float32 tensor on `device`, and
+    its mean power (cached: power-of-two FFT lengths repeat across channels)."""
+    import torch
+    r = _rrc_response(nfft)
+    return torch.from_numpy(r.astype(np.float32)).to(device), float(np.mean(r ** 2))
+
+
 def gen_channel_torch(nsym: int, fibre_km: float, osnr_db: float, seed: int, device,
                       ntaps: int | None = None):
     """gen_channel's recipe with torch FFTs on `device`.  Returns (samples int8
@@ -302,7 +312,7 @@ def gen_channel_torch(nsym: int, fibre_km: float, osnr_db: float, seed: int, dev
     sym = torch.zeros((ng, 4), dtype=torch.float32, device=device)
     sym[:nsym] = (torch.randint(0, 4, (nsym, 4), generator=g, device=device) * 2 - 3).float()
     nfft = SPS * ng
-    rrc = torch.from_numpy(_rrc_response(nfft).astype(np.float32)).to(device)
+    rrc, p_rrc = _rrc_on_device(nfft, str(device))
     fhz = torch.fft.fftfreq(nfft, device=device, dtype=torch.float64) * (BAUD * SPS)
     ph = (-dispersion_beta(fibre_km) * fhz * fhz)
     cd = torch.polar(torch.ones_like(ph), ph).to(torch.complex64)
@@ -316,7 +326,6 @@ def gen_channel_torch(nsym: int, fibre_km: float, osnr_db: float, seed: int, dev
     rot = [uc[0, 0] * spec[0] + uc[0, 1] * spec[1], uc[1, 0] * spec[0] + uc[1, 1] * spec[1]]
     del spec
     out = torch.empty((nfft, 4), dtype=torch.float32, device=device)
-    p_rrc = float(np.mean(_rrc_response(nfft) ** 2))
     for p in range(2):
         sig = rot[p] * rrc
         p_sig = float(torch.mean(sig.real ** 2 + sig.imag ** 2)) / nfft

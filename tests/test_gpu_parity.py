@@ -333,6 +333,21 @@ def test_plan_autotune_and_eager(torch_dev, tmp_path):
     assert os.path.exists(cache) and "wpg" in open(cache).read()
     info = plan.info()
     assert info["graph"] == 0 and info["cdc_blocks_per_wave"] >= 1
+    # the two stages launched one by one reproduce a whole run
+    for c in pc:
+        c["taps"].copy_(to_dev(torch, dev, c["w0"]))
+        c["out"].fill_(-7)
+    note("plan staged run")
+    plan.run_stage(fnt.FNT_STAGE_CDC)
+    plan.run_stage(fnt.FNT_STAGE_AEQ)
+    torch.cuda.synchronize()
+    for c in pc:
+        outr, wr, _ = O.cdc_aeq(c["ch"].samples, c["ch"].taps, c["ch"].requant_shift, c["w0"],
+                                O.params(**c["prm"]))
+        assert np.array_equal(c["out"].cpu().numpy(), outr)
+        assert np.array_equal(c["taps"].cpu().numpy(), wr)
+    with pytest.raises(fnt.FntError):
+        plan.run_stage(4)
     plan.close()
     fnt.fnt_check()
 
