@@ -350,7 +350,8 @@ def bench_batched(args, torch, dev):
             "hbm_algorithmic_gbs": round(aeq_blocks * 16 * AEQ_BYTES_PER_SYMBOL / aeq_ms / 1e6, 1),
             "hbm_frac": round(aeq_blocks * 16 * AEQ_BYTES_PER_SYMBOL / aeq_ms / 1e6 / PEAK_HBM_GBS, 5)}
     kernels = {
-        "cdc": {"kernel": "cdc_kernel<0>", "ms": round(cdc_ms, 3),
+        "cdc": {"kernel": ("cdc_lane_kernel<%d>" % info["cdc_waves_per_group"]) if info["cdc_blocks_per_wave"] == 0
+                          else "cdc_kernel<false>", "ms": round(cdc_ms, 3),
                 "gops": round(cdc_ops / cdc_ms / 1e6, 1), "frac_alu": round(cdc_ops / cdc_ms / 1e6 / PEAK_ALU_GOPS, 5),
                 "gbs": round(inst * CDC_BYTES_PER_INSTANT / cdc_ms / 1e6, 1)},
         "aeq": {"kernel": kname, "ms": round(aeq_ms, 3), "gops": round(achieved, 1),

@@ -180,7 +180,7 @@ typedef struct fnt_plan_info {
     uint64_t cdc_blocks;   /* total 32-instant CDC blocks */
     uint64_t aeq_blocks_max;  /* longest per-channel AEQ chain, in 16-symbol blocks */
     int32_t cdc_waves_per_group;  /* chosen schedule */
-    int32_t cdc_blocks_per_wave;
+    int32_t cdc_blocks_per_wave;  /* 0 = one block per lane (64 blocks per wave) */
     int32_t aeq_variant;   /* 0 = Fermat-domain filtering (the method), 1 = direct comparator,
                               2 = Fermat-domain, one wave per channel */
     int32_t aeq_waves_per_pol;  /* variant 0: waves per polarisation half (1, 2 or 4) */
@@ -230,8 +230,12 @@ int fnt_plan_set_aeq_waves(fnt_plan *plan, int waves_per_pol);
  * launch concurrent with the rest, which run with `wpp` waves per half
  * (fewer waves, higher throughput).  long_channels = 0 disables the split. */
 int fnt_plan_set_aeq_split(fnt_plan *plan, uint64_t long_channels, int wpp_long, int wpp);
-/* CDC launch schedule: waves per workgroup (1, 2 or 4) and consecutive 32-instant
- * blocks per wave (1 .. 1024).  Results do not depend on it. */
+/* CDC launch schedule: waves per workgroup (1, 2 or 4) and the block mapping.
+ * blocks_per_wave = 0 (default): every lane transforms one whole 32-instant block
+ * in its registers, a wave takes 64 consecutive blocks of one channel;
+ * blocks_per_wave = 1 .. 1024: the lanes of a wave share one block at a time
+ * (16 lanes per 64-point transform) and a wave takes that many consecutive
+ * blocks.  Results do not depend on it. */
 int fnt_plan_set_cdc_schedule(fnt_plan *plan, int waves_per_group, int blocks_per_wave);
 
 /* ------------------------------------------------------------------------

@@ -118,11 +118,23 @@ void fill_aeq_item(AeqItem &it, const int8_t *a, uint64_t m, int16_t *taps, cons
     it.update_enable = p->update_enable;
 }
 
-// Default CDC schedule: enough waves to fill 256 CUs several times over.
+// Default CDC schedule: the lane-per-block kernel (blocks_per_wave = 0), four
+// waves per workgroup.
 void default_cdc_schedule(uint64_t total_blocks, int *wpg, int *bpw) {
+    (void)total_blocks;
     *wpg = 4;
-    uint64_t b = total_blocks / (256ull * 4 * 16);
-    *bpw = (int)std::max<uint64_t>(1, std::min<uint64_t>(64, b));
+    *bpw = 0;
+}
+
+// Launch the CDC with a schedule (wpg, bpw): bpw = 0 is the lane-per-block
+// kernel, bpw >= 1 the wave-per-block kernel with bpw consecutive blocks per
+// wave.  The exact output z only exists in the wave-per-block kernel, which then
+// runs with enough waves to fill 256 CUs several times over.
+hipError_t run_cdc(const CdcItem *items, int nitems, const CdcItem &single, uint64_t blocks,
+                   uint64_t chunks, int wpg, int bpw, bool with_z, int *err, hipStream_t s) {
+    if (bpw == 0 && !with_z) return launch_cdc(items, nitems, single, blocks, chunks, 0, wpg, 1, false, err, s);
+    const int b = bpw ? bpw : (int)std::max<uint64_t>(1, std::min<uint64_t>(64, blocks / (256ull * 4 * 16)));
+    return launch_cdc(items, nitems, single, blocks, chunks, 1, wpg, b, with_z, err, s);
 }
 
 }  // namespace fnti
@@ -197,8 +209,8 @@ int fnt_cdc(const int8_t *in, uint64_t n, const fnt_cdc_params *p, int32_t *out_
     it.a_out = out_1sps;
     int wpg, bpw;
     default_cdc_schedule(cdc_blocks(n), &wpg, &bpw);
-    hipError_t e = launch_cdc(nullptr, 0, it, cdc_blocks(n), wpg, bpw, out_exact != nullptr, err,
-                              (hipStream_t)stream);
+    hipError_t e = run_cdc(nullptr, 0, it, cdc_blocks(n), cdc_chunks(n), wpg, bpw, out_exact != nullptr, err,
+                           (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "fnt_cdc launch");
     return FNT_OK;
 }
@@ -243,7 +255,7 @@ int fnt_cdc_aeq(const int8_t *in, uint64_t n, const fnt_cdc_params *cp, int16_t 
         ci.a_out = abuf;
         int wpg, bpw;
         default_cdc_schedule(cdc_blocks(n), &wpg, &bpw);
-        e = launch_cdc(nullptr, 0, ci, cdc_blocks(n), wpg, bpw, false, err, s);
+        e = run_cdc(nullptr, 0, ci, cdc_blocks(n), cdc_chunks(n), wpg, bpw, false, err, s);
         if (e != hipSuccess) {
             (void)hipFreeAsync(abuf, s);
             return hip_fail(e, "fnt_cdc_aeq: cdc launch");
@@ -269,9 +281,9 @@ struct fnt_plan {
     AeqItem *aeq_dev = nullptr;
     int8_t *abuf = nullptr;
     int *err = nullptr;
-    uint64_t total_blocks = 0;
+    uint64_t total_blocks = 0, total_chunks = 0;
     fnt_plan_info info{};
-    int wpg = 4, bpw = 1, variant = 0, wpp = 1;
+    int wpg = 4, bpw = 0, variant = 0, wpp = 1;   // CDC: bpw = 0 is the lane-per-block kernel
     // AEQ split: the n_long longest chains (table prefix) run with wpp_long waves
     // per half in a launch concurrent with the rest
     int wpp_long = 4;
@@ -287,8 +299,8 @@ struct fnt_plan {
 // the long chains on s concurrently with the AEQ of the others on a side stream
 // (fork / join by events, which a graph capture turns into parallel branches).
 static int plan_launch_cdc(fnt_plan *p, hipStream_t s) {
-    hipError_t e = launch_cdc(p->cdc_dev, (int)p->cdc_host.size(), CdcItem{}, p->total_blocks, p->wpg,
-                              p->bpw, false, p->err, s);
+    hipError_t e = run_cdc(p->cdc_dev, (int)p->cdc_host.size(), CdcItem{}, p->total_blocks, p->total_chunks,
+                           p->wpg, p->bpw, false, p->err, s);
     if (e != hipSuccess) return hip_fail(e, "plan: cdc launch");
     return FNT_OK;
 }
@@ -457,11 +469,11 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
     double best_cdc = 1e30;
     int bw = p->wpg, bb = p->bpw;
     for (int wpg : {1, 2, 4})
-        for (int bpw : {1, 2, 4, 8, 16, 32, 64}) {
+        for (int bpw : {0, 1, 4, 16, 64}) {
             if ((uint64_t)bpw > std::max<uint64_t>(1, p->total_blocks)) continue;
             double ms = time_it([&] {
-                return launch_cdc(p->cdc_dev, (int)p->cdc_host.size(), CdcItem{}, p->total_blocks, wpg, bpw,
-                                  false, p->err, s);
+                return run_cdc(p->cdc_dev, (int)p->cdc_host.size(), CdcItem{}, p->total_blocks, p->total_chunks,
+                               wpg, bpw, false, p->err, s);
             });
             if (ms < best_cdc) {
                 best_cdc = ms;
@@ -562,7 +574,7 @@ int fnt_plan_create(fnt_plan **out, const fnt_channel_desc *ch, size_t nch, cons
         delete p;
         return rc;
     }
-    uint64_t sym_total = 0, blocks = 0, inst = 0, chain_max = 0;
+    uint64_t sym_total = 0, blocks = 0, chunks = 0, inst = 0, chain_max = 0;
     std::vector<uint64_t> aoff(nch);
     for (size_t i = 0; i < nch; ++i) {
         const fnt_channel_desc &d = ch[i];
@@ -597,7 +609,9 @@ int fnt_plan_create(fnt_plan **out, const fnt_channel_desc *ch, size_t nch, cons
         fill_cdc_item(ci, d.in, d.n, &d.cdc);
         ci.a_out = p->abuf + aoff[i] * 4;
         ci.block0 = blocks;
+        ci.chunk0 = chunks;
         blocks += cdc_blocks(d.n);
+        chunks += cdc_chunks(d.n);
         AeqItem &ai = p->aeq_host[i];
         fill_aeq_item(ai, ci.a_out, n_symbols(d.n, d.cdc.decim_phase), d.taps, &d.aeq, d.out);
     }
@@ -605,6 +619,7 @@ int fnt_plan_create(fnt_plan **out, const fnt_channel_desc *ch, size_t nch, cons
     std::stable_sort(p->aeq_host.begin(), p->aeq_host.end(),
                      [](const AeqItem &a, const AeqItem &b) { return a.m > b.m; });
     p->total_blocks = blocks;
+    p->total_chunks = chunks;
     hipError_t e = hipSuccess;
     if (nch > 0) {
         e = hipMalloc(&p->cdc_dev, nch * sizeof(CdcItem));
@@ -725,7 +740,7 @@ int fnt_plan_set_aeq_split(fnt_plan *p, uint64_t long_channels, int wpp_long, in
 int fnt_plan_set_cdc_schedule(fnt_plan *p, int wpg, int bpw) {
     if (!p) return fail(FNT_E_INVAL, "plan: NULL");
     if (wpg != 1 && wpg != 2 && wpg != 4) return fail(FNT_E_INVAL, "plan: waves per group %d", wpg);
-    if (bpw < 1 || bpw > 1024) return fail(FNT_E_INVAL, "plan: blocks per wave %d", bpw);
+    if (bpw < 0 || bpw > 1024) return fail(FNT_E_INVAL, "plan: blocks per wave %d", bpw);
     p->wpg = wpg;
     p->bpw = bpw;
     if (p->exec) return plan_capture(p, nullptr);

@@ -18,5 +18,7 @@ void fill_cdc_item(CdcItem &it, const int8_t *in, uint64_t n, const fnt_cdc_para
 void fill_aeq_item(AeqItem &it, const int8_t *a, uint64_t m, int16_t *taps, const fnt_aeq_params *p,
                    int16_t *out);
 void default_cdc_schedule(uint64_t total_blocks, int *wpg, int *bpw);
+hipError_t run_cdc(const CdcItem *items, int nitems, const CdcItem &single, uint64_t blocks,
+                   uint64_t chunks, int wpg, int bpw, bool with_z, int *err, hipStream_t s);
 
 }  // namespace fnti

@@ -17,12 +17,17 @@ struct CdcItem {
     int8_t *a_out;         // [M][4] or nullptr, M = (n + 1 - phase) / 2
     uint64_t n;
     uint64_t block0;       // first global block index of this item (prefix sum)
+    uint64_t chunk0;       // first global chunk (CDC_CHUNK blocks of this item) index (prefix sum)
     int8_t taps[32][2];
     int32_t ntaps;
     int32_t shift;
     int32_t phase;
     int32_t pad_;
 };
+
+// The lane-per-block CDC kernel gives each wave one chunk: up to CDC_CHUNK
+// consecutive blocks of one item, one block per lane.
+constexpr int CDC_CHUNK = 64;
 
 // One channel's AEQ run over m symbols (serial chain of 16-symbol blocks).
 struct AeqItem {
@@ -44,6 +49,7 @@ struct AeqItem {
 };
 
 __host__ __device__ inline uint64_t cdc_blocks(uint64_t n) { return (n + 31) / 32; }
+__host__ __device__ inline uint64_t cdc_chunks(uint64_t n) { return (cdc_blocks(n) + CDC_CHUNK - 1) / CDC_CHUNK; }
 __host__ __device__ inline uint64_t n_symbols(uint64_t n, int phase) {
     return n + 1 > (uint64_t)phase ? (n + 1 - (uint64_t)phase) / 2 : 0;
 }
@@ -52,9 +58,15 @@ __host__ __device__ inline uint64_t n_symbols(uint64_t n, int phase) {
 // case `single` is used (passed by value in the kernel arguments).
 hipError_t launch_transform(const uint32_t *x, uint32_t *X, size_t batch, int t, int log2n,
                             int alpha_kind, bool inverse, int *err, hipStream_t s);
+// CDC variant 0 (default): one block per lane, CDC_CHUNK blocks per wave, the
+// 64-point transforms in registers; needs total_chunks (sum of cdc_chunks) and
+// waves_per_group; blocks_per_wave is unused.  Variant 1: one block per wave,
+// 16 lanes per transform, blocks_per_wave consecutive blocks per wave.  The
+// exact output z (with_z) always takes variant 1.
 hipError_t launch_cdc(const CdcItem *items, int nitems, const CdcItem &single,
-                      uint64_t total_blocks, int waves_per_group, int blocks_per_wave,
-                      bool with_z, int *err, hipStream_t s);
+                      uint64_t total_blocks, uint64_t total_chunks, int variant,
+                      int waves_per_group, int blocks_per_wave, bool with_z, int *err,
+                      hipStream_t s);
 // variant 0: Fermat-domain AEQ split by output polarisation, waves_per_pol in
 // {1, 2, 4}; 1: direct time-domain comparator; 2: Fermat-domain, one wave per channel.
 hipError_t launch_aeq(const AeqItem *items, int nitems, const AeqItem &single, int variant,

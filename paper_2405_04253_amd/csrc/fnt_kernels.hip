@@ -12,6 +12,8 @@
 //    a comparator with bit-identical output.
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include "fnt_device.hpp"
 #include "fnt_internal.hpp"
 
@@ -303,6 +305,326 @@ __global__ __launch_bounds__(256) void cdc_kernel(const CdcItem *items, int nite
             if ((uint64_t)i < it.n) reinterpret_cast<uint32_t *>(it.a_out)[(i - it.phase) >> 1] = outw[il];
         }
         wave_lds_sync();
+    }
+}
+
+// ------------------------------------------------------- CDC, lane per block --
+//
+// One lane computes one whole 32-instant block: the 64-point forward
+// transforms of u = x_r + 2^8 x_i and v = x_r - 2^8 x_i (Eqs. (7)-(8) by
+// linearity) stay in its registers, with no exchange between lanes.  Only the
+// instants the resampler keeps are recovered: for decimation phase 0 the even
+// positions 2r of the 64-point inverse are the 32-point inverse (radix
+// alpha^2 = 2) of the folded spectrum T[k] = S[k] + S[k + 32]; for phase 1 the
+// odd positions are the same inverse of T[k] = alpha^-k (S[k] - S[k + 32]).
+// A wave takes CDC_CHUNK consecutive blocks of one channel and first computes
+// that channel's tap spectra H+, H- into LDS, one bin per lane.
+
+// Compile-time loop: f(std::integral_constant<int, 0>{}), ..., f(<N - 1>).
+template <typename F, int... I>
+__device__ __forceinline__ void sfor_(F &&f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void sfor(F &&f) {
+    sfor_(f, std::make_integer_sequence<int, N>{});
+}
+
+// One fold of a loose residue: 2^16 xh + xl == xl - xh.  Any int32 in, result
+// in (-2^15, 2^16 + 2^15).
+__device__ __forceinline__ int32_t fold16(int32_t x) {
+    return (int32_t)((uint32_t)x & 0xFFFFu) - (x >> 16);
+}
+
+// x * 2^e for 1 <= e <= 14, any int32 x: fold, shift (stays below 2^31), fold.
+__device__ __forceinline__ int32_t mul_pow2(int32_t x, int e) { return fold16(fold16(x) << e); }
+
+// (a - b) * alpha^E, E a compile-time exponent (alpha = sqrt 2, alpha^(2f) = 2^f,
+// 2^16 = -1).  Powers of two below 2^15 take mul_pow2 (any int32 a - b); the
+// others take mulmod (|a - b| < 2^23).  Result magnitude < 2^16 + 2^15, or
+// |a - b| itself for E = 0, 32.
+template <int E>
+__device__ __forceinline__ int32_t tw_diff(int32_t a, int32_t b) {
+    constexpr int e = E & 63;
+    if constexpr (e == 0) {
+        return a - b;
+    } else if constexpr (e == 32) {
+        return b - a;
+    } else if constexpr ((e & 1) == 0 && e / 2 < 15) {
+        return mul_pow2(a - b, e / 2);
+    } else if constexpr ((e & 1) == 0 && e / 2 > 16 && e / 2 < 31) {
+        return mul_pow2(b - a, e / 2 - 16);
+    } else {
+        constexpr AlphaPow tab = make_alpha_pow();
+        return mulmod(a - b, opq(tab.v[e]));
+    }
+}
+
+// Stages h = 16 .. 1 of the 64-point DIF forward transform (radix sqrt 2) on
+// one half of the registers.  After the first stage (h = 32) the halves
+// x[0..31] (even bins) and x[32..63] (odd bins) are independent 32-point
+// transforms with the same twiddles alpha^(j 32 / h); on return x[n] of half
+// `hf` holds bin bitrev6(32 hf + n).  In: |x| < 2^16.6; out: |X| < 2^21.6.
+template <int H>
+__device__ __forceinline__ void fnt64_half_stage(int32_t (&x)[32]) {
+    sfor<16 / H>([&](auto gc) {
+        constexpr int g = decltype(gc)::value * 2 * H;
+        sfor<H>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            const int32_t a = x[g + j], b = x[g + j + H];
+            x[g + j] = a + b;
+            x[g + j + H] = tw_diff<j * (32 / H)>(a, b);
+        });
+    });
+}
+__device__ __forceinline__ void fnt64_half(int32_t (&x)[32]) {
+    fnt64_half_stage<16>(x);
+    fnt64_half_stage<8>(x);
+    fnt64_half_stage<4>(x);
+    fnt64_half_stage<2>(x);
+    fnt64_half_stage<1>(x);
+}
+
+// b * 2^-e (mod 65537) subtracted from / added to a, e compile-time in [0, 16):
+// 2^-e = -2^(16 - e).  Returns (a + b 2^-e, a - b 2^-e).
+template <int E>
+__device__ __forceinline__ void inv_bfly(int32_t a, int32_t b, int32_t &lo, int32_t &hi) {
+    if constexpr (E == 0) {
+        lo = a + b;
+        hi = a - b;
+    } else if constexpr (E == 1) {
+        const int32_t t = mulmod(b, opq(32768));      // b 2^15 = -b 2^-1
+        lo = a - t;
+        hi = a + t;
+    } else {
+        const int32_t t = mul_pow2(b, 16 - E);       // b 2^(16-E) = -b 2^-E
+        lo = a - t;
+        hi = a + t;
+    }
+}
+
+// 32-point DIT inverse (radix 2, unnormalised), bit-reversed order in; returns
+// the natural-order outputs 16..31 in y[16..31].  In: |y| < 2^16.6 (|b| < 2^23
+// where mulmod is used); out: |y| < 2^21.6.
+template <int H>
+__device__ __forceinline__ void ifnt32_stage(int32_t (&y)[32]) {
+    sfor<16 / H>([&](auto gc) {
+        constexpr int g = decltype(gc)::value * 2 * H;
+        sfor<H>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            int32_t lo, hi;
+            inv_bfly<j * (16 / H)>(y[g + j], y[g + j + H], lo, hi);
+            if constexpr (H < 16) y[g + j] = lo;       // the last stage keeps the upper half
+            y[g + j + H] = hi;
+        });
+    });
+}
+__device__ __forceinline__ void ifnt32_upper_regs(int32_t (&y)[32]) {
+    ifnt32_stage<1>(y);
+    ifnt32_stage<2>(y);
+    ifnt32_stage<4>(y);
+    ifnt32_stage<8>(y);
+    ifnt32_stage<16>(y);
+}
+
+// Centred value of a loose residue r congruent to a z with |z| <= 32768, for
+// |r| < 2^31 - 2^16: fold once into (-2^15, 2^16 + 2^15), where z or z + 65537
+// is the only candidate.
+__device__ __forceinline__ int32_t lift_z(int32_t r) {
+    const int32_t f = fold16(r);
+    return f > 32768 ? f - 65537 : f;
+}
+
+// rs(z, s) then saturate to 5 bit, for |z| <= 2^16 and 0 <= s < 16.
+__device__ __forceinline__ int32_t requant5(int32_t z, int s) {
+    const int32_t r = (z + ((1 << s) >> 1)) >> s;
+    return r < -16 ? -16 : (r > 15 ? 15 : r);
+}
+
+template <int WPG>
+__global__ __launch_bounds__(64 * WPG) void cdc_lane_kernel(const CdcItem *items, int nitems,
+                                                            CdcItem single, uint64_t total_chunks,
+                                                            int *err) {
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    __shared__ int32_t hs_s[WPG][2][64];               // per wave: H+, H- by register index
+    __shared__ __align__(16) uint32_t edge_s[WPG][2][64];  // per wave: windows of edge blocks
+    int32_t(*hs)[64] = hs_s[wv];
+
+    const uint64_t chunk = (uint64_t)blockIdx.x * WPG + wv;
+    if (chunk >= total_chunks) return;
+    int idx = 0;
+    if (items) {                                        // last item whose chunk range starts <= chunk
+        int lo = 0, hi = nitems - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (items[mid].chunk0 <= chunk) lo = mid; else hi = mid - 1;
+        }
+        idx = lo;
+    }
+    const CdcItem *ip = items ? &items[idx] : &single;
+    const uint64_t n = ip->n;
+    const uint64_t nb = fnti::cdc_blocks(n);
+    const uint64_t lb0 = (chunk - (items ? ip->chunk0 : 0)) * fnti::CDC_CHUNK;
+    if (lb0 >= nb) return;                              // a table that does not cover the chunk
+    const int ntaps = ip->ntaps < 32 ? ip->ntaps : 32;
+    const int shift = ip->shift, phase = ip->phase;
+    const int8_t *in = ip->in;
+    const int8_t *hist = ip->hist;
+    int8_t *a_out = ip->a_out;
+
+    {   // tap spectra, bin k = lane: H+- = sum_n (h_r[n] +- 2^8 h_i[n]) alpha^(n k)
+        const int8_t *tp = &ip->taps[0][0];
+        const int32_t ak = kAlphaPow.v[lane];
+        int32_t a = 1, sr = 0, si = 0;                  // |sums| < 32 * 32 * 2^16.6
+        for (int k = 0; k < ntaps; ++k) {
+            sr += (int32_t)tp[2 * k] * sext24(a);
+            si += (int32_t)tp[2 * k + 1] * sext24(a);
+            a = mulmod(a, ak);
+        }
+        const int32_t r = fold16(sr), i8 = mul_pow2(si, 8);
+        const int reg = bitrev(lane, 6);
+        hs[0][reg] = r + i8;                           // |.| < 2^17.6
+        hs[1][reg] = r - i8;
+    }
+    wave_lds_sync();
+
+    const uint64_t lb = lb0 + (uint64_t)lane;
+    const bool active = lb < nb;                        // lanes past the channel's end idle
+    const int64_t i0 = 32 * (int64_t)lb - 32;           // first instant of the window
+    // interior blocks read their window straight from the input; the first block
+    // (history before instant 0) and a partial last block (zeros past n) -- at
+    // most two lanes of the wave -- read a copy the wave builds in LDS
+    const bool interior = active && lb >= 1 && (uint64_t)(i0 + 64) <= n;
+    const uint64_t edges = __ballot(active && !interior);
+    const int e0 = edges ? __ffsll((unsigned long long)edges) - 1 : 0;
+    const int e1 = edges ? 63 - __clzll((long long)edges) : 0;
+    uint32_t bad = 0u;
+    for (int k = 0; k < 2; ++k) {                       // uniform: staging of edge windows
+        if (k == 1 && e1 == e0) break;
+        if (!edges) break;
+        const int L = k ? e1 : e0;
+        const int64_t i = 32 * (int64_t)(lb0 + L) - 32 + lane;
+        uint32_t w = 0u;
+        if (i < 0) {
+            if (hist) w = reinterpret_cast<const uint32_t *>(hist)[32 + i];
+        } else if ((uint64_t)i < n) {
+            w = reinterpret_cast<const uint32_t *>(in)[i];
+            if (lane >= 32) bad |= w ^ (w << 1);        // new word of block lb0 + L
+        }
+        edge_s[wv][k][lane] = w;
+    }
+    wave_lds_sync();
+    // this lane's 64 window words, through a flat pointer into global memory or LDS
+    const uint32_t *wp = interior ? reinterpret_cast<const uint32_t *>(in) + i0
+                                  : &edge_s[wv][(active && lane == e1 && e1 != e0) ? 1 : 0][0];
+    const bool vec = ((uintptr_t)in & 15u) == 0u;       // uniform: 16-byte loads possible
+    if (interior) {                                     // range check of the 32 new words
+        if (vec) {
+            const uint4 *w4p = reinterpret_cast<const uint4 *>(wp);
+#pragma unroll
+            for (int q = 8; q < 16; ++q) {
+                const uint4 w4 = w4p[q];
+                bad |= (w4.x ^ (w4.x << 1)) | (w4.y ^ (w4.y << 1)) | (w4.z ^ (w4.z << 1)) | (w4.w ^ (w4.w << 1));
+            }
+        } else {
+#pragma unroll 8
+            for (int q = 32; q < 64; ++q) bad |= wp[q] ^ (wp[q] << 1);
+        }
+    }
+    const uint64_t M = fnti::n_symbols(n, phase);
+    const int64_t m0 = 16 * (int64_t)lb;                // first symbol of the block
+    uint32_t o[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) o[q] = 0u;
+
+#pragma unroll 1
+    for (int pol = 0; pol < 2; ++pol) {
+        int32_t ys[32], yd[32];
+        sfor<2>([&](auto hc) {
+            constexpr int hf = decltype(hc)::value;
+            // first DIF stage fused with unpacking: half 0 takes u[j] + u[j + 32],
+            // half 1 takes (u[j] - u[j + 32]) alpha^j, u = x_r + 2^8 x_i (v: -)
+            int32_t u[32], v[32];
+            auto unpack = [&](auto jc, uint32_t w0, uint32_t w1) {
+                constexpr int j = decltype(jc)::value;
+                const int32_t r0 = sbyte(w0, 2 * pol), i0b = sbyte(w0, 2 * pol + 1);
+                const int32_t r1 = sbyte(w1, 2 * pol), i1b = sbyte(w1, 2 * pol + 1);
+                if constexpr (hf == 0) {
+                    const int32_t xr = r0 + r1, xi = i0b + i1b;
+                    u[j] = xr + 256 * xi;                   // |.| <= 8224
+                    v[j] = xr - 256 * xi;
+                } else {
+                    const int32_t xr = r0 - r1, xi = i0b - i1b;
+                    u[j] = tw_diff<j>(xr + 256 * xi, 0);
+                    v[j] = tw_diff<j>(xr - 256 * xi, 0);
+                }
+            };
+            if (vec) {
+                const uint4 *w4p = reinterpret_cast<const uint4 *>(wp);
+                sfor<8>([&](auto qc) {
+                    constexpr int q = decltype(qc)::value;
+                    const uint4 lo4 = w4p[q], hi4 = w4p[q + 8];
+                    unpack(std::integral_constant<int, 4 * q + 0>{}, lo4.x, hi4.x);
+                    unpack(std::integral_constant<int, 4 * q + 1>{}, lo4.y, hi4.y);
+                    unpack(std::integral_constant<int, 4 * q + 2>{}, lo4.z, hi4.z);
+                    unpack(std::integral_constant<int, 4 * q + 3>{}, lo4.w, hi4.w);
+                });
+            } else {
+                sfor<32>([&](auto jc) { unpack(jc, wp[decltype(jc)::value], wp[decltype(jc)::value + 32]); });
+            }
+            fnt64_half(u);
+            fnt64_half(v);
+            // P = U H+, Q = V H-; S = P + Q, D = P - Q, folded to the kept phase
+#pragma unroll
+            for (int r = 0; r < 32; r += 2) {
+                const int32_t P0 = mulmod(u[r], hs[0][32 * hf + r]), Q0 = mulmod(v[r], hs[1][32 * hf + r]);
+                const int32_t P1 = mulmod(u[r + 1], hs[0][32 * hf + r + 1]);
+                const int32_t Q1 = mulmod(v[r + 1], hs[1][32 * hf + r + 1]);
+                u[r] = P0 + Q0;                         // |.| < 2^17.4
+                v[r] = P0 - Q0;
+                u[r + 1] = P1 + Q1;
+                v[r + 1] = P1 - Q1;
+            }
+            if (phase == 0) {
+#pragma unroll
+                for (int m = 0; m < 16; ++m) {
+                    ys[16 * hf + m] = fold16(u[2 * m] + u[2 * m + 1]);
+                    yd[16 * hf + m] = fold16(v[2 * m] + v[2 * m + 1]);
+                }
+            } else {
+                sfor<16>([&](auto mc) {
+                    constexpr int m = 16 * hf + decltype(mc)::value;
+                    constexpr int k = ((m & 1) << 4) | ((m & 2) << 2) | (m & 4) | ((m & 8) >> 2) | ((m & 16) >> 4);
+                    ys[m] = tw_diff<64 - k>(u[2 * (m - 16 * hf)], u[2 * (m - 16 * hf) + 1]);
+                    yd[m] = tw_diff<64 - k>(v[2 * (m - 16 * hf)], v[2 * (m - 16 * hf) + 1]);
+                });
+            }
+            __asm__ volatile("" ::: "memory");          // reload the window for the next pass
+        });
+        ifnt32_upper_regs(ys);
+        ifnt32_upper_regs(yd);
+        // Eq. (7): z = -2^15 64^-1 IFNT' = -512 IFNT'; Eq. (8): z^ = -2^7 64^-1 IFNT' = -2 IFNT'
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int32_t zr = lift_z(sext24(ys[16 + q]) * -512);
+            const int32_t zi = lift_z(sext24(yd[16 + q]) * -2);
+            const uint32_t b2 = ((uint32_t)requant5(zr, shift) & 0xFFu) |
+                                (((uint32_t)requant5(zi, shift) & 0xFFu) << 8);
+            o[q] |= b2 << (16 * pol);
+        }
+    }
+    if ((bad & 0xE0E0E0E0u) != 0u) flag(err, RANGE_SAMPLE);
+    if (a_out == nullptr || !active) return;
+    uint32_t *dst = reinterpret_cast<uint32_t *>(a_out) + m0;
+    if ((uint64_t)(m0 + 16) <= M && ((uintptr_t)dst & 15u) == 0u) {
+        uint4 *d4 = reinterpret_cast<uint4 *>(dst);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) d4[q] = make_uint4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            if ((uint64_t)(m0 + q) < M) dst[q] = o[q];
     }
 }
 
@@ -1055,11 +1377,25 @@ hipError_t launch_transform(const uint32_t *x, uint32_t *X, size_t batch, int t,
 }
 
 hipError_t launch_cdc(const CdcItem *items, int nitems, const CdcItem &single,
-                      uint64_t total_blocks, int waves_per_group, int blocks_per_wave,
-                      bool with_z, int *err, hipStream_t s) {
+                      uint64_t total_blocks, uint64_t total_chunks, int variant,
+                      int waves_per_group, int blocks_per_wave, bool with_z, int *err,
+                      hipStream_t s) {
     if (total_blocks == 0) return hipSuccess;
-    if (waves_per_group < 1 || waves_per_group > 4 || blocks_per_wave < 1)
-        return hipErrorInvalidValue;
+    if (waves_per_group < 1 || waves_per_group > 4) return hipErrorInvalidValue;
+    if (variant == 0 && !with_z) {
+        if (total_chunks == 0) return hipErrorInvalidValue;
+        const uint64_t grid = (total_chunks + waves_per_group - 1) / waves_per_group;
+        if (grid > 0x7FFFFFFFull) return hipErrorInvalidValue;
+        switch (waves_per_group) {
+        case 1: cdc_lane_kernel<1><<<(unsigned)grid, 64, 0, s>>>(items, nitems, single, total_chunks, err); break;
+        case 2: cdc_lane_kernel<2><<<(unsigned)grid, 128, 0, s>>>(items, nitems, single, total_chunks, err); break;
+        case 3: cdc_lane_kernel<3><<<(unsigned)grid, 192, 0, s>>>(items, nitems, single, total_chunks, err); break;
+        default: cdc_lane_kernel<4><<<(unsigned)grid, 256, 0, s>>>(items, nitems, single, total_chunks, err); break;
+        }
+        return hipGetLastError();
+    }
+    if (variant != 0 && variant != 1) return hipErrorInvalidValue;
+    if (blocks_per_wave < 1) return hipErrorInvalidValue;
     const uint64_t waves = (total_blocks + blocks_per_wave - 1) / blocks_per_wave;
     const uint64_t grid = (waves + waves_per_group - 1) / waves_per_group;
     if (grid > 0x7FFFFFFFull) return hipErrorInvalidValue;

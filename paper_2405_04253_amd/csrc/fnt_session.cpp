@@ -187,7 +187,7 @@ int build_tick(fnt_session *s, TickSlot &slot) {
     const uint32_t chunk = s->cfg.chunk_blocks;
     const uint32_t cap = s->cfg.max_active;
     int nitems = 0;
-    uint64_t block0 = 0;
+    uint64_t block0 = 0, chunk0 = 0;
     slot.finishing.clear();
     std::vector<uint32_t> served, waiting;
     served.reserve(s->rr.size());
@@ -230,7 +230,9 @@ int build_tick(fnt_session *s, TickSlot &slot) {
         ci.hist = st->cdc_tail;
         ci.a_out = slot.scratch + (uint64_t)nitems * chunk * 16 * 4;
         ci.block0 = block0;
+        ci.chunk0 = chunk0;
         block0 += nb;
+        chunk0 += cdc_chunks(ci.n);
         AeqItem &ai = slot.aeq_host[nitems];
         fill_aeq_item(ai, ci.a_out, nb * 16, st->taps, &ch.aeq, r.out + r.issued * 16 * 4);
         ai.hist_in = st->aeq_tail;
@@ -289,12 +291,15 @@ void scheduler_main(fnt_session *s) {
         if (e == hipSuccess)
             e = hipMemcpyAsync(slot.aeq_dev, slot.aeq_host, nitems * sizeof(AeqItem),
                                hipMemcpyHostToDevice, st);
-        uint64_t total_blocks = 0;
-        for (int k = 0; k < nitems; ++k) total_blocks += cdc_blocks(slot.cdc_host[k].n);
+        uint64_t total_blocks = 0, total_chunks = 0;
+        for (int k = 0; k < nitems; ++k) {
+            total_blocks += cdc_blocks(slot.cdc_host[k].n);
+            total_chunks += cdc_chunks(slot.cdc_host[k].n);
+        }
         if (e == hipSuccess) {
             int wpg, bpw;
             default_cdc_schedule(total_blocks, &wpg, &bpw);
-            e = launch_cdc(slot.cdc_dev, nitems, CdcItem{}, total_blocks, wpg, bpw, false, s->err, st);
+            e = run_cdc(slot.cdc_dev, nitems, CdcItem{}, total_blocks, total_chunks, wpg, bpw, false, s->err, st);
         }
         if (e == hipSuccess) e = launch_aeq(slot.aeq_dev, nitems, AeqItem{}, 0, nitems >= 512 ? 1 : 2, s->err, st);
         for (auto &c : d2h)

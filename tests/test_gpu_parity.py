@@ -114,6 +114,15 @@ def test_cdc_random_vs_oracle(torch_dev, n, L, shift, phase):
     z, a = fnt.fnt_cdc(to_dev(torch, dev, x), fnt.cdc_params(h, shift, phase))
     assert np.array_equal(z.cpu().numpy(), zr)
     assert np.array_equal(a.cpu().numpy(), ar)
+    # without the exact output: the lane-per-block kernel, 16-byte aligned input
+    # (vector loads) and an input 4 bytes off alignment (word loads)
+    note(f"fnt_cdc lane kernel n={n} L={L} shift={shift} phase={phase}")
+    _, a = fnt.fnt_cdc(to_dev(torch, dev, x), fnt.cdc_params(h, shift, phase), exact=False)
+    assert np.array_equal(a.cpu().numpy(), ar)
+    xb = torch.zeros((n + 1, 4), dtype=torch.int8, device=dev)
+    xb[1:] = to_dev(torch, dev, x)
+    _, a = fnt.fnt_cdc(xb[1:], fnt.cdc_params(h, shift, phase), exact=False)
+    assert np.array_equal(a.cpu().numpy(), ar)
     fnt.fnt_check()
 
 
@@ -128,6 +137,10 @@ def test_cdc_eq5_worst_case(torch_dev):
         z, a = fnt.fnt_cdc(to_dev(torch, dev, x), fnt.cdc_params(h, 11))
         assert np.array_equal(z.cpu().numpy(), zr)
         assert np.array_equal(a.cpu().numpy(), ar)
+        for ph in (0, 1):
+            _, ar2 = O.cdc(x, h, 0, ph)
+            _, a = fnt.fnt_cdc(to_dev(torch, dev, x), fnt.cdc_params(h, 0, ph), exact=False)
+            assert np.array_equal(a.cpu().numpy(), ar2)
     assert np.abs(zr).max() <= 32768
     fnt.fnt_check()
 
@@ -276,8 +289,8 @@ def test_plan_determinism_across_schedules(torch_dev):
     plan = fnt.Plan([(c["x"], c["out"], c["taps"], fnt.cdc_params(c["ch"].taps, c["ch"].requant_shift),
                       fnt.aeq_params(**c["prm"])) for c in pc], autotune=False, use_graph=True)
     ref = None
-    for wpg, bpw, wpp, variant in [(4, 1, 1, 0), (1, 1, 2, 0), (2, 3, 4, 0), (4, 64, 1, 0), (1, 7, 2, 0),
-                                   (2, 2, 1, 1), (4, 5, 1, 2)]:
+    for wpg, bpw, wpp, variant in [(4, 0, 1, 0), (4, 1, 1, 0), (1, 1, 2, 0), (2, 3, 4, 0), (4, 64, 1, 0),
+                                   (1, 7, 2, 0), (1, 0, 2, 0), (2, 0, 4, 0), (2, 2, 1, 1), (4, 5, 1, 2)]:
         plan.set_cdc_schedule(wpg, bpw)
         plan.set_aeq_waves(wpp)
         plan.set_aeq_variant(variant)
