@@ -197,6 +197,11 @@ def _time_events(torch, fn, reps, stream):
 
 def aeq_kernel_name(info) -> str:
     lpt = {1: 4, 2: 8, 4: 16}
+    if info["aeq_variant"] == 0 and info["aeq_waves_per_pol"] == 0:
+        k = "aeq_lane_kernel<1>"
+        if info["aeq_long_channels"]:
+            k = "aeq_pol_kernel<%d>+" % lpt[info["aeq_waves_long"]] + k
+        return k
     if info["aeq_variant"] == 1:
         return "aeq_direct_kernel"
     if info["aeq_variant"] == 2:

@@ -317,7 +317,7 @@ static int plan_launch_aeq(fnt_plan *p, hipStream_t s, hipStream_t side) {
     }
     e = hipEventRecord(p->fork, s);
     if (e == hipSuccess) e = hipStreamWaitEvent(side, p->fork, 0);
-    if (e == hipSuccess) e = launch_aeq(p->aeq_dev, nl, AeqItem{}, 0, p->wpp_long, p->err, s);
+    if (e == hipSuccess) e = launch_aeq(p->aeq_dev, nl, AeqItem{}, 0, p->wpp_long, p->err, s, true);
     if (e == hipSuccess) e = launch_aeq(p->aeq_dev + nl, n - nl, AeqItem{}, 0, p->wpp, p->err, side);
     if (e == hipSuccess) e = hipEventRecord(p->join, side);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, p->join, 0);
@@ -502,20 +502,22 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
             e = hipMemcpyAsync(tdev, tab.data(), nch * sizeof(AeqItem), hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e == hipSuccess) {
-            // split points: channels whose chain is at least 1/2, 1/4, ... of the longest
             std::vector<size_t> splits = {0};
             const uint64_t longest = (p->aeq_host[0].m + 15) / 16;
-            for (int d = 2; d <= 64; d *= 2) {
+            // split points: channels whose chain is at least 2/3, 1/2, 1/3, ... 1/64 of the longest
+            const int ratio[][2] = {{2, 3}, {1, 2}, {1, 3}, {1, 4}, {1, 6}, {1, 8}, {1, 12}, {1, 16}, {1, 32}, {1, 64}};
+            for (const auto &r : ratio) {
                 size_t k = 0;
-                while (k < nch && (p->aeq_host[k].m + 15) / 16 * d >= longest) ++k;
+                while (k < nch && (p->aeq_host[k].m + 15) / 16 * (uint64_t)r[1] >= longest * (uint64_t)r[0]) ++k;
                 if (k > 0 && k < nch && k != splits.back()) splits.push_back(k);
             }
             AeqItem *saved = p->aeq_dev;
             p->aeq_dev = tdev;
             for (size_t nl : splits)
-                for (int q : {1, 2, 4}) {
-                    const int ql = 4;                           // long chains: shortest latency
-                    if (nl > 0 && q == 4) continue;             // a split only pays with fewer waves
+                for (int ql : {1, 2, 4})                        // long chains: latency-leaning forms
+                for (int q : {0, 1, 2, 4}) {
+                    if (nl == 0 && ql != 4) continue;           // no split: one form for all
+                    if (nl > 0 && q >= ql) continue;            // a split only pays with cheaper forms for the rest
                     {
                         p->n_long = nl;
                         p->wpp_long = ql;
@@ -719,7 +721,7 @@ int fnt_plan_set_aeq_variant(fnt_plan *p, int variant) {
 
 int fnt_plan_set_aeq_waves(fnt_plan *p, int wpp) {
     if (!p) return fail(FNT_E_INVAL, "plan: NULL");
-    if (wpp != 1 && wpp != 2 && wpp != 4) return fail(FNT_E_INVAL, "plan: waves per half %d", wpp);
+    if (wpp != 0 && wpp != 1 && wpp != 2 && wpp != 4) return fail(FNT_E_INVAL, "plan: waves per half %d", wpp);
     p->wpp = wpp;
     p->n_long = 0;
     if (p->exec) return plan_capture(p, nullptr);
@@ -728,7 +730,8 @@ int fnt_plan_set_aeq_waves(fnt_plan *p, int wpp) {
 
 int fnt_plan_set_aeq_split(fnt_plan *p, uint64_t long_channels, int wpp_long, int wpp) {
     if (!p) return fail(FNT_E_INVAL, "plan: NULL");
-    if ((wpp_long != 1 && wpp_long != 2 && wpp_long != 4) || (wpp != 1 && wpp != 2 && wpp != 4))
+    if ((wpp_long != 0 && wpp_long != 1 && wpp_long != 2 && wpp_long != 4) ||
+        (wpp != 0 && wpp != 1 && wpp != 2 && wpp != 4))
         return fail(FNT_E_INVAL, "plan: waves per half %d / %d", wpp_long, wpp);
     p->n_long = (size_t)std::min<uint64_t>(long_channels, p->aeq_host.size());
     p->wpp_long = wpp_long;

@@ -213,9 +213,11 @@ __device__ __forceinline__ int32_t lift_loose(int32_t r) {
 // ds_swizzle inside 32-lane groups, else ds_bpermute).
 template <int X>
 __device__ __forceinline__ int32_t xor_lane(int32_t v) {
-    if constexpr (X == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
-    else if constexpr (X == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);  // quad_perm 2,3,0,1
-    else if constexpr (X == 8) return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false); // row_ror:8
+    // update_dpp with old = 0 and bound_ctrl: every lane has a partner here, and
+    // the form lets the compiler fold the move into the consuming add / sub
+    if constexpr (X == 1) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, true);   // quad_perm 1,0,3,2
+    else if constexpr (X == 2) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, true);  // quad_perm 2,3,0,1
+    else if constexpr (X == 8) return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, true); // row_ror:8
     else if constexpr (X == 4 || X == 16) return __builtin_amdgcn_ds_swizzle(v, (X << 10) | 0x1F);
     else return __shfl_xor(v, X);
 }
@@ -237,7 +239,7 @@ __device__ __forceinline__ int lane_pos(int l) {
 template <int X>
 __device__ __forceinline__ int32_t xor_pos(int32_t v) {
 #if FNT_DPP_LANE_ORDER
-    if constexpr (X == 4) return __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false);     // row_half_mirror
+    if constexpr (X == 4) return __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, true);  // row_half_mirror
 #endif
     return xor_lane<X>(v);
 }

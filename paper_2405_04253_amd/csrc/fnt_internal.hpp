@@ -70,6 +70,7 @@ hipError_t launch_cdc(const CdcItem *items, int nitems, const CdcItem &single,
 // variant 0: Fermat-domain AEQ split by output polarisation, waves_per_pol in
 // {1, 2, 4}; 1: direct time-domain comparator; 2: Fermat-domain, one wave per channel.
 hipError_t launch_aeq(const AeqItem *items, int nitems, const AeqItem &single, int variant,
-                      int waves_per_pol, int *err, hipStream_t s);
+                      int waves_per_pol, int *err, hipStream_t s,
+                      bool high_priority = false);
 
 }  // namespace fnti

@@ -337,7 +337,9 @@ __device__ __forceinline__ int32_t fold16(int32_t x) {
 }
 
 // x * 2^e for 1 <= e <= 14, any int32 x: fold, shift (stays below 2^31), fold.
-__device__ __forceinline__ int32_t mul_pow2(int32_t x, int e) { return fold16(fold16(x) << e); }
+// The shifted value passes through opq so the compiler keeps shift + one SDWA
+// subtract instead of rewriting the second fold into mask-and-shift pairs.
+__device__ __forceinline__ int32_t mul_pow2(int32_t x, int e) { return fold16(opq(fold16(x) << e)); }
 
 // (a - b) * alpha^E, E a compile-time exponent (alpha = sqrt 2, alpha^(2f) = 2^f,
 // 2^16 = -1).  Powers of two below 2^15 take mul_pow2 (any int32 a - b); the
@@ -435,7 +437,7 @@ __device__ __forceinline__ int32_t lift_z(int32_t r) {
     return f > 32768 ? f - 65537 : f;
 }
 
-// rs(z, s) then saturate to 5 bit, for |z| <= 2^16 and 0 <= s < 16.
+// rs(z, s) then saturate to 5 bit, for |z| <= 2^16 and 0 <= s <= 16.
 __device__ __forceinline__ int32_t requant5(int32_t z, int s) {
     const int32_t r = (z + ((1 << s) >> 1)) >> s;
     return r < -16 ? -16 : (r > 15 ? 15 : r);
@@ -1063,7 +1065,10 @@ __device__ __forceinline__ uint32_t aeq_sym(const AeqItem &it, int64_t i) {
 
 template <int LPT>
 __global__ __launch_bounds__(64 * (LPT / 4)) void aeq_pol_kernel(const AeqItem *items, AeqItem single,
-                                                                 int *err) {
+                                                                 int *err, int prio) {
+    // latency-critical chains (the longest of a batch) issue ahead of the
+    // throughput work that shares their SIMDs
+    if (prio) __builtin_amdgcn_s_setprio(3);
     constexpr int WPP = LPT / 4;                       // waves per polarisation half
     constexpr int PPL = 32 / LPT;                      // bins per lane
     constexpr int NT = 16 / LPT;                       // taps owned per lane (= PPL / 2)
@@ -1247,6 +1252,286 @@ __global__ __launch_bounds__(64 * (LPT / 4)) void aeq_pol_kernel(const AeqItem *
     finish();
 }
 
+// ------------------------------------------------------------------------
+// FNT-AEQ, one whole transform per lane (throughput form).
+//
+// A wave runs two channels, one per 32-lane slot.  Lane t of a slot owns the
+// tap filter f = t / 2 (S1 = f / 4, S2 = f % 4) and digit d = t % 2 (0: the
+// high 7-bit digit, 1: the low one): its 32-bin tap-digit spectrum W stays in
+// its registers and every transform it needs runs in its registers, with no
+// exchange between lanes inside a transform.  Per 16-symbol block:
+//   * the input spectra A_S1 come from LDS, computed eight blocks ahead, one
+//     transform per lane (stream S1 = t % 4, block t / 4 of the batch);
+//   * P = A_S1 W; lanes t and t ^ 8 (S1 = 2g, 2g + 1) sum their products (the
+//     Eq. (5) bound of the balanced digits holds for the pair), and the lanes
+//     with S1 even invert the sum (upper half of the 32-point inverse);
+//   * y_S2 = 2^7 (high-digit sums) + (low-digit sums): lanes t ^ 1 (digits) and
+//     t ^ 16 (pairs) add up, and the S2 lanes hand the 16 outputs over LDS to
+//     the output / error lanes (symbol t / 2, polarisation t % 2);
+//   * the RDE gradient of Eq. (6) for the lane's 8 taps by 4-byte dot products
+//     over the staged input bytes, the tap update, the other 8 taps from the
+//     digit partner t ^ 1, and the new digit spectrum.
+// ------------------------------------------------------------------------
+
+// (a - b) * 2^E for a compile-time E in [0, 16).
+template <int E>
+__device__ __forceinline__ int32_t tw2_diff(int32_t a, int32_t b) {
+    if constexpr (E == 0) return a - b;
+    else if constexpr (E < 15) return mul_pow2(a - b, E);
+    else return mulmod(a - b, opq(32768));
+}
+
+// 32-point DIF forward transform (radix 2) in registers, natural order in,
+// x[n] = bin bitrev5(n) out.  ZP: inputs 16..31 are zero.
+// In: |x| <= 2^17; out: |X| < 2^21.1.
+template <int H>
+__device__ __forceinline__ void fnt32_stage(int32_t (&x)[32]) {
+    sfor<16 / H>([&](auto gc) {
+        constexpr int g = decltype(gc)::value * 2 * H;
+        sfor<H>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            const int32_t a = x[g + j], b = x[g + j + H];
+            x[g + j] = a + b;
+            x[g + j + H] = tw2_diff<j * (16 / H)>(a, b);
+        });
+    });
+}
+template <bool ZP>
+__device__ __forceinline__ void fnt32_regs(int32_t (&x)[32]) {
+    if constexpr (ZP) {
+        sfor<16>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            x[j + 16] = tw2_diff<j>(x[j], 0);
+        });
+    } else {
+        fnt32_stage<16>(x);
+    }
+    fnt32_stage<8>(x);
+    fnt32_stage<4>(x);
+    fnt32_stage<2>(x);
+    fnt32_stage<1>(x);
+}
+
+template <int WPG>
+__global__ __launch_bounds__(64 * WPG) void aeq_lane_kernel(const AeqItem *items, int nitems,
+                                                            AeqItem single, int *err, int prio) {
+    if (prio) __builtin_amdgcn_s_setprio(3);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int slot = lane >> 5, t = lane & 31;
+    const int item = ((int)blockIdx.x * WPG + wv) * 2 + slot;
+    const bool has = items ? item < nitems : item == 0;
+    // LDS of this wave, by slot
+    __shared__ __align__(16) int32_t aspec_s[WPG][2][8][4][32];   // input spectra [block of batch][S1][bin]
+    __shared__ __align__(16) uint32_t abytes_s[WPG][2][4][40];    // staged input bytes [S1][160]
+    __shared__ __align__(16) int32_t ybuf_s[WPG][2][4][16];       // outputs y [S2][symbol]
+    __shared__ __align__(16) uint32_t eps_s[WPG][2][4][4];        // RDE errors, bytes [S2][symbol]
+    int32_t(*aspec)[4][32] = aspec_s[wv][slot];
+    uint32_t(*abytes)[40] = abytes_s[wv][slot];
+    int32_t(*ybuf)[16] = ybuf_s[wv][slot];
+    uint32_t(*epsw)[4] = eps_s[wv][slot];
+
+    const AeqItem *ip = items ? &items[has ? item : 0] : &single;
+    const uint64_t M = has ? ip->m : 0;
+    const int8_t *ain = ip->a;
+    const int8_t *hist_in = ip->hist_in;
+    int16_t *outp = ip->out;
+    int16_t *taps = ip->taps;
+    // rs(G, s) of a gradient |G| <= 32768 is 0 for every s >= 17, so a shift
+    // clamped to 20 gives the same result in 32-bit arithmetic
+    const int out_shift = ip->out_shift, err_shift = ip->err_shift;
+    const int mu_shift = ip->mu_shift < 20 ? ip->mu_shift : 20;
+    const int64_t c2 = (int64_t)ip->const_unit * ip->const_unit;
+    const bool upd = has && ip->update_enable != 0;
+    const uint32_t nb = (uint32_t)((M + 15) / 16);
+    const uint32_t nbw = max((uint32_t)__shfl((int)nb, 0), (uint32_t)__shfl((int)nb, 32));
+
+    // tap role
+    const int f = t >> 1, d = t & 1;
+    const int S1 = f >> 2, S2 = f & 3;
+    int32_t w[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        int32_t val = has ? taps[f * 16 + k] : 0;
+        if (val < -8192 || val > 8191) flag(err, RANGE_TAP);
+        w[k] = clamp32(val, -8192, 8191);
+    }
+    auto finish = [&]() {                              // the slot's channel is done
+        if (!has) return;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) taps[f * 16 + 8 * d + i] = (int16_t)(d ? w[8 + i] : w[i]);
+        if (ip->hist_out) {
+            uint32_t h = 0u;
+            if (t < 16) {
+                const int64_t i = (int64_t)M - 16 + t;
+                if (i >= 0) h = reinterpret_cast<const uint32_t *>(ain)[i];
+                else if (hist_in) h = reinterpret_cast<const uint32_t *>(hist_in)[16 + i];
+            }
+            if (t < 16) reinterpret_cast<uint32_t *>(ip->hist_out)[t] = h;
+        }
+        if (ip->cdc_tail) {
+            const int64_t j = (int64_t)ip->cdc_n - 32 + t;
+            const uint32_t tl = j >= 0 ? reinterpret_cast<const uint32_t *>(ip->cdc_in)[j]
+                                       : reinterpret_cast<const uint32_t *>(ip->cdc_tail)[32 + j];
+            reinterpret_cast<uint32_t *>(ip->cdc_tail)[t] = tl;
+        }
+    };
+    if (M == 0) finish();
+    if (nbw == 0) return;
+
+    // tap-digit spectrum of this lane, N^-1 = 32^-1 = -2048 folded in
+    int32_t W[32];
+    // digits w = 2^7 hi + lo, hi = (w + 64) >> 7 in [-64, 64], lo in [-64, 63]:
+    // digit d times -2048 is w A + hi B with A = 0, B = -2048 (d = 0) or
+    // A = -2048, B = 2^18 (d = 1), one 24-bit multiply-add per tap
+    const int32_t dA = d ? -2048 : 0, dB = d ? 262144 : -2048;
+    auto transform_taps = [&]() {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int32_t hi = (w[k] + 64) >> 7;
+            W[k] = sext24(w[k]) * dA + sext24(hi) * dB;      // |.| <= 2^17
+            W[k + 16] = 0;
+        }
+        fnt32_regs<true>(W);
+    };
+    transform_taps();
+    if (t < 4) abytes[t][36] = abytes[t][37] = abytes[t][38] = abytes[t][39] = 0u;
+    uint32_t bad = 0u;
+    const int om = t >> 1, opol = t & 1;                // output / error role
+
+    for (uint32_t b = 0; b < nbw; ++b) {
+        const int j = (int)(b & 7);
+        if (j == 0) {
+            // stage symbols 16 b - 16 .. 16 b + 127 of the four streams as bytes
+            wave_lds_sync();
+#pragma unroll
+            for (int r = 0; r < 5; ++r) {
+                const int p = t + 32 * r;
+                if (p < 144) {
+                    const int64_t i = 16 * (int64_t)b - 16 + p;
+                    uint32_t v = 0u;
+                    if (i < 0) {
+                        if (hist_in) v = reinterpret_cast<const uint32_t *>(hist_in)[16 + i];
+                    } else if ((uint64_t)i < M) {
+                        v = reinterpret_cast<const uint32_t *>(ain)[i];
+                        bad |= v ^ (v << 1);
+                    }
+                    uint8_t *ab = reinterpret_cast<uint8_t *>(&abytes[0][0]);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) ab[c * 160 + p] = (uint8_t)(v >> (8 * c));
+                }
+            }
+            wave_lds_sync();
+            {   // input spectra of the batch: stream t % 4, block t / 4
+                const int s1 = t & 3, jb = t >> 2;
+                const uint4 *src = reinterpret_cast<const uint4 *>(&abytes[s1][4 * jb]);
+                int32_t x[32];
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const uint4 v4 = src[q];
+                    const uint32_t vv[4] = {v4.x, v4.y, v4.z, v4.w};
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) x[16 * q + 4 * c + e] = sbyte(vv[c], e);
+                }
+                fnt32_regs<false>(x);
+                int4 *dst = reinterpret_cast<int4 *>(&aspec[jb][s1][0]);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) dst[q] = make_int4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
+            }
+            wave_lds_sync();
+        }
+        const bool live = b < nb;
+        // products, pair sums over S1 = 2g, 2g + 1, and the inverse
+        int32_t Y[32];
+        {
+            const int4 *A4 = reinterpret_cast<const int4 *>(&aspec[j][S1][0]);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int4 a4 = A4[q];
+                Y[4 * q] = mulmod(a4.x, W[4 * q]);
+                Y[4 * q + 1] = mulmod(a4.y, W[4 * q + 1]);
+                Y[4 * q + 2] = mulmod(a4.z, W[4 * q + 2]);
+                Y[4 * q + 3] = mulmod(a4.w, W[4 * q + 3]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 32; ++k) Y[k] += xor_lane<8>(Y[k]);   // |.| < 2^17.4
+        ifnt32_upper_regs(Y);
+        // y_S2 = 2^7 (hi sums) + (lo sums): digits from t ^ 1, pairs from t ^ 16
+        int32_t yv[16];
+        const int32_t dscale = d ? 1 : 128;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            int32_t v = sext24(lift_z(Y[16 + q])) * dscale;
+            v += xor_lane<1>(v);
+            v += xor_lane<16>(v);
+            yv[q] = v;                                  // |.| < 2^23.1
+        }
+        if (t < 8 && d == 0) {                          // lanes of g = 0, digit 0: S2 = t / 2
+            int4 *yd4 = reinterpret_cast<int4 *>(&ybuf[S2][0]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) yd4[q] = make_int4(yv[4 * q], yv[4 * q + 1], yv[4 * q + 2], yv[4 * q + 3]);
+        }
+        wave_lds_sync();
+        // outputs and RDE errors: symbol om, streams 2 opol (I), 2 opol + 1 (Q)
+        const int64_t m = 16 * (int64_t)b + om;
+        const bool valid = live && (uint64_t)m < M;
+        const int32_t yi = ybuf[2 * opol][om], yq = ybuf[2 * opol + 1][om];
+        const int32_t hi_ = clamp32((yi + ((1 << out_shift) >> 1)) >> out_shift, -32768, 32767);
+        const int32_t hq_ = clamp32((yq + ((1 << out_shift) >> 1)) >> out_shift, -32768, 32767);
+        if (valid)
+            reinterpret_cast<uint32_t *>(outp)[2 * m + opol] = ((uint32_t)hi_ & 0xFFFFu) | ((uint32_t)hq_ << 16);
+        if (__ballot(upd && live)) {
+            const int64_t r2 = (int64_t)hi_ * hi_ + (int64_t)hq_ * hq_;
+            const int64_t R2 = r2 < 6 * c2 ? 2 * c2 : (r2 < 14 * c2 ? 10 * c2 : 18 * c2);
+            int32_t ei = (int32_t)clamp64(rs64((R2 - r2) * hi_, err_shift), -128, 127);
+            int32_t eq = (int32_t)clamp64(rs64((R2 - r2) * hq_, err_shift), -128, 127);
+            if (!valid) ei = eq = 0;
+            uint8_t *eb = reinterpret_cast<uint8_t *>(&epsw[0][0]);
+            eb[(2 * opol) * 16 + om] = (uint8_t)ei;
+            eb[(2 * opol + 1) * 16 + om] = (uint8_t)eq;
+            wave_lds_sync();
+            // G[k] = sum_m eps_S2[m] a_S1[16 b + m - k] for k = 8 d + i (i < 8)
+            uint32_t e4[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) e4[q] = epsw[S2][q];
+            uint32_t dd[7];
+            const int q0 = 4 * j + 2 - 2 * d;            // byte 4 q0 = 16 j + 8 - 8 d
+#pragma unroll
+            for (int r = 0; r < 7; ++r) dd[r] = abytes[S1][q0 + r];
+            int32_t g[8];
+            sfor<8>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                constexpr int o = 8 - i;                    // a_S1[16 b - k] is byte o of dd
+                int32_t gs = 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    gs = __builtin_amdgcn_sdot4((int)e4[q],
+                                                (int)__builtin_amdgcn_alignbyte(dd[(o >> 2) + q + 1],
+                                                                                dd[(o >> 2) + q], o & 3),
+                                                gs, false);
+                g[i] = gs;                                  // |.| <= 32768
+            });
+            const bool step = upd && live;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int32_t mine = d ? w[8 + i] : w[i];
+                const int32_t nw = clamp32(mine + ((g[i] + ((1 << mu_shift) >> 1)) >> mu_shift), -8192, 8191);
+                const int32_t upd_w = step ? nw : mine;
+                const int32_t other = xor_lane<1>(upd_w);   // the digit partner's taps 8 (1 - d) + i
+                w[i] = d ? other : upd_w;
+                w[8 + i] = d ? upd_w : other;
+            }
+            transform_taps();
+            // the next block rewrites the error bytes: keep the reads above in front
+            wave_lds_sync();
+        }
+        if (live && b + 1 == nb) finish();
+    }
+    if ((bad & 0xE0E0E0E0u) != 0u) flag(err, RANGE_SYMBOL);
+}
+
 // Direct comparator: y by integer dot products in the time domain, same RDE.
 __global__ __launch_bounds__(64) void aeq_direct_kernel(const AeqItem *items, AeqItem single,
                                                         int *err) {
@@ -1410,16 +1695,19 @@ hipError_t launch_cdc(const CdcItem *items, int nitems, const CdcItem &single,
 }
 
 hipError_t launch_aeq(const AeqItem *items, int nitems, const AeqItem &single, int variant,
-                      int waves_per_pol, int *err, hipStream_t s) {
+                      int waves_per_pol, int *err, hipStream_t s, bool high_priority) {
+    const int prio = high_priority ? 1 : 0;
     const int n = items ? nitems : 1;
     if (n <= 0) return hipSuccess;
     if (variant == 0) {
-        if (waves_per_pol == 1)
-            aeq_pol_kernel<4><<<2 * n, 64, 0, s>>>(items, single, err);
+        if (waves_per_pol == 0)
+            aeq_lane_kernel<1><<<(n + 1) / 2, 64, 0, s>>>(items, n, single, err, prio);
+        else if (waves_per_pol == 1)
+            aeq_pol_kernel<4><<<2 * n, 64, 0, s>>>(items, single, err, prio);
         else if (waves_per_pol == 2)
-            aeq_pol_kernel<8><<<2 * n, 128, 0, s>>>(items, single, err);
+            aeq_pol_kernel<8><<<2 * n, 128, 0, s>>>(items, single, err, prio);
         else if (waves_per_pol == 4)
-            aeq_pol_kernel<16><<<2 * n, 256, 0, s>>>(items, single, err);
+            aeq_pol_kernel<16><<<2 * n, 256, 0, s>>>(items, single, err, prio);
         else
             return hipErrorInvalidValue;
     } else if (variant == 1) {

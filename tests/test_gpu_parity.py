@@ -250,7 +250,7 @@ def _plan_channels(torch, dev, chans, rng):
     return out
 
 
-@pytest.mark.parametrize("variant,wpp", [(0, 1), (0, 2), (0, 4), (1, 1), (2, 1)])
+@pytest.mark.parametrize("variant,wpp", [(0, 0), (0, 1), (0, 2), (0, 4), (1, 1), (2, 1)])
 def test_plan_batched_vs_oracle(torch_dev, variant, wpp):
     torch, dev = torch_dev
     chans = _batch(40, 6, 11, seed=variant)
@@ -281,6 +281,35 @@ def test_plan_batched_vs_oracle(torch_dev, variant, wpp):
     fnt.fnt_check()
 
 
+EXTREME_AEQ = [dict(out_shift=24, err_shift=62, mu_shift=40, const_unit=4096, update_enable=1),
+               dict(out_shift=0, err_shift=0, mu_shift=0, const_unit=1, update_enable=1),
+               dict(out_shift=3, err_shift=20, mu_shift=17, const_unit=700, update_enable=1),
+               dict(out_shift=9, err_shift=12, mu_shift=1, const_unit=33, update_enable=0)]
+
+
+@pytest.mark.parametrize("wpp", [0, 1])
+def test_plan_extreme_aeq_params(torch_dev, wpp):
+    """Shift and constant extremes (saturating taps and errors) on the batched kernels."""
+    torch, dev = torch_dev
+    chans = _batch(8, 6, 10, seed=77)
+    pc = _plan_channels(torch, dev, chans, None)
+    for i, c in enumerate(pc):
+        c["prm"] = EXTREME_AEQ[i % len(EXTREME_AEQ)]
+    plan = fnt.Plan([(c["x"], c["out"], c["taps"], fnt.cdc_params(c["ch"].taps, c["ch"].requant_shift),
+                      fnt.aeq_params(**c["prm"])) for c in pc], autotune=False, use_graph=False)
+    plan.set_aeq_waves(wpp)
+    note(f"plan extreme AEQ params wpp={wpp}")
+    plan.run()
+    torch.cuda.synchronize()
+    for c in pc:
+        outr, wr, _ = O.cdc_aeq(c["ch"].samples, c["ch"].taps, c["ch"].requant_shift, c["w0"],
+                                O.params(**c["prm"]))
+        assert np.array_equal(c["out"].cpu().numpy(), outr), c["prm"]
+        assert np.array_equal(c["taps"].cpu().numpy(), wr), c["prm"]
+    plan.close()
+    fnt.fnt_check()
+
+
 def test_plan_determinism_across_schedules(torch_dev):
     """Race check: identical outputs for every launch schedule and wave split."""
     torch, dev = torch_dev
@@ -290,7 +319,8 @@ def test_plan_determinism_across_schedules(torch_dev):
                       fnt.aeq_params(**c["prm"])) for c in pc], autotune=False, use_graph=True)
     ref = None
     for wpg, bpw, wpp, variant in [(4, 0, 1, 0), (4, 1, 1, 0), (1, 1, 2, 0), (2, 3, 4, 0), (4, 64, 1, 0),
-                                   (1, 7, 2, 0), (1, 0, 2, 0), (2, 0, 4, 0), (2, 2, 1, 1), (4, 5, 1, 2)]:
+                                   (1, 7, 2, 0), (1, 0, 2, 0), (2, 0, 4, 0), (4, 0, 0, 0), (2, 2, 1, 1),
+                                   (4, 5, 1, 2)]:
         plan.set_cdc_schedule(wpg, bpw)
         plan.set_aeq_waves(wpp)
         plan.set_aeq_variant(variant)
@@ -312,7 +342,7 @@ def test_plan_determinism_across_schedules(torch_dev):
                     assert np.array_equal(o, o2) and np.array_equal(w, w2)
     # longest chains in their own concurrent launch
     plan.set_aeq_variant(0)
-    for nl, wl, ws in [(5, 4, 1), (12, 2, 1), (1, 4, 2), (24, 4, 1)]:
+    for nl, wl, ws in [(5, 4, 1), (12, 2, 1), (1, 4, 2), (24, 4, 1), (3, 4, 0), (8, 2, 0), (23, 4, 0)]:
         plan.set_aeq_split(nl, wl, ws)
         for c in pc:
             c["taps"].copy_(to_dev(torch, dev, c["w0"]))
