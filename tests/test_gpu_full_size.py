@@ -1,0 +1,197 @@
+"""GPU parity at the full workload sizes, in the launch configurations the
+benchmark uses, checked on sampled channels that the oracle computes one by one.
+
+* 4096 channels, log-uniform 2^12..2^20 symbols per polarisation, fibre
+  U(10, 80) km, OSNR U(18, 26) dB: one autotuned plan, hipGraph replay and the
+  staged launches the benchmark times.
+* 16384 channels, log-uniform 2^14..2^22 symbols (about 2^34 instants in all):
+  one plan over ~100 GB of inputs' worth of channels.  Each channel is its own
+  slice (length and start) of one of 16 generated 2^22-symbol streams, with the
+  CD taps matched to that stream's fibre, so lengths, tap counts and sample
+  statistics are those of the workload while generation stays short.
+* Serving: 1024 persistent channels, Poisson arrivals at 20 k requests/s for
+  0.5 s, segments log-uniform 2^13..2^18 symbols; every sampled channel's
+  outputs equal the oracle's over its whole concatenated stream.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2405_04253_amd import fnt, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    fnt.lib()
+    fnt.fnt_check()
+    return torch, torch.device("cuda:0")
+
+
+def note(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def _check_channel(q, taps, shift, prm, out, w):
+    outr, wr, _ = O.cdc_aeq(q.cpu().numpy(), taps, shift, synth.centre_spike_taps(), O.params(**prm))
+    assert np.array_equal(out.cpu().numpy(), outr)
+    assert np.array_equal(w.cpu().numpy(), wr)
+
+
+def test_full_size_batched_4096(torch_dev):
+    torch, dev = torch_dev
+    t0 = time.perf_counter()
+    specs = synth.batched_specs(4096, 12, 20, tag="bench-batched")
+    chans = []
+    for k, sp in enumerate(specs):
+        chans.append(synth.gen_channel_torch(sp.nsym, sp.fibre_km, sp.osnr_db, sp.seed, dev))
+        if k % 1024 == 0:
+            torch.cuda.synchronize()
+            note(f"4096-channel batch: generated {k} ({time.perf_counter() - t0:.1f} s)")
+    w0 = torch.from_numpy(synth.centre_spike_taps()).to(dev)
+    taps_all = w0.unsqueeze(0).repeat(len(chans), 1, 1, 1).contiguous()
+    prms, entries = [], []
+    for i, (q, taps, sh, unit) in enumerate(chans):
+        prm = dict(synth.AEQ_DEFAULTS, const_unit=unit)
+        prms.append(prm)
+        out = torch.full((q.shape[0] // 2, 4), -1, dtype=torch.int16, device=dev)
+        entries.append((q, out, taps_all[i], fnt.cdc_params(taps, sh), fnt.aeq_params(**prm)))
+    note("4096-channel batch: plan with autotuning")
+    plan = fnt.Plan(entries, autotune=True, use_graph=True)
+    note(f"4096-channel batch: {plan.info()}")
+    # the benchmark's timed form: the two stages launched directly
+    plan.run_stage(fnt.FNT_STAGE_CDC)
+    plan.run_stage(fnt.FNT_STAGE_AEQ)
+    torch.cuda.synchronize()
+    fnt.fnt_check()
+    staged = [e[1].clone() for e in entries]
+    staged_taps = taps_all.clone()
+    # the captured graph from the same initial taps gives the same results
+    taps_all.copy_(w0.unsqueeze(0).expand_as(taps_all))
+    note("4096-channel batch: graph replay")
+    plan.run()
+    torch.cuda.synchronize()
+    fnt.fnt_check()
+    assert torch.equal(taps_all, staged_taps)
+    assert all(torch.equal(e[1], s) for e, s in zip(entries, staged))
+    order = sorted(range(len(chans)), key=lambda i: chans[i][0].shape[0])
+    rng = np.random.default_rng(3)
+    pick = sorted(set([order[0], order[1], order[len(order) // 2], order[-2], order[-1]] +
+                      [int(i) for i in rng.choice(len(chans), 4, replace=False)]))
+    for i in pick:
+        note(f"4096-channel batch: oracle on channel {i} ({chans[i][0].shape[0]} instants)")
+        q, taps, sh, _ = chans[i]
+        _check_channel(q, taps, sh, prms[i], entries[i][1], taps_all[i])
+    plan.close()
+
+
+def test_full_size_large_batch_16384(torch_dev):
+    torch, dev = torch_dev
+    t0 = time.perf_counter()
+    rng = np.random.default_rng(2024)
+    nbase = 16
+    bases = []
+    for b in range(nbase):
+        km, osnr = float(rng.uniform(10, 80)), float(rng.uniform(18, 26))
+        bases.append(synth.gen_channel_torch(1 << 22, km, osnr, synth.seed_for(0, "large-base", b), dev))
+    torch.cuda.synchronize()
+    note(f"16384-channel batch: {nbase} base streams in {time.perf_counter() - t0:.1f} s")
+    specs = synth.batched_specs(16384, 14, 22, tag="large")
+    w0 = torch.from_numpy(synth.centre_spike_taps()).to(dev)
+    taps_all = w0.unsqueeze(0).repeat(len(specs), 1, 1, 1).contiguous()
+    chans, entries, prms = [], [], []
+    total = 0
+    for i, sp in enumerate(specs):
+        q0, taps, sh, unit = bases[i % nbase]
+        n = 2 * sp.nsym
+        start = 32 * int(rng.integers(0, (q0.shape[0] - n) // 32 + 1))
+        q = q0[start:start + n]
+        prm = dict(synth.AEQ_DEFAULTS, const_unit=unit)
+        out = torch.empty((sp.nsym, 4), dtype=torch.int16, device=dev)
+        chans.append((q, taps, sh))
+        prms.append(prm)
+        entries.append((q, out, taps_all[i], fnt.cdc_params(taps, sh), fnt.aeq_params(**prm)))
+        total += n
+    note(f"16384-channel batch: {total} instants ({total / 2 ** 34:.2f} x 2^34), outputs allocated")
+    plan = fnt.Plan(entries, autotune=False, use_graph=False)
+    info = plan.info()
+    assert info["instants"] == total and info["channels"] == len(specs)
+    plan.set_aeq_split(len(specs) // 8, 1, 0)      # the longest eighth on the latency-leaning kernel
+    note("16384-channel batch: run")
+    t1 = time.perf_counter()
+    plan.run()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    fnt.fnt_check()
+    note(f"16384-channel batch: {dt:.2f} s, {total / dt / 1e9:.2f} Gsamples/s")
+    order = sorted(range(len(specs)), key=lambda i: specs[i].nsym)
+    pick = sorted(set([order[0], order[len(order) // 2], order[-1]] +
+                      [int(i) for i in rng.choice(len(specs), 3, replace=False)]))
+    for i in pick:
+        note(f"16384-channel batch: oracle on channel {i} ({chans[i][0].shape[0]} instants)")
+        q, taps, sh = chans[i]
+        _check_channel(q, taps, sh, prms[i], entries[i][1], taps_all[i])
+    plan.close()
+
+
+def test_full_size_served_1024(torch_dev):
+    torch, dev = torch_dev
+    rng = np.random.default_rng(12345)
+    nch, rate, window = 1024, 20000.0, 0.5
+    times, t = [], 0.0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t > window:
+            break
+        times.append(t)
+    seg = [16 * max(1, int(2 ** rng.uniform(13, 18)) // 16) for _ in times]
+    owner = rng.integers(0, nch, size=len(times))
+    per = np.zeros(nch, np.int64)
+    for i, c in enumerate(owner):
+        per[c] += seg[i]
+    t0 = time.perf_counter()
+    streams, params = {}, {}
+    sess = fnt.Session(max_channels=nch, hbm_budget_bytes=1 << 30, chunk_blocks=64, max_active=nch)
+    for c in range(nch):
+        r = np.random.default_rng(synth.seed_for(0, "served", c))
+        km, osnr = float(r.uniform(10, 80)), float(r.uniform(18, 26))
+        q, taps, sh, unit = synth.gen_channel_torch(max(int(per[c]), 16), km, osnr,
+                                                    synth.seed_for(1, "served", c), dev)
+        streams[c] = q
+        prm = dict(synth.AEQ_DEFAULTS, const_unit=unit)
+        params[c] = (taps, sh, prm)
+        sess.add_channel(c, fnt.cdc_params(taps, sh), fnt.aeq_params(**prm))
+        if c % 256 == 0:
+            torch.cuda.synchronize()
+            note(f"served: generated {c} streams ({time.perf_counter() - t0:.1f} s)")
+    outs = {c: torch.full((streams[c].shape[0] // 2, 4), -1, dtype=torch.int16, device=dev) for c in range(nch)}
+    reqs, offs = [], [0] * nch
+    for i in range(len(times)):
+        c = int(owner[i])
+        n = 2 * seg[i]
+        o = offs[c]
+        reqs.append((c, streams[c][o:o + n], outs[c][o // 2:(o + n) // 2], int(times[i] * 1e9)))
+        offs[c] += n
+    torch.cuda.synchronize()
+    note(f"served: replaying {len(reqs)} requests")
+    sess.replay(reqs)
+    sess.drain()
+    st = sess.stats()
+    sess.close()
+    fnt.fnt_check()
+    assert st["completed"] == len(reqs)
+    note(f"served: {st['gsamples_per_s']:.2f} Gsamples/s, p50 {st['p50_us']:.0f} us, p99 {st['p99_us']:.0f} us")
+    busiest = sorted(range(nch), key=lambda c: -offs[c])
+    pick = sorted(set(busiest[:2] + [int(c) for c in rng.choice(nch, 4, replace=False) if offs[int(c)] > 0]))
+    for c in pick:
+        taps, sh, prm = params[c]
+        n = offs[c]
+        note(f"served: oracle on channel {c} ({n} instants)")
+        outr, _, _ = O.cdc_aeq(streams[c][:n].cpu().numpy(), taps, sh, synth.centre_spike_taps(), O.params(**prm))
+        assert np.array_equal(outs[c][: n // 2].cpu().numpy(), outr)
