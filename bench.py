@@ -197,10 +197,15 @@ def _time_events(torch, fn, reps, stream):
 
 def aeq_kernel_name(info) -> str:
     lpt = {1: 4, 2: 8, 4: 16}
-    if info["aeq_variant"] == 0 and info["aeq_waves_per_pol"] == 0:
-        k = "aeq_lane_kernel<1>"
+    form = {0: "aeq_lane_kernel<1>", 3: "aeq_duo_kernel<1>", 1: "aeq_pol_kernel<4>", 2: "aeq_pol_kernel<8>",
+            4: "aeq_pol_kernel<16>"}
+    if info["aeq_variant"] == 0:
+        wl, ws = info["aeq_waves_long"], info["aeq_waves_per_pol"]
+        if info["aeq_long_channels"] and (wl, ws) in ((1, 0), (1, 3), (3, 0)):
+            return "aeq_split_kernel<%d, %d>" % (wl, ws)     # one launch, long chains first
+        k = form[ws]
         if info["aeq_long_channels"]:
-            k = "aeq_pol_kernel<%d>+" % lpt[info["aeq_waves_long"]] + k
+            k = form[wl] + "+" + k
         return k
     if info["aeq_variant"] == 1:
         return "aeq_direct_kernel"

@@ -183,10 +183,9 @@ typedef struct fnt_plan_info {
     int32_t cdc_blocks_per_wave;  /* 0 = one block per lane (64 blocks per wave) */
     int32_t aeq_variant;   /* 0 = Fermat-domain filtering (the method), 1 = direct comparator,
                               2 = Fermat-domain, one wave per channel */
-    int32_t aeq_waves_per_pol;  /* variant 0: waves per polarisation half (1, 2 or 4), or 0:
-                                   one transform per lane, two channels per wave */
+    int32_t aeq_waves_per_pol;  /* variant 0: AEQ form (0, 3, 1, 2, 4; see fnt_plan_set_aeq_waves) */
     int32_t graph;         /* 1 if a hipGraph is replayed */
-    int32_t aeq_waves_long;     /* waves per half for the long chains (see fnt_plan_set_aeq_split) */
+    int32_t aeq_waves_long;     /* AEQ form of the long chains (see fnt_plan_set_aeq_split) */
     double tune_ms;        /* AEQ time of the chosen schedule during autotune, ms (0 if none) */
     uint64_t aeq_long_channels; /* longest channels run in their own concurrent launch */
 } fnt_plan_info;
@@ -222,11 +221,13 @@ int fnt_plan_destroy(fnt_plan *plan);
  * bit-identical results and no Fermat-domain arithmetic, 2 = Fermat-domain
  * filtering with one wave per channel. */
 int fnt_plan_set_aeq_variant(fnt_plan *plan, int variant);
-/* Waves per polarisation half for AEQ variant 0: 1, 2 or 4 (more waves shorten
- * each channel's serial chain; fewer use the chip more efficiently when there
- * are many channels), or 0: every lane runs whole transforms in its registers,
- * 32 lanes per channel, two channels per wave (the fewest instructions per
- * block, the longest chain latency).  Overrides the default / autotuned choice. */
+/* Form of AEQ variant 0 (the Fermat-domain method), from the fewest
+ * instructions per block to the shortest serial latency per block:
+ *   0: every lane runs whole transforms in its registers, 32 lanes per channel,
+ *      two channels per wave;
+ *   3: two lanes per transform, one channel per wave;
+ *   1, 2, 4: split by output polarisation, that many waves per half.
+ * Overrides the default / autotuned choice. */
 int fnt_plan_set_aeq_waves(fnt_plan *plan, int waves_per_pol);
 /* Split the AEQ of a plan: the `long_channels` channels with the longest chains
  * run with `wpp_long` waves per polarisation half (short serial latency) in a

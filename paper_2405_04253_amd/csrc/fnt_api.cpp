@@ -315,6 +315,11 @@ static int plan_launch_aeq(fnt_plan *p, hipStream_t s, hipStream_t side) {
         if (e != hipSuccess) return hip_fail(e, "plan: aeq launch");
         return FNT_OK;
     }
+    if (aeq_split_fusable(p->wpp_long, p->wpp)) {      // one launch, long chains dispatched first
+        e = launch_aeq_split(p->aeq_dev, nl, n, p->wpp_long, p->wpp, p->err, s);
+        if (e != hipSuccess) return hip_fail(e, "plan: aeq split launch");
+        return FNT_OK;
+    }
     e = hipEventRecord(p->fork, s);
     if (e == hipSuccess) e = hipStreamWaitEvent(side, p->fork, 0);
     if (e == hipSuccess) e = launch_aeq(p->aeq_dev, nl, AeqItem{}, 0, p->wpp_long, p->err, s, true);
@@ -436,7 +441,13 @@ static void tune_cache_store(const char *path, const std::string &key, int wpg, 
 
 // Default AEQ schedule: with few channels the chip is idle, so spread each
 // polarisation half over more waves to shorten the serial chain.
-static int default_wpp(size_t nch) { return nch >= 512 ? 1 : (nch >= 128 ? 2 : 4); }
+// AEQ forms of a plan (the `waves per half` value): 0 = one transform per lane
+// (two channels per wave), 3 = two lanes per transform (one channel per wave),
+// 1 / 2 / 4 = split by output polarisation with that many waves per half.
+// Cost per block rises, and the serial latency per block falls, in this order.
+static bool valid_form(int f) { return f == 0 || f == 1 || f == 2 || f == 3 || f == 4; }
+static int form_rank(int f) { return f == 0 ? 0 : f == 3 ? 1 : f == 1 ? 2 : f == 2 ? 3 : 4; }
+static int default_wpp(size_t nch) { return nch >= 512 ? 3 : (nch >= 128 ? 2 : 4); }
 
 static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
     std::string key = tune_key(p);
@@ -514,10 +525,10 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
             AeqItem *saved = p->aeq_dev;
             p->aeq_dev = tdev;
             for (size_t nl : splits)
-                for (int ql : {1, 2, 4})                        // long chains: latency-leaning forms
-                for (int q : {0, 1, 2, 4}) {
+                for (int ql : {3, 1, 2, 4})                     // long chains: latency-leaning forms
+                for (int q : {0, 3, 1, 2, 4}) {
                     if (nl == 0 && ql != 4) continue;           // no split: one form for all
-                    if (nl > 0 && q >= ql) continue;            // a split only pays with cheaper forms for the rest
+                    if (nl > 0 && form_rank(q) >= form_rank(ql)) continue;  // cheaper form for the rest
                     {
                         p->n_long = nl;
                         p->wpp_long = ql;
@@ -721,7 +732,7 @@ int fnt_plan_set_aeq_variant(fnt_plan *p, int variant) {
 
 int fnt_plan_set_aeq_waves(fnt_plan *p, int wpp) {
     if (!p) return fail(FNT_E_INVAL, "plan: NULL");
-    if (wpp != 0 && wpp != 1 && wpp != 2 && wpp != 4) return fail(FNT_E_INVAL, "plan: waves per half %d", wpp);
+    if (!valid_form(wpp)) return fail(FNT_E_INVAL, "plan: AEQ form %d", wpp);
     p->wpp = wpp;
     p->n_long = 0;
     if (p->exec) return plan_capture(p, nullptr);
@@ -730,8 +741,7 @@ int fnt_plan_set_aeq_waves(fnt_plan *p, int wpp) {
 
 int fnt_plan_set_aeq_split(fnt_plan *p, uint64_t long_channels, int wpp_long, int wpp) {
     if (!p) return fail(FNT_E_INVAL, "plan: NULL");
-    if ((wpp_long != 0 && wpp_long != 1 && wpp_long != 2 && wpp_long != 4) ||
-        (wpp != 0 && wpp != 1 && wpp != 2 && wpp != 4))
+    if (!valid_form(wpp_long) || !valid_form(wpp))
         return fail(FNT_E_INVAL, "plan: waves per half %d / %d", wpp_long, wpp);
     p->n_long = (size_t)std::min<uint64_t>(long_channels, p->aeq_host.size());
     p->wpp_long = wpp_long;

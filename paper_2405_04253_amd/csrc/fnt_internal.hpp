@@ -67,6 +67,12 @@ hipError_t launch_cdc(const CdcItem *items, int nitems, const CdcItem &single,
                       uint64_t total_blocks, uint64_t total_chunks, int variant,
                       int waves_per_group, int blocks_per_wave, bool with_z, int *err,
                       hipStream_t s);
+// One launch for the split of a longest-first table: items [0, nlong) in form
+// form_long at raised wave priority (dispatched first), the rest in form_rest.
+// Fusable pairs (one-wave workgroups): (1, 0), (1, 3), (3, 0).
+hipError_t launch_aeq_split(const AeqItem *items, int nlong, int nitems, int form_long, int form_rest,
+                           int *err, hipStream_t s);
+bool aeq_split_fusable(int form_long, int form_rest);
 // variant 0: Fermat-domain AEQ split by output polarisation, waves_per_pol in
 // {1, 2, 4}; 1: direct time-domain comparator; 2: Fermat-domain, one wave per channel.
 hipError_t launch_aeq(const AeqItem *items, int nitems, const AeqItem &single, int variant,

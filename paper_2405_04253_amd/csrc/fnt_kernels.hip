@@ -1064,16 +1064,16 @@ __device__ __forceinline__ uint32_t aeq_sym(const AeqItem &it, int64_t i) {
 }
 
 template <int LPT>
-__global__ __launch_bounds__(64 * (LPT / 4)) void aeq_pol_kernel(const AeqItem *items, AeqItem single,
-                                                                 int *err, int prio) {
+__device__ __forceinline__ void aeq_pol_body(const AeqItem *items, const AeqItem &single, int *err,
+                                             int prio, unsigned bid) {
     // latency-critical chains (the longest of a batch) issue ahead of the
     // throughput work that shares their SIMDs
     if (prio) __builtin_amdgcn_s_setprio(3);
     constexpr int WPP = LPT / 4;                       // waves per polarisation half
     constexpr int PPL = 32 / LPT;                      // bins per lane
     constexpr int NT = 16 / LPT;                       // taps owned per lane (= PPL / 2)
-    const AeqItem it = items ? items[blockIdx.x >> 1] : single;
-    const int pol = blockIdx.x & 1;
+    const AeqItem it = items ? items[bid >> 1] : single;
+    const int pol = bid & 1;
     const int tid = threadIdx.x;
     const int v = tid >> 6, lane = tid & 63;
     const int pos = lane & 31;
@@ -1252,6 +1252,12 @@ __global__ __launch_bounds__(64 * (LPT / 4)) void aeq_pol_kernel(const AeqItem *
     finish();
 }
 
+template <int LPT>
+__global__ __launch_bounds__(64 * (LPT / 4)) void aeq_pol_kernel(const AeqItem *items, AeqItem single,
+                                                                 int *err, int prio) {
+    aeq_pol_body<LPT>(items, single, err, prio, blockIdx.x);
+}
+
 // ------------------------------------------------------------------------
 // FNT-AEQ, one whole transform per lane (throughput form).
 //
@@ -1313,12 +1319,12 @@ __device__ __forceinline__ void fnt32_regs(int32_t (&x)[32]) {
 }
 
 template <int WPG>
-__global__ __launch_bounds__(64 * WPG) void aeq_lane_kernel(const AeqItem *items, int nitems,
-                                                            AeqItem single, int *err, int prio) {
+__device__ __forceinline__ void aeq_lane_body(const AeqItem *items, int nitems, const AeqItem &single,
+                                              int *err, int prio, unsigned bid) {
     if (prio) __builtin_amdgcn_s_setprio(3);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int slot = lane >> 5, t = lane & 31;
-    const int item = ((int)blockIdx.x * WPG + wv) * 2 + slot;
+    const int item = ((int)bid * WPG + wv) * 2 + slot;
     const bool has = items ? item < nitems : item == 0;
     // LDS of this wave, by slot
     __shared__ __align__(16) int32_t aspec_s[WPG][2][8][4][32];   // input spectra [block of batch][S1][bin]
@@ -1516,7 +1522,7 @@ __global__ __launch_bounds__(64 * WPG) void aeq_lane_kernel(const AeqItem *items
             const bool step = upd && live;
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                const int32_t mine = d ? w[8 + i] : w[i];
+                const int32_t mine = d ? opq(w[8 + i]) : opq(w[i]);
                 const int32_t nw = clamp32(mine + ((g[i] + ((1 << mu_shift) >> 1)) >> mu_shift), -8192, 8191);
                 const int32_t upd_w = step ? nw : mine;
                 const int32_t other = xor_lane<1>(upd_w);   // the digit partner's taps 8 (1 - d) + i
@@ -1530,6 +1536,329 @@ __global__ __launch_bounds__(64 * WPG) void aeq_lane_kernel(const AeqItem *items
         if (live && b + 1 == nb) finish();
     }
     if ((bad & 0xE0E0E0E0u) != 0u) flag(err, RANGE_SYMBOL);
+}
+
+template <int WPG>
+__global__ __launch_bounds__(64 * WPG) void aeq_lane_kernel(const AeqItem *items, int nitems,
+                                                            AeqItem single, int *err, int prio) {
+    aeq_lane_body<WPG>(items, nitems, single, err, prio, blockIdx.x);
+}
+
+// ------------------------------------------------------------------------
+// FNT-AEQ, one channel per wave, two lanes per transform (latency + throughput).
+//
+// Lane L plays role L: bit 0 = half h of the 32 bins (positions 16 h + j, j < 16,
+// in registers), bit 1 = digit d, bit 2 = g and bit 3 = s of S1 = 2 g + s,
+// bits 4-5 = S2.  Only the first stage of the forward transform and the last
+// stage of the inverse cross the two halves; both lanes of a transform hold all
+// 16 taps, so the forward one needs no exchange at all (the upper half is the
+// zero-padded half: its first-stage value is digit * 2^j).  Partners: pair sum
+// over s (lanes L ^ 8, DPP row_ror:8), digit sum (L ^ 2, quad_perm), group sum
+// over g (L ^ 4, swizzle), inverse halves (L ^ 1, quad_perm); the four lanes of
+// a filter (L ^ 0..3) share its taps by quad broadcasts.
+// ------------------------------------------------------------------------
+
+// Radix-2 stages of the 32-point forward (DIF) / inverse (DIT) transforms on
+// N consecutive positions held in registers (N = 16: one half).
+template <int H, int N>
+__device__ __forceinline__ void fwd_stage_n(int32_t (&x)[N]) {
+    sfor<N / (2 * H)>([&](auto gc) {
+        constexpr int g = decltype(gc)::value * 2 * H;
+        sfor<H>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            const int32_t a = x[g + j], b = x[g + j + H];
+            x[g + j] = a + b;
+            x[g + j + H] = tw2_diff<j * (16 / H)>(a, b);
+        });
+    });
+}
+template <int H, int N>
+__device__ __forceinline__ void inv_stage_n(int32_t (&y)[N]) {
+    sfor<N / (2 * H)>([&](auto gc) {
+        constexpr int g = decltype(gc)::value * 2 * H;
+        sfor<H>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            int32_t lo, hi;
+            inv_bfly<j * (16 / H)>(y[g + j], y[g + j + H], lo, hi);
+            y[g + j] = lo;
+            y[g + j + H] = hi;
+        });
+    });
+}
+
+// -b 2^-E (mod 65537) for a compile-time E in [0, 16): 2^-E = -2^(16 - E).
+template <int E>
+__device__ __forceinline__ int32_t neg_inv_tw(int32_t b) {
+    if constexpr (E == 0) return -b;
+    else if constexpr (E == 1) return mulmod(b, opq(32768));
+    else return mul_pow2(b, 16 - E);
+}
+
+// Value of lane (L & ~3) | Q of the lane's quad.
+template <int Q>
+__device__ __forceinline__ int32_t quad_bcast(int32_t v) {
+    return __builtin_amdgcn_update_dpp(0, v, Q * 0x55, 0xF, 0xF, true);
+}
+
+template <int WPG>
+__device__ __forceinline__ void aeq_duo_body(const AeqItem *items, int nitems, const AeqItem &single,
+                                             int *err, int prio, unsigned bid) {
+    if (prio) __builtin_amdgcn_s_setprio(3);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int item = (int)bid * WPG + wv;
+    if (items ? item >= nitems : item != 0) return;
+    const AeqItem *ip = items ? &items[item] : &single;
+    const int hh = lane & 1, d = (lane >> 1) & 1, gs = (lane >> 2) & 1, ss = (lane >> 3) & 1;
+    const int S1 = 2 * gs + ss, S2 = lane >> 4;
+    const int f = S1 * 4 + S2, qd = lane & 3;           // filter, position in the filter's quad
+    __shared__ __align__(16) int32_t aspec_s[WPG][16][4][32];   // input spectra of 16 blocks
+    __shared__ __align__(16) uint32_t abytes_s[WPG][4][72];     // staged input bytes [S1][288]
+    __shared__ __align__(16) int32_t ybuf_s[WPG][4][16];        // outputs y [S2][symbol]
+    __shared__ __align__(16) uint32_t eps_s[WPG][4][4];         // RDE errors, bytes [S2][symbol]
+    int32_t(*aspec)[4][32] = aspec_s[wv];
+    uint32_t(*abytes)[72] = abytes_s[wv];
+    int32_t(*ybuf)[16] = ybuf_s[wv];
+    uint32_t(*epsw)[4] = eps_s[wv];
+
+    const uint64_t M = ip->m;
+    const int8_t *ain = ip->a;
+    const int8_t *hist_in = ip->hist_in;
+    int16_t *outp = ip->out;
+    int16_t *taps = ip->taps;
+    const int out_shift = ip->out_shift, err_shift = ip->err_shift;
+    const int mu_shift = ip->mu_shift < 20 ? ip->mu_shift : 20;   // rs of |G| <= 2^15 is 0 from 17 on
+    const int64_t c2 = (int64_t)ip->const_unit * ip->const_unit;
+    const bool upd = ip->update_enable != 0;
+    const uint32_t nb = (uint32_t)((M + 15) / 16);
+
+    int32_t w[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int32_t val = taps[f * 16 + k];
+        if (val < -8192 || val > 8191) flag(err, RANGE_TAP);
+        w[k] = clamp32(val, -8192, 8191);
+    }
+    auto finish = [&]() {
+        if (qd == 0) {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) taps[f * 16 + k] = (int16_t)w[k];
+        }
+        if (ip->hist_out) {
+            uint32_t h = 0u;
+            if (lane < 16) {
+                const int64_t i = (int64_t)M - 16 + lane;
+                if (i >= 0) h = reinterpret_cast<const uint32_t *>(ain)[i];
+                else if (hist_in) h = reinterpret_cast<const uint32_t *>(hist_in)[16 + i];
+            }
+            if (lane < 16) reinterpret_cast<uint32_t *>(ip->hist_out)[lane] = h;
+        }
+        if (ip->cdc_tail) {
+            uint32_t tl = 0u;
+            if (lane < 32) {
+                const int64_t j = (int64_t)ip->cdc_n - 32 + lane;
+                tl = j >= 0 ? reinterpret_cast<const uint32_t *>(ip->cdc_in)[j]
+                            : reinterpret_cast<const uint32_t *>(ip->cdc_tail)[32 + j];
+            }
+            if (lane < 32) reinterpret_cast<uint32_t *>(ip->cdc_tail)[lane] = tl;
+        }
+    };
+    if (nb == 0) {
+        finish();
+        return;
+    }
+
+    // half hh of the digit-d spectrum (N^-1 = -2048 folded in): digit * -2048 =
+    // w A + hi B with hi = (w + 64) >> 7; the upper half's first stage is
+    // digit * 2^j (its own inputs are the zero padding)
+    const int32_t dA = d ? -2048 : 0, dB = d ? 262144 : -2048;
+    int32_t W[16];
+    auto transform_taps = [&]() {
+        sfor<16>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            const int32_t hi = (w[k] + 64) >> 7;
+            const int32_t v = sext24(w[k]) * dA + sext24(hi) * dB;   // |.| <= 2^17
+            W[k] = hh ? tw2_diff<k>(v, 0) : v;
+        });
+        fwd_stage_n<8, 16>(W);
+        fwd_stage_n<4, 16>(W);
+        fwd_stage_n<2, 16>(W);
+        fwd_stage_n<1, 16>(W);
+    };
+    transform_taps();
+    if (lane < 16) abytes[lane >> 2][68 + (lane & 3)] = 0u;
+    uint32_t bad = 0u;
+    const int om = (lane >> 1) & 15, opol = lane & 1;   // output / error role (lanes < 32)
+    const int32_t dscale = d ? 1 : 128;
+
+    for (uint32_t b = 0; b < nb; ++b) {
+        const int j = (int)(b & 15);
+        if (j == 0) {
+            // stage symbols 16 b - 16 .. 16 b + 255 of the four streams as bytes
+            wave_lds_sync();
+#pragma unroll
+            for (int r = 0; r < 5; ++r) {
+                const int p = lane + 64 * r;
+                if (p < 272) {
+                    const int64_t i = 16 * (int64_t)b - 16 + p;
+                    uint32_t v = 0u;
+                    if (i < 0) {
+                        if (hist_in) v = reinterpret_cast<const uint32_t *>(hist_in)[16 + i];
+                    } else if ((uint64_t)i < M) {
+                        v = reinterpret_cast<const uint32_t *>(ain)[i];
+                        bad |= v ^ (v << 1);
+                    }
+                    uint8_t *ab = reinterpret_cast<uint8_t *>(&abytes[0][0]);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) ab[c * 288 + p] = (uint8_t)(v >> (8 * c));
+                }
+            }
+            wave_lds_sync();
+            {   // input spectra of the batch: stream lane % 4, block lane / 4
+                const int s1 = lane & 3, jb = lane >> 2;
+                const uint4 *src = reinterpret_cast<const uint4 *>(&abytes[s1][4 * jb]);
+                int32_t x[32];
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const uint4 v4 = src[q];
+                    const uint32_t vv[4] = {v4.x, v4.y, v4.z, v4.w};
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) x[16 * q + 4 * c + e] = sbyte(vv[c], e);
+                }
+                fnt32_regs<false>(x);
+                int4 *dst = reinterpret_cast<int4 *>(&aspec[jb][s1][0]);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) dst[q] = make_int4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
+            }
+            wave_lds_sync();
+        }
+        // products on this half, pair sums over s, inverse stages inside the half
+        int32_t Y[16];
+        {
+            const int4 *A4 = reinterpret_cast<const int4 *>(&aspec[j][S1][16 * hh]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int4 a4 = A4[q];
+                Y[4 * q] = mulmod(a4.x, W[4 * q]);
+                Y[4 * q + 1] = mulmod(a4.y, W[4 * q + 1]);
+                Y[4 * q + 2] = mulmod(a4.z, W[4 * q + 2]);
+                Y[4 * q + 3] = mulmod(a4.w, W[4 * q + 3]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) Y[k] += xor_lane<8>(Y[k]);   // |.| < 2^17.4
+        inv_stage_n<1, 16>(Y);
+        inv_stage_n<2, 16>(Y);
+        inv_stage_n<4, 16>(Y);
+        inv_stage_n<8, 16>(Y);
+        // last inverse stage: output 16 + q = y_lo[q] - y_hi[q] 2^-q; half 0 makes
+        // outputs q < 8, half 1 outputs q >= 8, each taking the other's value
+        int32_t yv[8];
+        sfor<8>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            const int32_t recv = xor_lane<1>(hh ? Y[i] : Y[8 + i]);
+            const int32_t a = hh ? recv : Y[i];
+            const int32_t bb = hh ? Y[8 + i] : recv;
+            const int32_t t = hh ? neg_inv_tw<8 + i>(bb) : neg_inv_tw<i>(bb);
+            int32_t v = sext24(lift_z(a + t)) * dscale;   // |lifted| <= 2^15
+            v += xor_lane<2>(v);                           // digits
+            v += xor_lane<4>(v);                           // S1 groups
+            yv[i] = v;                                     // |.| < 2^23.1
+        });
+        if ((lane & 14) == 0) {                          // d = 0, S1 = 0: S2 = lane / 16, half hh
+            int4 *yd4 = reinterpret_cast<int4 *>(&ybuf[S2][8 * hh]);
+            yd4[0] = make_int4(yv[0], yv[1], yv[2], yv[3]);
+            yd4[1] = make_int4(yv[4], yv[5], yv[6], yv[7]);
+        }
+        wave_lds_sync();
+        // outputs and RDE errors: lanes < 32, symbol om, streams 2 opol (I), 2 opol + 1 (Q)
+        const int64_t m = 16 * (int64_t)b + om;
+        const bool valid = lane < 32 && (uint64_t)m < M;
+        const int32_t yi = ybuf[2 * opol][om], yq = ybuf[2 * opol + 1][om];
+        const int32_t hi_ = clamp32((yi + ((1 << out_shift) >> 1)) >> out_shift, -32768, 32767);
+        const int32_t hq_ = clamp32((yq + ((1 << out_shift) >> 1)) >> out_shift, -32768, 32767);
+        if (valid)
+            reinterpret_cast<uint32_t *>(outp)[2 * m + opol] = ((uint32_t)hi_ & 0xFFFFu) | ((uint32_t)hq_ << 16);
+        if (upd) {
+            const int64_t r2 = (int64_t)hi_ * hi_ + (int64_t)hq_ * hq_;
+            const int64_t R2 = r2 < 6 * c2 ? 2 * c2 : (r2 < 14 * c2 ? 10 * c2 : 18 * c2);
+            int32_t ei = (int32_t)clamp64(rs64((R2 - r2) * hi_, err_shift), -128, 127);
+            int32_t eq = (int32_t)clamp64(rs64((R2 - r2) * hq_, err_shift), -128, 127);
+            if (!valid) ei = eq = 0;
+            if (lane < 32) {
+                uint8_t *eb = reinterpret_cast<uint8_t *>(&epsw[0][0]);
+                eb[(2 * opol) * 16 + om] = (uint8_t)ei;
+                eb[(2 * opol + 1) * 16 + om] = (uint8_t)eq;
+            }
+            wave_lds_sync();
+            // G[k] = sum_m eps_S2[m] a_S1[16 b + m - k] for k = 4 qd + i (i < 4)
+            uint32_t e4[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) e4[q] = epsw[S2][q];
+            uint32_t dd[6];
+            const int q0 = 4 * j + 3 - qd;               // byte 4 q0 = 16 j + 12 - 4 qd
+#pragma unroll
+            for (int r = 0; r < 6; ++r) dd[r] = abytes[S1][q0 + r];
+            int32_t nw[4];
+            sfor<4>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                constexpr int o = 4 - i;                    // a_S1[16 b - k] is byte o of dd
+                int32_t gsum = 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    gsum = __builtin_amdgcn_sdot4((int)e4[q],
+                                                  (int)__builtin_amdgcn_alignbyte(dd[(o >> 2) + q + 1],
+                                                                                  dd[(o >> 2) + q], o & 3),
+                                                  gsum, false);
+                // opaque values: a select of array loads would be folded into one
+                // dynamically indexed load, which moves w to scratch memory
+                const int32_t c01 = (qd & 1) ? opq(w[4 + i]) : opq(w[i]);
+                const int32_t c23 = (qd & 1) ? opq(w[12 + i]) : opq(w[8 + i]);
+                const int32_t cur = (qd & 2) ? c23 : c01;
+                nw[i] = clamp32(cur + ((gsum + ((1 << mu_shift) >> 1)) >> mu_shift), -8192, 8191);
+            });
+            sfor<4>([&](auto qc) {                        // every lane of the quad takes all 16 taps
+                constexpr int q = decltype(qc)::value;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) w[4 * q + i] = quad_bcast<q>(nw[i]);
+            });
+            transform_taps();
+        }
+        // the next block rewrites the output and error bytes: reads above first
+        wave_lds_sync();
+        if (b + 1 == nb) finish();
+    }
+    if ((bad & 0xE0E0E0E0u) != 0u) flag(err, RANGE_SYMBOL);
+}
+
+template <int WPG>
+__global__ __launch_bounds__(64 * WPG) void aeq_duo_kernel(const AeqItem *items, int nitems,
+                                                           AeqItem single, int *err, int prio) {
+    aeq_duo_body<WPG>(items, nitems, single, err, prio, blockIdx.x);
+}
+
+// One launch for a split plan: its first workgroups run the longest chains in
+// form LF at raised priority (they are dispatched first), the others the rest
+// of the table in form RF.  Forms with one-wave workgroups: 0 (one transform
+// per lane), 3 (two lanes per transform), 1 (split by polarisation, one wave
+// per half).
+__host__ __device__ constexpr unsigned aeq_form_blocks(int form, int n) {
+    return form == 0 ? (unsigned)((n + 1) / 2) : form == 3 ? (unsigned)n : (unsigned)(2 * n);
+}
+template <int F>
+__device__ __forceinline__ void aeq_form_body(const AeqItem *items, int n, int *err, int prio, unsigned bid) {
+    const AeqItem none{};
+    if constexpr (F == 0) aeq_lane_body<1>(items, n, none, err, prio, bid);
+    else if constexpr (F == 3) aeq_duo_body<1>(items, n, none, err, prio, bid);
+    else aeq_pol_body<4>(items, none, err, prio, bid);
+}
+template <int LF, int RF>
+__global__ __launch_bounds__(64) void aeq_split_kernel(const AeqItem *items, int nlong, int nitems,
+                                                       int *err) {
+    const unsigned nbl = aeq_form_blocks(LF, nlong);
+    if (blockIdx.x < nbl) aeq_form_body<LF>(items, nlong, err, 1, blockIdx.x);
+    else aeq_form_body<RF>(items + nlong, nitems - nlong, err, 0, blockIdx.x - nbl);
 }
 
 // Direct comparator: y by integer dot products in the time domain, same RDE.
@@ -1694,6 +2023,24 @@ hipError_t launch_cdc(const CdcItem *items, int nitems, const CdcItem &single,
     return hipGetLastError();
 }
 
+hipError_t launch_aeq_split(const AeqItem *items, int nlong, int nitems, int form_long, int form_rest,
+                           int *err, hipStream_t s) {
+    if (!items || nlong <= 0 || nlong >= nitems) return hipErrorInvalidValue;
+    const unsigned grid = aeq_form_blocks(form_long, nlong) + aeq_form_blocks(form_rest, nitems - nlong);
+#define FNT_SPLIT(L, R)                                                                        \
+    if (form_long == L && form_rest == R) {                                                    \
+        aeq_split_kernel<L, R><<<grid, 64, 0, s>>>(items, nlong, nitems, err);                  \
+        return hipGetLastError();                                                              \
+    }
+    FNT_SPLIT(1, 0) FNT_SPLIT(1, 3) FNT_SPLIT(3, 0) FNT_SPLIT(1, 1) FNT_SPLIT(3, 3) FNT_SPLIT(0, 0)
+#undef FNT_SPLIT
+    return hipErrorInvalidValue;
+}
+
+bool aeq_split_fusable(int form_long, int form_rest) {
+    return (form_long == 1 && (form_rest == 0 || form_rest == 3)) || (form_long == 3 && form_rest == 0);
+}
+
 hipError_t launch_aeq(const AeqItem *items, int nitems, const AeqItem &single, int variant,
                       int waves_per_pol, int *err, hipStream_t s, bool high_priority) {
     const int prio = high_priority ? 1 : 0;
@@ -1702,6 +2049,8 @@ hipError_t launch_aeq(const AeqItem *items, int nitems, const AeqItem &single, i
     if (variant == 0) {
         if (waves_per_pol == 0)
             aeq_lane_kernel<1><<<(n + 1) / 2, 64, 0, s>>>(items, n, single, err, prio);
+        else if (waves_per_pol == 3)
+            aeq_duo_kernel<1><<<n, 64, 0, s>>>(items, n, single, err, prio);
         else if (waves_per_pol == 1)
             aeq_pol_kernel<4><<<2 * n, 64, 0, s>>>(items, single, err, prio);
         else if (waves_per_pol == 2)

@@ -250,7 +250,7 @@ def _plan_channels(torch, dev, chans, rng):
     return out
 
 
-@pytest.mark.parametrize("variant,wpp", [(0, 0), (0, 1), (0, 2), (0, 4), (1, 1), (2, 1)])
+@pytest.mark.parametrize("variant,wpp", [(0, 0), (0, 3), (0, 1), (0, 2), (0, 4), (1, 1), (2, 1)])
 def test_plan_batched_vs_oracle(torch_dev, variant, wpp):
     torch, dev = torch_dev
     chans = _batch(40, 6, 11, seed=variant)
@@ -287,7 +287,7 @@ EXTREME_AEQ = [dict(out_shift=24, err_shift=62, mu_shift=40, const_unit=4096, up
                dict(out_shift=9, err_shift=12, mu_shift=1, const_unit=33, update_enable=0)]
 
 
-@pytest.mark.parametrize("wpp", [0, 1])
+@pytest.mark.parametrize("wpp", [0, 3, 1])
 def test_plan_extreme_aeq_params(torch_dev, wpp):
     """Shift and constant extremes (saturating taps and errors) on the batched kernels."""
     torch, dev = torch_dev
@@ -319,8 +319,8 @@ def test_plan_determinism_across_schedules(torch_dev):
                       fnt.aeq_params(**c["prm"])) for c in pc], autotune=False, use_graph=True)
     ref = None
     for wpg, bpw, wpp, variant in [(4, 0, 1, 0), (4, 1, 1, 0), (1, 1, 2, 0), (2, 3, 4, 0), (4, 64, 1, 0),
-                                   (1, 7, 2, 0), (1, 0, 2, 0), (2, 0, 4, 0), (4, 0, 0, 0), (2, 2, 1, 1),
-                                   (4, 5, 1, 2)]:
+                                   (1, 7, 2, 0), (1, 0, 2, 0), (2, 0, 4, 0), (4, 0, 0, 0), (4, 0, 3, 0),
+                                   (2, 2, 1, 1), (4, 5, 1, 2)]:
         plan.set_cdc_schedule(wpg, bpw)
         plan.set_aeq_waves(wpp)
         plan.set_aeq_variant(variant)
@@ -342,7 +342,8 @@ def test_plan_determinism_across_schedules(torch_dev):
                     assert np.array_equal(o, o2) and np.array_equal(w, w2)
     # longest chains in their own concurrent launch
     plan.set_aeq_variant(0)
-    for nl, wl, ws in [(5, 4, 1), (12, 2, 1), (1, 4, 2), (24, 4, 1), (3, 4, 0), (8, 2, 0), (23, 4, 0)]:
+    for nl, wl, ws in [(5, 4, 1), (12, 2, 1), (1, 4, 2), (24, 4, 1), (3, 4, 0), (8, 2, 0), (23, 4, 0),
+                       (6, 3, 0), (9, 1, 3), (2, 4, 3)]:
         plan.set_aeq_split(nl, wl, ws)
         for c in pc:
             c["taps"].copy_(to_dev(torch, dev, c["w0"]))
