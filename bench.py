@@ -419,7 +419,7 @@ def bench_served(args, torch, dev):
     t0 = time.perf_counter()
     streams, params = {}, {}
     sess = fnt.Session(max_channels=nch, hbm_budget_bytes=1 << 30, chunk_blocks=args.chunk,
-                       max_active=nch)
+                       max_active=nch, aeq_form=args.served_form)
     progress(f"served: {len(times)} requests over {nch} channels; generating streams")
     for c in range(nch):
         if c % 128 == 0:
@@ -469,7 +469,8 @@ def bench_served(args, torch, dev):
             "requests": int(st["completed"]), "ticks": int(st["ticks"]),
             "offered_gsamples_per_s": round(inst / args.window / 1e9, 3),
             "workload": f"{nch} channels, Poisson {args.rate:.0f} req/s for {args.window} s, segments "
-                        f"log-uniform 2^13..2^18 symbols, chunk {args.chunk} blocks/tick",
+                        f"log-uniform 2^13..2^18 symbols, chunk {args.chunk} blocks/tick, "
+                        f"AEQ form {args.served_form}",
             "parity": f"bit-exact vs oracle on channels {busiest} (whole streams)", "gen_s": round(gen_s, 1)}
 
 
@@ -493,7 +494,9 @@ def main():
     ap.add_argument("--served-channels", type=int, default=1024)
     ap.add_argument("--rate", type=float, default=20000.0)
     ap.add_argument("--window", type=float, default=0.5)
-    ap.add_argument("--chunk", type=int, default=64)
+    ap.add_argument("--chunk", type=int, default=512)
+    ap.add_argument("--served-form", type=int, default=-1,
+                    help="AEQ form of the session ticks (0, 3, 1, 2, 4; -1: automatic)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run 5 plain 256 MiB elementwise copies (counter calibration)")
     args = ap.parse_args()

@@ -250,8 +250,11 @@ typedef struct fnt_session_config {
     int32_t device;
     uint32_t max_channels;     /* channel ids are 0 .. max_channels-1 */
     uint64_t hbm_budget_bytes; /* staging pool for FNT_SUBMIT_HOST requests + scratch */
-    uint32_t chunk_blocks;     /* AEQ blocks advanced per request per tick (0: 64) */
+    uint32_t chunk_blocks;     /* AEQ blocks advanced per request per tick (0: 512) */
     uint32_t max_active;       /* requests advanced per tick (0: max_channels) */
+    int32_t aeq_form;          /* AEQ form of the ticks (see fnt_plan_set_aeq_waves), -1: by the
+                                  number of requests in the tick (shortest tick for that load) */
+    int32_t reserved;          /* 0 */
 } fnt_session_config;
 
 typedef struct fnt_session_stats {

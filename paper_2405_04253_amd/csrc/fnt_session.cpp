@@ -255,6 +255,26 @@ int build_tick(fnt_session *s, TickSlot &slot) {
     return nitems;
 }
 
+// AEQ form for a tick of `nitems` chains of equal length: the one with the
+// shortest tick, per block max(serial latency, work / issue rate), from the
+// forms' measured per-block latency (us, one chain alone) and VALU instructions
+// per chain-block on MI355X (1024 SIMDs, 0.6e12 wave instructions/s, taken at
+// 70 % efficiency).
+int tick_form(int nitems) {
+    struct Form { int code; double lat_us, instr; };
+    static const Form forms[] = {{4, 1.00, 2552}, {2, 1.20, 1864}, {1, 1.72, 1402}, {3, 2.11, 740}, {0, 2.65, 600}};
+    int best = 4;
+    double best_t = 1e30;
+    for (const Form &f : forms) {
+        const double t = std::max(f.lat_us, nitems * f.instr / (0.7 * 0.6e12) * 1e6);
+        if (t < best_t) {
+            best_t = t;
+            best = f.code;
+        }
+    }
+    return best;
+}
+
 void scheduler_main(fnt_session *s) {
     (void)hipSetDevice(s->device);
     std::unique_lock<std::mutex> lk(s->mu);
@@ -301,7 +321,10 @@ void scheduler_main(fnt_session *s) {
             default_cdc_schedule(total_blocks, &wpg, &bpw);
             e = run_cdc(slot.cdc_dev, nitems, CdcItem{}, total_blocks, total_chunks, wpg, bpw, false, s->err, st);
         }
-        if (e == hipSuccess) e = launch_aeq(slot.aeq_dev, nitems, AeqItem{}, 0, nitems >= 512 ? 1 : 2, s->err, st);
+        if (e == hipSuccess) {
+            const int form = s->cfg.aeq_form >= 0 ? s->cfg.aeq_form : tick_form(nitems);
+            e = launch_aeq(slot.aeq_dev, nitems, AeqItem{}, 0, form, s->err, st);
+        }
         for (auto &c : d2h)
             if (e == hipSuccess)
                 e = hipMemcpyAsync(c.first, c.second.first, c.second.second, hipMemcpyDeviceToHost, st);
@@ -381,10 +404,14 @@ int fnt_session_create(fnt_session **out, const fnt_session_config *cfg) {
         return fail(FNT_E_INVAL, "session: max_channels %u outside [1, 2^20]", cfg->max_channels);
     fnt_session *s = new fnt_session();
     s->cfg = *cfg;
-    if (s->cfg.chunk_blocks == 0) s->cfg.chunk_blocks = 64;
+    if (s->cfg.chunk_blocks == 0) s->cfg.chunk_blocks = 512;
     if (s->cfg.chunk_blocks > 4096) {
         delete s;
         return fail(FNT_E_INVAL, "session: chunk_blocks %u > 4096", cfg->chunk_blocks);
+    }
+    if (cfg->aeq_form < -1 || cfg->aeq_form > 4) {
+        delete s;
+        return fail(FNT_E_INVAL, "session: aeq_form %d outside [-1, 4]", cfg->aeq_form);
     }
     if (s->cfg.max_active == 0 || s->cfg.max_active > s->cfg.max_channels)
         s->cfg.max_active = s->cfg.max_channels;

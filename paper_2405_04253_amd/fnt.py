@@ -69,7 +69,7 @@ class PlanInfo(ctypes.Structure):
 class SessionConfig(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("max_channels", ctypes.c_uint32),
                 ("hbm_budget_bytes", ctypes.c_uint64), ("chunk_blocks", ctypes.c_uint32),
-                ("max_active", ctypes.c_uint32)]
+                ("max_active", ctypes.c_uint32), ("aeq_form", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class SessionStats(ctypes.Structure):
@@ -319,9 +319,9 @@ class Session:
     """fnt_session_*: continuing channel streams with HBM-resident state."""
 
     def __init__(self, max_channels: int, hbm_budget_bytes: int, chunk_blocks: int = 0,
-                 max_active: int = 0, device: int = 0):
+                 max_active: int = 0, device: int = 0, aeq_form: int = -1):
         cfg = SessionConfig(int(device), int(max_channels), int(hbm_budget_bytes),
-                            int(chunk_blocks), int(max_active))
+                            int(chunk_blocks), int(max_active), int(aeq_form), 0)
         h = ctypes.c_void_p()
         _ok(lib().fnt_session_create(ctypes.byref(h), ctypes.byref(cfg)))
         self._h = h

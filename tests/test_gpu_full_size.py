@@ -157,7 +157,7 @@ def test_full_size_served_1024(torch_dev):
         per[c] += seg[i]
     t0 = time.perf_counter()
     streams, params = {}, {}
-    sess = fnt.Session(max_channels=nch, hbm_budget_bytes=1 << 30, chunk_blocks=64, max_active=nch)
+    sess = fnt.Session(max_channels=nch, hbm_budget_bytes=1 << 30, chunk_blocks=512, max_active=nch)
     for c in range(nch):
         r = np.random.default_rng(synth.seed_for(0, "served", c))
         km, osnr = float(r.uniform(10, 80)), float(r.uniform(18, 26))

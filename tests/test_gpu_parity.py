@@ -416,10 +416,12 @@ def _oracle_stream(ch, w0=None):
     return outr, wr
 
 
-def test_session_streams_vs_oracle(torch_dev):
+@pytest.mark.parametrize("form", [-1, 0, 3, 1, 2, 4])
+def test_session_streams_vs_oracle(torch_dev, form):
+    """Tick after tick through every AEQ form: taps, CDC tail and AEQ tail carry over."""
     torch, dev = torch_dev
     chans = _session_channels(6, 40, seed=1)
-    s = fnt.Session(max_channels=8, hbm_budget_bytes=64 << 20, chunk_blocks=8)
+    s = fnt.Session(max_channels=8, hbm_budget_bytes=64 << 20, chunk_blocks=8, aeq_form=form)
     outs = []
     for c, (ch, segs) in enumerate(chans):
         s.add_channel(c, fnt.cdc_params(ch.taps, ch.requant_shift), fnt.aeq_params(**synth.aeq_params_for(ch)))
@@ -433,7 +435,7 @@ def test_session_streams_vs_oracle(torch_dev):
             order.append((k, c, off, n))
             off += n
     order.sort()
-    note("session submit interleaved segments")
+    note(f"session submit interleaved segments, AEQ form {form}")
     tickets = [s.submit(c, xs[c][off:off + n], outs[c][off // 2:(off + n) // 2]) for _, c, off, n in order]
     s.drain()
     assert all(s.poll(t) for t in tickets)
@@ -509,6 +511,8 @@ def test_session_host_buffers_admission_and_errors(torch_dev):
     chans = _session_channels(3, 30, seed=8)
     fixed = 3 * 2 * 8 * 64 + 4 * fnt.FNT_STATE_BYTES
     biggest = max(sum(segs) for _, segs in chans)
+    with pytest.raises(fnt.FntError):
+        fnt.Session(max_channels=4, hbm_budget_bytes=64 << 20, chunk_blocks=8, aeq_form=7)
     # staging pool that holds roughly one request at a time
     s = fnt.Session(max_channels=4, hbm_budget_bytes=fixed + 8 * biggest + 4096, chunk_blocks=8, max_active=2)
     host_out = {}
