@@ -201,8 +201,8 @@ def aeq_kernel_name(info) -> str:
             4: "aeq_pol_kernel<16>"}
     if info["aeq_variant"] == 0:
         wl, ws = info["aeq_waves_long"], info["aeq_waves_per_pol"]
-        if info["aeq_long_channels"] and (wl, ws) in ((1, 0), (1, 3), (3, 0)):
-            return "aeq_split_kernel<%d, %d>" % (wl, ws)     # one launch, long chains first
+        if info["aeq_long_channels"] and ((wl in (1, 2, 4) and ws in (0, 3)) or (wl, ws) == (3, 0)):
+            return "aeq_split_kernel<%d, %d, %d>" % (wl, ws, {1: 1, 3: 1, 2: 2, 4: 4}[wl])  # one launch
         k = form[ws]
         if info["aeq_long_channels"]:
             k = form[wl] + "+" + k
@@ -346,6 +346,32 @@ def bench_batched(args, torch, dev):
 
     plain_ms = _time_events(torch, plain_loop, 1, stream)
     plain_gsps = s_inst / (plain_ms / 1e3) / 1e9
+    # comparator: the same plan with the direct time-domain CDC and AEQ kernels
+    # (no Fermat-domain arithmetic), bit-identical outputs
+    progress("batched: direct time-domain comparator")
+    ref_out = {i: entries[i][1].clone() for i in pick}
+    ref_taps = {i: taps_all[i].clone() for i in pick}
+    plan.set_cdc_variant(1)
+    plan.set_aeq_variant(1)
+    cmp_ev = []
+    for k in range(2):
+        taps_all.copy_(w_all)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record(stream)
+        plan.run_stage(fnt.FNT_STAGE_CDC, stream)
+        ev[1].record(stream)
+        plan.run_stage(fnt.FNT_STAGE_AEQ, stream)
+        ev[2].record(stream)
+        cmp_ev.append(ev)
+    torch.cuda.synchronize()
+    fnt.fnt_check()
+    for i in pick:
+        if not (torch.equal(entries[i][1], ref_out[i]) and torch.equal(taps_all[i], ref_taps[i])):
+            raise SystemExit(f"direct comparator differs on channel {i}")
+    d_cdc = float(np.mean([e[0].elapsed_time(e[1]) for e in cmp_ev]))
+    d_aeq = float(np.mean([e[1].elapsed_time(e[2]) for e in cmp_ev]))
+    plan.set_cdc_variant(0)
+    plan.set_aeq_variant(0)
     value = inst / (ms / 1e3) / 1e9
     aeq_blocks = sum((e[0].shape[0] // 2 + 15) // 16 for e in entries)
     cdc_blocks = sum((e[0].shape[0] + 31) // 32 for e in entries)
@@ -383,6 +409,11 @@ def bench_batched(args, torch, dev):
         "roofline": roof,
         "kernels": kernels,
         "graph_ms_per_run": round(graph_ms, 3),
+        "direct_comparator": {
+            "value": round(inst / ((d_cdc + d_aeq) / 1e3) / 1e9, 4), "unit": "Gsamples/s",
+            "cdc_ms": round(d_cdc, 3), "aeq_ms": round(d_aeq, 3),
+            "what": "same plan, time-domain CDC (int8 dot products over the 32-instant window) and "
+                    "time-domain AEQ, no Fermat-domain arithmetic; bit-identical on the parity channels"},
         "roofline_whole_path": {"bound": "alu", "achieved": round((aeq_ops + cdc_ops) / (ms / 1e3) / 1e9, 1),
                                 "peak": PEAK_ALU_GOPS, "unit": "Gops/s",
                                 "frac": round((aeq_ops + cdc_ops) / (ms / 1e3) / 1e9 / PEAK_ALU_GOPS, 5)},

@@ -188,6 +188,8 @@ typedef struct fnt_plan_info {
     int32_t aeq_waves_long;     /* AEQ form of the long chains (see fnt_plan_set_aeq_split) */
     double tune_ms;        /* AEQ time of the chosen schedule during autotune, ms (0 if none) */
     uint64_t aeq_long_channels; /* longest channels run in their own concurrent launch */
+    int32_t cdc_variant;   /* 0 = Fermat-domain (the method), 1 = direct comparator */
+    int32_t reserved;
 } fnt_plan_info;
 
 typedef struct fnt_plan fnt_plan;
@@ -234,6 +236,11 @@ int fnt_plan_set_aeq_waves(fnt_plan *plan, int waves_per_pol);
  * launch concurrent with the rest, which run with `wpp` waves per half
  * (fewer waves, higher throughput).  long_channels = 0 disables the split. */
 int fnt_plan_set_aeq_split(fnt_plan *plan, uint64_t long_channels, int wpp_long, int wpp);
+/* Select the CDC kernel of a plan: 0 = overlap-save in the Fermat domain with the
+ * complex product of Eqs. (7)-(8) (default, the method), 1 = direct time-domain
+ * comparator (4-byte integer dot products over the 32-instant window, no
+ * Fermat-domain arithmetic) with bit-identical results.  FNT_E_INVAL otherwise. */
+int fnt_plan_set_cdc_variant(fnt_plan *plan, int variant);
 /* CDC launch schedule: waves per workgroup (1, 2 or 4) and the block mapping.
  * blocks_per_wave = 0 (default): every lane transforms one whole 32-instant block
  * in its registers, a wave takes 64 consecutive blocks of one channel;

@@ -284,6 +284,7 @@ struct fnt_plan {
     uint64_t total_blocks = 0, total_chunks = 0;
     fnt_plan_info info{};
     int wpg = 4, bpw = 0, variant = 0, wpp = 1;   // CDC: bpw = 0 is the lane-per-block kernel
+    int cdc_variant = 0;                          // 1: direct time-domain comparator
     // AEQ split: the n_long longest chains (table prefix) run with wpp_long waves
     // per half in a launch concurrent with the rest
     int wpp_long = 4;
@@ -299,8 +300,11 @@ struct fnt_plan {
 // the long chains on s concurrently with the AEQ of the others on a side stream
 // (fork / join by events, which a graph capture turns into parallel branches).
 static int plan_launch_cdc(fnt_plan *p, hipStream_t s) {
-    hipError_t e = run_cdc(p->cdc_dev, (int)p->cdc_host.size(), CdcItem{}, p->total_blocks, p->total_chunks,
-                           p->wpg, p->bpw, false, p->err, s);
+    hipError_t e = p->cdc_variant == 1
+                       ? launch_cdc(p->cdc_dev, (int)p->cdc_host.size(), CdcItem{}, p->total_blocks,
+                                    p->total_chunks, 2, p->wpg, 1, false, p->err, s)
+                       : run_cdc(p->cdc_dev, (int)p->cdc_host.size(), CdcItem{}, p->total_blocks, p->total_chunks,
+                                 p->wpg, p->bpw, false, p->err, s);
     if (e != hipSuccess) return hip_fail(e, "plan: cdc launch");
     return FNT_OK;
 }
@@ -380,6 +384,8 @@ static int plan_capture(fnt_plan *p, hipStream_t s) {
     return FNT_OK;
 }
 
+constexpr int kTuneVersion = 3;
+
 static std::string tune_key(const fnt_plan *p) {
     // length histogram (log2 buckets of instants) + channel count + variant
     int hist[48] = {0};
@@ -391,7 +397,9 @@ static std::string tune_key(const fnt_plan *p) {
     std::ostringstream k;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) k << prop.gcnArchName;
-    k << "|v" << p->variant << "|ch" << p->cdc_host.size() << "|";
+    // the schedule vocabulary (CDC mappings, AEQ forms, split rules) is versioned
+    // so that entries written by a build with other meanings are not reused
+    k << "|s" << kTuneVersion << "|v" << p->variant << "|ch" << p->cdc_host.size() << "|";
     for (int i = 0; i < 48; ++i)
         if (hist[i]) k << i << ":" << hist[i] << ",";
     return k.str();
@@ -453,7 +461,8 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
     std::string key = tune_key(p);
     int w, b, q, ql;
     long long nl;
-    if (tune_cache_lookup(cache, key, &w, &b, &q, &ql, &nl)) {
+    if (tune_cache_lookup(cache, key, &w, &b, &q, &ql, &nl) && (w == 1 || w == 2 || w == 4) && b >= 0 &&
+        b <= 1024 && valid_form(q) && valid_form(ql) && nl >= 0) {
         p->wpg = w;
         p->bpw = b;
         p->wpp = q;
@@ -464,9 +473,10 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(FNT_E_DEVICE, "plan: autotune events");
+    int reps = 2;
     auto time_it = [&](auto &&launch) -> double {
         float ms = 0, best = 1e30f;
-        for (int rep = 0; rep < 2; ++rep) {
+        for (int rep = 0; rep < reps; ++rep) {
             (void)hipEventRecord(e0, s);
             if (launch() != hipSuccess) return 1e30;
             (void)hipEventRecord(e1, s);
@@ -520,30 +530,45 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
             for (const auto &r : ratio) {
                 size_t k = 0;
                 while (k < nch && (p->aeq_host[k].m + 15) / 16 * (uint64_t)r[1] >= longest * (uint64_t)r[0]) ++k;
-                if (k > 0 && k < nch && k != splits.back()) splits.push_back(k);
+                if (k > 0 && k < nch) splits.push_back(k);
             }
+            // and fixed counts of longest chains
+            for (size_t k = 16; k < nch && k <= 2048; k *= 2) splits.push_back(k);
+            std::sort(splits.begin(), splits.end());
+            splits.erase(std::unique(splits.begin(), splits.end()), splits.end());
             AeqItem *saved = p->aeq_dev;
             p->aeq_dev = tdev;
+            struct Cand { size_t nl; int ql, q; double ms; };
+            std::vector<Cand> cands;
+            auto time_aeq = [&](const Cand &c) {
+                p->n_long = c.nl;
+                p->wpp_long = c.ql;
+                p->wpp = c.q;
+                return time_it([&] {
+                    int rc = plan_launch_aeq(p, s, p->side);
+                    return rc ? hipErrorUnknown : hipSuccess;
+                });
+            };
+            reps = 1;                                           // one pass, then the best few again
             for (size_t nl : splits)
                 for (int ql : {3, 1, 2, 4})                     // long chains: latency-leaning forms
                 for (int q : {0, 3, 1, 2, 4}) {
                     if (nl == 0 && ql != 4) continue;           // no split: one form for all
                     if (nl > 0 && form_rank(q) >= form_rank(ql)) continue;  // cheaper form for the rest
-                    {
-                        p->n_long = nl;
-                        p->wpp_long = ql;
-                        p->wpp = q;
-                        double ms = time_it([&] {
-                            int rc = plan_launch(p, s, p->side);
-                            return rc ? hipErrorUnknown : hipSuccess;
-                        });
-                        if (ms < best_aeq) {
-                            best_aeq = ms;
-                            bq = q;
-                            bql = ql;
-                            bnl = nl;
-                        }
-                    }
+                    Cand c{nl, ql, q, 0};
+                    c.ms = time_aeq(c);
+                    cands.push_back(c);
+                }
+            // the best few again (run-to-run spread is several percent)
+            std::sort(cands.begin(), cands.end(), [](const Cand &a, const Cand &b) { return a.ms < b.ms; });
+            for (size_t i = 0; i < cands.size() && i < 4; ++i)
+                for (int rep = 0; rep < 2; ++rep) cands[i].ms = std::min(cands[i].ms, time_aeq(cands[i]));
+            for (size_t i = 0; i < cands.size() && i < 4; ++i)
+                if (cands[i].ms < best_aeq) {
+                    best_aeq = cands[i].ms;
+                    bq = cands[i].q;
+                    bql = cands[i].ql;
+                    bnl = cands[i].nl;
                 }
             p->aeq_dev = saved;
         }
@@ -719,6 +744,7 @@ int fnt_plan_get_info(const fnt_plan *p, fnt_plan_info *info) {
     info->aeq_waves_long = p->wpp_long;
     info->aeq_long_channels = p->variant == 0 ? std::min(p->n_long, p->aeq_host.size()) : 0;
     info->graph = p->exec ? 1 : 0;
+    info->cdc_variant = p->cdc_variant;
     return FNT_OK;
 }
 
@@ -726,6 +752,14 @@ int fnt_plan_set_aeq_variant(fnt_plan *p, int variant) {
     if (!p) return fail(FNT_E_INVAL, "plan: NULL");
     if (variant < 0 || variant > 2) return fail(FNT_E_INVAL, "plan: variant %d", variant);
     p->variant = variant;
+    if (p->exec) return plan_capture(p, nullptr);
+    return FNT_OK;
+}
+
+int fnt_plan_set_cdc_variant(fnt_plan *p, int variant) {
+    if (!p) return fail(FNT_E_INVAL, "plan: NULL");
+    if (variant != 0 && variant != 1) return fail(FNT_E_INVAL, "plan: CDC variant %d", variant);
+    p->cdc_variant = variant;
     if (p->exec) return plan_capture(p, nullptr);
     return FNT_OK;
 }

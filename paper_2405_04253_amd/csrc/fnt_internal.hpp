@@ -62,14 +62,15 @@ hipError_t launch_transform(const uint32_t *x, uint32_t *X, size_t batch, int t,
 // 64-point transforms in registers; needs total_chunks (sum of cdc_chunks) and
 // waves_per_group; blocks_per_wave is unused.  Variant 1: one block per wave,
 // 16 lanes per transform, blocks_per_wave consecutive blocks per wave.  The
-// exact output z (with_z) always takes variant 1.
+// exact output z (with_z) always takes variant 1.  Variant 2: the direct
+// time-domain comparator (no Fermat-domain arithmetic), chunks as variant 0.
 hipError_t launch_cdc(const CdcItem *items, int nitems, const CdcItem &single,
                       uint64_t total_blocks, uint64_t total_chunks, int variant,
                       int waves_per_group, int blocks_per_wave, bool with_z, int *err,
                       hipStream_t s);
 // One launch for the split of a longest-first table: items [0, nlong) in form
 // form_long at raised wave priority (dispatched first), the rest in form_rest.
-// Fusable pairs (one-wave workgroups): (1, 0), (1, 3), (3, 0).
+// Fusable pairs: long form 1, 2 or 4 with rest 0 or 3, and (3, 0).
 hipError_t launch_aeq_split(const AeqItem *items, int nlong, int nitems, int form_long, int form_rest,
                            int *err, hipStream_t s);
 bool aeq_split_fusable(int form_long, int form_rest);

@@ -630,6 +630,116 @@ __global__ __launch_bounds__(64 * WPG) void cdc_lane_kernel(const CdcItem *items
     }
 }
 
+// ----------------------------------------------------- CDC, direct comparator --
+//
+// The same 1-sps 5-bit output by the plain time-domain definition, with no
+// Fermat-domain arithmetic: lane m of a wave computes symbol m's four
+// components z = sum_k h[k] x[i - k] (i = 2 m + phase) as 4-byte dot products
+// of the 32-instant window (stream bytes staged in LDS, stream-major) with the
+// taps reversed and packed as int8.  Chunks of 64 blocks per wave, as in
+// cdc_lane_kernel; 16 passes of 64 symbols each.
+template <int WPG>
+__global__ __launch_bounds__(64 * WPG) void cdc_direct_kernel(const CdcItem *items, int nitems,
+                                                              CdcItem single, uint64_t total_chunks,
+                                                              int *err) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // per wave: 160 staged bytes of each stream (+ 16 pad: the last window's
+    // ninth word is read as the ignored high operand of an aligned alignbyte)
+    __shared__ __align__(16) uint32_t xb_s[WPG][4][44];
+    uint32_t(*xb)[44] = xb_s[wv];
+    const uint64_t chunk = (uint64_t)blockIdx.x * WPG + wv;
+    if (chunk >= total_chunks) return;
+    int idx = 0;
+    if (items) {
+        int lo = 0, hi = nitems - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (items[mid].chunk0 <= chunk) lo = mid; else hi = mid - 1;
+        }
+        idx = lo;
+    }
+    const CdcItem *ip = items ? &items[idx] : &single;
+    const uint64_t n = ip->n;
+    const uint64_t lb0 = (chunk - (items ? ip->chunk0 : 0)) * fnti::CDC_CHUNK;
+    if (lb0 >= fnti::cdc_blocks(n)) return;
+    const int ntaps = ip->ntaps < 32 ? ip->ntaps : 32;
+    const int shift = ip->shift, phase = ip->phase;
+    const int8_t *in = ip->in;
+    const int8_t *hist = ip->hist;
+    int8_t *a_out = ip->a_out;
+    const uint64_t M = fnti::n_symbols(n, phase);
+    // taps reversed (byte t of the window meets h[31 - t]) and packed as int8
+    const int8_t *tp = &ip->taps[0][0];
+    uint32_t hr[8], hi[8], hn[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        uint32_t r = 0, im = 0, ng = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int k = 31 - (4 * q + b);
+            const int32_t vr = k < ntaps ? tp[2 * k] : 0, vi = k < ntaps ? tp[2 * k + 1] : 0;
+            r |= ((uint32_t)vr & 0xFFu) << (8 * b);
+            im |= ((uint32_t)vi & 0xFFu) << (8 * b);
+            ng |= ((uint32_t)(-vi) & 0xFFu) << (8 * b);
+        }
+        hr[q] = r;
+        hi[q] = im;
+        hn[q] = ng;
+    }
+    uint32_t bad = 0u;
+    const int64_t sym0 = 16 * (int64_t)lb0;             // first symbol of the chunk
+    for (int sub = 0; sub < fnti::CDC_CHUNK / 4; ++sub) {
+        const int64_t s0 = sym0 + 64 * sub;
+        if ((uint64_t)s0 >= M) break;
+        const int64_t base = 2 * s0 - 32;               // instant at staged byte 0
+        wave_lds_sync();
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const int p = lane + 64 * r;
+            if (p < 160) {
+                const int64_t i = base + p;
+                uint32_t w = 0u;
+                if (i < 0) {
+                    if (hist) w = reinterpret_cast<const uint32_t *>(hist)[32 + i];
+                } else if ((uint64_t)i < n) {
+                    w = reinterpret_cast<const uint32_t *>(in)[i];
+                    if (p >= 32) bad |= w ^ (w << 1);   // instants new to this pass
+                }
+                uint8_t *xbb = reinterpret_cast<uint8_t *>(&xb[0][0]);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) xbb[c * 176 + p] = (uint8_t)(w >> (8 * c));
+            }
+        }
+        wave_lds_sync();
+        const int64_t m = s0 + lane;
+        const int sb = 2 * lane + phase + 1;            // window bytes sb .. sb + 31
+        uint32_t o = 0u;
+#pragma unroll
+        for (int pol = 0; pol < 2; ++pol) {
+            uint32_t dr[9], di[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                dr[q] = xb[2 * pol][(sb >> 2) + q];
+                di[q] = xb[2 * pol + 1][(sb >> 2) + q];
+            }
+            int32_t re = 0, im = 0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int xr = (int)__builtin_amdgcn_alignbyte(dr[q + 1], dr[q], sb & 3);
+                const int xi = (int)__builtin_amdgcn_alignbyte(di[q + 1], di[q], sb & 3);
+                re = __builtin_amdgcn_sdot4(xr, (int)hr[q], re, false);
+                re = __builtin_amdgcn_sdot4(xi, (int)hn[q], re, false);
+                im = __builtin_amdgcn_sdot4(xi, (int)hr[q], im, false);
+                im = __builtin_amdgcn_sdot4(xr, (int)hi[q], im, false);
+            }
+            o |= (((uint32_t)requant5(re, shift) & 0xFFu) | (((uint32_t)requant5(im, shift) & 0xFFu) << 8))
+                 << (16 * pol);
+        }
+        if (a_out && (uint64_t)m < M) reinterpret_cast<uint32_t *>(a_out)[m] = o;
+    }
+    if ((bad & 0xE0E0E0E0u) != 0u) flag(err, RANGE_SAMPLE);
+}
+
 // ----------------------------------------------------------------------- AEQ --
 
 __device__ __forceinline__ uint32_t aeq_load(const AeqItem &it, int64_t i, int *err) {
@@ -1840,25 +1950,27 @@ __global__ __launch_bounds__(64 * WPG) void aeq_duo_kernel(const AeqItem *items,
 
 // One launch for a split plan: its first workgroups run the longest chains in
 // form LF at raised priority (they are dispatched first), the others the rest
-// of the table in form RF.  Forms with one-wave workgroups: 0 (one transform
-// per lane), 3 (two lanes per transform), 1 (split by polarisation, one wave
-// per half).
-__host__ __device__ constexpr unsigned aeq_form_blocks(int form, int n) {
-    return form == 0 ? (unsigned)((n + 1) / 2) : form == 3 ? (unsigned)n : (unsigned)(2 * n);
+// of the table in form RF, with WPG waves per workgroup throughout.  Forms:
+// 0 (one transform per lane, 2 channels per wave), 3 (two lanes per transform,
+// 1 channel per wave), 1 / 2 / 4 (split by polarisation with 1 / 2 / 4 waves per
+// half: one workgroup per half, so WPG = 1 / 2 / 4).
+__host__ __device__ constexpr unsigned aeq_form_blocks(int form, int n, int wpg) {
+    return form == 0 ? (unsigned)((n + 2 * wpg - 1) / (2 * wpg))
+         : form == 3 ? (unsigned)((n + wpg - 1) / wpg) : (unsigned)(2 * n);
 }
-template <int F>
+template <int F, int WPG>
 __device__ __forceinline__ void aeq_form_body(const AeqItem *items, int n, int *err, int prio, unsigned bid) {
     const AeqItem none{};
-    if constexpr (F == 0) aeq_lane_body<1>(items, n, none, err, prio, bid);
-    else if constexpr (F == 3) aeq_duo_body<1>(items, n, none, err, prio, bid);
-    else aeq_pol_body<4>(items, none, err, prio, bid);
+    if constexpr (F == 0) aeq_lane_body<WPG>(items, n, none, err, prio, bid);
+    else if constexpr (F == 3) aeq_duo_body<WPG>(items, n, none, err, prio, bid);
+    else aeq_pol_body<4 * WPG>(items, none, err, prio, bid);
 }
-template <int LF, int RF>
-__global__ __launch_bounds__(64) void aeq_split_kernel(const AeqItem *items, int nlong, int nitems,
-                                                       int *err) {
-    const unsigned nbl = aeq_form_blocks(LF, nlong);
-    if (blockIdx.x < nbl) aeq_form_body<LF>(items, nlong, err, 1, blockIdx.x);
-    else aeq_form_body<RF>(items + nlong, nitems - nlong, err, 0, blockIdx.x - nbl);
+template <int LF, int RF, int WPG>
+__global__ __launch_bounds__(64 * WPG) void aeq_split_kernel(const AeqItem *items, int nlong, int nitems,
+                                                             int *err) {
+    const unsigned nbl = aeq_form_blocks(LF, nlong, WPG);
+    if (blockIdx.x < nbl) aeq_form_body<LF, WPG>(items, nlong, err, 1, blockIdx.x);
+    else aeq_form_body<RF, WPG>(items + nlong, nitems - nlong, err, 0, blockIdx.x - nbl);
 }
 
 // Direct comparator: y by integer dot products in the time domain, same RDE.
@@ -2008,6 +2120,18 @@ hipError_t launch_cdc(const CdcItem *items, int nitems, const CdcItem &single,
         }
         return hipGetLastError();
     }
+    if (variant == 2 && !with_z) {
+        if (total_chunks == 0) return hipErrorInvalidValue;
+        const uint64_t grid = (total_chunks + waves_per_group - 1) / waves_per_group;
+        if (grid > 0x7FFFFFFFull) return hipErrorInvalidValue;
+        switch (waves_per_group) {
+        case 1: cdc_direct_kernel<1><<<(unsigned)grid, 64, 0, s>>>(items, nitems, single, total_chunks, err); break;
+        case 2: cdc_direct_kernel<2><<<(unsigned)grid, 128, 0, s>>>(items, nitems, single, total_chunks, err); break;
+        case 3: cdc_direct_kernel<3><<<(unsigned)grid, 192, 0, s>>>(items, nitems, single, total_chunks, err); break;
+        default: cdc_direct_kernel<4><<<(unsigned)grid, 256, 0, s>>>(items, nitems, single, total_chunks, err); break;
+        }
+        return hipGetLastError();
+    }
     if (variant != 0 && variant != 1) return hipErrorInvalidValue;
     if (blocks_per_wave < 1) return hipErrorInvalidValue;
     const uint64_t waves = (total_blocks + blocks_per_wave - 1) / blocks_per_wave;
@@ -2023,22 +2147,27 @@ hipError_t launch_cdc(const CdcItem *items, int nitems, const CdcItem &single,
     return hipGetLastError();
 }
 
+static int split_wpg(int form_long) { return form_long == 2 ? 2 : form_long == 4 ? 4 : 1; }
+
 hipError_t launch_aeq_split(const AeqItem *items, int nlong, int nitems, int form_long, int form_rest,
                            int *err, hipStream_t s) {
     if (!items || nlong <= 0 || nlong >= nitems) return hipErrorInvalidValue;
-    const unsigned grid = aeq_form_blocks(form_long, nlong) + aeq_form_blocks(form_rest, nitems - nlong);
-#define FNT_SPLIT(L, R)                                                                        \
+    const int wpg = split_wpg(form_long);
+    const unsigned grid = aeq_form_blocks(form_long, nlong, wpg) + aeq_form_blocks(form_rest, nitems - nlong, wpg);
+#define FNT_SPLIT(L, R, W)                                                                     \
     if (form_long == L && form_rest == R) {                                                    \
-        aeq_split_kernel<L, R><<<grid, 64, 0, s>>>(items, nlong, nitems, err);                  \
+        aeq_split_kernel<L, R, W><<<grid, 64 * W, 0, s>>>(items, nlong, nitems, err);           \
         return hipGetLastError();                                                              \
     }
-    FNT_SPLIT(1, 0) FNT_SPLIT(1, 3) FNT_SPLIT(3, 0) FNT_SPLIT(1, 1) FNT_SPLIT(3, 3) FNT_SPLIT(0, 0)
+    FNT_SPLIT(1, 0, 1) FNT_SPLIT(1, 3, 1) FNT_SPLIT(3, 0, 1)
+    FNT_SPLIT(2, 0, 2) FNT_SPLIT(2, 3, 2) FNT_SPLIT(4, 0, 4) FNT_SPLIT(4, 3, 4)
 #undef FNT_SPLIT
     return hipErrorInvalidValue;
 }
 
 bool aeq_split_fusable(int form_long, int form_rest) {
-    return (form_long == 1 && (form_rest == 0 || form_rest == 3)) || (form_long == 3 && form_rest == 0);
+    return ((form_long == 1 || form_long == 2 || form_long == 4) && (form_rest == 0 || form_rest == 3)) ||
+           (form_long == 3 && form_rest == 0);
 }
 
 hipError_t launch_aeq(const AeqItem *items, int nitems, const AeqItem &single, int variant,

@@ -63,7 +63,8 @@ class PlanInfo(ctypes.Structure):
                 ("cdc_blocks_per_wave", ctypes.c_int32), ("aeq_variant", ctypes.c_int32),
                 ("aeq_waves_per_pol", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("aeq_waves_long", ctypes.c_int32), ("tune_ms", ctypes.c_double),
-                ("aeq_long_channels", ctypes.c_uint64)]
+                ("aeq_long_channels", ctypes.c_uint64), ("cdc_variant", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class SessionConfig(ctypes.Structure):
@@ -104,6 +105,7 @@ SIGNATURES = {
     "fnt_plan_run_stage": (_i32, [_vp, _i32, _vp]),
     "fnt_plan_get_info": (_i32, [_vp, ctypes.POINTER(PlanInfo)]),
     "fnt_plan_set_aeq_variant": (_i32, [_vp, _i32]),
+    "fnt_plan_set_cdc_variant": (_i32, [_vp, _i32]),
     "fnt_plan_set_aeq_waves": (_i32, [_vp, _i32]),
     "fnt_plan_set_cdc_schedule": (_i32, [_vp, _i32, _i32]),
     "fnt_plan_set_aeq_split": (_i32, [_vp, _u64, _i32, _i32]),
@@ -292,6 +294,9 @@ class Plan:
 
     def set_aeq_variant(self, variant: int):
         _ok(lib().fnt_plan_set_aeq_variant(self._h, int(variant)))
+
+    def set_cdc_variant(self, variant: int):
+        _ok(lib().fnt_plan_set_cdc_variant(self._h, int(variant)))
 
     def set_aeq_waves(self, waves_per_pol: int):
         _ok(lib().fnt_plan_set_aeq_waves(self._h, int(waves_per_pol)))

@@ -310,6 +310,49 @@ def test_plan_extreme_aeq_params(torch_dev, wpp):
     fnt.fnt_check()
 
 
+@pytest.mark.parametrize("aeq_variant", [0, 1])
+def test_plan_direct_cdc_comparator(torch_dev, aeq_variant):
+    """The direct time-domain CDC (and AEQ) comparators give the method's results bit for bit."""
+    torch, dev = torch_dev
+    rng = np.random.default_rng(31)
+    chans = []
+    for i, n in enumerate([1, 31, 32, 33, 95, 2048, 2049, 4133, 70000, 131072 + 96]):
+        L = int(rng.integers(1, 33))
+        x = synth.random_samples(n, seed=500 + i)
+        h = synth.random_taps(L, seed=600 + i)
+        if i == 3:                                     # Eq. (5) extreme for this channel
+            x[:] = -16
+            h[:, 0], h[:, 1] = -32, 31
+        chans.append((x, h, int(rng.integers(0, 9)), i % 2))
+    entries, refs = [], []
+    w0 = synth.centre_spike_taps()
+    for x, h, sh, ph in chans:
+        prm = dict(synth.AEQ_DEFAULTS, const_unit=40)
+        M = O.n_symbols(x.shape[0], ph)
+        xd = to_dev(torch, dev, x)
+        out = torch.full((M, 4), 777, dtype=torch.int16, device=dev)
+        taps = to_dev(torch, dev, w0)
+        entries.append((xd, out, taps, fnt.cdc_params(h, sh, ph), fnt.aeq_params(**prm)))
+        refs.append(O.cdc_aeq(x, h, sh, w0, O.params(**prm), phase=ph))
+    plan = fnt.Plan(entries, autotune=False, use_graph=True)
+    plan.set_cdc_variant(1)
+    plan.set_aeq_variant(aeq_variant)
+    assert plan.info()["cdc_variant"] == 1
+    for rep in range(2):
+        for e in entries:
+            e[2].copy_(to_dev(torch, dev, w0))
+        note(f"plan with the direct CDC, AEQ variant {aeq_variant}, replay {rep}")
+        plan.run()
+        torch.cuda.synchronize()
+        for e, (outr, wr, _) in zip(entries, refs):
+            assert np.array_equal(e[1].cpu().numpy(), outr)
+            assert np.array_equal(e[2].cpu().numpy(), wr)
+    with pytest.raises(fnt.FntError):
+        plan.set_cdc_variant(2)
+    plan.close()
+    fnt.fnt_check()
+
+
 def test_plan_determinism_across_schedules(torch_dev):
     """Race check: identical outputs for every launch schedule and wave split."""
     torch, dev = torch_dev
