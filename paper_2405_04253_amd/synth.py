@@ -131,6 +131,7 @@ class Channel:
     osnr_db: float
     symbols: np.ndarray = field(repr=False)   # int8 [nsym][4] transmitted levels (for BER sanity)
     const_unit: int = 64                      # expected 16QAM unit at the equaliser output
+    float_rx: np.ndarray | None = field(default=None, repr=False)   # see gen_channel(keep_float=True)
 
     @property
     def ntaps(self) -> int:
@@ -142,8 +143,11 @@ class Channel:
 
 
 def gen_channel(nsym: int, fibre_km: float = 75.0, osnr_db: float = 22.0,
-                seed: int = 0, ntaps: int | None = None) -> Channel:
-    """Generate ``nsym`` symbols per polarisation -> int8 [2*nsym][4] samples."""
+                seed: int = 0, ntaps: int | None = None, keep_float: bool = False) -> Channel:
+    """Generate ``nsym`` symbols per polarisation -> int8 [2*nsym][4] samples.
+
+    keep_float: also keep the received signal before rounding (float32, on the
+    5-bit grid's scale, over the whole circular FFT length) in ``float_rx``."""
     rng = np.random.default_rng(seed)
     nsym = int(nsym)
     symbols = rng.integers(0, 4, size=(nsym, 4), dtype=np.int8) * 2 - 3
@@ -180,10 +184,15 @@ def gen_channel(nsym: int, fibre_km: float = 75.0, osnr_db: float = 22.0,
         out[:, 2 * p] = y.real
         out[:, 2 * p + 1] = y.imag
     del rot
+    full = out
     out = out[: SPS * nsym]
     rms = float(np.sqrt(np.mean(out.astype(np.float64) ** 2)))
-    q = np.clip(np.rint(out * (SAMPLE_RMS / max(rms, 1e-30))), -16, 15).astype(np.int8)
-    return Channel(np.ascontiguousarray(q), taps, shift, fibre_km, osnr_db, symbols, unit)
+    scale = SAMPLE_RMS / max(rms, 1e-30)
+    q = np.clip(np.rint(out * scale), -16, 15).astype(np.int8)
+    ch = Channel(np.ascontiguousarray(q), taps, shift, fibre_km, osnr_db, symbols, unit)
+    if keep_float:
+        ch.float_rx = full * np.float32(scale)
+    return ch
 
 
 # ---------------------------------------------------------------------------
