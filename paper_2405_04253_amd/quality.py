@@ -17,10 +17,13 @@ that comparison on the synthetic channels of ``synth``:
   (FNT-CDC with 6-bit taps and 5-bit requantisation, FNT-AEQ with 14-bit taps in
   two 7-bit digits), with the given RDE step shifts.
 
-Every output stream is aligned to the transmitted symbols by a data-aided search
-(delay, polarisation, a complex gain, and conjugation, which a real-valued 4x4
-MIMO may converge to), decided to the nearest 16QAM point, and the SER counts
-the second half of the stream (after convergence).
+Every output stream first passes a blind carrier-phase recovery (the fourth-power
+estimator of Viterbi and Viterbi over a sliding window, unwrapped), which only
+matters when the channel carries laser phase noise (``--linewidth``); it is then
+aligned to the transmitted symbols by a data-aided search (delay, polarisation,
+a complex gain, and conjugation, which a real-valued 4x4 MIMO may converge to),
+decided to the nearest 16QAM point, and the SER and the BER (Gray-mapped levels,
+two bits per dimension) count the second half of the stream (after convergence).
 
 ``python -m paper_2405_04253_amd.quality --osnr 14,16,18,20,22,24`` prints one
 JSON line per OSNR and the OSNR each receiver needs for a target SER.
@@ -101,20 +104,42 @@ def float_receiver(rx: np.ndarray, fibre_km: float, nsym: int, mu: float = 1e-5,
     return float_aeq(_normalise(z), mu, cma_blocks=cma_blocks)
 
 
+# ------------------------------------------------------ carrier recovery --
+def cpe_4th_power(y: np.ndarray, window: int = 128) -> np.ndarray:
+    """Blind carrier-phase recovery of complex [2][m]: per symbol, the phase of the
+    window's sum of y^4 (for square 16QAM E[s^4] is a negative real number, so
+    arg(-sum y^4) = 4 theta), unwrapped over the stream; returns y e^{-j theta}.
+    The estimate is ambiguous by multiples of pi/2, which the alignment's complex
+    gain absorbs."""
+    out = np.empty_like(y)
+    k = np.ones(window)
+    for q in range(y.shape[0]):
+        acc = np.convolve(y[q] ** 4, k, mode="same")
+        theta = np.unwrap(np.angle(-acc)) / 4
+        out[q] = y[q] * np.exp(-1j * theta)
+    return out
+
+
 # ---------------------------------------------------------------------- SER --
+def gray_bits(levels: np.ndarray) -> np.ndarray:
+    """Gray code of the 16QAM levels -3, -1, 1, 3 per dimension: 00, 01, 11, 10."""
+    idx = np.rint((np.asarray(levels, np.float64) + 3) / 2).astype(np.int64)
+    return idx ^ (idx >> 1)
+
+
 def tx_complex(symbols: np.ndarray) -> np.ndarray:
     s = symbols.astype(np.float64)
     return np.stack([s[:, 0] + 1j * s[:, 1], s[:, 2] + 1j * s[:, 3]])
 
 
 def align_and_count(y: np.ndarray, symbols: np.ndarray, max_delay: int = 48) -> dict:
-    """SER of equalised complex [2][m] against the transmitted levels int8 [n][4]
-    over the second half of the stream, after a data-aided search for delay,
-    polarisation, complex gain and conjugation per output."""
+    """SER and BER of equalised complex [2][m] against the transmitted levels
+    int8 [n][4] over the second half of the stream, after a data-aided search for
+    delay, polarisation, complex gain and conjugation per output."""
     s = tx_complex(symbols)
     m = min(y.shape[1], s.shape[1])
     lo, hi = m // 2, m - max_delay
-    errors, count, picks = 0, 0, []
+    errors, bit_errors, count, picks = 0, 0, 0, []
     for q in range(2):
         yq = y[q, lo:hi]
         best = None
@@ -133,9 +158,13 @@ def align_and_count(y: np.ndarray, symbols: np.ndarray, max_delay: int = 48) -> 
         dec = LEVELS[np.abs(yn.real[:, None] - LEVELS[None, :]).argmin(1)] + \
             1j * LEVELS[np.abs(yn.imag[:, None] - LEVELS[None, :]).argmin(1)]
         errors += int(np.count_nonzero(dec != ref))
+        for part in (np.real, np.imag):
+            diff = gray_bits(part(dec)) ^ gray_bits(part(ref))
+            bit_errors += int(np.sum((diff & 1) + (diff >> 1)))
         count += ref.shape[0]
         picks.append(dict(out=q, tx=p, conj=conj, delay=d))
-    return dict(ser=errors / max(count, 1), errors=errors, symbols=count, alignment=picks)
+    return dict(ser=errors / max(count, 1), ber=bit_errors / max(4 * count, 1), errors=errors,
+                bit_errors=bit_errors, symbols=count, alignment=picks)
 
 
 # -------------------------------------------------------------- FNT receiver --
@@ -174,6 +203,8 @@ def main(argv=None):
     ap.add_argument("--km", type=float, default=75.0)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--target", type=float, default=1e-2)
+    ap.add_argument("--linewidth", type=float, default=0.0, help="combined laser linewidth, Hz")
+    ap.add_argument("--cpe-window", type=int, default=128)
     ap.add_argument("--no-gpu", action="store_true", help="float receivers only")
     args = ap.parse_args(argv)
     osnrs = [float(v) for v in args.osnr.split(",")]
@@ -182,17 +213,19 @@ def main(argv=None):
     for se, sm in settings:
         curves[f"fnt_{se}_{sm}"] = []
     for o in osnrs:
-        ch = synth.gen_channel(args.nsym, args.km, o, synth.seed_for(args.seed, "quality", o), keep_float=True)
-        row = {"osnr_db": o, "fibre_km": args.km, "nsym": args.nsym}
-        row["float_ideal"] = align_and_count(float_receiver(ch.float_rx, args.km, args.nsym), ch.symbols)["ser"]
-        row["float_5bit"] = align_and_count(float_receiver(ch.samples, args.km, args.nsym), ch.symbols)["ser"]
+        ch = synth.gen_channel(args.nsym, args.km, o, synth.seed_for(args.seed, "quality", o), keep_float=True,
+                               linewidth_hz=args.linewidth)
+        row = {"osnr_db": o, "fibre_km": args.km, "nsym": args.nsym, "linewidth_hz": args.linewidth,
+               "ser": {}, "ber": {}}
+        outs = {"float_ideal": lambda: float_receiver(ch.float_rx, args.km, args.nsym),
+                "float_5bit": lambda: float_receiver(ch.samples, args.km, args.nsym)}
         if not args.no_gpu:
             for se, sm in settings:
-                row[f"fnt_{se}_{sm}"] = align_and_count(fnt_receiver(ch, err_shift=se, mu_shift=sm),
-                                                        ch.symbols)["ser"]
-        for k in curves:
-            if k in row:
-                curves[k].append(row[k])
+                outs[f"fnt_{se}_{sm}"] = (lambda se=se, sm=sm: fnt_receiver(ch, err_shift=se, mu_shift=sm))
+        for name, run in outs.items():
+            r = align_and_count(cpe_4th_power(run(), args.cpe_window), ch.symbols)
+            row["ser"][name], row["ber"][name] = r["ser"], r["ber"]
+            curves[name].append(r["ser"])
         print(json.dumps(row), flush=True)
     need = {k: required_osnr(osnrs, v, args.target) for k, v in curves.items() if v}
     print(json.dumps({"target_ser": args.target, "required_osnr_db": need}), flush=True)

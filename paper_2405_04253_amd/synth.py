@@ -143,11 +143,16 @@ class Channel:
 
 
 def gen_channel(nsym: int, fibre_km: float = 75.0, osnr_db: float = 22.0,
-                seed: int = 0, ntaps: int | None = None, keep_float: bool = False) -> Channel:
+                seed: int = 0, ntaps: int | None = None, keep_float: bool = False,
+                linewidth_hz: float = 0.0) -> Channel:
     """Generate ``nsym`` symbols per polarisation -> int8 [2*nsym][4] samples.
 
     keep_float: also keep the received signal before rounding (float32, on the
-    5-bit grid's scale, over the whole circular FFT length) in ``float_rx``."""
+    5-bit grid's scale, over the whole circular FFT length) in ``float_rx``.
+    linewidth_hz: combined laser linewidth; > 0 rotates the received signal of
+    both polarisations by one Wiener phase process (increment variance
+    2 pi linewidth / sample rate per sample), drawn from its own generator so
+    that every other value of the channel stays as without it."""
     rng = np.random.default_rng(seed)
     nsym = int(nsym)
     symbols = rng.integers(0, 4, size=(nsym, 4), dtype=np.int8) * 2 - 3
@@ -184,6 +189,15 @@ def gen_channel(nsym: int, fibre_km: float = 75.0, osnr_db: float = 22.0,
         out[:, 2 * p] = y.real
         out[:, 2 * p + 1] = y.imag
     del rot
+    if linewidth_hz > 0:
+        prng = np.random.default_rng([seed, 0x9E37])
+        step = math.sqrt(2 * math.pi * linewidth_hz / (BAUD * SPS))
+        phi = np.cumsum(prng.standard_normal(nfft) * step)
+        rotc = np.exp(1j * phi)
+        for p in range(2):
+            z = (out[:, 2 * p] + 1j * out[:, 2 * p + 1]) * rotc
+            out[:, 2 * p] = z.real
+            out[:, 2 * p + 1] = z.imag
     full = out
     out = out[: SPS * nsym]
     rms = float(np.sqrt(np.mean(out.astype(np.float64) ** 2)))
