@@ -195,16 +195,25 @@ def _time_events(torch, fn, reps, stream):
     return float(np.mean([a.elapsed_time(b) for a, b in evs]))
 
 
+AEQ_FORM_KERNEL = {0: "aeq_lane_kernel<1>", 3: "aeq_duo_kernel<1>", 1: "aeq_pol_kernel<4>",
+                   2: "aeq_pol_kernel<8>", 4: "aeq_pol_kernel<16>"}
+
+
 def aeq_kernel_name(info) -> str:
+    """Kernel of the AEQ launch on the launch stream (the channels after a
+    pipelined lead, or every channel)."""
     lpt = {1: 4, 2: 8, 4: 16}
-    form = {0: "aeq_lane_kernel<1>", 3: "aeq_duo_kernel<1>", 1: "aeq_pol_kernel<4>", 2: "aeq_pol_kernel<8>",
-            4: "aeq_pol_kernel<16>"}
+    form = AEQ_FORM_KERNEL
     if info["aeq_variant"] == 0:
         wl, ws = info["aeq_waves_long"], info["aeq_waves_per_pol"]
-        if info["aeq_long_channels"] and ((wl in (1, 2, 4) and ws in (0, 3)) or (wl, ws) == (3, 0)):
+        nlong = max(info["aeq_long_channels"] - info["lead_channels"], 0)
+        rest = info["channels"] - info["lead_channels"]
+        if nlong >= rest:
+            return form[wl]
+        if nlong and ((wl in (1, 2, 4) and ws in (0, 3)) or (wl, ws) == (3, 0)):
             return "aeq_split_kernel<%d, %d, %d>" % (wl, ws, {1: 1, 3: 1, 2: 2, 4: 4}[wl])  # one launch
         k = form[ws]
-        if info["aeq_long_channels"]:
+        if nlong:
             k = form[wl] + "+" + k
         return k
     if info["aeq_variant"] == 1:
@@ -287,37 +296,34 @@ def bench_batched(args, torch, dev):
     progress(f"batched: plan ready in {tune_s:.1f} s: {info}")
     w_all = w0.unsqueeze(0).expand_as(taps_all)
 
-    def step(ev=None):
+    def step():
         taps_all.copy_(w_all)               # fresh adaptive state every step
-        if ev is not None:
-            ev[0].record(stream)
-        plan.run_stage(fnt.FNT_STAGE_CDC, stream)
-        if ev is not None:
-            ev[1].record(stream)
-        plan.run_stage(fnt.FNT_STAGE_AEQ, stream)
-        if ev is not None:
-            ev[2].record(stream)
+        # the plan's launch sequence, launched directly with HIP events around
+        # every launch on the stream it runs on (the lead's AEQ on the plan's
+        # side stream); waits for the step to end
+        return plan.run_timed(stream)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     fnt.fnt_check()
     progress(f"batched: timing {args.steps} steps")
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(evs[k])
+    times = [step() for _ in range(args.steps)]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     fnt.fnt_check()
-    cdc_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
-    aeq_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    cdc_ms = float(np.mean([t["cdc_ms"] for t in times]))
+    aeq_ms = float(np.mean([t["aeq_ms"] for t in times]))
+    lead_ms = float(np.mean([t["aeq_lead_ms"] for t in times]))
+    event_step_ms = float(np.mean([t["step_ms"] for t in times]))
     ms = wall / max(args.steps, 1) * 1e3
-    progress(f"batched: {ms:.1f} ms per step (cdc {cdc_ms:.1f} ms, aeq {aeq_ms:.1f} ms)")
-    # the captured graph of the same plan, for comparison
+    progress(f"batched: {ms:.1f} ms per step (events {event_step_ms:.1f}: cdc {cdc_ms:.1f} ms, "
+             f"aeq {aeq_ms:.1f} ms, lead aeq {lead_ms:.1f} ms)")
+    # fnt_plan_run of the same plan (the graph replay when no lead is in effect), for comparison
     taps_all.copy_(w_all)
-    graph_ms = _time_events(torch, plan.run, 2, stream)
+    run_ms = _time_events(torch, plan.run, 2, stream)
     # parity on sampled channels: reset the taps, run once more, compare with the oracle
     taps_all.copy_(w_all)
     plan.run(stream)
@@ -353,29 +359,26 @@ def bench_batched(args, torch, dev):
     ref_taps = {i: taps_all[i].clone() for i in pick}
     plan.set_cdc_variant(1)
     plan.set_aeq_variant(1)
-    cmp_ev = []
+    cmp_t = []
     for k in range(2):
         taps_all.copy_(w_all)
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-        ev[0].record(stream)
-        plan.run_stage(fnt.FNT_STAGE_CDC, stream)
-        ev[1].record(stream)
-        plan.run_stage(fnt.FNT_STAGE_AEQ, stream)
-        ev[2].record(stream)
-        cmp_ev.append(ev)
+        cmp_t.append(plan.run_timed(stream))
     torch.cuda.synchronize()
     fnt.fnt_check()
     for i in pick:
         if not (torch.equal(entries[i][1], ref_out[i]) and torch.equal(taps_all[i], ref_taps[i])):
             raise SystemExit(f"direct comparator differs on channel {i}")
-    d_cdc = float(np.mean([e[0].elapsed_time(e[1]) for e in cmp_ev]))
-    d_aeq = float(np.mean([e[1].elapsed_time(e[2]) for e in cmp_ev]))
+    d_cdc = float(np.mean([t["cdc_ms"] for t in cmp_t]))
+    d_aeq = float(np.mean([t["aeq_ms"] for t in cmp_t]))
+    d_step = float(np.mean([t["step_ms"] for t in cmp_t]))
     plan.set_cdc_variant(0)
     plan.set_aeq_variant(0)
     value = inst / (ms / 1e3) / 1e9
-    aeq_blocks = sum((e[0].shape[0] // 2 + 15) // 16 for e in entries)
+    aeq_blocks = times[0]["aeq_blocks"]           # the AEQ launch on the launch stream
+    lead_blocks = times[0]["aeq_lead_blocks"]
     cdc_blocks = sum((e[0].shape[0] + 31) // 32 for e in entries)
     aeq_ops = AEQ_OPS_PER_BLOCK * aeq_blocks
+    all_aeq_ops = AEQ_OPS_PER_BLOCK * (aeq_blocks + lead_blocks)
     cdc_ops = CDC_OPS_PER_BLOCK * cdc_blocks
     achieved = aeq_ops / (aeq_ms / 1e3) / 1e9
     kname = aeq_kernel_name(info)
@@ -390,9 +393,17 @@ def bench_batched(args, torch, dev):
                           else "cdc_kernel<false>", "ms": round(cdc_ms, 3),
                 "gops": round(cdc_ops / cdc_ms / 1e6, 1), "frac_alu": round(cdc_ops / cdc_ms / 1e6 / PEAK_ALU_GOPS, 5),
                 "gbs": round(inst * CDC_BYTES_PER_INSTANT / cdc_ms / 1e6, 1)},
-        "aeq": {"kernel": kname, "ms": round(aeq_ms, 3), "gops": round(achieved, 1),
-                "us_per_block_per_channel_longest": round(aeq_ms * 1e3 / max(info["aeq_blocks_max"], 1), 4)},
+        "aeq": {"kernel": kname, "ms": round(aeq_ms, 3), "gops": round(achieved, 1), "blocks": aeq_blocks,
+                "us_per_block_per_channel_longest":
+                    round(max(aeq_ms, lead_ms) * 1e3 / max(info["aeq_blocks_max"], 1), 4)},
     }
+    if info["lead_channels"]:
+        kernels["aeq_lead"] = {
+            "kernel": AEQ_FORM_KERNEL[info["aeq_waves_long"]], "channels": info["lead_channels"],
+            "ms": round(lead_ms, 3), "blocks": lead_blocks,
+            "gops": round(AEQ_OPS_PER_BLOCK * lead_blocks / lead_ms / 1e6, 1),
+            "what": "the longest channels' AEQ, started after their own CDC on a second stream, "
+                    "concurrent with the other channels' CDC and AEQ"}
     res = {
         "metric": METRIC,
         "value": round(value, 4), "unit": "Gsamples/s", "n_gpus": 1,
@@ -408,17 +419,19 @@ def bench_batched(args, torch, dev):
                        "sample": f"{len(sample)} random channels, fnt_cdc_aeq one after another"},
         "roofline": roof,
         "kernels": kernels,
-        "graph_ms_per_run": round(graph_ms, 3),
+        "plan_run_ms": round(run_ms, 3),
+        "event_ms_per_step": round(event_step_ms, 3),
         "direct_comparator": {
-            "value": round(inst / ((d_cdc + d_aeq) / 1e3) / 1e9, 4), "unit": "Gsamples/s",
-            "cdc_ms": round(d_cdc, 3), "aeq_ms": round(d_aeq, 3),
+            "value": round(inst / (d_step / 1e3) / 1e9, 4), "unit": "Gsamples/s",
+            "cdc_ms": round(d_cdc, 3), "aeq_ms": round(d_aeq, 3), "step_ms": round(d_step, 3),
             "what": "same plan, time-domain CDC (int8 dot products over the 32-instant window) and "
                     "time-domain AEQ, no Fermat-domain arithmetic; bit-identical on the parity channels"},
-        "roofline_whole_path": {"bound": "alu", "achieved": round((aeq_ops + cdc_ops) / (ms / 1e3) / 1e9, 1),
+        "roofline_whole_path": {"bound": "alu", "achieved": round((all_aeq_ops + cdc_ops) / (ms / 1e3) / 1e9, 1),
                                 "peak": PEAK_ALU_GOPS, "unit": "Gops/s",
-                                "frac": round((aeq_ops + cdc_ops) / (ms / 1e3) / 1e9 / PEAK_ALU_GOPS, 5)},
+                                "frac": round((all_aeq_ops + cdc_ops) / (ms / 1e3) / 1e9 / PEAK_ALU_GOPS, 5)},
         "plan": {k: info[k] for k in ("cdc_waves_per_group", "cdc_blocks_per_wave", "aeq_variant",
-                                      "aeq_waves_per_pol", "aeq_waves_long", "aeq_long_channels", "graph")},
+                                      "aeq_waves_per_pol", "aeq_waves_long", "aeq_long_channels",
+                                      "lead_channels", "graph")},
         "parity": f"bit-exact vs oracle on channels {pick}", "gen_s": round(gen_s, 1),
         "autotune_s": round(tune_s, 1),
     }

@@ -184,12 +184,12 @@ typedef struct fnt_plan_info {
     int32_t aeq_variant;   /* 0 = Fermat-domain filtering (the method), 1 = direct comparator,
                               2 = Fermat-domain, one wave per channel */
     int32_t aeq_waves_per_pol;  /* variant 0: AEQ form (0, 3, 1, 2, 4; see fnt_plan_set_aeq_waves) */
-    int32_t graph;         /* 1 if a hipGraph is replayed */
+    int32_t graph;         /* 1 if fnt_plan_run replays a hipGraph (never while a lead is in effect) */
     int32_t aeq_waves_long;     /* AEQ form of the long chains (see fnt_plan_set_aeq_split) */
     double tune_ms;        /* AEQ time of the chosen schedule during autotune, ms (0 if none) */
     uint64_t aeq_long_channels; /* longest channels run in their own concurrent launch */
     int32_t cdc_variant;   /* 0 = Fermat-domain (the method), 1 = direct comparator */
-    int32_t reserved;
+    int32_t lead_channels; /* pipelined lead channels in effect (see fnt_plan_set_lead) */
 } fnt_plan_info;
 
 typedef struct fnt_plan fnt_plan;
@@ -210,7 +210,8 @@ int fnt_plan_run(fnt_plan *plan, void *stream);
 #define FNT_STAGE_ALL 3
 /* Launch the stages in `stages` (a mask of FNT_STAGE_*) directly on `stream`,
  * outside the plan's graph, so that a caller can bracket each with its own
- * events.  FNT_STAGE_CDC then FNT_STAGE_AEQ is exactly one fnt_plan_run; the
+ * events.  FNT_STAGE_CDC then FNT_STAGE_AEQ computes exactly what one
+ * fnt_plan_run does (the stages never pipeline a lead, fnt_plan_set_lead); the
  * AEQ stage alone recomputes the AEQ from whatever the last CDC stage left in
  * the scratch (taps continue from their current state).  FNT_E_INVAL for a
  * mask outside FNT_STAGE_ALL. */
@@ -229,7 +230,7 @@ int fnt_plan_set_aeq_variant(fnt_plan *plan, int variant);
  *      two channels per wave;
  *   3: two lanes per transform, one channel per wave;
  *   1, 2, 4: split by output polarisation, that many waves per half.
- * Overrides the default / autotuned choice. */
+ * Overrides the default / autotuned choice, including any split and lead. */
 int fnt_plan_set_aeq_waves(fnt_plan *plan, int waves_per_pol);
 /* Split the AEQ of a plan: the `long_channels` channels with the longest chains
  * run with `wpp_long` waves per polarisation half (short serial latency) in a
@@ -248,6 +249,36 @@ int fnt_plan_set_cdc_variant(fnt_plan *plan, int variant);
  * (16 lanes per 64-point transform) and a wave takes that many consecutive
  * blocks.  Results do not depend on it. */
 int fnt_plan_set_cdc_schedule(fnt_plan *plan, int waves_per_group, int blocks_per_wave);
+/* Pipelined lead: the CDC of the `lead_channels` channels with the longest AEQ
+ * chains runs first; their AEQ (in the long chains' form, at raised wave
+ * priority) then starts on the plan's side stream while the CDC and the AEQ of
+ * the other channels run on the launch stream, so the longest serial chains do
+ * not wait for the whole batch's CDC.  The other channels keep the split of
+ * fnt_plan_set_aeq_split for those of them among the long channels.  0 (default
+ * unless the autotuner chose one) runs every CDC before any AEQ.  In effect only
+ * with the Fermat-domain AEQ, for 0 < lead_channels < channels, and when the
+ * other channels' AEQ is one launch (no long channels left among them, or a
+ * split that runs as one launch); otherwise the plan runs without a lead.
+ * While a lead is in effect fnt_plan_run launches the sequence directly instead
+ * of replaying the plan's graph.  Results never depend on it.  FNT_E_INVAL for a NULL plan; FNT_E_DEVICE if the
+ * table of the other channels cannot be uploaded. */
+int fnt_plan_set_lead(fnt_plan *plan, uint64_t lead_channels);
+
+typedef struct fnt_plan_timing {
+    float step_ms;          /* first launch to the end of the last, on the launch stream */
+    float cdc_ms;           /* the CDC launches, back to back on the launch stream */
+    float aeq_ms;           /* the AEQ launch on the launch stream: the channels after the lead
+                               (every channel without a lead) */
+    float aeq_lead_ms;      /* the lead channels' AEQ launch on the side stream (0 without a lead) */
+    uint64_t aeq_blocks;    /* 16-symbol AEQ blocks of the channels aeq_ms covers */
+    uint64_t aeq_lead_blocks;  /* 16-symbol AEQ blocks of the lead channels */
+} fnt_plan_timing;
+/* Run every channel once, as fnt_plan_run does, but launch the sequence
+ * directly (never the graph) with HIP events around every launch on the stream
+ * it runs on; wait for the run to end and report the durations in `timing`
+ * (caller-owned host struct).  Blocks the calling thread.  FNT_E_INVAL for NULL
+ * arguments, FNT_E_DEVICE on a HIP error. */
+int fnt_plan_run_timed(fnt_plan *plan, fnt_plan_timing *timing, void *stream);
 
 /* ------------------------------------------------------------------------
  * Serving sessions: continuing per-channel streams with device-resident state.

@@ -289,39 +289,69 @@ struct fnt_plan {
     // per half in a launch concurrent with the rest
     int wpp_long = 4;
     size_t n_long = 0;
+    // pipelined lead: the n_lead longest channels' CDC first, their AEQ on the side
+    // stream concurrently with the others' CDC and AEQ; cdc_rest_dev holds the
+    // items [n_lead, n) with block0 / chunk0 rebased to 0 (built for rest_lead)
+    size_t n_lead = 0, rest_lead = 0;
+    CdcItem *cdc_rest_dev = nullptr;
     hipStream_t side = nullptr;        // second stream for the concurrent AEQ launch
     hipEvent_t fork = nullptr, join = nullptr;
+    hipEvent_t tev[6] = {};            // fnt_plan_run_timed
     bool use_graph = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
 
-// Launch sequence of a plan on stream s: CDC over all blocks, then the AEQ of
-// the long chains on s concurrently with the AEQ of the others on a side stream
-// (fork / join by events, which a graph capture turns into parallel branches).
+// The CDC of the table `tab` (nitems items whose block0 / chunk0 start at 0).
+static hipError_t plan_cdc(fnt_plan *p, const CdcItem *tab, int nitems, uint64_t blocks, uint64_t chunks,
+                           hipStream_t s) {
+    return p->cdc_variant == 1 ? launch_cdc(tab, nitems, CdcItem{}, blocks, chunks, 2, p->wpg, 1, false, p->err, s)
+                               : run_cdc(tab, nitems, CdcItem{}, blocks, chunks, p->wpg, p->bpw, false, p->err, s);
+}
+
 static int plan_launch_cdc(fnt_plan *p, hipStream_t s) {
-    hipError_t e = p->cdc_variant == 1
-                       ? launch_cdc(p->cdc_dev, (int)p->cdc_host.size(), CdcItem{}, p->total_blocks,
-                                    p->total_chunks, 2, p->wpg, 1, false, p->err, s)
-                       : run_cdc(p->cdc_dev, (int)p->cdc_host.size(), CdcItem{}, p->total_blocks, p->total_chunks,
-                                 p->wpg, p->bpw, false, p->err, s);
+    hipError_t e = plan_cdc(p, p->cdc_dev, (int)p->cdc_host.size(), p->total_blocks, p->total_chunks, s);
     if (e != hipSuccess) return hip_fail(e, "plan: cdc launch");
     return FNT_OK;
+}
+
+// The AEQ of the items [first, n) of the longest-first table, of which the
+// first nl run in the long chains' form: one launch on s when possible.
+static bool plan_aeq_one_launch(const fnt_plan *p, int nl, int count) {
+    return p->variant != 0 || nl == 0 || nl >= count || aeq_split_fusable(p->wpp_long, p->wpp);
+}
+
+static hipError_t plan_aeq_range(fnt_plan *p, int first, int nl, int count, hipStream_t s) {
+    const AeqItem *items = p->aeq_dev + first;
+    if (p->variant != 0 || nl == 0 || nl >= count) {
+        const int w = (p->variant == 0 && nl >= count) ? p->wpp_long : p->wpp;
+        return launch_aeq(items, count, AeqItem{}, p->variant, w, p->err, s);
+    }
+    return launch_aeq_split(items, nl, count, p->wpp_long, p->wpp, p->err, s);   // long chains dispatched first
+}
+
+// Lead channels in effect for the plan's current schedule (0: none).
+static size_t plan_lead(const fnt_plan *p) {
+    const size_t n = p->aeq_host.size();
+    if (p->variant != 0 || p->n_lead == 0 || p->n_lead >= n || p->rest_lead != p->n_lead || !p->cdc_rest_dev)
+        return 0;
+    const size_t rest_long = p->n_long > p->n_lead ? p->n_long - p->n_lead : 0;
+    return plan_aeq_one_launch(p, (int)rest_long, (int)(n - p->n_lead)) ? p->n_lead : 0;
+}
+
+static uint64_t aeq_blocks_of(const fnt_plan *p, size_t lo, size_t hi) {
+    uint64_t b = 0;
+    for (size_t i = lo; i < hi; ++i) b += (p->aeq_host[i].m + 15) / 16;
+    return b;
 }
 
 static int plan_launch_aeq(fnt_plan *p, hipStream_t s, hipStream_t side) {
     const int n = (int)p->aeq_host.size();
     const int nl = (int)std::min<size_t>(p->n_long, (size_t)n);
     hipError_t e;
-    if (nl == 0 || nl == n || p->variant != 0) {
-        const int w = (p->variant == 0 && nl == n) ? p->wpp_long : p->wpp;
-        e = launch_aeq(p->aeq_dev, n, AeqItem{}, p->variant, w, p->err, s);
+    if (plan_aeq_one_launch(p, nl, n)) {
+        e = plan_aeq_range(p, 0, nl, n, s);
         if (e != hipSuccess) return hip_fail(e, "plan: aeq launch");
-        return FNT_OK;
-    }
-    if (aeq_split_fusable(p->wpp_long, p->wpp)) {      // one launch, long chains dispatched first
-        e = launch_aeq_split(p->aeq_dev, nl, n, p->wpp_long, p->wpp, p->err, s);
-        if (e != hipSuccess) return hip_fail(e, "plan: aeq split launch");
         return FNT_OK;
     }
     e = hipEventRecord(p->fork, s);
@@ -334,12 +364,68 @@ static int plan_launch_aeq(fnt_plan *p, hipStream_t s, hipStream_t side) {
     return FNT_OK;
 }
 
-// Launch sequence of a plan on stream s: CDC over all blocks, then the AEQ of
-// the long chains on s concurrently with the AEQ of the others on a side stream
-// (fork / join by events, which a graph capture turns into parallel branches).
-static int plan_launch(fnt_plan *p, hipStream_t s, hipStream_t side) {
-    int rc = plan_launch_cdc(p, s);
-    return rc ? rc : plan_launch_aeq(p, s, side);
+// Launch sequence of a plan on stream s.  Without a lead: the CDC over all
+// blocks, then the AEQ (one launch, or the long chains on s concurrently with
+// the others on the side stream).  With a lead of L channels: the CDC of the L
+// longest channels; fork; their AEQ on the side stream; the CDC of the others
+// and their AEQ on s; join.  Fork / join are events, which a graph capture
+// turns into parallel branches.  `ev` (timing, direct launches only) receives
+// start, CDC end, lead AEQ start, lead AEQ end, AEQ end and done.
+static int plan_launch(fnt_plan *p, hipStream_t s, hipStream_t side, hipEvent_t *ev = nullptr) {
+    auto rec = [&](int i, hipStream_t st) { return ev ? hipEventRecord(ev[i], st) : hipSuccess; };
+    hipError_t e = rec(0, s);
+    const size_t lead = plan_lead(p);
+    if (lead == 0) {
+        int rc = e == hipSuccess ? plan_launch_cdc(p, s) : hip_fail(e, "plan: timing event");
+        if (!rc && (e = rec(1, s)) != hipSuccess) rc = hip_fail(e, "plan: timing event");
+        if (!rc) rc = plan_launch_aeq(p, s, side);
+        if (!rc && (e = rec(4, s)) != hipSuccess) rc = hip_fail(e, "plan: timing event");
+        if (!rc && (e = rec(5, s)) != hipSuccess) rc = hip_fail(e, "plan: timing event");
+        return rc;
+    }
+    const size_t n = p->aeq_host.size();
+    const CdcItem &r0 = p->cdc_host[lead];
+    const int rest_long = (int)(p->n_long > lead ? p->n_long - lead : 0);
+    if (e == hipSuccess) e = plan_cdc(p, p->cdc_dev, (int)lead, r0.block0, r0.chunk0, s);
+    if (e == hipSuccess) e = hipEventRecord(p->fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side, p->fork, 0);
+    if (e == hipSuccess) e = rec(2, side);
+    if (e == hipSuccess) e = launch_aeq(p->aeq_dev, (int)lead, AeqItem{}, 0, p->wpp_long, p->err, side, true);
+    if (e == hipSuccess) e = rec(3, side);
+    if (e == hipSuccess)
+        e = plan_cdc(p, p->cdc_rest_dev, (int)(n - lead), p->total_blocks - r0.block0, p->total_chunks - r0.chunk0, s);
+    if (e == hipSuccess) e = rec(1, s);
+    if (e == hipSuccess) e = plan_aeq_range(p, (int)lead, rest_long, (int)(n - lead), s);
+    if (e == hipSuccess) e = rec(4, s);
+    if (e == hipSuccess) e = hipEventRecord(p->join, side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, p->join, 0);
+    if (e == hipSuccess) e = rec(5, s);
+    if (e != hipSuccess) return hip_fail(e, "plan: pipelined launch");
+    return FNT_OK;
+}
+
+// Upload the table of the items after a lead of `lead` channels, rebased so that
+// its first item starts at block 0 and chunk 0 (synchronous on s).
+static int plan_build_rest(fnt_plan *p, size_t lead, hipStream_t s) {
+    const size_t n = p->cdc_host.size();
+    if (lead == 0 || lead >= n) {
+        p->rest_lead = 0;
+        return FNT_OK;
+    }
+    hipError_t e = hipSuccess;
+    if (!p->cdc_rest_dev) e = hipMalloc(&p->cdc_rest_dev, n * sizeof(CdcItem));
+    if (e != hipSuccess) return fail(FNT_E_NOMEM, "plan: lead table: %s", hipGetErrorString(e));
+    std::vector<CdcItem> rest(p->cdc_host.begin() + lead, p->cdc_host.end());
+    const uint64_t b0 = rest[0].block0, c0 = rest[0].chunk0;
+    for (CdcItem &c : rest) {
+        c.block0 -= b0;
+        c.chunk0 -= c0;
+    }
+    e = hipMemcpyAsync(p->cdc_rest_dev, rest.data(), rest.size() * sizeof(CdcItem), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "plan: upload lead table");
+    p->rest_lead = lead;
+    return FNT_OK;
 }
 
 static void plan_drop_graph(fnt_plan *p) {
@@ -384,7 +470,7 @@ static int plan_capture(fnt_plan *p, hipStream_t s) {
     return FNT_OK;
 }
 
-constexpr int kTuneVersion = 3;
+constexpr int kTuneVersion = 4;
 
 static std::string tune_key(const fnt_plan *p) {
     // length histogram (log2 buckets of instants) + channel count + variant
@@ -405,13 +491,15 @@ static std::string tune_key(const fnt_plan *p) {
     return k.str();
 }
 
+// The last entry for `key`; the values are range-checked by the caller.
 static bool tune_cache_lookup(const char *path, const std::string &key, int *wpg, int *bpw, int *wpp,
-                              int *wpp_long, long long *n_long) {
+                              int *wpp_long, long long *n_long, long long *n_lead) {
     if (!path) return false;
     std::ifstream f(path);
     std::string line;
+    bool found = false;
     while (std::getline(f, line)) {
-        // one JSON object per line: {"key": "...", "wpg": W, "bpw": B}
+        // one JSON object per line: {"key": "...", "wpg": W, "bpw": B, ...}
         size_t a = line.find("\"key\": \"");
         if (a == std::string::npos) continue;
         size_t b = line.find('"', a + 8);
@@ -422,29 +510,27 @@ static bool tune_cache_lookup(const char *path, const std::string &key, int *wpg
         w = std::atoi(line.c_str() + pw + 7);
         bb = std::atoi(line.c_str() + pb + 7);
         pp = std::atoi(line.c_str() + pq + 7);
-        size_t pl = line.find("\"wpp_long\": "), pn = line.find("\"n_long\": ");
-        if (pl == std::string::npos || pn == std::string::npos) continue;
-        int ql = std::atoi(line.c_str() + pl + 12);
-        long long nl = std::atoll(line.c_str() + pn + 10);
-        if (w >= 1 && w <= 4 && bb >= 1 && (pp == 1 || pp == 2 || pp == 4) &&
-            (ql == 1 || ql == 2 || ql == 4) && nl >= 0) {
-            *wpg = w;
-            *bpw = bb;
-            *wpp = pp;
-            *wpp_long = ql;
-            *n_long = nl;
-            return true;
-        }
+        size_t pl = line.find("\"wpp_long\": "), pn = line.find("\"n_long\": "),
+               pd = line.find("\"n_lead\": ");
+        if (pl == std::string::npos || pn == std::string::npos || pd == std::string::npos) continue;
+        *wpg = w;
+        *bpw = bb;
+        *wpp = pp;
+        *wpp_long = std::atoi(line.c_str() + pl + 12);
+        *n_long = std::atoll(line.c_str() + pn + 10);
+        *n_lead = std::atoll(line.c_str() + pd + 10);
+        found = true;
     }
-    return false;
+    return found;
 }
 
 static void tune_cache_store(const char *path, const std::string &key, int wpg, int bpw, int wpp,
-                             int wpp_long, long long n_long, double ms) {
+                             int wpp_long, long long n_long, long long n_lead, double ms) {
     if (!path) return;
     std::ofstream f(path, std::ios::app);
     f << "{\"key\": \"" << key << "\", \"wpg\": " << wpg << ", \"bpw\": " << bpw << ", \"wpp\": " << wpp
-      << ", \"wpp_long\": " << wpp_long << ", \"n_long\": " << n_long << ", \"ms\": " << ms << "}\n";
+      << ", \"wpp_long\": " << wpp_long << ", \"n_long\": " << n_long << ", \"n_lead\": " << n_lead
+      << ", \"ms\": " << ms << "}\n";
 }
 
 // Default AEQ schedule: with few channels the chip is idle, so spread each
@@ -460,14 +546,16 @@ static int default_wpp(size_t nch) { return nch >= 512 ? 3 : (nch >= 128 ? 2 : 4
 static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
     std::string key = tune_key(p);
     int w, b, q, ql;
-    long long nl;
-    if (tune_cache_lookup(cache, key, &w, &b, &q, &ql, &nl) && (w == 1 || w == 2 || w == 4) && b >= 0 &&
-        b <= 1024 && valid_form(q) && valid_form(ql) && nl >= 0) {
+    long long nl, nd;
+    if (tune_cache_lookup(cache, key, &w, &b, &q, &ql, &nl, &nd) && (w == 1 || w == 2 || w == 4) && b >= 0 &&
+        b <= 1024 && valid_form(q) && valid_form(ql) && nl >= 0 && nd >= 0 &&
+        (size_t)nd < std::max<size_t>(1, p->aeq_host.size())) {
         p->wpg = w;
         p->bpw = b;
         p->wpp = q;
         p->wpp_long = ql;
         p->n_long = (size_t)nl;
+        p->n_lead = (size_t)nd;
         return FNT_OK;
     }
     hipEvent_t e0, e1;
@@ -509,7 +597,7 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
     AeqItem *tdev = nullptr;
     double best_aeq = 1e30;
     int bq = p->wpp, bql = p->wpp_long;
-    size_t bnl = p->n_long;
+    size_t bnl = p->n_long, bnd = 0;
     if (p->variant == 0 && hipMalloc(&tscratch, nch * 256 * sizeof(int16_t)) == hipSuccess &&
         hipMalloc(&tdev, nch * sizeof(AeqItem)) == hipSuccess) {
         std::vector<AeqItem> tab = p->aeq_host;
@@ -570,6 +658,45 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
                     bql = cands[i].ql;
                     bnl = cands[i].nl;
                 }
+            // pipelined lead (whole runs, CDC + AEQ, timed): the lead's size, how
+            // many of the following chains still take the long chains' form, and
+            // the form of the rest; the long chains' form is the one chosen above
+            p->wpg = bw;
+            p->bpw = bb;
+            p->wpp_long = bql;
+            struct LCand { size_t lead, nl; int q; double ms; };
+            std::vector<LCand> leads;
+            auto time_lead = [&](const LCand &c) -> double {
+                if (plan_build_rest(p, c.lead, s)) return 1e30;
+                p->n_lead = c.lead;
+                p->n_long = c.nl;
+                p->wpp = c.q;
+                if (plan_lead(p) != c.lead) return 1e30;
+                return time_it([&] { return plan_launch(p, s, p->side) ? hipErrorUnknown : hipSuccess; });
+            };
+            leads.push_back({0, bnl, bq, 0});                   // the choice above, without a lead
+            for (size_t lead : {32, 128, 256, 512, 768, 1024})
+                for (size_t extra : {0, 128, 256, 512})
+                    for (int q : {0, 3}) {
+                        const size_t nl = lead + extra;
+                        if (lead >= nch || nl > nch) continue;
+                        if (extra > 0 && form_rank(q) >= form_rank(bql)) continue;
+                        leads.push_back({lead, nl, q, 0});
+                    }
+            for (LCand &c : leads) c.ms = time_lead(c);
+            std::sort(leads.begin(), leads.end(), [](const LCand &a, const LCand &b) { return a.ms < b.ms; });
+            for (size_t i = 0; i < leads.size() && i < 4; ++i)
+                for (int rep = 0; rep < 2; ++rep) leads[i].ms = std::min(leads[i].ms, time_lead(leads[i]));
+            double best_run = 1e30;
+            for (size_t i = 0; i < leads.size() && i < 4; ++i)
+                if (leads[i].ms < best_run) {
+                    best_run = leads[i].ms;
+                    bnd = leads[i].lead;
+                    bnl = leads[i].nl;
+                    bq = leads[i].q;
+                }
+            p->n_lead = 0;
+            p->rest_lead = 0;
             p->aeq_dev = saved;
         }
     }
@@ -582,8 +709,9 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
     p->wpp = bq;
     p->wpp_long = bql;
     p->n_long = bnl;
+    p->n_lead = bnd;
     p->info.tune_ms = best_aeq < 1e29 ? best_aeq : best_cdc;
-    tune_cache_store(cache, key, bw, bb, bq, bql, (long long)bnl, p->info.tune_ms);
+    tune_cache_store(cache, key, bw, bb, bq, bql, (long long)bnl, (long long)bnd, p->info.tune_ms);
     return FNT_OK;
 }
 
@@ -639,23 +767,28 @@ int fnt_plan_create(fnt_plan **out, const fnt_channel_desc *ch, size_t nch, cons
                         hipGetErrorString(e));
         }
     }
+    // both tables longest AEQ chain first (the chains bound the makespan), in
+    // the same order, so that a prefix of channels is a prefix of each table
+    std::vector<size_t> order(nch);
+    for (size_t i = 0; i < nch; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+        return n_symbols(ch[a].n, ch[a].cdc.decim_phase) > n_symbols(ch[b].n, ch[b].cdc.decim_phase);
+    });
     p->cdc_host.resize(nch);
     p->aeq_host.resize(nch);
-    for (size_t i = 0; i < nch; ++i) {
+    for (size_t k = 0; k < nch; ++k) {
+        const size_t i = order[k];
         const fnt_channel_desc &d = ch[i];
-        CdcItem &ci = p->cdc_host[i];
+        CdcItem &ci = p->cdc_host[k];
         fill_cdc_item(ci, d.in, d.n, &d.cdc);
         ci.a_out = p->abuf + aoff[i] * 4;
         ci.block0 = blocks;
         ci.chunk0 = chunks;
         blocks += cdc_blocks(d.n);
         chunks += cdc_chunks(d.n);
-        AeqItem &ai = p->aeq_host[i];
+        AeqItem &ai = p->aeq_host[k];
         fill_aeq_item(ai, ci.a_out, n_symbols(d.n, d.cdc.decim_phase), d.taps, &d.aeq, d.out);
     }
-    // longest AEQ chains first: they bound the makespan
-    std::stable_sort(p->aeq_host.begin(), p->aeq_host.end(),
-                     [](const AeqItem &a, const AeqItem &b) { return a.m > b.m; });
     p->total_blocks = blocks;
     p->total_chunks = chunks;
     hipError_t e = hipSuccess;
@@ -694,6 +827,10 @@ int fnt_plan_create(fnt_plan **out, const fnt_channel_desc *ch, size_t nch, cons
             return rc;
         }
     }
+    if ((rc = plan_build_rest(p, p->n_lead, s))) {
+        fnt_plan_destroy(p);
+        return rc;
+    }
     p->use_graph = c.use_graph != 0;
     if (p->use_graph && nch > 0) {
         if ((rc = plan_capture(p, s))) {
@@ -715,7 +852,9 @@ int fnt_plan_run(fnt_plan *p, void *stream) {
     if (!p) return fail(FNT_E_INVAL, "plan: NULL");
     if (p->cdc_host.empty()) return FNT_OK;
     hipStream_t s = (hipStream_t)stream;
-    if (p->exec) {
+    // with a lead the sequence is launched directly: replays of its two-branch
+    // graph ran the branches with less overlap than the direct launches
+    if (p->exec && plan_lead(p) == 0) {
         hipError_t e = hipGraphLaunch(p->exec, s);
         if (e != hipSuccess) return hip_fail(e, "plan: graph launch");
         return FNT_OK;
@@ -743,8 +882,48 @@ int fnt_plan_get_info(const fnt_plan *p, fnt_plan_info *info) {
     info->aeq_waves_per_pol = p->wpp;
     info->aeq_waves_long = p->wpp_long;
     info->aeq_long_channels = p->variant == 0 ? std::min(p->n_long, p->aeq_host.size()) : 0;
-    info->graph = p->exec ? 1 : 0;
+    info->graph = (p->exec && plan_lead(p) == 0) ? 1 : 0;
     info->cdc_variant = p->cdc_variant;
+    info->lead_channels = (int32_t)plan_lead(p);
+    return FNT_OK;
+}
+
+int fnt_plan_set_lead(fnt_plan *p, uint64_t lead) {
+    if (!p) return fail(FNT_E_INVAL, "plan: NULL");
+    const size_t n = p->aeq_host.size();
+    const size_t l = lead < n ? (size_t)lead : 0;
+    int rc = plan_build_rest(p, l, nullptr);
+    if (rc) return rc;
+    p->n_lead = l;
+    if (p->exec) return plan_capture(p, nullptr);
+    return FNT_OK;
+}
+
+int fnt_plan_run_timed(fnt_plan *p, fnt_plan_timing *t, void *stream) {
+    if (!p || !t) return fail(FNT_E_INVAL, "plan run timed: NULL");
+    std::memset(t, 0, sizeof *t);
+    if (p->cdc_host.empty()) return FNT_OK;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 6 && e == hipSuccess; ++i)
+        if (!p->tev[i]) e = hipEventCreate(&p->tev[i]);
+    if (e != hipSuccess) return hip_fail(e, "plan: timing events");
+    const size_t lead = plan_lead(p);
+    int rc = plan_launch(p, s, p->side, p->tev);
+    if (rc) return rc;
+    e = hipEventSynchronize(p->tev[5]);
+    float ms = 0;
+    auto el = [&](int a, int b, float *out) {
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, p->tev[a], p->tev[b]);
+        if (e == hipSuccess) *out = ms;
+    };
+    el(0, 5, &t->step_ms);
+    el(0, 1, &t->cdc_ms);
+    el(1, 4, &t->aeq_ms);
+    if (lead) el(2, 3, &t->aeq_lead_ms);
+    if (e != hipSuccess) return hip_fail(e, "plan: timing");
+    t->aeq_lead_blocks = aeq_blocks_of(p, 0, lead);
+    t->aeq_blocks = aeq_blocks_of(p, lead, p->aeq_host.size());
     return FNT_OK;
 }
 
@@ -769,6 +948,7 @@ int fnt_plan_set_aeq_waves(fnt_plan *p, int wpp) {
     if (!valid_form(wpp)) return fail(FNT_E_INVAL, "plan: AEQ form %d", wpp);
     p->wpp = wpp;
     p->n_long = 0;
+    p->n_lead = 0;
     if (p->exec) return plan_capture(p, nullptr);
     return FNT_OK;
 }
@@ -800,6 +980,9 @@ int fnt_plan_destroy(fnt_plan *p) {
     if (p->side) (void)hipStreamDestroy(p->side);
     if (p->fork) (void)hipEventDestroy(p->fork);
     if (p->join) (void)hipEventDestroy(p->join);
+    for (hipEvent_t ev : p->tev)
+        if (ev) (void)hipEventDestroy(ev);
+    if (p->cdc_rest_dev) (void)hipFree(p->cdc_rest_dev);
     if (p->cdc_dev) (void)hipFree(p->cdc_dev);
     if (p->aeq_dev) (void)hipFree(p->aeq_dev);
     if (p->abuf) (void)hipFree(p->abuf);

@@ -64,7 +64,13 @@ class PlanInfo(ctypes.Structure):
                 ("aeq_waves_per_pol", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("aeq_waves_long", ctypes.c_int32), ("tune_ms", ctypes.c_double),
                 ("aeq_long_channels", ctypes.c_uint64), ("cdc_variant", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("lead_channels", ctypes.c_int32)]
+
+
+class PlanTiming(ctypes.Structure):
+    _fields_ = [("step_ms", ctypes.c_float), ("cdc_ms", ctypes.c_float), ("aeq_ms", ctypes.c_float),
+                ("aeq_lead_ms", ctypes.c_float), ("aeq_blocks", ctypes.c_uint64),
+                ("aeq_lead_blocks", ctypes.c_uint64)]
 
 
 class SessionConfig(ctypes.Structure):
@@ -109,6 +115,8 @@ SIGNATURES = {
     "fnt_plan_set_aeq_waves": (_i32, [_vp, _i32]),
     "fnt_plan_set_cdc_schedule": (_i32, [_vp, _i32, _i32]),
     "fnt_plan_set_aeq_split": (_i32, [_vp, _u64, _i32, _i32]),
+    "fnt_plan_set_lead": (_i32, [_vp, _u64]),
+    "fnt_plan_run_timed": (_i32, [_vp, ctypes.POINTER(PlanTiming), _vp]),
     "fnt_plan_destroy": (_i32, [_vp]),
     "fnt_now_ns": (_u64, []),
     "fnt_session_create": (_i32, [ctypes.POINTER(_vp), ctypes.POINTER(SessionConfig)]),
@@ -306,6 +314,16 @@ class Plan:
 
     def set_cdc_schedule(self, waves_per_group: int, blocks_per_wave: int):
         _ok(lib().fnt_plan_set_cdc_schedule(self._h, int(waves_per_group), int(blocks_per_wave)))
+
+    def set_lead(self, lead_channels: int):
+        _ok(lib().fnt_plan_set_lead(self._h, int(lead_channels)))
+
+    def run_timed(self, stream=None) -> dict:
+        """One run launched directly with events around every launch; blocks
+        until it ends and returns the durations (ms) and block counts."""
+        t = PlanTiming()
+        _ok(lib().fnt_plan_run_timed(self._h, ctypes.byref(t), _stream(stream)))
+        return {k: getattr(t, k) for k, _ in PlanTiming._fields_}
 
     def close(self):
         if getattr(self, "_h", None):

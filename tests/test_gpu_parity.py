@@ -397,6 +397,34 @@ def test_plan_determinism_across_schedules(torch_dev):
         assert info["aeq_long_channels"] == min(nl, len(pc)) and info["aeq_waves_long"] == wl
         for c, (o, w) in zip(pc, ref):
             assert np.array_equal(c["out"].cpu().numpy(), o) and np.array_equal(c["taps"].cpu().numpy(), w)
+    # pipelined lead: the longest channels' CDC first, their AEQ on the side stream
+    # while the others' CDC and AEQ run (graph replay, direct launch, timed launch)
+    n = len(pc)
+    for lead, nl, wl, ws, active in [(1, 1, 1, 0, True), (3, 5, 1, 3, True), (5, 12, 2, 1, False),
+                                     (n - 1, n, 4, 0, True), (10, 2, 4, 3, True), (4, 9, 3, 0, True),
+                                     (n, 3, 1, 0, False), (0, 3, 1, 0, False)]:
+        plan.set_aeq_split(nl, wl, ws)
+        plan.set_lead(lead)
+        assert plan.info()["lead_channels"] == (lead if active else 0)
+        for mode in ("run", "timed", "stages"):
+            for c in pc:
+                c["taps"].copy_(to_dev(torch, dev, c["w0"]))
+                c["out"].fill_(-3)
+            note(f"plan lead={lead} long={nl} wl={wl} ws={ws} {mode}")
+            if mode == "run":
+                plan.run()
+            elif mode == "timed":
+                t = plan.run_timed()
+                assert t["step_ms"] > 0 and t["cdc_ms"] > 0 and t["aeq_ms"] > 0
+                assert (t["aeq_lead_ms"] > 0) == active
+                assert t["aeq_blocks"] + t["aeq_lead_blocks"] == sum((c["out"].shape[0] + 15) // 16 for c in pc)
+            else:
+                plan.run_stage(fnt.FNT_STAGE_ALL)
+            torch.cuda.synchronize()
+            for c, (o, w) in zip(pc, ref):
+                assert np.array_equal(c["out"].cpu().numpy(), o) and np.array_equal(c["taps"].cpu().numpy(), w)
+    plan.set_aeq_waves(1)
+    assert plan.info()["lead_channels"] == 0
     plan.close()
     fnt.fnt_check()
 
@@ -419,7 +447,18 @@ def test_plan_autotune_and_eager(torch_dev, tmp_path):
         assert np.array_equal(c["taps"].cpu().numpy(), wr)
     assert os.path.exists(cache) and "wpg" in open(cache).read()
     info = plan.info()
-    assert info["graph"] == 0 and info["cdc_blocks_per_wave"] >= 1
+    assert info["graph"] == 0 and 0 <= info["cdc_blocks_per_wave"] <= 64
+    assert 0 <= info["lead_channels"] < len(pc)
+    # a second plan over the same channels takes the schedule from the cache
+    plan2 = fnt.Plan([(c["x"], c["out"], c["taps"], fnt.cdc_params(c["ch"].taps, c["ch"].requant_shift),
+                       fnt.aeq_params(**c["prm"])) for c in pc], autotune=True, use_graph=False,
+                     tune_cache=cache)
+    info2 = plan2.info()
+    assert info2["tune_ms"] == 0.0
+    for k in ("cdc_waves_per_group", "cdc_blocks_per_wave", "aeq_waves_per_pol", "aeq_waves_long",
+              "aeq_long_channels", "lead_channels"):
+        assert info2[k] == info[k], k
+    plan2.close()
     # the two stages launched one by one reproduce a whole run
     for c in pc:
         c["taps"].copy_(to_dev(torch, dev, c["w0"]))
