@@ -190,6 +190,8 @@ typedef struct fnt_plan_info {
     uint64_t aeq_long_channels; /* longest channels run in their own concurrent launch */
     int32_t cdc_variant;   /* 0 = Fermat-domain (the method), 1 = direct comparator */
     int32_t lead_channels; /* pipelined lead channels in effect (see fnt_plan_set_lead) */
+    int32_t lead_form;     /* AEQ form of the lead channels */
+    int32_t reserved;
 } fnt_plan_info;
 
 typedef struct fnt_plan fnt_plan;
@@ -250,19 +252,21 @@ int fnt_plan_set_cdc_variant(fnt_plan *plan, int variant);
  * blocks.  Results do not depend on it. */
 int fnt_plan_set_cdc_schedule(fnt_plan *plan, int waves_per_group, int blocks_per_wave);
 /* Pipelined lead: the CDC of the `lead_channels` channels with the longest AEQ
- * chains runs first; their AEQ (in the long chains' form, at raised wave
- * priority) then starts on the plan's side stream while the CDC and the AEQ of
- * the other channels run on the launch stream, so the longest serial chains do
- * not wait for the whole batch's CDC.  The other channels keep the split of
- * fnt_plan_set_aeq_split for those of them among the long channels.  0 (default
- * unless the autotuner chose one) runs every CDC before any AEQ.  In effect only
- * with the Fermat-domain AEQ, for 0 < lead_channels < channels, and when the
- * other channels' AEQ is one launch (no long channels left among them, or a
- * split that runs as one launch); otherwise the plan runs without a lead.
- * While a lead is in effect fnt_plan_run launches the sequence directly instead
- * of replaying the plan's graph.  Results never depend on it.  FNT_E_INVAL for a NULL plan; FNT_E_DEVICE if the
- * table of the other channels cannot be uploaded. */
-int fnt_plan_set_lead(fnt_plan *plan, uint64_t lead_channels);
+ * chains runs first; their AEQ (in form `lead_form`, see fnt_plan_set_aeq_waves,
+ * or the long chains' form for -1; at raised wave priority) then starts on the
+ * plan's side stream while the CDC and the AEQ of the other channels run on the
+ * launch stream, so the longest serial chains do not wait for the whole batch's
+ * CDC.  The other channels keep the split of fnt_plan_set_aeq_split for those of
+ * them among the long channels.  0 (default unless the autotuner chose one) runs
+ * every CDC before any AEQ.  In effect only with the Fermat-domain AEQ, for
+ * 0 < lead_channels < channels, and when the other channels' AEQ is one launch
+ * (no long channels left among them, or a split that runs as one launch);
+ * otherwise the plan runs without a lead.  While a lead is in effect
+ * fnt_plan_run launches the sequence directly instead of replaying the plan's
+ * graph.  Results never depend on it.  FNT_E_INVAL for a NULL plan or another
+ * form; FNT_E_NOMEM / FNT_E_DEVICE if the table of the other channels cannot be
+ * allocated / uploaded. */
+int fnt_plan_set_lead(fnt_plan *plan, uint64_t lead_channels, int lead_form);
 
 typedef struct fnt_plan_timing {
     float step_ms;          /* first launch to the end of the last, on the launch stream */

@@ -293,6 +293,7 @@ struct fnt_plan {
     // stream concurrently with the others' CDC and AEQ; cdc_rest_dev holds the
     // items [n_lead, n) with block0 / chunk0 rebased to 0 (built for rest_lead)
     size_t n_lead = 0, rest_lead = 0;
+    int lead_form = -1;                // AEQ form of the lead (-1: the long chains' form)
     CdcItem *cdc_rest_dev = nullptr;
     hipStream_t side = nullptr;        // second stream for the concurrent AEQ launch
     hipEvent_t fork = nullptr, join = nullptr;
@@ -390,7 +391,8 @@ static int plan_launch(fnt_plan *p, hipStream_t s, hipStream_t side, hipEvent_t 
     if (e == hipSuccess) e = hipEventRecord(p->fork, s);
     if (e == hipSuccess) e = hipStreamWaitEvent(side, p->fork, 0);
     if (e == hipSuccess) e = rec(2, side);
-    if (e == hipSuccess) e = launch_aeq(p->aeq_dev, (int)lead, AeqItem{}, 0, p->wpp_long, p->err, side, true);
+    const int lf = p->lead_form >= 0 ? p->lead_form : p->wpp_long;
+    if (e == hipSuccess) e = launch_aeq(p->aeq_dev, (int)lead, AeqItem{}, 0, lf, p->err, side, true);
     if (e == hipSuccess) e = rec(3, side);
     if (e == hipSuccess)
         e = plan_cdc(p, p->cdc_rest_dev, (int)(n - lead), p->total_blocks - r0.block0, p->total_chunks - r0.chunk0, s);
@@ -470,7 +472,7 @@ static int plan_capture(fnt_plan *p, hipStream_t s) {
     return FNT_OK;
 }
 
-constexpr int kTuneVersion = 4;
+constexpr int kTuneVersion = 5;
 
 static std::string tune_key(const fnt_plan *p) {
     // length histogram (log2 buckets of instants) + channel count + variant
@@ -493,7 +495,7 @@ static std::string tune_key(const fnt_plan *p) {
 
 // The last entry for `key`; the values are range-checked by the caller.
 static bool tune_cache_lookup(const char *path, const std::string &key, int *wpg, int *bpw, int *wpp,
-                              int *wpp_long, long long *n_long, long long *n_lead) {
+                              int *wpp_long, long long *n_long, long long *n_lead, int *lead_form) {
     if (!path) return false;
     std::ifstream f(path);
     std::string line;
@@ -511,26 +513,29 @@ static bool tune_cache_lookup(const char *path, const std::string &key, int *wpg
         bb = std::atoi(line.c_str() + pb + 7);
         pp = std::atoi(line.c_str() + pq + 7);
         size_t pl = line.find("\"wpp_long\": "), pn = line.find("\"n_long\": "),
-               pd = line.find("\"n_lead\": ");
-        if (pl == std::string::npos || pn == std::string::npos || pd == std::string::npos) continue;
+               pd = line.find("\"n_lead\": "), pf = line.find("\"lead_form\": ");
+        if (pl == std::string::npos || pn == std::string::npos || pd == std::string::npos ||
+            pf == std::string::npos)
+            continue;
         *wpg = w;
         *bpw = bb;
         *wpp = pp;
         *wpp_long = std::atoi(line.c_str() + pl + 12);
         *n_long = std::atoll(line.c_str() + pn + 10);
         *n_lead = std::atoll(line.c_str() + pd + 10);
+        *lead_form = std::atoi(line.c_str() + pf + 13);
         found = true;
     }
     return found;
 }
 
 static void tune_cache_store(const char *path, const std::string &key, int wpg, int bpw, int wpp,
-                             int wpp_long, long long n_long, long long n_lead, double ms) {
+                             int wpp_long, long long n_long, long long n_lead, int lead_form, double ms) {
     if (!path) return;
     std::ofstream f(path, std::ios::app);
     f << "{\"key\": \"" << key << "\", \"wpg\": " << wpg << ", \"bpw\": " << bpw << ", \"wpp\": " << wpp
       << ", \"wpp_long\": " << wpp_long << ", \"n_long\": " << n_long << ", \"n_lead\": " << n_lead
-      << ", \"ms\": " << ms << "}\n";
+      << ", \"lead_form\": " << lead_form << ", \"ms\": " << ms << "}\n";
 }
 
 // Default AEQ schedule: with few channels the chip is idle, so spread each
@@ -545,17 +550,18 @@ static int default_wpp(size_t nch) { return nch >= 512 ? 3 : (nch >= 128 ? 2 : 4
 
 static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
     std::string key = tune_key(p);
-    int w, b, q, ql;
+    int w, b, q, ql, lf;
     long long nl, nd;
-    if (tune_cache_lookup(cache, key, &w, &b, &q, &ql, &nl, &nd) && (w == 1 || w == 2 || w == 4) && b >= 0 &&
-        b <= 1024 && valid_form(q) && valid_form(ql) && nl >= 0 && nd >= 0 &&
-        (size_t)nd < std::max<size_t>(1, p->aeq_host.size())) {
+    if (tune_cache_lookup(cache, key, &w, &b, &q, &ql, &nl, &nd, &lf) && (w == 1 || w == 2 || w == 4) &&
+        b >= 0 && b <= 1024 && valid_form(q) && valid_form(ql) && nl >= 0 && nd >= 0 &&
+        (size_t)nd < std::max<size_t>(1, p->aeq_host.size()) && (lf == -1 || valid_form(lf))) {
         p->wpg = w;
         p->bpw = b;
         p->wpp = q;
         p->wpp_long = ql;
         p->n_long = (size_t)nl;
         p->n_lead = (size_t)nd;
+        p->lead_form = lf;
         return FNT_OK;
     }
     hipEvent_t e0, e1;
@@ -598,6 +604,7 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
     double best_aeq = 1e30;
     int bq = p->wpp, bql = p->wpp_long;
     size_t bnl = p->n_long, bnd = 0;
+    int blf = -1;
     if (p->variant == 0 && hipMalloc(&tscratch, nch * 256 * sizeof(int16_t)) == hipSuccess &&
         hipMalloc(&tdev, nch * sizeof(AeqItem)) == hipSuccess) {
         std::vector<AeqItem> tab = p->aeq_host;
@@ -664,25 +671,27 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
             p->wpg = bw;
             p->bpw = bb;
             p->wpp_long = bql;
-            struct LCand { size_t lead, nl; int q; double ms; };
+            struct LCand { size_t lead, nl; int q, lf; double ms; };
             std::vector<LCand> leads;
             auto time_lead = [&](const LCand &c) -> double {
                 if (plan_build_rest(p, c.lead, s)) return 1e30;
                 p->n_lead = c.lead;
                 p->n_long = c.nl;
                 p->wpp = c.q;
+                p->lead_form = c.lf;
                 if (plan_lead(p) != c.lead) return 1e30;
                 return time_it([&] { return plan_launch(p, s, p->side) ? hipErrorUnknown : hipSuccess; });
             };
-            leads.push_back({0, bnl, bq, 0});                   // the choice above, without a lead
-            for (size_t lead : {32, 128, 256, 512, 768, 1024})
-                for (size_t extra : {0, 128, 256, 512})
-                    for (int q : {0, 3}) {
-                        const size_t nl = lead + extra;
-                        if (lead >= nch || nl > nch) continue;
-                        if (extra > 0 && form_rank(q) >= form_rank(bql)) continue;
-                        leads.push_back({lead, nl, q, 0});
-                    }
+            leads.push_back({0, bnl, bq, -1, 0});               // the choice above, without a lead
+            for (size_t lead : {32, 128, 256, 512, 768, 1024, 1536})
+                for (size_t extra : {0, 256, 512, 1024})
+                    for (int q : {0, 3})
+                        for (int lf : {-1, 2}) {                // lead in the long form, or two waves per half
+                            const size_t nl = lead + extra;
+                            if (lead >= nch || nl > nch || lf == bql) continue;
+                            if (extra > 0 && form_rank(q) >= form_rank(bql)) continue;
+                            leads.push_back({lead, nl, q, lf, 0});
+                        }
             for (LCand &c : leads) c.ms = time_lead(c);
             std::sort(leads.begin(), leads.end(), [](const LCand &a, const LCand &b) { return a.ms < b.ms; });
             for (size_t i = 0; i < leads.size() && i < 4; ++i)
@@ -694,8 +703,10 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
                     bnd = leads[i].lead;
                     bnl = leads[i].nl;
                     bq = leads[i].q;
+                    blf = leads[i].lf;
                 }
             p->n_lead = 0;
+            p->lead_form = -1;
             p->rest_lead = 0;
             p->aeq_dev = saved;
         }
@@ -710,8 +721,9 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
     p->wpp_long = bql;
     p->n_long = bnl;
     p->n_lead = bnd;
+    p->lead_form = blf;
     p->info.tune_ms = best_aeq < 1e29 ? best_aeq : best_cdc;
-    tune_cache_store(cache, key, bw, bb, bq, bql, (long long)bnl, (long long)bnd, p->info.tune_ms);
+    tune_cache_store(cache, key, bw, bb, bq, bql, (long long)bnl, (long long)bnd, blf, p->info.tune_ms);
     return FNT_OK;
 }
 
@@ -885,16 +897,19 @@ int fnt_plan_get_info(const fnt_plan *p, fnt_plan_info *info) {
     info->graph = (p->exec && plan_lead(p) == 0) ? 1 : 0;
     info->cdc_variant = p->cdc_variant;
     info->lead_channels = (int32_t)plan_lead(p);
+    info->lead_form = p->lead_form >= 0 ? p->lead_form : p->wpp_long;
     return FNT_OK;
 }
 
-int fnt_plan_set_lead(fnt_plan *p, uint64_t lead) {
+int fnt_plan_set_lead(fnt_plan *p, uint64_t lead, int lead_form) {
     if (!p) return fail(FNT_E_INVAL, "plan: NULL");
+    if (lead_form != -1 && !valid_form(lead_form)) return fail(FNT_E_INVAL, "plan: lead form %d", lead_form);
     const size_t n = p->aeq_host.size();
     const size_t l = lead < n ? (size_t)lead : 0;
     int rc = plan_build_rest(p, l, nullptr);
     if (rc) return rc;
     p->n_lead = l;
+    p->lead_form = lead_form;
     if (p->exec) return plan_capture(p, nullptr);
     return FNT_OK;
 }

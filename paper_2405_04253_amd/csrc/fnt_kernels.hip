@@ -1086,8 +1086,16 @@ __device__ __forceinline__ int32_t xor_lpt_lane(int32_t v) { return xor_lane<LPT
 template <int H>
 __device__ __forceinline__ int32_t xor_h(int32_t v) { return xor_lane<H>(v); }
 
+// x * s for |x| < 2^23 and a lane constant s = +-1: one 24-bit multiply (the
+// sign passes through opq, or the compiler turns the product into a negate
+// and a select).
+__device__ __forceinline__ int32_t mul_sign(int32_t x, int32_t s) { return sext24(x) * sext24(opq(s)); }
+
 // In-register and cross-lane DIF of 16 tap-digit positions zero-padded to 32.
 // In: |x| <= 2^17; out: |X| <= 2^21; register j of lane t holds bin bitrev5(t + LPT j).
+// Twiddles are powers of two: exponents up to 14 for every lane take the
+// shift form (mul_pow2), the register whose exponent reaches 15 in some lane
+// takes mulmod, and the last cross-lane stage (twiddle 1) is a signed sum.
 template <int LPT>
 __device__ __forceinline__ void tap_fnt_lpt(int32_t (&x)[32 / LPT], int t) {
     constexpr int PPL = 32 / LPT;
@@ -1097,27 +1105,34 @@ __device__ __forceinline__ void tap_fnt_lpt(int32_t (&x)[32 / LPT], int t) {
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
             if (j & jd) continue;
-            const int e = (16 / h) * t + (16 * LPT / h) * (j & (jd - 1));   // < 16
+            const int jp = j & (jd - 1);
+            const int e = (16 / h) * t + (16 * LPT / h) * jp;               // < 16
+            const bool shift_ok = (16 / h) * (LPT - 1) + (16 * LPT / h) * jp <= 14;   // every lane
             if (h == 16) {
-                x[j + jd] = mulmod(x[j], opq(1 << e));   // the partner is zero padding
+                // the partner is zero padding
+                x[j + jd] = shift_ok ? mul_pow2(x[j], e) : mulmod(x[j], opq(1 << e));
             } else {
                 int32_t a = x[j], b = x[j + jd];
                 x[j] = a + b;
-                x[j + jd] = mulmod(a - b, opq(1 << e));
+                x[j + jd] = shift_ok ? mul_pow2(a - b, e) : mulmod(a - b, opq(1 << e));
             }
         }
     }
-    // across lanes: lower lane x + p, upper lane (p - x) * 2^e
+    // across lanes: lower lane x + p, upper lane (p - x) * 2^e, e <= 14
 #pragma unroll
-    for (int h = LPT / 2; h >= 1; h >>= 1) {
+    for (int h = LPT / 2; h >= 2; h >>= 1) {
         const bool up = (t & h) != 0;
-        const int32_t c = opq(1 << ((16 / h) * (t & (h - 1))));
+        const int e = (16 / h) * (t & (h - 1));
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
-            int32_t p = h == 8 ? xor_pos<8>(x[j]) : h == 4 ? xor_pos<4>(x[j])
-                      : h == 2 ? xor_pos<2>(x[j]) : xor_pos<1>(x[j]);
-            x[j] = blend(up, mulmod(p - x[j], c), x[j] + p);
+            int32_t p = h == 8 ? xor_pos<8>(x[j]) : h == 4 ? xor_pos<4>(x[j]) : xor_pos<2>(x[j]);
+            x[j] = blend(up, mul_pow2(p - x[j], e), x[j] + p);
         }
+    }
+    {   // distance 1, twiddle 1: lower lane p + x, upper lane p - x  (|x| <= 2^20)
+        const int32_t sg = (t & 1) ? -1 : 1;
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) x[j] = xor_pos<1>(x[j]) + mul_sign(x[j], sg);
     }
 }
 
@@ -1129,18 +1144,26 @@ __device__ __forceinline__ int32_t inv_pow2(int e) { return e ? -(1 << (16 - e))
 template <int LPT>
 __device__ __forceinline__ void ifnt_upper_lpt(int32_t (&x)[32 / LPT], int t) {
     constexpr int PPL = 32 / LPT;
-    // across lanes: the upper lane twiddles its value first, then
+    {   // distance 1, twiddle 1: lower lane x + p, upper lane p - x  (|x| < 2^18)
+        const int32_t sg = (t & 1) ? -1 : 1;
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) x[j] = xor_pos<1>(x[j]) + mul_sign(x[j], sg);
+    }
+    // across lanes: the upper lane twiddles its value by 2^-e first (2^-e =
+    // -2^(16-e), 16 - e <= 14 for e > 0; the other lanes fold theirs), then
     // lower = own + partner, upper = partner - own
 #pragma unroll
-    for (int h = 1; h < LPT; h <<= 1) {
+    for (int h = 2; h < LPT; h <<= 1) {
         const bool up = (t & h) != 0;
-        const int32_t c = opq(inv_pow2((16 / h) * (t & (h - 1))));
+        const int e = (16 / h) * (t & (h - 1));
+        const bool tw = up && e != 0;
+        const int sh = tw ? 16 - e : 0;
+        const int32_t sg_in = tw ? -1 : 1, sg_out = up ? -1 : 1;
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
-            int32_t tt = blend(up, mulmod(x[j], c), x[j]);
-            int32_t p = h == 8 ? xor_pos<8>(tt) : h == 4 ? xor_pos<4>(tt)
-                      : h == 2 ? xor_pos<2>(tt) : xor_pos<1>(tt);
-            x[j] = blend(up, p - tt, x[j] + p);
+            int32_t tt = mul_pow2(mul_sign(x[j], sg_in), sh);                  // |.| < 2^17
+            int32_t p = h == 8 ? xor_pos<8>(tt) : h == 4 ? xor_pos<4>(tt) : xor_pos<2>(tt);
+            x[j] = p + mul_sign(tt, sg_out);
         }
     }
 #pragma unroll
@@ -1149,14 +1172,26 @@ __device__ __forceinline__ void ifnt_upper_lpt(int32_t (&x)[32 / LPT], int t) {
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
             if (j & jd) continue;
-            const int e = (16 / h) * t + (16 * LPT / h) * (j & (jd - 1));
-            int32_t tt = mulmod(x[j + jd], opq(inv_pow2(e)));
-            if (h == 16) {
-                x[j + jd] = x[j] - tt;                // only the upper half is kept
+            const int jp = j & (jd - 1);
+            const int e = (16 / h) * t + (16 * LPT / h) * jp;
+            const int32_t a = x[j];
+            if ((16 * LPT / h) * jp >= 2) {
+                // every lane has 2 <= e: tt = -m with m = x 2^(16-e), 16 - e <= 14
+                const int32_t m = mul_pow2(x[j + jd], 16 - e);
+                if (h == 16) {
+                    x[j + jd] = a + m;                // only the upper half is kept
+                } else {
+                    x[j] = a - m;
+                    x[j + jd] = a + m;
+                }
             } else {
-                int32_t a = x[j];
-                x[j] = a + tt;
-                x[j + jd] = a - tt;
+                const int32_t tt = mulmod(x[j + jd], opq(inv_pow2(e)));
+                if (h == 16) {
+                    x[j + jd] = a - tt;
+                } else {
+                    x[j] = a + tt;
+                    x[j + jd] = a - tt;
+                }
             }
         }
     }
@@ -1290,15 +1325,20 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, const AeqItem
             const int8_t *wb = reinterpret_cast<const int8_t *>(winw) + (lane >> 4) * 32;
             int32_t x0 = wb[kp], x1 = wb[kp + 16];
             int32_t u0 = x0 + x1;
-            int32_t u1 = mulmod(x0 - x1, opq(1 << kp));
+            int32_t u1 = fold16(opq((x0 - x1) << kp));   // |x0 - x1| <= 31: no overflow
 #pragma unroll
-            for (int h = 8; h >= 1; h >>= 1) {
+            for (int h = 8; h >= 2; h >>= 1) {
                 const bool up = (kp & h) != 0;
-                const int32_t c = opq(1 << ((16 / h) * (kp & (h - 1))));
-                int32_t p0 = h == 8 ? xor_pos<8>(u0) : h == 4 ? xor_pos<4>(u0) : h == 2 ? xor_pos<2>(u0) : xor_pos<1>(u0);
-                int32_t p1 = h == 8 ? xor_pos<8>(u1) : h == 4 ? xor_pos<4>(u1) : h == 2 ? xor_pos<2>(u1) : xor_pos<1>(u1);
-                u0 = blend(up, mulmod(p0 - u0, c), u0 + p0);
-                u1 = blend(up, mulmod(p1 - u1, c), u1 + p1);
+                const int e = (16 / h) * (kp & (h - 1));   // <= 14
+                int32_t p0 = h == 8 ? xor_pos<8>(u0) : h == 4 ? xor_pos<4>(u0) : xor_pos<2>(u0);
+                int32_t p1 = h == 8 ? xor_pos<8>(u1) : h == 4 ? xor_pos<4>(u1) : xor_pos<2>(u1);
+                u0 = blend(up, mul_pow2(p0 - u0, e), u0 + p0);
+                u1 = blend(up, mul_pow2(p1 - u1, e), u1 + p1);
+            }
+            {   // distance 1, twiddle 1
+                const int32_t sg = (kp & 1) ? -1 : 1;
+                u0 = xor_pos<1>(u0) + mul_sign(u0, sg);
+                u1 = xor_pos<1>(u1) + mul_sign(u1, sg);
             }
             aspec[lane >> 4][kp] = u0;                  // |.| <= 2^21
             aspec[lane >> 4][kp + 16] = u1;

@@ -400,12 +400,15 @@ def test_plan_determinism_across_schedules(torch_dev):
     # pipelined lead: the longest channels' CDC first, their AEQ on the side stream
     # while the others' CDC and AEQ run (graph replay, direct launch, timed launch)
     n = len(pc)
-    for lead, nl, wl, ws, active in [(1, 1, 1, 0, True), (3, 5, 1, 3, True), (5, 12, 2, 1, False),
-                                     (n - 1, n, 4, 0, True), (10, 2, 4, 3, True), (4, 9, 3, 0, True),
-                                     (n, 3, 1, 0, False), (0, 3, 1, 0, False)]:
+    for lead, lf, nl, wl, ws, active in [(1, -1, 1, 1, 0, True), (3, 2, 5, 1, 3, True), (5, -1, 12, 2, 1, False),
+                                         (n - 1, -1, n, 4, 0, True), (10, 0, 2, 4, 3, True),
+                                         (4, 4, 9, 3, 0, True), (7, 3, 7, 1, 0, True),
+                                         (n, -1, 3, 1, 0, False), (0, 2, 3, 1, 0, False)]:
         plan.set_aeq_split(nl, wl, ws)
-        plan.set_lead(lead)
-        assert plan.info()["lead_channels"] == (lead if active else 0)
+        plan.set_lead(lead, lf)
+        info = plan.info()
+        assert info["lead_channels"] == (lead if active else 0)
+        assert info["lead_form"] == (wl if lf == -1 else lf)
         for mode in ("run", "timed", "stages"):
             for c in pc:
                 c["taps"].copy_(to_dev(torch, dev, c["w0"]))
@@ -423,6 +426,8 @@ def test_plan_determinism_across_schedules(torch_dev):
             torch.cuda.synchronize()
             for c, (o, w) in zip(pc, ref):
                 assert np.array_equal(c["out"].cpu().numpy(), o) and np.array_equal(c["taps"].cpu().numpy(), w)
+    with pytest.raises(fnt.FntError):
+        plan.set_lead(2, 5)
     plan.set_aeq_waves(1)
     assert plan.info()["lead_channels"] == 0
     plan.close()
@@ -456,7 +461,7 @@ def test_plan_autotune_and_eager(torch_dev, tmp_path):
     info2 = plan2.info()
     assert info2["tune_ms"] == 0.0
     for k in ("cdc_waves_per_group", "cdc_blocks_per_wave", "aeq_waves_per_pol", "aeq_waves_long",
-              "aeq_long_channels", "lead_channels"):
+              "aeq_long_channels", "lead_channels", "lead_form"):
         assert info2[k] == info[k], k
     plan2.close()
     # the two stages launched one by one reproduce a whole run
