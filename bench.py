@@ -289,7 +289,7 @@ def bench_batched(args, torch, dev):
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
     progress(f"batched: plan create + autotune over {len(entries)} channels")
-    plan = fnt.Plan(entries, autotune=True, use_graph=True, stream=stream)
+    plan = fnt.Plan(entries, autotune=True, use_graph=True, stream=stream, tune_cache=args.tune_cache)
     torch.cuda.synchronize()
     tune_s = time.perf_counter() - t0
     info = plan.info()
@@ -551,6 +551,9 @@ def main():
     ap.add_argument("--chunk", type=int, default=512)
     ap.add_argument("--served-form", type=int, default=-1,
                     help="AEQ form of the session ticks (0, 3, 1, 2, 4; -1: automatic)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON-lines file for the plan autotuner: reuse a schedule stored there for the same "
+                         "workload, else tune and append it (keeps profiled runs on one schedule)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run 5 plain 256 MiB elementwise copies (counter calibration)")
     args = ap.parse_args()

@@ -1208,17 +1208,26 @@ __device__ __forceinline__ uint32_t aeq_sym(const AeqItem &it, int64_t i) {
     return v;
 }
 
+// Workgroups of the polarisation-split AEQ: each run of 16 workgroup indices
+// holds 8 channels, the two halves of a channel 8 indices apart.  Workgroups
+// are dealt round-robin over the 8 XCDs, so both halves of a channel run on one
+// XCD and share its L2: the input window both read, and the output records
+// whose 16-bit pieces both write, then cross HBM once.
+__host__ __device__ constexpr unsigned pol_blocks(int n) { return 16u * (unsigned)((n + 7) / 8); }
+
 template <int LPT>
-__device__ __forceinline__ void aeq_pol_body(const AeqItem *items, const AeqItem &single, int *err,
+__device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const AeqItem &single, int *err,
                                              int prio, unsigned bid) {
+    const unsigned ch = (bid >> 4) * 8 + (bid & 7);
+    if (ch >= (unsigned)(items ? n : 1)) return;       // padding of the last run of 16
     // latency-critical chains (the longest of a batch) issue ahead of the
     // throughput work that shares their SIMDs
     if (prio) __builtin_amdgcn_s_setprio(3);
     constexpr int WPP = LPT / 4;                       // waves per polarisation half
     constexpr int PPL = 32 / LPT;                      // bins per lane
     constexpr int NT = 16 / LPT;                       // taps owned per lane (= PPL / 2)
-    const AeqItem it = items ? items[bid >> 1] : single;
-    const int pol = bid & 1;
+    const AeqItem it = items ? items[ch] : single;
+    const int pol = (bid >> 3) & 1;
     const int tid = threadIdx.x;
     const int v = tid >> 6, lane = tid & 63;
     const int pos = lane & 31;
@@ -1234,14 +1243,16 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, const AeqItem
     const int om = (lane >> 1) & 15, oS2l = lane & 1;
     const int kk = lane & 15;
 
-    __shared__ int32_t aspec_s[WPP][4][32];            // per wave: input spectra by position
+    // rows padded to 33 words: lanes reading the same position of different
+    // rows hit different LDS banks
+    __shared__ int32_t aspec_s[WPP][4][33];            // per wave: input spectra by position
     // [block parity][g*2+d][m*2+S2l], shared by the waves; double-buffered so a
     // wave that runs ahead (one barrier per block) never overwrites partials
     // another wave is still reading
-    __shared__ int32_t part_s[2][4][32];
+    __shared__ int32_t part_s[2][4][33];
     __shared__ uint32_t epsw_s[WPP][8];                // per wave: bytes [S2l][m]
     __shared__ uint32_t winw_s[WPP][36];               // per wave: bytes [S1][32] + pad
-    int32_t(*aspec)[32] = aspec_s[v];
+    int32_t(*aspec)[33] = aspec_s[v];
     uint32_t *epsw = epsw_s[v];
     uint32_t *winw = winw_s[v];
 
@@ -1359,7 +1370,7 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, const AeqItem
         if (WPP > 1) __syncthreads(); else wave_lds_sync();
         // symbol om, stream 2 pol + oS2l: y = 2^7 (high-digit sums) + (low-digit sums)
         const int pi = lane & 31;
-        const int32_t(*part)[32] = part_s[b & 1];
+        const int32_t(*part)[33] = part_s[b & 1];
         const int32_t y = 128 * (part[0][pi] + part[2][pi]) + part[1][pi] + part[3][pi];
         const int32_t yh = clamp32(rs32(y, it.out_shift), -32768, 32767);
         const bool valid = lane < 32 && om < left;
@@ -1403,9 +1414,9 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, const AeqItem
 }
 
 template <int LPT>
-__global__ __launch_bounds__(64 * (LPT / 4)) void aeq_pol_kernel(const AeqItem *items, AeqItem single,
+__global__ __launch_bounds__(64 * (LPT / 4)) void aeq_pol_kernel(const AeqItem *items, int n, AeqItem single,
                                                                  int *err, int prio) {
-    aeq_pol_body<LPT>(items, single, err, prio, blockIdx.x);
+    aeq_pol_body<LPT>(items, n, single, err, prio, blockIdx.x);
 }
 
 // ------------------------------------------------------------------------
@@ -1996,14 +2007,14 @@ __global__ __launch_bounds__(64 * WPG) void aeq_duo_kernel(const AeqItem *items,
 // half: one workgroup per half, so WPG = 1 / 2 / 4).
 __host__ __device__ constexpr unsigned aeq_form_blocks(int form, int n, int wpg) {
     return form == 0 ? (unsigned)((n + 2 * wpg - 1) / (2 * wpg))
-         : form == 3 ? (unsigned)((n + wpg - 1) / wpg) : (unsigned)(2 * n);
+         : form == 3 ? (unsigned)((n + wpg - 1) / wpg) : pol_blocks(n);
 }
 template <int F, int WPG>
 __device__ __forceinline__ void aeq_form_body(const AeqItem *items, int n, int *err, int prio, unsigned bid) {
     const AeqItem none{};
     if constexpr (F == 0) aeq_lane_body<WPG>(items, n, none, err, prio, bid);
     else if constexpr (F == 3) aeq_duo_body<WPG>(items, n, none, err, prio, bid);
-    else aeq_pol_body<4 * WPG>(items, none, err, prio, bid);
+    else aeq_pol_body<4 * WPG>(items, n, none, err, prio, bid);
 }
 template <int LF, int RF, int WPG>
 __global__ __launch_bounds__(64 * WPG) void aeq_split_kernel(const AeqItem *items, int nlong, int nitems,
@@ -2191,7 +2202,7 @@ static int split_wpg(int form_long) { return form_long == 2 ? 2 : form_long == 4
 
 hipError_t launch_aeq_split(const AeqItem *items, int nlong, int nitems, int form_long, int form_rest,
                            int *err, hipStream_t s) {
-    if (!items || nlong <= 0 || nlong >= nitems) return hipErrorInvalidValue;
+    if (!items || nlong <= 0 || nlong >= nitems || nitems > (1 << 26)) return hipErrorInvalidValue;
     const int wpg = split_wpg(form_long);
     const unsigned grid = aeq_form_blocks(form_long, nlong, wpg) + aeq_form_blocks(form_rest, nitems - nlong, wpg);
 #define FNT_SPLIT(L, R, W)                                                                     \
@@ -2215,17 +2226,18 @@ hipError_t launch_aeq(const AeqItem *items, int nitems, const AeqItem &single, i
     const int prio = high_priority ? 1 : 0;
     const int n = items ? nitems : 1;
     if (n <= 0) return hipSuccess;
+    if (n > (1 << 26)) return hipErrorInvalidValue;    // grid sizes stay far below 2^31
     if (variant == 0) {
         if (waves_per_pol == 0)
             aeq_lane_kernel<1><<<(n + 1) / 2, 64, 0, s>>>(items, n, single, err, prio);
         else if (waves_per_pol == 3)
             aeq_duo_kernel<1><<<n, 64, 0, s>>>(items, n, single, err, prio);
         else if (waves_per_pol == 1)
-            aeq_pol_kernel<4><<<2 * n, 64, 0, s>>>(items, single, err, prio);
+            aeq_pol_kernel<4><<<pol_blocks(n), 64, 0, s>>>(items, n, single, err, prio);
         else if (waves_per_pol == 2)
-            aeq_pol_kernel<8><<<2 * n, 128, 0, s>>>(items, single, err, prio);
+            aeq_pol_kernel<8><<<pol_blocks(n), 128, 0, s>>>(items, n, single, err, prio);
         else if (waves_per_pol == 4)
-            aeq_pol_kernel<16><<<2 * n, 256, 0, s>>>(items, single, err, prio);
+            aeq_pol_kernel<16><<<pol_blocks(n), 256, 0, s>>>(items, n, single, err, prio);
         else
             return hipErrorInvalidValue;
     } else if (variant == 1) {
