@@ -452,6 +452,31 @@ def bench_batched(args, torch, dev):
     return res
 
 
+def bench_transforms(args, torch, dev):
+    """fnt_forward / fnt_inverse throughput for every supported (t, N, alpha):
+    2^26 residues per call (uint32 in, uint32 out, 512 MiB moved), HBM-bound by construction."""
+    from paper_2405_04253_amd import fnt
+    stream = torch.cuda.current_stream()
+    out = []
+    for t, log2n, kind, name in [(2, 3, fnt.FNT_ALPHA_2, "2"), (2, 4, fnt.FNT_ALPHA_SQRT2, "sqrt2"),
+                                 (3, 4, fnt.FNT_ALPHA_2, "2"), (3, 5, fnt.FNT_ALPHA_SQRT2, "sqrt2"),
+                                 (4, 5, fnt.FNT_ALPHA_2, "2"), (4, 6, fnt.FNT_ALPHA_SQRT2, "sqrt2")]:
+        F = (1 << (1 << t)) + 1
+        n = 1 << 26
+        x = torch.randint(0, F, (n >> log2n, 1 << log2n), dtype=torch.int32, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(2):
+            fnt.fnt_forward(x, t, log2n, kind, out=y, stream=stream)
+        fwd = _time_events(torch, lambda: fnt.fnt_forward(x, t, log2n, kind, out=y, stream=stream), 5, stream)
+        inv = _time_events(torch, lambda: fnt.fnt_inverse(y, t, log2n, kind, out=x, stream=stream), 5, stream)
+        fnt.fnt_check()
+        gbs = 8 * n / (fwd / 1e3) / 1e9
+        out.append({"t": t, "F": F, "N": 1 << log2n, "alpha": name, "forward_ms": round(fwd, 4),
+                    "inverse_ms": round(inv, 4), "forward_gbs": round(gbs, 1),
+                    "hbm_frac": round(gbs / PEAK_HBM_GBS, 4)})
+    return out
+
+
 def bench_served(args, torch, dev):
     """Poisson arrivals of stream segments into a session; p50/p99 latency."""
     import oracle as O
@@ -542,6 +567,7 @@ def main():
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-served", action="store_true")
     ap.add_argument("--skip-single", action="store_true")
+    ap.add_argument("--skip-transforms", action="store_true")
     ap.add_argument("--nch", type=int, default=4096)
     ap.add_argument("--log2-min", type=int, default=12)
     ap.add_argument("--log2-max", type=int, default=20)
@@ -587,6 +613,9 @@ def main():
         progress(f"single done: {res['plain_single_stream']['value']}")
         if "value" in res:
             res["vs_single_stream"] = round(res["value"] / res["plain_single_stream"]["value"], 1)
+    if not args.skip_transforms:
+        progress("transforms")
+        res["transforms"] = bench_transforms(args, torch, dev)
     if not args.skip_served:
         progress("served")
         res["served"] = bench_served(args, torch, dev)

@@ -70,12 +70,17 @@ int fnt_check(void *stream);
 
 /* ------------------------------------------------------------------------
  * Transforms -- Eq. (1) (forward) and Eq. (2) (inverse, including N^-1) over
- * Z_F with F = 2^(2^t) + 1 (FNT section).  Supported (t, N, alpha):
+ * Z_F with F = 2^(2^t) + 1 (FNT section), t in {2, 3, 4}, N the order of the
+ * radix (Eq. (4) with alpha^(N/2) = -1): N = 2^(t+1) for alpha = 2 and
+ * N = 2^(t+2) for alpha = sqrt 2 = 2^(3q/4) - 2^(q/4), q = 2^t (6 mod 17,
+ * 60 mod 257, 4080 mod 65537).  Among them:
  *   (2,  8, 2)      the 8-point, radix-2, modulus-17 example of Fig. 1
  *   (4, 32, 2)      the FNT-AEQ transform (Proposed structure, AEQ part)
  *   (4, 64, sqrt 2) the FNT-CDC transform (Proposed structure, CDC part),
  *                   alpha = 2^12 - 2^4 = 4080, the square root of 2 whose
- *                   powers are sums of two powers of two.
+ *                   powers are sums of two powers of two
+ *   (2, 16, sqrt 2), (3, 16, 2), (3, 32, sqrt 2): the same construction over
+ *                   the smaller Fermat primes, for narrower word widths.
  * x, X : uint32[batch][N], natural order, canonical residues in [0, F).  In-place
  * (x == X) is allowed.  Inputs >= F are a range error (flagged, see fnt_check).
  * log2n must equal log2 of N above; other combinations return FNT_E_INVAL.

@@ -166,9 +166,10 @@ int fnt_check(void *stream) {
 
 static int transform_common(const uint32_t *x, uint32_t *X, size_t batch, int t, int log2n,
                             int alpha_kind, bool inv, void *stream) {
-    bool legal = (t == 2 && log2n == 3 && alpha_kind == FNT_ALPHA_2) ||
-                 (t == 4 && log2n == 5 && alpha_kind == FNT_ALPHA_2) ||
-                 (t == 4 && log2n == 6 && alpha_kind == FNT_ALPHA_SQRT2);
+    // t in {2, 3, 4}; N is the radix's order: 2^(t+1) for alpha = 2, 2^(t+2) for sqrt 2
+    const bool legal = t >= 2 && t <= 4 &&
+                       ((alpha_kind == FNT_ALPHA_2 && log2n == t + 1) ||
+                        (alpha_kind == FNT_ALPHA_SQRT2 && log2n == t + 2));
     if (!legal)
         return fail(FNT_E_INVAL, "unsupported transform (t=%d, log2n=%d, alpha=%d)", t, log2n,
                     alpha_kind);

@@ -1,7 +1,8 @@
 // gfx950 kernels of the FNT-CDC + FNT-AEQ receiver path.
 //
-//  * fnt_transform_kernel : batched Eq. (1) / Eq. (2) transforms (Fig. 1 case,
-//    the AEQ's N = 32 / alpha = 2 and the CDC's N = 64 / alpha = sqrt 2).
+//  * fnt_transform_kernel : batched Eq. (1) / Eq. (2) transforms modulo F_2, F_3,
+//    F_4 at the full radix order (Fig. 1 case, the AEQ's N = 32 / alpha = 2, the
+//    CDC's N = 64 / alpha = sqrt 2, and the F_2 / F_3 variants).
 //  * cdc_kernel           : overlap-save FNT-CDC (Fig. 2), complex product through
 //    the two real Fermat-domain products of Eqs. (7)-(8), exact centred lift,
 //    resampling to 1 sample/symbol and requantisation to 5 bit.
@@ -2145,7 +2146,11 @@ hipError_t launch_transform(const uint32_t *x, uint32_t *X, size_t batch, int t,
         else                                                                                  \
             fnt_transform_kernel<Q, L, S, false><<<grid, threads, 0, s>>>(x, X, total, err); \
     } while (0)
+    // N = order of the radix: 2^(t+1) for alpha = 2, 2^(t+2) for alpha = sqrt 2
     if (t == 2 && log2n == 3 && alpha_kind == FNT_ALPHA_2) FNT_LAUNCH(4, 3, false);
+    else if (t == 2 && log2n == 4 && alpha_kind == FNT_ALPHA_SQRT2) FNT_LAUNCH(4, 4, true);
+    else if (t == 3 && log2n == 4 && alpha_kind == FNT_ALPHA_2) FNT_LAUNCH(8, 4, false);
+    else if (t == 3 && log2n == 5 && alpha_kind == FNT_ALPHA_SQRT2) FNT_LAUNCH(8, 5, true);
     else if (t == 4 && log2n == 5 && alpha_kind == FNT_ALPHA_2) FNT_LAUNCH(16, 5, false);
     else if (t == 4 && log2n == 6 && alpha_kind == FNT_ALPHA_SQRT2) FNT_LAUNCH(16, 6, true);
     else return hipErrorInvalidValue;

@@ -37,7 +37,8 @@ def to_dev(torch, dev, a):
 
 # ---------------------------------------------------------------- transforms --
 TRANSFORMS = [(2, 3, fnt.FNT_ALPHA_2, 17, 2), (4, 5, fnt.FNT_ALPHA_2, 65537, 2),
-              (4, 6, fnt.FNT_ALPHA_SQRT2, 65537, 4080)]
+              (4, 6, fnt.FNT_ALPHA_SQRT2, 65537, 4080), (2, 4, fnt.FNT_ALPHA_SQRT2, 17, 6),
+              (3, 4, fnt.FNT_ALPHA_2, 257, 2), (3, 5, fnt.FNT_ALPHA_SQRT2, 257, 60)]
 
 
 def test_transform_fig1_golden(torch_dev):
@@ -97,6 +98,20 @@ def test_transform_range_and_shape_errors(torch_dev):
     with pytest.raises(fnt.FntError) as e:
         fnt.fnt_forward(torch.zeros((2, 64), dtype=torch.int32, device=dev), 4, 6, fnt.FNT_ALPHA_2)
     assert e.value.code == fnt.FNT_E_INVAL
+    # lengths other than the radix's order, and moduli outside F_2..F_4
+    for t, log2n, kind in [(3, 6, fnt.FNT_ALPHA_SQRT2), (3, 5, fnt.FNT_ALPHA_2), (2, 5, fnt.FNT_ALPHA_SQRT2),
+                           (1, 2, fnt.FNT_ALPHA_2), (5, 6, fnt.FNT_ALPHA_2)]:
+        with pytest.raises(fnt.FntError) as e:
+            fnt.fnt_forward(torch.zeros((2, 1 << log2n), dtype=torch.int32, device=dev), t, log2n, kind)
+        assert e.value.code == fnt.FNT_E_INVAL
+    # a residue >= 257 is out of range for F_3
+    y = torch.zeros((3, 32), dtype=torch.int32, device=dev)
+    y[2, 31] = 257
+    note("fnt_inverse out-of-range residue mod 257")
+    fnt.fnt_inverse(y, 3, 5, fnt.FNT_ALPHA_SQRT2)
+    with pytest.raises(fnt.FntError) as e:
+        fnt.fnt_check()
+    assert e.value.code == fnt.FNT_E_RANGE
 
 
 # ----------------------------------------------------------------------- CDC --

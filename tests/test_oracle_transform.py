@@ -14,7 +14,7 @@ from oracle import fnt_ref as R
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 # The three (t, radix) pairs the paper uses: Fig. 1, the AEQ and the CDC.
-CASES = [(2, "2", 8), (4, "2", 32), (4, "sqrt2", 64)]
+CASES = [(2, "2", 8), (2, "sqrt2", 16), (3, "2", 16), (3, "sqrt2", 32), (4, "2", 32), (4, "sqrt2", 64)]
 
 
 def is_prime(n):
