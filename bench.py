@@ -70,9 +70,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel: str, workload: str):
+def load_traffic(kernel: str, workload: str, blocks: int | None = None):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
-    taken on the current kernel source; else None."""
+    taken on the current kernel source (and, given `blocks`, on a launch of the
+    same number of AEQ blocks); else None."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         d = json.load(open(p))
@@ -80,6 +81,8 @@ def load_traffic(kernel: str, workload: str):
         return None
     e = d.get(workload, {}).get(kernel)
     if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    if blocks is not None and e.get("aeq_blocks") not in (None, blocks):
         return None
     return e.get("bytes_per_launch")
 
@@ -317,10 +320,11 @@ def bench_batched(args, torch, dev):
     cdc_ms = float(np.mean([t["cdc_ms"] for t in times]))
     aeq_ms = float(np.mean([t["aeq_ms"] for t in times]))
     lead_ms = float(np.mean([t["aeq_lead_ms"] for t in times]))
+    top_ms = float(np.mean([t["aeq_top_ms"] for t in times]))
     event_step_ms = float(np.mean([t["step_ms"] for t in times]))
     ms = wall / max(args.steps, 1) * 1e3
     progress(f"batched: {ms:.1f} ms per step (events {event_step_ms:.1f}: cdc {cdc_ms:.1f} ms, "
-             f"aeq {aeq_ms:.1f} ms, lead aeq {lead_ms:.1f} ms)")
+             f"aeq {aeq_ms:.1f} ms, lead aeq {lead_ms:.1f} ms, first-level aeq {top_ms:.1f} ms)")
     # fnt_plan_run of the same plan (the graph replay when no lead is in effect), for comparison
     taps_all.copy_(w_all)
     run_ms = _time_events(torch, plan.run, 2, stream)
@@ -376,26 +380,31 @@ def bench_batched(args, torch, dev):
     value = inst / (ms / 1e3) / 1e9
     aeq_blocks = times[0]["aeq_blocks"]           # the AEQ launch on the launch stream
     lead_blocks = times[0]["aeq_lead_blocks"]
+    top_blocks = times[0]["aeq_top_blocks"]
     cdc_blocks = sum((e[0].shape[0] + 31) // 32 for e in entries)
     aeq_ops = AEQ_OPS_PER_BLOCK * aeq_blocks
-    all_aeq_ops = AEQ_OPS_PER_BLOCK * (aeq_blocks + lead_blocks)
+    all_aeq_ops = AEQ_OPS_PER_BLOCK * (aeq_blocks + lead_blocks + top_blocks)
     cdc_ops = CDC_OPS_PER_BLOCK * cdc_blocks
     achieved = aeq_ops / (aeq_ms / 1e3) / 1e9
     kname = aeq_kernel_name(info)
     lead_name = AEQ_FORM_KERNEL[info["lead_form"]] if info["lead_channels"] else None
+    top_name = AEQ_FORM_KERNEL[info["top_form"]] if info["top_channels"] else None
     # the dominant kernel: the AEQ launch with the most algorithmic work (with a
-    # lead, the lead's launch on the plan's side stream can be the larger one)
-    if lead_name and lead_blocks > aeq_blocks:
-        dom_name, dom_blocks, dom_ms, dom_key = lead_name, lead_blocks, lead_ms, lead_name + " (lead)"
-    else:
-        dom_name, dom_blocks, dom_ms, dom_key = kname, aeq_blocks, aeq_ms, kname
+    # lead, a launch on one of the plan's side streams can be the largest)
+    launches = [(aeq_blocks, kname, aeq_ms, kname, "launch stream")]
+    if lead_name:
+        launches.append((lead_blocks, lead_name, lead_ms, lead_name + " (lead)", "lead channels, plan side stream"))
+    if top_name:
+        launches.append((top_blocks, top_name, top_ms, top_name + " (first level)",
+                         "first lead level, plan third stream"))
+    dom_blocks, dom_name, dom_ms, dom_key, dom_where = max(launches, key=lambda x: x[0])
     dom_ops = AEQ_OPS_PER_BLOCK * dom_blocks
     dom_achieved = dom_ops / (dom_ms / 1e3) / 1e9
     roof = {"kernel": dom_name, "bound": "alu", "achieved": round(dom_achieved, 1), "peak": PEAK_ALU_GOPS,
             "unit": "Gops/s", "frac": round(dom_achieved / PEAK_ALU_GOPS, 5),
-            "traffic": load_traffic(dom_key, "batched"),
+            "traffic": load_traffic(dom_key, "batched", dom_blocks),
             "algorithmic_ops_per_launch": dom_ops,
-            "launch": "lead channels, plan side stream" if dom_key != kname else "launch stream",
+            "launch": dom_where,
             "hbm_algorithmic_gbs": round(dom_blocks * 16 * AEQ_BYTES_PER_SYMBOL / dom_ms / 1e6, 1),
             "hbm_frac": round(dom_blocks * 16 * AEQ_BYTES_PER_SYMBOL / dom_ms / 1e6 / PEAK_HBM_GBS, 5)}
     kernels = {
@@ -409,11 +418,17 @@ def bench_batched(args, torch, dev):
     }
     if info["lead_channels"]:
         kernels["aeq_lead"] = {
-            "kernel": lead_name, "channels": info["lead_channels"],
+            "kernel": lead_name, "channels": info["lead_channels"] - info["top_channels"],
             "ms": round(lead_ms, 3), "blocks": lead_blocks,
             "gops": round(AEQ_OPS_PER_BLOCK * lead_blocks / lead_ms / 1e6, 1),
             "what": "the longest channels' AEQ, started after their own CDC on a second stream, "
                     "concurrent with the other channels' CDC and AEQ"}
+    if info["top_channels"]:
+        kernels["aeq_top"] = {
+            "kernel": top_name, "channels": info["top_channels"],
+            "ms": round(top_ms, 3), "blocks": top_blocks,
+            "gops": round(AEQ_OPS_PER_BLOCK * top_blocks / top_ms / 1e6, 1),
+            "what": "the first lead level: the very longest channels, CDC first of all, AEQ on a third stream"}
     res = {
         "metric": METRIC,
         "value": round(value, 4), "unit": "Gsamples/s", "n_gpus": 1,
@@ -441,7 +456,7 @@ def bench_batched(args, torch, dev):
                                 "frac": round((all_aeq_ops + cdc_ops) / (ms / 1e3) / 1e9 / PEAK_ALU_GOPS, 5)},
         "plan": {k: info[k] for k in ("cdc_waves_per_group", "cdc_blocks_per_wave", "aeq_variant",
                                       "aeq_waves_per_pol", "aeq_waves_long", "aeq_long_channels",
-                                      "lead_channels", "lead_form", "graph")},
+                                      "lead_channels", "lead_form", "top_channels", "top_form", "graph")},
         "parity": f"bit-exact vs oracle on channels {pick}", "gen_s": round(gen_s, 1),
         "autotune_s": round(tune_s, 1),
     }

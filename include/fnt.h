@@ -194,9 +194,11 @@ typedef struct fnt_plan_info {
     double tune_ms;        /* AEQ time of the chosen schedule during autotune, ms (0 if none) */
     uint64_t aeq_long_channels; /* longest channels run in their own concurrent launch */
     int32_t cdc_variant;   /* 0 = Fermat-domain (the method), 1 = direct comparator */
-    int32_t lead_channels; /* pipelined lead channels in effect (see fnt_plan_set_lead) */
-    int32_t lead_form;     /* AEQ form of the lead channels */
-    int32_t reserved;
+    int32_t lead_channels; /* pipelined lead channels in effect, first level included
+                              (see fnt_plan_set_lead) */
+    int32_t lead_form;     /* AEQ form of the lead channels after the first level */
+    int32_t top_channels;  /* channels of the lead's first level (0: one level) */
+    int32_t top_form;      /* AEQ form of the first level */
 } fnt_plan_info;
 
 typedef struct fnt_plan fnt_plan;
@@ -261,26 +263,35 @@ int fnt_plan_set_cdc_schedule(fnt_plan *plan, int waves_per_group, int blocks_pe
  * or the long chains' form for -1; at raised wave priority) then starts on the
  * plan's side stream while the CDC and the AEQ of the other channels run on the
  * launch stream, so the longest serial chains do not wait for the whole batch's
- * CDC.  The other channels keep the split of fnt_plan_set_aeq_split for those of
- * them among the long channels.  0 (default unless the autotuner chose one) runs
- * every CDC before any AEQ.  In effect only with the Fermat-domain AEQ, for
+ * CDC.  With 0 < top_channels < lead_channels the lead has two levels: the CDC
+ * of the `top_channels` longest runs first of all and their AEQ (form
+ * `top_form`, -1 as above) starts on a third stream, then the CDC of the rest
+ * of the lead and its AEQ on the side stream.  The other channels keep the
+ * split of fnt_plan_set_aeq_split for those of them among the long channels.
+ * lead_channels = 0 (default unless the autotuner chose a lead) runs every CDC
+ * before any AEQ.  In effect only with the Fermat-domain AEQ, for
  * 0 < lead_channels < channels, and when the other channels' AEQ is one launch
  * (no long channels left among them, or a split that runs as one launch);
  * otherwise the plan runs without a lead.  While a lead is in effect
  * fnt_plan_run launches the sequence directly instead of replaying the plan's
  * graph.  Results never depend on it.  FNT_E_INVAL for a NULL plan or another
- * form; FNT_E_NOMEM / FNT_E_DEVICE if the table of the other channels cannot be
+ * form; FNT_E_NOMEM / FNT_E_DEVICE if the segmented CDC table cannot be
  * allocated / uploaded. */
-int fnt_plan_set_lead(fnt_plan *plan, uint64_t lead_channels, int lead_form);
+int fnt_plan_set_lead(fnt_plan *plan, uint64_t lead_channels, int lead_form, uint64_t top_channels,
+                      int top_form);
 
 typedef struct fnt_plan_timing {
     float step_ms;          /* first launch to the end of the last, on the launch stream */
     float cdc_ms;           /* the CDC launches, back to back on the launch stream */
     float aeq_ms;           /* the AEQ launch on the launch stream: the channels after the lead
                                (every channel without a lead) */
-    float aeq_lead_ms;      /* the lead channels' AEQ launch on the side stream (0 without a lead) */
+    float aeq_lead_ms;      /* the lead's AEQ launch on the side stream (after the first level;
+                               0 without a lead) */
     uint64_t aeq_blocks;    /* 16-symbol AEQ blocks of the channels aeq_ms covers */
-    uint64_t aeq_lead_blocks;  /* 16-symbol AEQ blocks of the lead channels */
+    uint64_t aeq_lead_blocks;  /* 16-symbol AEQ blocks of the channels aeq_lead_ms covers */
+    float aeq_top_ms;       /* the first level's AEQ launch on the third stream (0 if none) */
+    int32_t reserved;
+    uint64_t aeq_top_blocks;   /* 16-symbol AEQ blocks of the first level */
 } fnt_plan_timing;
 /* Run every channel once, as fnt_plan_run does, but launch the sequence
  * directly (never the graph) with HIP events around every launch on the stream

@@ -291,14 +291,17 @@ struct fnt_plan {
     int wpp_long = 4;
     size_t n_long = 0;
     // pipelined lead: the n_lead longest channels' CDC first, their AEQ on the side
-    // stream concurrently with the others' CDC and AEQ; cdc_rest_dev holds the
-    // items [n_lead, n) with block0 / chunk0 rebased to 0 (built for rest_lead)
-    size_t n_lead = 0, rest_lead = 0;
-    int lead_form = -1;                // AEQ form of the lead (-1: the long chains' form)
-    CdcItem *cdc_rest_dev = nullptr;
+    // stream concurrently with the others' CDC and AEQ; the n_top longest of them
+    // may form a first level of their own (CDC first of all, AEQ on side2).
+    // cdc_seg_dev is the CDC table with each segment [0, top), [top, lead),
+    // [lead, n) rebased to block 0 / chunk 0, built for (seg_top, seg_lead)
+    size_t n_lead = 0, n_top = 0, seg_lead = 0, seg_top = 0;
+    int lead_form = -1, top_form = -1;  // AEQ forms of the levels (-1: the long chains' form)
+    CdcItem *cdc_seg_dev = nullptr;
     hipStream_t side = nullptr;        // second stream for the concurrent AEQ launch
-    hipEvent_t fork = nullptr, join = nullptr;
-    hipEvent_t tev[6] = {};            // fnt_plan_run_timed
+    hipStream_t side2 = nullptr;       // third stream: the first lead level
+    hipEvent_t fork = nullptr, join = nullptr, fork2 = nullptr, join2 = nullptr;
+    hipEvent_t tev[8] = {};            // fnt_plan_run_timed
     bool use_graph = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -332,10 +335,14 @@ static hipError_t plan_aeq_range(fnt_plan *p, int first, int nl, int count, hipS
     return launch_aeq_split(items, nl, count, p->wpp_long, p->wpp, p->err, s);   // long chains dispatched first
 }
 
-// Lead channels in effect for the plan's current schedule (0: none).
+// Lead channels in effect for the plan's current schedule (0: none), and the
+// first level's channels among them (0: one level).
+static size_t plan_top(const fnt_plan *p) { return p->n_top > 0 && p->n_top < p->n_lead ? p->n_top : 0; }
+
 static size_t plan_lead(const fnt_plan *p) {
     const size_t n = p->aeq_host.size();
-    if (p->variant != 0 || p->n_lead == 0 || p->n_lead >= n || p->rest_lead != p->n_lead || !p->cdc_rest_dev)
+    if (p->variant != 0 || p->n_lead == 0 || p->n_lead >= n || p->seg_lead != p->n_lead ||
+        p->seg_top != plan_top(p) || !p->cdc_seg_dev)
         return 0;
     const size_t rest_long = p->n_long > p->n_lead ? p->n_long - p->n_lead : 0;
     return plan_aeq_one_launch(p, (int)rest_long, (int)(n - p->n_lead)) ? p->n_lead : 0;
@@ -370,13 +377,17 @@ static int plan_launch_aeq(fnt_plan *p, hipStream_t s, hipStream_t side) {
 // blocks, then the AEQ (one launch, or the long chains on s concurrently with
 // the others on the side stream).  With a lead of L channels: the CDC of the L
 // longest channels; fork; their AEQ on the side stream; the CDC of the others
-// and their AEQ on s; join.  Fork / join are events, which a graph capture
-// turns into parallel branches.  `ev` (timing, direct launches only) receives
-// start, CDC end, lead AEQ start, lead AEQ end, AEQ end and done.
-static int plan_launch(fnt_plan *p, hipStream_t s, hipStream_t side, hipEvent_t *ev = nullptr) {
+// and their AEQ on s; join.  With a first level of T < L channels: the CDC of
+// the T longest; fork; their AEQ on side2; then as above for channels [T, L).
+// Fork / join are events, which a graph capture turns into parallel branches.
+// `ev` (timing, direct launches only) receives start, CDC end, lead AEQ start,
+// lead AEQ end, AEQ end, done, first-level AEQ start and end.
+static int plan_launch(fnt_plan *p, hipStream_t s, hipStream_t side, hipStream_t side2,
+                       hipEvent_t *ev = nullptr) {
     auto rec = [&](int i, hipStream_t st) { return ev ? hipEventRecord(ev[i], st) : hipSuccess; };
     hipError_t e = rec(0, s);
     const size_t lead = plan_lead(p);
+    const size_t top = lead ? plan_top(p) : 0;
     if (lead == 0) {
         int rc = e == hipSuccess ? plan_launch_cdc(p, s) : hip_fail(e, "plan: timing event");
         if (!rc && (e = rec(1, s)) != hipSuccess) rc = hip_fail(e, "plan: timing event");
@@ -386,48 +397,70 @@ static int plan_launch(fnt_plan *p, hipStream_t s, hipStream_t side, hipEvent_t 
         return rc;
     }
     const size_t n = p->aeq_host.size();
-    const CdcItem &r0 = p->cdc_host[lead];
     const int rest_long = (int)(p->n_long > lead ? p->n_long - lead : 0);
-    if (e == hipSuccess) e = plan_cdc(p, p->cdc_dev, (int)lead, r0.block0, r0.chunk0, s);
-    if (e == hipSuccess) e = hipEventRecord(p->fork, s);
-    if (e == hipSuccess) e = hipStreamWaitEvent(side, p->fork, 0);
-    if (e == hipSuccess) e = rec(2, side);
+    // the CDC of the segment [a, b) from the rebased table
+    auto seg_cdc = [&](size_t a, size_t b) {
+        const CdcItem &ca = p->cdc_host[a];
+        const uint64_t blocks = (b < n ? p->cdc_host[b].block0 : p->total_blocks) - ca.block0;
+        const uint64_t chunks = (b < n ? p->cdc_host[b].chunk0 : p->total_chunks) - ca.chunk0;
+        return plan_cdc(p, p->cdc_seg_dev + a, (int)(b - a), blocks, chunks, s);
+    };
+    // the AEQ of the lead segment [a, b) on stream st after its CDC
+    auto seg_aeq = [&](size_t a, size_t b, int form, hipStream_t st, hipEvent_t fk, int ev0) {
+        hipError_t r = hipEventRecord(fk, s);
+        if (r == hipSuccess) r = hipStreamWaitEvent(st, fk, 0);
+        if (r == hipSuccess) r = rec(ev0, st);
+        if (r == hipSuccess) r = launch_aeq(p->aeq_dev + a, (int)(b - a), AeqItem{}, 0, form, p->err, st, true);
+        if (r == hipSuccess) r = rec(ev0 + 1, st);
+        return r;
+    };
     const int lf = p->lead_form >= 0 ? p->lead_form : p->wpp_long;
-    if (e == hipSuccess) e = launch_aeq(p->aeq_dev, (int)lead, AeqItem{}, 0, lf, p->err, side, true);
-    if (e == hipSuccess) e = rec(3, side);
-    if (e == hipSuccess)
-        e = plan_cdc(p, p->cdc_rest_dev, (int)(n - lead), p->total_blocks - r0.block0, p->total_chunks - r0.chunk0, s);
+    const int tf = p->top_form >= 0 ? p->top_form : p->wpp_long;
+    if (top) {
+        if (e == hipSuccess) e = seg_cdc(0, top);
+        if (e == hipSuccess) e = seg_aeq(0, top, tf, side2, p->fork2, 6);
+    }
+    if (e == hipSuccess) e = seg_cdc(top, lead);
+    if (e == hipSuccess) e = seg_aeq(top, lead, lf, side, p->fork, 2);
+    if (e == hipSuccess) e = seg_cdc(lead, n);
     if (e == hipSuccess) e = rec(1, s);
     if (e == hipSuccess) e = plan_aeq_range(p, (int)lead, rest_long, (int)(n - lead), s);
     if (e == hipSuccess) e = rec(4, s);
     if (e == hipSuccess) e = hipEventRecord(p->join, side);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, p->join, 0);
+    if (top) {
+        if (e == hipSuccess) e = hipEventRecord(p->join2, side2);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, p->join2, 0);
+    }
     if (e == hipSuccess) e = rec(5, s);
     if (e != hipSuccess) return hip_fail(e, "plan: pipelined launch");
     return FNT_OK;
 }
 
-// Upload the table of the items after a lead of `lead` channels, rebased so that
-// its first item starts at block 0 and chunk 0 (synchronous on s).
-static int plan_build_rest(fnt_plan *p, size_t lead, hipStream_t s) {
+// Upload the CDC table with the segments [0, top), [top, lead), [lead, n) each
+// rebased to start at block 0 and chunk 0 (synchronous on s); top = 0: two
+// segments.  lead = 0 or >= n: no lead, nothing to build.
+static int plan_build_segments(fnt_plan *p, size_t top, size_t lead, hipStream_t s) {
     const size_t n = p->cdc_host.size();
     if (lead == 0 || lead >= n) {
-        p->rest_lead = 0;
+        p->seg_lead = p->seg_top = 0;
         return FNT_OK;
     }
+    if (top >= lead) top = 0;
     hipError_t e = hipSuccess;
-    if (!p->cdc_rest_dev) e = hipMalloc(&p->cdc_rest_dev, n * sizeof(CdcItem));
+    if (!p->cdc_seg_dev) e = hipMalloc(&p->cdc_seg_dev, n * sizeof(CdcItem));
     if (e != hipSuccess) return fail(FNT_E_NOMEM, "plan: lead table: %s", hipGetErrorString(e));
-    std::vector<CdcItem> rest(p->cdc_host.begin() + lead, p->cdc_host.end());
-    const uint64_t b0 = rest[0].block0, c0 = rest[0].chunk0;
-    for (CdcItem &c : rest) {
-        c.block0 -= b0;
-        c.chunk0 -= c0;
+    std::vector<CdcItem> tab(p->cdc_host);
+    for (size_t i = 0; i < n; ++i) {
+        const CdcItem &first = p->cdc_host[i < top ? 0 : i < lead ? top : lead];
+        tab[i].block0 -= first.block0;
+        tab[i].chunk0 -= first.chunk0;
     }
-    e = hipMemcpyAsync(p->cdc_rest_dev, rest.data(), rest.size() * sizeof(CdcItem), hipMemcpyHostToDevice, s);
+    e = hipMemcpyAsync(p->cdc_seg_dev, tab.data(), n * sizeof(CdcItem), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "plan: upload lead table");
-    p->rest_lead = lead;
+    p->seg_lead = lead;
+    p->seg_top = top;
     return FNT_OK;
 }
 
@@ -440,24 +473,28 @@ static void plan_drop_graph(fnt_plan *p) {
 
 static int plan_capture(fnt_plan *p, hipStream_t s) {
     plan_drop_graph(p);
-    hipStream_t cs = nullptr, cs2 = nullptr;
+    hipStream_t cs = nullptr, cs2 = nullptr, cs3 = nullptr;
+    auto drop = [&]() {
+        if (cs) (void)hipStreamDestroy(cs);
+        if (cs2) (void)hipStreamDestroy(cs2);
+        if (cs3) (void)hipStreamDestroy(cs3);
+    };
     hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs2, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs3, hipStreamNonBlocking);
     if (e != hipSuccess) {
-        if (cs) (void)hipStreamDestroy(cs);
+        drop();
         return hip_fail(e, "plan: capture streams");
     }
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) {
-        (void)hipStreamDestroy(cs);
-        (void)hipStreamDestroy(cs2);
+        drop();
         return hip_fail(e, "plan: begin capture");
     }
-    int rc = plan_launch(p, cs, cs2);
+    int rc = plan_launch(p, cs, cs2, cs3);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(cs, &g);
-    (void)hipStreamDestroy(cs);
-    (void)hipStreamDestroy(cs2);
+    drop();
     if (rc) {
         if (g) (void)hipGraphDestroy(g);
         return rc;
@@ -473,7 +510,7 @@ static int plan_capture(fnt_plan *p, hipStream_t s) {
     return FNT_OK;
 }
 
-constexpr int kTuneVersion = 5;
+constexpr int kTuneVersion = 6;
 
 static std::string tune_key(const fnt_plan *p) {
     // length histogram (log2 buckets of instants) + channel count + variant
@@ -496,7 +533,8 @@ static std::string tune_key(const fnt_plan *p) {
 
 // The last entry for `key`; the values are range-checked by the caller.
 static bool tune_cache_lookup(const char *path, const std::string &key, int *wpg, int *bpw, int *wpp,
-                              int *wpp_long, long long *n_long, long long *n_lead, int *lead_form) {
+                              int *wpp_long, long long *n_long, long long *n_lead, int *lead_form,
+                              long long *n_top, int *top_form) {
     if (!path) return false;
     std::ifstream f(path);
     std::string line;
@@ -514,9 +552,10 @@ static bool tune_cache_lookup(const char *path, const std::string &key, int *wpg
         bb = std::atoi(line.c_str() + pb + 7);
         pp = std::atoi(line.c_str() + pq + 7);
         size_t pl = line.find("\"wpp_long\": "), pn = line.find("\"n_long\": "),
-               pd = line.find("\"n_lead\": "), pf = line.find("\"lead_form\": ");
+               pd = line.find("\"n_lead\": "), pf = line.find("\"lead_form\": "),
+               pt = line.find("\"n_top\": "), ptf = line.find("\"top_form\": ");
         if (pl == std::string::npos || pn == std::string::npos || pd == std::string::npos ||
-            pf == std::string::npos)
+            pf == std::string::npos || pt == std::string::npos || ptf == std::string::npos)
             continue;
         *wpg = w;
         *bpw = bb;
@@ -525,18 +564,22 @@ static bool tune_cache_lookup(const char *path, const std::string &key, int *wpg
         *n_long = std::atoll(line.c_str() + pn + 10);
         *n_lead = std::atoll(line.c_str() + pd + 10);
         *lead_form = std::atoi(line.c_str() + pf + 13);
+        *n_top = std::atoll(line.c_str() + pt + 9);
+        *top_form = std::atoi(line.c_str() + ptf + 12);
         found = true;
     }
     return found;
 }
 
 static void tune_cache_store(const char *path, const std::string &key, int wpg, int bpw, int wpp,
-                             int wpp_long, long long n_long, long long n_lead, int lead_form, double ms) {
+                             int wpp_long, long long n_long, long long n_lead, int lead_form, long long n_top,
+                             int top_form, double ms) {
     if (!path) return;
     std::ofstream f(path, std::ios::app);
     f << "{\"key\": \"" << key << "\", \"wpg\": " << wpg << ", \"bpw\": " << bpw << ", \"wpp\": " << wpp
       << ", \"wpp_long\": " << wpp_long << ", \"n_long\": " << n_long << ", \"n_lead\": " << n_lead
-      << ", \"lead_form\": " << lead_form << ", \"ms\": " << ms << "}\n";
+      << ", \"lead_form\": " << lead_form << ", \"n_top\": " << n_top << ", \"top_form\": " << top_form
+      << ", \"ms\": " << ms << "}\n";
 }
 
 // Default AEQ schedule: with few channels the chip is idle, so spread each
@@ -551,11 +594,12 @@ static int default_wpp(size_t nch) { return nch >= 512 ? 3 : (nch >= 128 ? 2 : 4
 
 static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
     std::string key = tune_key(p);
-    int w, b, q, ql, lf;
-    long long nl, nd;
-    if (tune_cache_lookup(cache, key, &w, &b, &q, &ql, &nl, &nd, &lf) && (w == 1 || w == 2 || w == 4) &&
+    int w, b, q, ql, lf, tf;
+    long long nl, nd, nt;
+    if (tune_cache_lookup(cache, key, &w, &b, &q, &ql, &nl, &nd, &lf, &nt, &tf) && (w == 1 || w == 2 || w == 4) &&
         b >= 0 && b <= 1024 && valid_form(q) && valid_form(ql) && nl >= 0 && nd >= 0 &&
-        (size_t)nd < std::max<size_t>(1, p->aeq_host.size()) && (lf == -1 || valid_form(lf))) {
+        (size_t)nd < std::max<size_t>(1, p->aeq_host.size()) && (lf == -1 || valid_form(lf)) && nt >= 0 &&
+        (nt == 0 || nt < nd) && (tf == -1 || valid_form(tf))) {
         p->wpg = w;
         p->bpw = b;
         p->wpp = q;
@@ -563,6 +607,8 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
         p->n_long = (size_t)nl;
         p->n_lead = (size_t)nd;
         p->lead_form = lf;
+        p->n_top = (size_t)nt;
+        p->top_form = tf;
         return FNT_OK;
     }
     hipEvent_t e0, e1;
@@ -604,8 +650,8 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
     AeqItem *tdev = nullptr;
     double best_aeq = 1e30;
     int bq = p->wpp, bql = p->wpp_long;
-    size_t bnl = p->n_long, bnd = 0;
-    int blf = -1;
+    size_t bnl = p->n_long, bnd = 0, btop = 0;
+    int blf = -1, btf = -1;
     if (p->variant == 0 && hipMalloc(&tscratch, nch * 256 * sizeof(int16_t)) == hipSuccess &&
         hipMalloc(&tdev, nch * sizeof(AeqItem)) == hipSuccess) {
         std::vector<AeqItem> tab = p->aeq_host;
@@ -666,49 +712,67 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
                     bql = cands[i].ql;
                     bnl = cands[i].nl;
                 }
-            // pipelined lead (whole runs, CDC + AEQ, timed): the lead's size, how
-            // many of the following chains still take the long chains' form, and
-            // the form of the rest; the long chains' form is the one chosen above
+            // pipelined lead (whole runs, CDC + AEQ, timed): the lead's size and
+            // form, how many of the following chains still take a latency form
+            // (the long chains' form chosen above, or two lanes per transform),
+            // and the form of the rest
             p->wpg = bw;
             p->bpw = bb;
-            p->wpp_long = bql;
-            struct LCand { size_t lead, nl; int q, lf; double ms; };
+            struct LCand { size_t lead, nl; int q, ql, lf; size_t top; int tf; double ms; };
             std::vector<LCand> leads;
             auto time_lead = [&](const LCand &c) -> double {
-                if (plan_build_rest(p, c.lead, s)) return 1e30;
+                if (plan_build_segments(p, c.top, c.lead, s)) return 1e30;
                 p->n_lead = c.lead;
+                p->n_top = c.top;
                 p->n_long = c.nl;
                 p->wpp = c.q;
+                p->wpp_long = c.ql;
                 p->lead_form = c.lf;
-                if (plan_lead(p) != c.lead) return 1e30;
-                return time_it([&] { return plan_launch(p, s, p->side) ? hipErrorUnknown : hipSuccess; });
+                p->top_form = c.tf;
+                if (plan_lead(p) != c.lead || plan_top(p) != c.top) return 1e30;
+                return time_it([&] { return plan_launch(p, s, p->side, p->side2) ? hipErrorUnknown : hipSuccess; });
             };
-            leads.push_back({0, bnl, bq, -1, 0});               // the choice above, without a lead
-            for (size_t lead : {32, 128, 256, 512, 768, 1024, 1536})
-                for (size_t extra : {0, 256, 512, 1024})
-                    for (int q : {0, 3})
-                        for (int lf : {-1, 2}) {                // lead in the long form, or two waves per half
-                            const size_t nl = lead + extra;
-                            if (lead >= nch || nl > nch || lf == bql) continue;
-                            if (extra > 0 && form_rank(q) >= form_rank(bql)) continue;
-                            leads.push_back({lead, nl, q, lf, 0});
-                        }
-            for (LCand &c : leads) c.ms = time_lead(c);
-            std::sort(leads.begin(), leads.end(), [](const LCand &a, const LCand &b) { return a.ms < b.ms; });
-            for (size_t i = 0; i < leads.size() && i < 4; ++i)
-                for (int rep = 0; rep < 2; ++rep) leads[i].ms = std::min(leads[i].ms, time_lead(leads[i]));
-            double best_run = 1e30;
-            for (size_t i = 0; i < leads.size() && i < 4; ++i)
-                if (leads[i].ms < best_run) {
-                    best_run = leads[i].ms;
-                    bnd = leads[i].lead;
-                    bnl = leads[i].nl;
-                    bq = leads[i].q;
-                    blf = leads[i].lf;
+            // one pass over all, then the best four by the median of three more
+            auto best_of = [&](std::vector<LCand> &cs) {
+                for (LCand &c : cs) c.ms = time_lead(c);
+                std::sort(cs.begin(), cs.end(), [](const LCand &x, const LCand &y) { return x.ms < y.ms; });
+                for (size_t i = 0; i < cs.size() && i < 4; ++i) {
+                    double r[3];
+                    for (double &v : r) v = time_lead(cs[i]);
+                    std::sort(r, r + 3);
+                    cs[i].ms = r[1];
                 }
-            p->n_lead = 0;
-            p->lead_form = -1;
-            p->rest_lead = 0;
+                std::sort(cs.begin(), cs.begin() + std::min<size_t>(4, cs.size()),
+                          [](const LCand &x, const LCand &y) { return x.ms < y.ms; });
+                return cs.front();
+            };
+            leads.push_back({0, bnl, bq, bql, -1, 0, -1, 0});   // the choice above, without a lead
+            for (size_t lead : {128, 256, 512, 768, 1024, 1536})
+                for (size_t extra : {0, 512, 1024})
+                    for (int q : {0, 3})
+                        for (int lf : {bql, 2})
+                            for (int ql : {bql, 3}) {
+                                const size_t nl = lead + extra;
+                                if (lead >= nch || nl > nch) continue;
+                                if (lf == 2 && bql == 2) continue;
+                                if (extra == 0 && ql != bql) continue;  // no latency form after the lead
+                                if (extra > 0 && form_rank(q) >= form_rank(ql)) continue;
+                                leads.push_back({lead, nl, q, ql, lf, 0, -1, 0});
+                            }
+            // (a first lead level of its own is not among the candidates: single
+            // passes sometimes timed it faster, steady runs slower, 130 against
+            // 106 ms on the 4096-channel batch)
+            const LCand best = best_of(leads);
+            bnd = best.lead;
+            bnl = best.nl;
+            bq = best.q;
+            bql = best.ql;
+            blf = best.lf;
+            btop = best.top;
+            btf = best.tf;
+            p->n_lead = p->n_top = 0;
+            p->lead_form = p->top_form = -1;
+            p->seg_lead = p->seg_top = 0;
             p->aeq_dev = saved;
         }
     }
@@ -723,8 +787,11 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
     p->n_long = bnl;
     p->n_lead = bnd;
     p->lead_form = blf;
+    p->n_top = btop;
+    p->top_form = btf;
     p->info.tune_ms = best_aeq < 1e29 ? best_aeq : best_cdc;
-    tune_cache_store(cache, key, bw, bb, bq, bql, (long long)bnl, (long long)bnd, blf, p->info.tune_ms);
+    tune_cache_store(cache, key, bw, bb, bq, bql, (long long)bnl, (long long)bnd, blf, (long long)btop, btf,
+                     p->info.tune_ms);
     return FNT_OK;
 }
 
@@ -827,8 +894,11 @@ int fnt_plan_create(fnt_plan **out, const fnt_channel_desc *ch, size_t nch, cons
     p->n_long = 0;
     {
         hipError_t ee = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
+        if (ee == hipSuccess) ee = hipStreamCreateWithFlags(&p->side2, hipStreamNonBlocking);
         if (ee == hipSuccess) ee = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
         if (ee == hipSuccess) ee = hipEventCreateWithFlags(&p->join, hipEventDisableTiming);
+        if (ee == hipSuccess) ee = hipEventCreateWithFlags(&p->fork2, hipEventDisableTiming);
+        if (ee == hipSuccess) ee = hipEventCreateWithFlags(&p->join2, hipEventDisableTiming);
         if (ee != hipSuccess) {
             fnt_plan_destroy(p);
             return hip_fail(ee, "plan: side stream");
@@ -840,7 +910,7 @@ int fnt_plan_create(fnt_plan **out, const fnt_channel_desc *ch, size_t nch, cons
             return rc;
         }
     }
-    if ((rc = plan_build_rest(p, p->n_lead, s))) {
+    if ((rc = plan_build_segments(p, p->n_top, p->n_lead, s))) {
         fnt_plan_destroy(p);
         return rc;
     }
@@ -872,7 +942,7 @@ int fnt_plan_run(fnt_plan *p, void *stream) {
         if (e != hipSuccess) return hip_fail(e, "plan: graph launch");
         return FNT_OK;
     }
-    return plan_launch(p, s, p->side);
+    return plan_launch(p, s, p->side, p->side2);
 }
 
 int fnt_plan_run_stage(fnt_plan *p, int stages, void *stream) {
@@ -897,20 +967,27 @@ int fnt_plan_get_info(const fnt_plan *p, fnt_plan_info *info) {
     info->aeq_long_channels = p->variant == 0 ? std::min(p->n_long, p->aeq_host.size()) : 0;
     info->graph = (p->exec && plan_lead(p) == 0) ? 1 : 0;
     info->cdc_variant = p->cdc_variant;
-    info->lead_channels = (int32_t)plan_lead(p);
+    const size_t lead = plan_lead(p);
+    info->lead_channels = (int32_t)lead;
     info->lead_form = p->lead_form >= 0 ? p->lead_form : p->wpp_long;
+    info->top_channels = lead ? (int32_t)plan_top(p) : 0;
+    info->top_form = p->top_form >= 0 ? p->top_form : p->wpp_long;
     return FNT_OK;
 }
 
-int fnt_plan_set_lead(fnt_plan *p, uint64_t lead, int lead_form) {
+int fnt_plan_set_lead(fnt_plan *p, uint64_t lead, int lead_form, uint64_t top, int top_form) {
     if (!p) return fail(FNT_E_INVAL, "plan: NULL");
     if (lead_form != -1 && !valid_form(lead_form)) return fail(FNT_E_INVAL, "plan: lead form %d", lead_form);
+    if (top_form != -1 && !valid_form(top_form)) return fail(FNT_E_INVAL, "plan: first-level form %d", top_form);
     const size_t n = p->aeq_host.size();
     const size_t l = lead < n ? (size_t)lead : 0;
-    int rc = plan_build_rest(p, l, nullptr);
+    const size_t t = top < l ? (size_t)top : 0;
+    int rc = plan_build_segments(p, t, l, nullptr);
     if (rc) return rc;
     p->n_lead = l;
+    p->n_top = t;
     p->lead_form = lead_form;
+    p->top_form = top_form;
     if (p->exec) return plan_capture(p, nullptr);
     return FNT_OK;
 }
@@ -921,11 +998,12 @@ int fnt_plan_run_timed(fnt_plan *p, fnt_plan_timing *t, void *stream) {
     if (p->cdc_host.empty()) return FNT_OK;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipSuccess;
-    for (int i = 0; i < 6 && e == hipSuccess; ++i)
+    for (int i = 0; i < 8 && e == hipSuccess; ++i)
         if (!p->tev[i]) e = hipEventCreate(&p->tev[i]);
     if (e != hipSuccess) return hip_fail(e, "plan: timing events");
     const size_t lead = plan_lead(p);
-    int rc = plan_launch(p, s, p->side, p->tev);
+    const size_t top = lead ? plan_top(p) : 0;
+    int rc = plan_launch(p, s, p->side, p->side2, p->tev);
     if (rc) return rc;
     e = hipEventSynchronize(p->tev[5]);
     float ms = 0;
@@ -937,8 +1015,10 @@ int fnt_plan_run_timed(fnt_plan *p, fnt_plan_timing *t, void *stream) {
     el(0, 1, &t->cdc_ms);
     el(1, 4, &t->aeq_ms);
     if (lead) el(2, 3, &t->aeq_lead_ms);
+    if (top) el(6, 7, &t->aeq_top_ms);
     if (e != hipSuccess) return hip_fail(e, "plan: timing");
-    t->aeq_lead_blocks = aeq_blocks_of(p, 0, lead);
+    t->aeq_top_blocks = aeq_blocks_of(p, 0, top);
+    t->aeq_lead_blocks = aeq_blocks_of(p, top, lead);
     t->aeq_blocks = aeq_blocks_of(p, lead, p->aeq_host.size());
     return FNT_OK;
 }
@@ -964,7 +1044,7 @@ int fnt_plan_set_aeq_waves(fnt_plan *p, int wpp) {
     if (!valid_form(wpp)) return fail(FNT_E_INVAL, "plan: AEQ form %d", wpp);
     p->wpp = wpp;
     p->n_long = 0;
-    p->n_lead = 0;
+    p->n_lead = p->n_top = 0;
     if (p->exec) return plan_capture(p, nullptr);
     return FNT_OK;
 }
@@ -994,11 +1074,12 @@ int fnt_plan_destroy(fnt_plan *p) {
     if (!p) return FNT_OK;
     plan_drop_graph(p);
     if (p->side) (void)hipStreamDestroy(p->side);
-    if (p->fork) (void)hipEventDestroy(p->fork);
-    if (p->join) (void)hipEventDestroy(p->join);
+    if (p->side2) (void)hipStreamDestroy(p->side2);
+    for (hipEvent_t ev : {p->fork, p->join, p->fork2, p->join2})
+        if (ev) (void)hipEventDestroy(ev);
     for (hipEvent_t ev : p->tev)
         if (ev) (void)hipEventDestroy(ev);
-    if (p->cdc_rest_dev) (void)hipFree(p->cdc_rest_dev);
+    if (p->cdc_seg_dev) (void)hipFree(p->cdc_seg_dev);
     if (p->cdc_dev) (void)hipFree(p->cdc_dev);
     if (p->aeq_dev) (void)hipFree(p->aeq_dev);
     if (p->abuf) (void)hipFree(p->abuf);

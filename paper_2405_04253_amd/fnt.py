@@ -65,13 +65,14 @@ class PlanInfo(ctypes.Structure):
                 ("aeq_waves_long", ctypes.c_int32), ("tune_ms", ctypes.c_double),
                 ("aeq_long_channels", ctypes.c_uint64), ("cdc_variant", ctypes.c_int32),
                 ("lead_channels", ctypes.c_int32), ("lead_form", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("top_channels", ctypes.c_int32), ("top_form", ctypes.c_int32)]
 
 
 class PlanTiming(ctypes.Structure):
     _fields_ = [("step_ms", ctypes.c_float), ("cdc_ms", ctypes.c_float), ("aeq_ms", ctypes.c_float),
                 ("aeq_lead_ms", ctypes.c_float), ("aeq_blocks", ctypes.c_uint64),
-                ("aeq_lead_blocks", ctypes.c_uint64)]
+                ("aeq_lead_blocks", ctypes.c_uint64), ("aeq_top_ms", ctypes.c_float),
+                ("reserved", ctypes.c_int32), ("aeq_top_blocks", ctypes.c_uint64)]
 
 
 class SessionConfig(ctypes.Structure):
@@ -116,7 +117,7 @@ SIGNATURES = {
     "fnt_plan_set_aeq_waves": (_i32, [_vp, _i32]),
     "fnt_plan_set_cdc_schedule": (_i32, [_vp, _i32, _i32]),
     "fnt_plan_set_aeq_split": (_i32, [_vp, _u64, _i32, _i32]),
-    "fnt_plan_set_lead": (_i32, [_vp, _u64, _i32]),
+    "fnt_plan_set_lead": (_i32, [_vp, _u64, _i32, _u64, _i32]),
     "fnt_plan_run_timed": (_i32, [_vp, ctypes.POINTER(PlanTiming), _vp]),
     "fnt_plan_destroy": (_i32, [_vp]),
     "fnt_now_ns": (_u64, []),
@@ -316,8 +317,9 @@ class Plan:
     def set_cdc_schedule(self, waves_per_group: int, blocks_per_wave: int):
         _ok(lib().fnt_plan_set_cdc_schedule(self._h, int(waves_per_group), int(blocks_per_wave)))
 
-    def set_lead(self, lead_channels: int, lead_form: int = -1):
-        _ok(lib().fnt_plan_set_lead(self._h, int(lead_channels), int(lead_form)))
+    def set_lead(self, lead_channels: int, lead_form: int = -1, top_channels: int = 0, top_form: int = -1):
+        _ok(lib().fnt_plan_set_lead(self._h, int(lead_channels), int(lead_form), int(top_channels),
+                                    int(top_form)))
 
     def run_timed(self, stream=None) -> dict:
         """One run launched directly with events around every launch; blocks

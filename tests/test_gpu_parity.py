@@ -415,27 +415,34 @@ def test_plan_determinism_across_schedules(torch_dev):
     # pipelined lead: the longest channels' CDC first, their AEQ on the side stream
     # while the others' CDC and AEQ run (graph replay, direct launch, timed launch)
     n = len(pc)
-    for lead, lf, nl, wl, ws, active in [(1, -1, 1, 1, 0, True), (3, 2, 5, 1, 3, True), (5, -1, 12, 2, 1, False),
-                                         (n - 1, -1, n, 4, 0, True), (10, 0, 2, 4, 3, True),
-                                         (4, 4, 9, 3, 0, True), (7, 3, 7, 1, 0, True),
-                                         (n, -1, 3, 1, 0, False), (0, 2, 3, 1, 0, False)]:
+    for lead, lf, top, tf, nl, wl, ws, active in [
+            (1, -1, 0, -1, 1, 1, 0, True), (3, 2, 0, -1, 5, 1, 3, True), (5, -1, 0, -1, 12, 2, 1, False),
+            (n - 1, -1, 0, -1, n, 4, 0, True), (10, 0, 0, -1, 2, 4, 3, True),
+            (4, 4, 0, -1, 9, 3, 0, True), (7, 3, 0, -1, 7, 1, 0, True),
+            (n, -1, 0, -1, 3, 1, 0, False), (0, 2, 0, -1, 3, 1, 0, False),
+            # two levels: the first level's CDC first and its AEQ on a third stream
+            (6, -1, 2, 2, 9, 1, 0, True), (12, 1, 1, -1, 12, 1, 3, True), (n - 1, 3, 5, 4, n, 2, 0, True),
+            (4, -1, 4, 2, 4, 1, 0, True), (5, -1, 2, 1, 12, 2, 1, False)]:
         plan.set_aeq_split(nl, wl, ws)
-        plan.set_lead(lead, lf)
+        plan.set_lead(lead, lf, top, tf)
         info = plan.info()
+        top_eff = top if active and top < lead else 0
         assert info["lead_channels"] == (lead if active else 0)
         assert info["lead_form"] == (wl if lf == -1 else lf)
+        assert info["top_channels"] == top_eff and info["top_form"] == (wl if tf == -1 else tf)
         for mode in ("run", "timed", "stages"):
             for c in pc:
                 c["taps"].copy_(to_dev(torch, dev, c["w0"]))
                 c["out"].fill_(-3)
-            note(f"plan lead={lead} long={nl} wl={wl} ws={ws} {mode}")
+            note(f"plan lead={lead}/{lf} top={top}/{tf} long={nl} wl={wl} ws={ws} {mode}")
             if mode == "run":
                 plan.run()
             elif mode == "timed":
                 t = plan.run_timed()
                 assert t["step_ms"] > 0 and t["cdc_ms"] > 0 and t["aeq_ms"] > 0
-                assert (t["aeq_lead_ms"] > 0) == active
-                assert t["aeq_blocks"] + t["aeq_lead_blocks"] == sum((c["out"].shape[0] + 15) // 16 for c in pc)
+                assert (t["aeq_lead_ms"] > 0) == active and (t["aeq_top_ms"] > 0) == (top_eff > 0)
+                assert t["aeq_blocks"] + t["aeq_lead_blocks"] + t["aeq_top_blocks"] == \
+                    sum((c["out"].shape[0] + 15) // 16 for c in pc)
             else:
                 plan.run_stage(fnt.FNT_STAGE_ALL)
             torch.cuda.synchronize()
@@ -443,6 +450,8 @@ def test_plan_determinism_across_schedules(torch_dev):
                 assert np.array_equal(c["out"].cpu().numpy(), o) and np.array_equal(c["taps"].cpu().numpy(), w)
     with pytest.raises(fnt.FntError):
         plan.set_lead(2, 5)
+    with pytest.raises(fnt.FntError):
+        plan.set_lead(4, 1, 2, 7)
     plan.set_aeq_waves(1)
     assert plan.info()["lead_channels"] == 0
     plan.close()
@@ -476,7 +485,7 @@ def test_plan_autotune_and_eager(torch_dev, tmp_path):
     info2 = plan2.info()
     assert info2["tune_ms"] == 0.0
     for k in ("cdc_waves_per_group", "cdc_blocks_per_wave", "aeq_waves_per_pol", "aeq_waves_long",
-              "aeq_long_channels", "lead_channels", "lead_form"):
+              "aeq_long_channels", "lead_channels", "lead_form", "top_channels", "top_form"):
         assert info2[k] == info[k], k
     plan2.close()
     # the two stages launched one by one reproduce a whole run
