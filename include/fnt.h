@@ -269,9 +269,9 @@ int fnt_plan_set_cdc_schedule(fnt_plan *plan, int waves_per_group, int blocks_pe
  * of the lead and its AEQ on the side stream.  The other channels keep the
  * split of fnt_plan_set_aeq_split for those of them among the long channels.
  * lead_channels = 0 (default unless the autotuner chose a lead) runs every CDC
- * before any AEQ.  In effect only with the Fermat-domain AEQ, for
- * 0 < lead_channels < channels, and when the other channels' AEQ is one launch
- * (no long channels left among them, or a split that runs as one launch);
+ * before any AEQ.  In effect for 0 < lead_channels < channels when the other
+ * channels' AEQ is one launch (no long channels left among them, a split that
+ * runs as one launch, or an AEQ variant other than 0, whose forms are ignored);
  * otherwise the plan runs without a lead.  While a lead is in effect
  * fnt_plan_run launches the sequence directly instead of replaying the plan's
  * graph.  Results never depend on it.  FNT_E_INVAL for a NULL plan or another

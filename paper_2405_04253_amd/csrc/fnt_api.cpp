@@ -341,7 +341,7 @@ static size_t plan_top(const fnt_plan *p) { return p->n_top > 0 && p->n_top < p-
 
 static size_t plan_lead(const fnt_plan *p) {
     const size_t n = p->aeq_host.size();
-    if (p->variant != 0 || p->n_lead == 0 || p->n_lead >= n || p->seg_lead != p->n_lead ||
+    if (p->n_lead == 0 || p->n_lead >= n || p->seg_lead != p->n_lead ||
         p->seg_top != plan_top(p) || !p->cdc_seg_dev)
         return 0;
     const size_t rest_long = p->n_long > p->n_lead ? p->n_long - p->n_lead : 0;
@@ -410,7 +410,8 @@ static int plan_launch(fnt_plan *p, hipStream_t s, hipStream_t side, hipStream_t
         hipError_t r = hipEventRecord(fk, s);
         if (r == hipSuccess) r = hipStreamWaitEvent(st, fk, 0);
         if (r == hipSuccess) r = rec(ev0, st);
-        if (r == hipSuccess) r = launch_aeq(p->aeq_dev + a, (int)(b - a), AeqItem{}, 0, form, p->err, st, true);
+        if (r == hipSuccess)
+            r = launch_aeq(p->aeq_dev + a, (int)(b - a), AeqItem{}, p->variant, form, p->err, st, true);
         if (r == hipSuccess) r = rec(ev0 + 1, st);
         return r;
     };

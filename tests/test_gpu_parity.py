@@ -362,6 +362,18 @@ def test_plan_direct_cdc_comparator(torch_dev, aeq_variant):
         for e, (outr, wr, _) in zip(entries, refs):
             assert np.array_equal(e[1].cpu().numpy(), outr)
             assert np.array_equal(e[2].cpu().numpy(), wr)
+    # with a two-level pipelined lead (the comparator kernels in every launch)
+    plan.set_lead(6, -1, 2, -1)
+    assert plan.info()["lead_channels"] == 6 and plan.info()["top_channels"] == 2
+    for e in entries:
+        e[2].copy_(to_dev(torch, dev, w0))
+        e[1].fill_(-5)
+    note(f"plan with the direct CDC, AEQ variant {aeq_variant}, pipelined lead")
+    t = plan.run_timed()
+    assert t["aeq_top_ms"] > 0 and t["aeq_lead_ms"] > 0
+    for e, (outr, wr, _) in zip(entries, refs):
+        assert np.array_equal(e[1].cpu().numpy(), outr)
+        assert np.array_equal(e[2].cpu().numpy(), wr)
     with pytest.raises(fnt.FntError):
         plan.set_cdc_variant(2)
     plan.close()
