@@ -292,6 +292,20 @@ def test_plan_batched_vs_oracle(torch_dev, variant, wpp):
     info = plan.info()
     assert info["channels"] == len(pc) and info["graph"] == 1 and info["aeq_variant"] == variant
     assert info["aeq_waves_per_pol"] == wpp
+    # leads that leave only the tiny and the empty channel (last in the longest-first
+    # order) to the others' CDC and AEQ, with and without a first level
+    for lead, lf, top, tf in [(len(pc) - 1, 1, 0, -1), (len(pc) - 2, 3, 5, 2), (len(pc) - 1, 0, 40, 4)]:
+        plan.set_lead(lead, lf, top, tf)
+        assert plan.info()["lead_channels"] == lead
+        for c in pc:
+            c["taps"].copy_(to_dev(torch, dev, c["w0"]))
+            c["out"].fill_(-1)
+        note(f"plan run variant={variant} wpp={wpp} lead={lead}/{lf} top={top}/{tf}")
+        plan.run()
+        torch.cuda.synchronize()
+        for c, (outr, wr, _) in zip(pc, refs):
+            assert np.array_equal(c["out"].cpu().numpy(), outr), (lead, c["ch"].n)
+            assert np.array_equal(c["taps"].cpu().numpy(), wr), (lead, c["ch"].n)
     plan.close()
     fnt.fnt_check()
 
