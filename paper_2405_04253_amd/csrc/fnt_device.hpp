@@ -1,16 +1,11 @@
 // Device-side arithmetic in Z_F, F = 2^Q + 1 (a Fermat number, FNT section of
-// the paper), and the cross-lane radix-2 transforms used by every kernel.
+// the paper): canonical residues, loose residues modulo 65537, lane exchanges.
 //
 // Residues are uint32 in canonical form [0, F).  For Q = 16 (F = 65537) all
 // reductions use 2^16 = -1 (mod F): a 32-bit value h*2^16 + l reduces to l - h.
 // Multiplication by a power of the radix is a shift (alpha = 2) or a shift plus
 // one multiply by 2^12 - 2^4 (alpha = sqrt 2), never a general product.
-//
-// Transforms run "across lanes": a group of N consecutive lanes of a wave64
-// holds one length-N vector, one element per lane.  The forward transform is
-// decimation in frequency (natural order in, bit-reversed order out); the
-// inverse is decimation in time (bit-reversed order in, natural order out,
-// unnormalised).  Each radix-2 stage exchanges partners with a lane xor.
+
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -98,46 +93,6 @@ struct Field {
         return r > (F - 1) / 2 ? (int32_t)r - (int32_t)F : (int32_t)r;
     }
 };
-
-// Forward transform (Eq. (1)) across N = 2^LOGN lanes, decimation in frequency.
-// Lane with position pos = lane & (N-1) holds x[pos]; on return it holds
-// X[bitrev(pos)].  All lanes of the wave must call it (shuffles).
-template <int Q, int LOGN, bool SQRT2>
-__device__ __forceinline__ uint32_t fwd_xlane(uint32_t x, int lane) {
-    using FF = Field<Q>;
-    constexpr int N = 1 << LOGN;
-    const int pos = lane & (N - 1);
-#pragma unroll
-    for (int h = N / 2; h >= 1; h >>= 1) {
-        uint32_t p = (uint32_t)__shfl_xor((int)x, h);
-        bool upper = (pos & h) != 0;
-        int e = (N / (2 * h)) * (pos & (h - 1));
-        uint32_t s = FF::add(x, p);
-        uint32_t d = FF::template mul_radix_pow<SQRT2>(FF::sub(p, x), e);
-        x = upper ? d : s;
-    }
-    return x;
-}
-
-// Inverse transform (Eq. (2) without the N^-1 factor) across N lanes,
-// decimation in time.  Lane pos holds X[bitrev(pos)]; on return it holds
-// N * x[pos].
-template <int Q, int LOGN, bool SQRT2>
-__device__ __forceinline__ uint32_t inv_xlane(uint32_t x, int lane) {
-    using FF = Field<Q>;
-    constexpr int N = 1 << LOGN;
-    const int pos = lane & (N - 1);
-#pragma unroll
-    for (int h = 1; h < N; h <<= 1) {
-        bool upper = (pos & h) != 0;
-        int e = (N / (2 * h)) * (pos & (h - 1));
-        // alpha^-e = alpha^(N - e); upper lanes twiddle their own value first
-        uint32_t t = upper ? FF::template mul_radix_pow<SQRT2>(x, e ? N - e : 0) : x;
-        uint32_t p = (uint32_t)__shfl_xor((int)t, h);
-        x = upper ? FF::sub(p, t) : FF::add(x, p);
-    }
-    return x;
-}
 
 __device__ __forceinline__ int bitrev(int v, int bits) {
     return (int)(__brev((uint32_t)v) >> (32 - bits));

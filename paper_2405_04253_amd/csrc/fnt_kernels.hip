@@ -30,6 +30,21 @@ __device__ __forceinline__ void flag(int *err, int bit) {
 
 // ---------------------------------------------------------------- transforms --
 
+// Powers of the CDC radix alpha = sqrt 2 = 4080 modulo 65537, alpha^e for e < 64.
+struct AlphaPow {
+    int32_t v[64];
+};
+constexpr AlphaPow make_alpha_pow() {
+    AlphaPow a{};
+    uint64_t x = 1;
+    for (int e = 0; e < 64; ++e) {
+        a.v[e] = (int32_t)x;
+        x = x * 4080u % 65537u;
+    }
+    return a;
+}
+__constant__ AlphaPow kAlphaPow = make_alpha_pow();
+
 constexpr uint32_t pow_mod(uint32_t b, uint32_t e, uint32_t m) {
     uint64_t r = 1, x = b % m;
     while (e) {
@@ -40,34 +55,129 @@ constexpr uint32_t pow_mod(uint32_t b, uint32_t e, uint32_t m) {
     return (uint32_t)r;
 }
 
+// Transforms across N = 2^LOGN lanes of a wave, one element per lane (position
+// pos = lane mod N).  Forward: decimation in frequency, natural order in, lane
+// pos ends with X[bitrev(pos)].  Inverse: decimation in time, bit-reversed
+// order in, lane pos ends with N x[pos] (unnormalised).  Each radix-2 stage
+// exchanges with lane ^ H by a DPP or swizzle move where one exists; residues
+// stay canonical in [0, F).
+template <int Q, int LOGN, bool SQRT2, int H>
+__device__ __forceinline__ uint32_t fwd_stage_x(uint32_t x, int pos) {
+    using FF = Field<Q>;
+    constexpr int N = 1 << LOGN;
+    const uint32_t p = (uint32_t)xor_lane<H>((int32_t)x);
+    const int e = (N / (2 * H)) * (pos & (H - 1));
+    const uint32_t s = FF::add(x, p);
+    const uint32_t d = FF::template mul_radix_pow<SQRT2>(FF::sub(p, x), e);
+    return (pos & H) ? d : s;
+}
+template <int Q, int LOGN, bool SQRT2, int H>
+__device__ __forceinline__ uint32_t inv_stage_x(uint32_t x, int pos) {
+    using FF = Field<Q>;
+    constexpr int N = 1 << LOGN;
+    const bool upper = (pos & H) != 0;
+    const int e = (N / (2 * H)) * (pos & (H - 1));
+    const uint32_t t = upper ? FF::template mul_radix_pow<SQRT2>(x, e ? N - e : 0) : x;
+    const uint32_t p = (uint32_t)xor_lane<H>((int32_t)t);
+    return upper ? FF::sub(p, t) : FF::add(x, p);
+}
+template <int Q, int LOGN, bool SQRT2, int H = (1 << LOGN) / 2>
+__device__ __forceinline__ uint32_t fwd_dpp(uint32_t x, int pos) {      // stages H = N/2 .. 1
+    x = fwd_stage_x<Q, LOGN, SQRT2, H>(x, pos);
+    if constexpr (H > 1) return fwd_dpp<Q, LOGN, SQRT2, H / 2>(x, pos);
+    else return x;
+}
+template <int Q, int LOGN, bool SQRT2, int H = 1>
+__device__ __forceinline__ uint32_t inv_dpp(uint32_t x, int pos) {      // stages H = 1 .. N/2
+    x = inv_stage_x<Q, LOGN, SQRT2, H>(x, pos);
+    if constexpr (2 * H < (1 << LOGN)) return inv_dpp<Q, LOGN, SQRT2, 2 * H>(x, pos);
+    else return x;
+}
+
+// The same transforms modulo 65537 on loose residues (signed int32, reduced
+// only inside mulmod): a stage is two DPP-fed sums and one 24-bit product.
+// Canonical input (< 2^17); after stage k the sums are below 2^(17+k) and the
+// products below 2^17 (the inverse multiplies every value, by 1 in the lower
+// lanes, so its sums stay below 2^18), and every mulmod input stays below 2^23
+// for N <= 64.
+// Twiddles alpha^(+-e), e < 32: 2^e / -2^(16-e) for alpha = 2, the table of
+// 4080^e for alpha = sqrt 2.
+template <int LOGN, bool SQRT2, int H>
+__device__ __forceinline__ int32_t fwd_stage_lazy(int32_t x, int pos) {
+    constexpr int N = 1 << LOGN;
+    const int e = (N / (2 * H)) * (pos & (H - 1));
+    const int32_t c = SQRT2 ? kAlphaPow.v[e] : (1 << e);
+    const int32_t p = xor_lane<H>(x);
+    const int32_t s = x + p;
+    const int32_t d = mulmod(p - x, c);
+    return (pos & H) ? d : s;
+}
+template <int LOGN, bool SQRT2, int H>
+__device__ __forceinline__ int32_t inv_stage_lazy(int32_t x, int pos) {
+    constexpr int N = 1 << LOGN;
+    const bool upper = (pos & H) != 0;
+    const int e = upper ? (N / (2 * H)) * (pos & (H - 1)) : 0;
+    // every lane multiplies (lower lanes by 1): no branch, and the twiddle load
+    // does not depend on the data, so it leaves the loop
+    const int32_t c = SQRT2 ? kAlphaPow.v[(N - e) & (N - 1)] : (e ? -(1 << (16 - e)) : 1);
+    const int32_t t = mulmod(x, c);
+    const int32_t p = xor_lane<H>(t);
+    return upper ? p - t : t + p;
+}
+template <int LOGN, bool SQRT2, int H = (1 << LOGN) / 2>
+__device__ __forceinline__ int32_t fwd_lazy(int32_t x, int pos) {
+    x = fwd_stage_lazy<LOGN, SQRT2, H>(x, pos);
+    if constexpr (H > 1) return fwd_lazy<LOGN, SQRT2, H / 2>(x, pos);
+    else return x;
+}
+template <int LOGN, bool SQRT2, int H = 1>
+__device__ __forceinline__ int32_t inv_lazy(int32_t x, int pos) {
+    x = inv_stage_lazy<LOGN, SQRT2, H>(x, pos);
+    if constexpr (2 * H < (1 << LOGN)) return inv_lazy<LOGN, SQRT2, 2 * H>(x, pos);
+    else return x;
+}
+// A loose residue mod 65537 (|v| < 2^31) to canonical [0, 65537).
+__device__ __forceinline__ uint32_t canon65537(int32_t v) {
+    int32_t f = (int32_t)((uint32_t)v & 0xFFFFu) - (v >> 16);      // (-2^15, 2^16 + 2^15)
+    f = f < 0 ? f + 65537 : f;
+    return (uint32_t)(f >= 65537 ? f - 65537 : f);
+}
+
+// Grid-stride over the batch: the stride is a multiple of 64, so a lane keeps
+// its position and its twiddles, and the lanes of one vector enter and leave
+// the loop together (their exchanges never read a lane that has left).
 template <int Q, int LOGN, bool SQRT2, bool INV>
 __global__ __launch_bounds__(256) void fnt_transform_kernel(const uint32_t *x, uint32_t *X,
                                                             uint64_t total, int *err) {
     using FF = Field<Q>;
     constexpr int N = 1 << LOGN;
     constexpr uint32_t NINV = pow_mod(N, FF::F - 2, FF::F);
-    const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = threadIdx.x & 63;
-    const int pos = lane & (N - 1);
-    const bool valid = gid < total;
-    const uint64_t base = gid - (uint64_t)pos;
-    uint32_t v = 0;
-    if (valid) {
-        v = x[INV ? base + (uint64_t)bitrev(pos, LOGN) : gid];
+    const int pos = (int)(threadIdx.x & 63) & (N - 1);
+    const int rpos = bitrev(pos, LOGN);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    bool bad = false;
+    for (uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; gid - (uint64_t)pos < total;
+         gid += stride) {
+        const uint64_t base = gid - (uint64_t)pos;
+        uint32_t v = x[INV ? base + (uint64_t)rpos : gid];
         if (v >= FF::F) {
-            flag(err, RANGE_RESIDUE);
+            bad = true;
             v %= FF::F;
         }
+        if constexpr (Q == 16) {
+            constexpr int32_t NINV_S = NINV > FF::F / 2 ? (int32_t)NINV - (int32_t)FF::F : (int32_t)NINV;
+            if constexpr (!INV)
+                v = canon65537(fwd_lazy<LOGN, SQRT2>((int32_t)v, pos));
+            else
+                v = canon65537(mulmod(inv_lazy<LOGN, SQRT2>((int32_t)v, pos), NINV_S));
+        } else if constexpr (!INV) {
+            v = fwd_dpp<Q, LOGN, SQRT2>(v, pos);
+        } else {
+            v = FF::mul(inv_dpp<Q, LOGN, SQRT2>(v, pos), NINV);
+        }
+        X[INV ? gid : base + (uint64_t)rpos] = v;
     }
-    uint64_t dst;
-    if constexpr (!INV) {
-        v = fwd_xlane<Q, LOGN, SQRT2>(v, lane);
-        dst = base + (uint64_t)bitrev(pos, LOGN);
-    } else {
-        v = FF::mul(inv_xlane<Q, LOGN, SQRT2>(v, lane), NINV);
-        dst = gid;
-    }
-    if (valid) X[dst] = v;
+    if (bad) flag(err, RANGE_RESIDUE);
 }
 
 // ----------------------------------------------------------------------- CDC --
@@ -96,20 +206,6 @@ __device__ __forceinline__ uint32_t cdc_load(const CdcItem &it, int64_t i) {
     return (uint64_t)i < it.n ? reinterpret_cast<const uint32_t *>(it.in)[i] : 0u;
 }
 
-// Powers of the CDC radix alpha = sqrt 2 = 4080 modulo 65537, alpha^e for e < 64.
-struct AlphaPow {
-    int32_t v[64];
-};
-constexpr AlphaPow make_alpha_pow() {
-    AlphaPow a{};
-    uint64_t x = 1;
-    for (int e = 0; e < 64; ++e) {
-        a.v[e] = (int32_t)x;
-        x = x * 4080u % 65537u;
-    }
-    return a;
-}
-__constant__ AlphaPow kAlphaPow = make_alpha_pow();
 
 // 64-point transforms of the CDC, 16 lanes per transform, 4 points per lane:
 // lane t of a group holds positions n = t + 16 j (j < 4).  Twiddle constants
@@ -2138,7 +2234,9 @@ hipError_t launch_transform(const uint32_t *x, uint32_t *X, size_t batch, int t,
     const uint64_t total = (uint64_t)batch << log2n;
     if (total == 0) return hipSuccess;
     const unsigned threads = 256;
-    const unsigned grid = (unsigned)((total + threads - 1) / threads);
+    // enough workgroups to fill 256 CUs many times over; each thread then
+    // loops over the batch (see fnt_transform_kernel)
+    const unsigned grid = (unsigned)std::min<uint64_t>((total + threads - 1) / threads, 8192);
 #define FNT_LAUNCH(Q, L, S)                                                                   \
     do {                                                                                      \
         if (inverse)                                                                          \
