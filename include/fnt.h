@@ -274,7 +274,9 @@ int fnt_plan_set_cdc_schedule(fnt_plan *plan, int waves_per_group, int blocks_pe
  * runs as one launch, or an AEQ variant other than 0, whose forms are ignored);
  * otherwise the plan runs without a lead.  While a lead is in effect
  * fnt_plan_run launches the sequence directly instead of replaying the plan's
- * graph.  Results never depend on it.  FNT_E_INVAL for a NULL plan or another
+ * graph.  Results never depend on it.  Waits for the device to finish its
+ * outstanding work (earlier runs may still read the plan's tables), then
+ * rewrites the segmented CDC table.  FNT_E_INVAL for a NULL plan or another
  * form; FNT_E_NOMEM / FNT_E_DEVICE if the segmented CDC table cannot be
  * allocated / uploaded. */
 int fnt_plan_set_lead(fnt_plan *plan, uint64_t lead_channels, int lead_form, uint64_t top_channels,

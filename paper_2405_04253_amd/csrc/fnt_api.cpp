@@ -983,6 +983,9 @@ int fnt_plan_set_lead(fnt_plan *p, uint64_t lead, int lead_form, uint64_t top, i
     const size_t n = p->aeq_host.size();
     const size_t l = lead < n ? (size_t)lead : 0;
     const size_t t = top < l ? (size_t)top : 0;
+    // the segmented table may be read by runs still in flight on any stream
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "plan: set lead");
     int rc = plan_build_segments(p, t, l, nullptr);
     if (rc) return rc;
     p->n_lead = l;
