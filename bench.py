@@ -169,7 +169,7 @@ def bench_single(args, torch, dev):
     achieved = aeq_ops / (aeq_ms / 1e3) / 1e9
     roof = {"kernel": "aeq_pol_kernel<16>", "bound": "alu", "achieved": round(achieved, 3),
             "peak": PEAK_ALU_GOPS, "unit": "Gops/s", "frac": round(achieved / PEAK_ALU_GOPS, 6),
-            "traffic": load_traffic("aeq_pol_kernel<16>", "single"),
+            "traffic": load_traffic("aeq_pol_kernel<16>", "single", blocks_aeq),
             "algorithmic_ops_per_launch": aeq_ops}
     res = {
         "value": round(n / (ms / 1e3) / 1e9, 6), "unit": "Gsamples/s",
