@@ -467,7 +467,8 @@ def bench_batched(args, torch, dev):
                                 "frac": round((all_aeq_ops + cdc_ops) / (ms / 1e3) / 1e9 / PEAK_ALU_GOPS, 5)},
         "plan": {k: info[k] for k in ("cdc_waves_per_group", "cdc_blocks_per_wave", "aeq_variant",
                                       "aeq_waves_per_pol", "aeq_waves_long", "aeq_long_channels",
-                                      "lead_channels", "lead_form", "top_channels", "top_form", "graph")},
+                                      "lead_channels", "lead_form", "top_channels", "top_form", "graph",
+                                      "tune_run_ms")},
         "parity": f"bit-exact vs oracle on channels {pick}", "gen_s": round(gen_s, 1),
         "autotune_s": round(tune_s, 1),
     }

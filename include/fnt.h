@@ -199,6 +199,8 @@ typedef struct fnt_plan_info {
     int32_t lead_form;     /* AEQ form of the lead channels after the first level */
     int32_t top_channels;  /* channels of the lead's first level (0: one level) */
     int32_t top_form;      /* AEQ form of the first level */
+    double tune_run_ms;    /* whole-run time (CDC + AEQ) of the chosen schedule during autotune,
+                              ms (0 if none) */
 } fnt_plan_info;
 
 typedef struct fnt_plan fnt_plan;

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <fstream>
 #include <map>
 #include <mutex>
@@ -733,15 +734,28 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
                 if (plan_lead(p) != c.lead || plan_top(p) != c.top) return 1e30;
                 return time_it([&] { return plan_launch(p, s, p->side, p->side2) ? hipErrorUnknown : hipSuccess; });
             };
-            // one pass over all, then the best four by the median of three more
+            // one pass over all, then the best four by the median of three more;
+            // FNT_TUNE_LOG names a file that receives every timing (diagnostics)
+            const char *log_path = std::getenv("FNT_TUNE_LOG");
+            std::ofstream tlog;
+            if (log_path) tlog.open(log_path, std::ios::app);
+            auto log_c = [&](const char *what, const LCand &c) {
+                if (tlog.is_open())
+                    tlog << what << " lead " << c.lead << " long " << c.nl << " q " << c.q << " ql " << c.ql << " lf "
+                         << c.lf << " top " << c.top << " tf " << c.tf << " wpg " << p->wpg << " ms " << c.ms << "\n";
+            };
             auto best_of = [&](std::vector<LCand> &cs) {
-                for (LCand &c : cs) c.ms = time_lead(c);
+                for (LCand &c : cs) {
+                    c.ms = time_lead(c);
+                    log_c("pass", c);
+                }
                 std::sort(cs.begin(), cs.end(), [](const LCand &x, const LCand &y) { return x.ms < y.ms; });
                 for (size_t i = 0; i < cs.size() && i < 4; ++i) {
                     double r[3];
                     for (double &v : r) v = time_lead(cs[i]);
                     std::sort(r, r + 3);
                     cs[i].ms = r[1];
+                    log_c("median", cs[i]);
                 }
                 std::sort(cs.begin(), cs.begin() + std::min<size_t>(4, cs.size()),
                           [](const LCand &x, const LCand &y) { return x.ms < y.ms; });
@@ -764,6 +778,30 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
             // passes sometimes timed it faster, steady runs slower, 130 against
             // 106 ms on the 4096-channel batch)
             const LCand best = best_of(leads);
+            p->info.tune_run_ms = best.ms;
+            // the CDC's waves per workgroup were chosen on the CDC alone; with a
+            // lead the CDC shares the chip with the lead's AEQ, so the best
+            // schedule is timed again with the other lane-CDC groupings
+            if (best.lead > 0 && bb == 0) {
+                for (int wpg : {1, 2, 4}) {
+                    if (wpg == bw) continue;
+                    const int keep = p->wpg;
+                    p->wpg = wpg;
+                    double r[3];
+                    for (double &v : r) v = time_lead(best);
+                    std::sort(r, r + 3);
+                    LCand c = best;
+                    c.ms = r[1];
+                    log_c("cdc-grouping", c);
+                    if (r[1] < p->info.tune_run_ms) {
+                        p->info.tune_run_ms = r[1];
+                        bw = wpg;
+                    } else {
+                        p->wpg = keep;
+                    }
+                }
+                p->wpg = bw;
+            }
             bnd = best.lead;
             bnl = best.nl;
             bq = best.q;

@@ -65,7 +65,8 @@ class PlanInfo(ctypes.Structure):
                 ("aeq_waves_long", ctypes.c_int32), ("tune_ms", ctypes.c_double),
                 ("aeq_long_channels", ctypes.c_uint64), ("cdc_variant", ctypes.c_int32),
                 ("lead_channels", ctypes.c_int32), ("lead_form", ctypes.c_int32),
-                ("top_channels", ctypes.c_int32), ("top_form", ctypes.c_int32)]
+                ("top_channels", ctypes.c_int32), ("top_form", ctypes.c_int32),
+                ("tune_run_ms", ctypes.c_double)]
 
 
 class PlanTiming(ctypes.Structure):
