@@ -33,7 +33,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0            # MI355X HBM3E
-PEAK_ALU_GOPS = 256 * 4 * 16 * 2.4   # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39321.6 G int32 ops/s
+# 32-bit VALU: the fastest forms (add, logic) issue a wave64 instruction in 2 cycles
+# per SIMD, i.e. 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 78643.2 G lane-ops/s (the
+# published fp32 vector rate, 157.3 TFLOP/s, counts an FMA as two); SDWA, shifts
+# and 24-bit multiplies take 4 cycles (half this rate)
+PEAK_ALU_GOPS = 256 * 4 * 32 * 2.4
 
 # Algorithmic integer operations of the method, per unit:
 # a radix-2 butterfly = 3 ops (add, sub, twiddle), a Z_F product or MAC = 2 ops, etc.
@@ -504,6 +508,39 @@ def bench_transforms(args, torch, dev):
     return out
 
 
+def measured_peaks(torch, dev):
+    """Measured ceilings beside the published ones: the 32-bit integer VALU rate
+    (a loop of independent v_add_u32 over 4096 workgroups) and the HBM copy
+    bandwidth (16-byte grid-stride copy of 1 GiB), from libfntprobe.so."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_2405_04253_amd", "libfntprobe.so")
+    if not os.path.exists(path):
+        return None
+    lib = ctypes.CDLL(path)
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    blocks, trips = 4096, 1024
+    sink = torch.empty(blocks * 256, dtype=torch.int32, device=dev)
+    ops, ops_base = ctypes.c_double(0), ctypes.c_double(0)
+    rc = lib.fntprobe_alu(0, ctypes.c_void_p(sink.data_ptr()), blocks, trips, ctypes.byref(ops), sp)
+    rc1 = lib.fntprobe_alu(1, ctypes.c_void_p(sink.data_ptr()), blocks, trips, ctypes.byref(ops_base), sp)
+    nbytes = 1 << 30
+    src = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    bw = ctypes.c_double(0)
+    rc2 = lib.fntprobe_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                            ctypes.c_size_t(nbytes), ctypes.byref(bw), sp)
+    torch.cuda.synchronize()
+    del src, dst, sink
+    return {"alu_gops": round(ops.value / 1e9, 1) if rc == 0 else None,
+            "alu_base_rate_gops": round(ops_base.value / 1e9, 1) if rc1 == 0 else None,
+            "alu_peak": PEAK_ALU_GOPS,
+            "copy_gbs": round(bw.value / 1e9, 1) if rc2 == 0 else None, "hbm_peak_published": PEAK_HBM_GBS,
+            "what": "16 independent chains of v_add_u32 (fastest 32-bit form) and of SDWA v_sub_u32 (the "
+                    "Fermat fold; base rate, like shifts and 24-bit multiplies) on every SIMD; 16-byte "
+                    "grid-stride copy of 1 GiB (read + write bytes)"}
+
+
 def bench_served(args, torch, dev):
     """Poisson arrivals of stream segments into a session; p50/p99 latency."""
     import oracle as O
@@ -634,6 +671,12 @@ def main():
         progress("batched")
         res = bench_batched(args, torch, dev)
         progress(f"batched done: {res['value']}")
+        peaks = measured_peaks(torch, dev)
+        if peaks:
+            res["measured_peaks"] = peaks
+            if peaks["alu_gops"]:
+                res["roofline"]["frac_of_measured_peak"] = round(res["roofline"]["achieved"] / peaks["alu_gops"], 5)
+            progress(f"measured peaks: {peaks}")
     if not args.skip_single:
         progress("plain single stream")
         res["plain_single_stream"] = bench_single(args, torch, dev)

@@ -9,6 +9,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfnt.so")
 SOURCES = ["fnt_kernels.hip", "fnt_api.cpp", "fnt_session.cpp"]
+# measured GPU ceilings for the benchmark's roofline objects (not the receiver path)
+PROBE_LIB = os.path.join(HERE, "libfntprobe.so")
+PROBE_SOURCE = "peak_probe.hip"
 ARCH = os.environ.get("FNT_OFFLOAD_ARCH", "gfx950")
 
 # Packed-FP32 instructions are kept out of every device code object.
@@ -50,7 +53,16 @@ def build(force: bool = True, jobs: int = 3, out: str | None = None, defines=())
     tmp = lib + ".tmp"
     _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"])
     os.replace(tmp, lib)
+    if out is None and not defines:
+        build_probe()
     return lib
+
+
+def build_probe() -> str:
+    tmp = PROBE_LIB + ".tmp"
+    _run(["hipcc", "-x", "hip", *HIP_FLAGS, "-shared", "-o", tmp, os.path.join(CSRC, PROBE_SOURCE)])
+    os.replace(tmp, PROBE_LIB)
+    return PROBE_LIB
 
 
 if __name__ == "__main__":
