@@ -21,6 +21,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import math
 import os
@@ -67,10 +68,17 @@ AEQ_BYTES_PER_SYMBOL = 4 + 8               # int8[4] in, int16[4] out
 
 
 def kernel_source_hash() -> str:
+    """Hash of the device code's source without comments and blank lines, so that
+    a profile summary stays tied to the code it measured but not to its prose."""
     h = hashlib.sha256()
     for f in ("fnt_kernels.hip", "fnt_device.hpp"):
-        with open(os.path.join(ROOT, "paper_2405_04253_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2405_04253_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for line in text.splitlines():
+            code = line.split("//", 1)[0].rstrip()
+            if code.strip():
+                h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

@@ -3,14 +3,21 @@
 //  * fnt_transform_kernel : batched Eq. (1) / Eq. (2) transforms modulo F_2, F_3,
 //    F_4 at the full radix order (Fig. 1 case, the AEQ's N = 32 / alpha = 2, the
 //    CDC's N = 64 / alpha = sqrt 2, and the F_2 / F_3 variants).
-//  * cdc_kernel           : overlap-save FNT-CDC (Fig. 2), complex product through
-//    the two real Fermat-domain products of Eqs. (7)-(8), exact centred lift,
-//    resampling to 1 sample/symbol and requantisation to 5 bit.
-//  * aeq_fnt_kernel       : FNT-AEQ (Fig. 3): 4x4 real MIMO filtering in the
-//    Fermat domain with 14-bit taps split into two 7-bit digit groups, the RDE
-//    error of Eq. (6) and the block tap update; one wave64 per channel.
-//  * aeq_direct_kernel    : the same AEQ with time-domain integer dot products,
-//    a comparator with bit-identical output.
+//  * cdc_lane_kernel      : overlap-save FNT-CDC (Fig. 2), one 32-instant block per
+//    lane; complex product through the two real Fermat-domain products of
+//    Eqs. (7)-(8), exact centred lift of the kept instants, resampling to 1
+//    sample/symbol and requantisation to 5 bit.
+//  * cdc_kernel           : the same CDC with one block per wave (16 lanes per
+//    64-point transform); the only form that also writes the exact output z.
+//  * aeq_lane_kernel, aeq_duo_kernel, aeq_pol_kernel<LPT>, aeq_split_kernel:
+//    FNT-AEQ (Fig. 3): 4x4 real MIMO filtering in the Fermat domain with 14-bit
+//    taps split into two 7-bit digit groups, the RDE error of Eq. (6) and the
+//    block tap update, in forms from throughput (one transform per lane) to
+//    latency (a channel's polarisation halves over several waves), and a split
+//    launch of two forms.
+//  * aeq_fnt_kernel       : the same AEQ with one wave64 per channel.
+//  * cdc_direct_kernel, aeq_direct_kernel : the same CDC and AEQ by time-domain
+//    integer dot products, comparators with bit-identical output.
 #include <hip/hip_runtime.h>
 
 #include <utility>
