@@ -262,8 +262,6 @@ int build_tick(fnt_session *s, TickSlot &slot) {
 // 70 % efficiency).
 int tick_form(int nitems) {
     struct Form { int code; double lat_us, instr; };
-    // measured on MI355X: per-block latency of one channel alone (µs) and VALU
-    // instructions per channel-block of each form
     static const Form forms[] = {{4, 0.88, 1904}, {2, 1.03, 1336}, {1, 1.38, 998}, {3, 2.09, 740}, {0, 2.69, 600}};
     int best = 4;
     double best_t = 1e30;
