@@ -211,7 +211,17 @@ def _time_events(torch, fn, reps, stream):
 
 
 AEQ_FORM_KERNEL = {0: "aeq_lane_kernel<1>", 3: "aeq_duo_kernel<1>", 1: "aeq_pol_kernel<4>",
-                   2: "aeq_pol_kernel<8>", 4: "aeq_pol_kernel<16>"}
+                   2: "aeq_pol_kernel<8>", 4: "aeq_pol_kernel<16>", 5: "aeq_pol_kernel<4, 2>"}
+SPLIT_WPG = {1: 1, 3: 1, 2: 2, 4: 4, 5: 2}
+
+
+def split_fusable(long_form: int, rest_form: int) -> bool:
+    """Form pairs that run as one split launch (the library's table)."""
+    return (long_form in (1, 2, 4, 5) and rest_form in (0, 3)) or (long_form, rest_form) in ((3, 0), (2, 5))
+
+
+def split_name(long_form: int, rest_form: int) -> str:
+    return "aeq_split_kernel<%d, %d, %d>" % (long_form, rest_form, SPLIT_WPG[long_form])
 
 
 def aeq_kernel_name(info) -> str:
@@ -225,8 +235,8 @@ def aeq_kernel_name(info) -> str:
         rest = info["channels"] - info["lead_channels"]
         if nlong >= rest:
             return form[wl]
-        if nlong and ((wl in (1, 2, 4) and ws in (0, 3)) or (wl, ws) == (3, 0)):
-            return "aeq_split_kernel<%d, %d, %d>" % (wl, ws, {1: 1, 3: 1, 2: 2, 4: 4}[wl])  # one launch
+        if nlong and split_fusable(wl, ws):
+            return split_name(wl, ws)                                   # one launch
         k = form[ws]
         if nlong:
             k = form[wl] + "+" + k
@@ -406,8 +416,12 @@ def bench_batched(args, torch, dev):
     cdc_ops = CDC_OPS_PER_BLOCK * cdc_blocks
     achieved = aeq_ops / (aeq_ms / 1e3) / 1e9
     kname = aeq_kernel_name(info)
-    lead_name = AEQ_FORM_KERNEL[info["lead_form"]] if info["lead_channels"] else None
-    top_name = AEQ_FORM_KERNEL[info["top_form"]] if info["top_channels"] else None
+    fused_top = bool(info["top_channels"]) and split_fusable(info["top_form"], info["lead_form"])
+    lead_name = None
+    if info["lead_channels"]:
+        lead_name = (split_name(info["top_form"], info["lead_form"]) if fused_top
+                     else AEQ_FORM_KERNEL[info["lead_form"]])
+    top_name = AEQ_FORM_KERNEL[info["top_form"]] if info["top_channels"] and not fused_top else None
     # the dominant kernel: the AEQ launch with the most algorithmic work (with a
     # lead, a launch on one of the plan's side streams can be the largest)
     launches = [(aeq_blocks, kname, aeq_ms, kname, "launch stream")]
@@ -437,12 +451,12 @@ def bench_batched(args, torch, dev):
     }
     if info["lead_channels"]:
         kernels["aeq_lead"] = {
-            "kernel": lead_name, "channels": info["lead_channels"] - info["top_channels"],
+            "kernel": lead_name, "channels": info["lead_channels"] - (info["top_channels"] if top_name else 0),
             "ms": round(lead_ms, 3), "blocks": lead_blocks,
             "gops": round(AEQ_OPS_PER_BLOCK * lead_blocks / lead_ms / 1e6, 1),
             "what": "the longest channels' AEQ, started after their own CDC on a second stream, "
                     "concurrent with the other channels' CDC and AEQ"}
-    if info["top_channels"]:
+    if top_name:
         kernels["aeq_top"] = {
             "kernel": top_name, "channels": info["top_channels"],
             "ms": round(top_ms, 3), "blocks": top_blocks,

@@ -188,7 +188,7 @@ typedef struct fnt_plan_info {
     int32_t cdc_blocks_per_wave;  /* 0 = one block per lane (64 blocks per wave) */
     int32_t aeq_variant;   /* 0 = Fermat-domain filtering (the method), 1 = direct comparator,
                               2 = Fermat-domain, one wave per channel */
-    int32_t aeq_waves_per_pol;  /* variant 0: AEQ form (0, 3, 1, 2, 4; see fnt_plan_set_aeq_waves) */
+    int32_t aeq_waves_per_pol;  /* variant 0: AEQ form (0, 3, 1, 5, 2, 4; see fnt_plan_set_aeq_waves) */
     int32_t graph;         /* 1 if fnt_plan_run replays a hipGraph (never while a lead is in effect) */
     int32_t aeq_waves_long;     /* AEQ form of the long chains (see fnt_plan_set_aeq_split) */
     double tune_ms;        /* AEQ time of the chosen schedule during autotune, ms (0 if none) */
@@ -240,13 +240,18 @@ int fnt_plan_set_aeq_variant(fnt_plan *plan, int variant);
  *   0: every lane runs whole transforms in its registers, 32 lanes per channel,
  *      two channels per wave;
  *   3: two lanes per transform, one channel per wave;
- *   1, 2, 4: split by output polarisation, that many waves per half.
+ *   1, 2, 4: split by output polarisation, that many waves per half, each half
+ *      its own workgroup;
+ *   5: split by output polarisation, one wave per half, both halves of a
+ *      channel in one workgroup (the same arithmetic as 1).
  * Overrides the default / autotuned choice, including any split and lead. */
 int fnt_plan_set_aeq_waves(fnt_plan *plan, int waves_per_pol);
 /* Split the AEQ of a plan: the `long_channels` channels with the longest chains
- * run with `wpp_long` waves per polarisation half (short serial latency) in a
- * launch concurrent with the rest, which run with `wpp` waves per half
- * (fewer waves, higher throughput).  long_channels = 0 disables the split. */
+ * run in form `wpp_long` (short serial latency, raised wave priority), the rest
+ * in form `wpp` (fewer instructions per block); forms as for
+ * fnt_plan_set_aeq_waves.  The pairs (1, 2, 4 or 5 with 0 or 3), (3, 0) and
+ * (2, 5) run as one launch with the long chains' workgroups first; other pairs
+ * as two concurrent launches.  long_channels = 0 disables the split. */
 int fnt_plan_set_aeq_split(fnt_plan *plan, uint64_t long_channels, int wpp_long, int wpp);
 /* Select the CDC kernel of a plan: 0 = overlap-save in the Fermat domain with the
  * complex product of Eqs. (7)-(8) (default, the method), 1 = direct time-domain
@@ -265,10 +270,12 @@ int fnt_plan_set_cdc_schedule(fnt_plan *plan, int waves_per_group, int blocks_pe
  * or the long chains' form for -1; at raised wave priority) then starts on the
  * plan's side stream while the CDC and the AEQ of the other channels run on the
  * launch stream, so the longest serial chains do not wait for the whole batch's
- * CDC.  With 0 < top_channels < lead_channels the lead has two levels: the CDC
- * of the `top_channels` longest runs first of all and their AEQ (form
- * `top_form`, -1 as above) starts on a third stream, then the CDC of the rest
- * of the lead and its AEQ on the side stream.  The other channels keep the
+ * CDC.  With 0 < top_channels < lead_channels the lead has two levels: the
+ * `top_channels` longest run in form `top_form` (-1 as above).  If that form
+ * pairs with the lead's in one split launch (see fnt_plan_set_aeq_split; e.g.
+ * 2 with 5) they are the first workgroups of the lead's own launch; otherwise
+ * their CDC runs first of all and their AEQ starts on a third stream, then the
+ * CDC of the rest of the lead and its AEQ on the side stream.  The other channels keep the
  * split of fnt_plan_set_aeq_split for those of them among the long channels.
  * lead_channels = 0 (default unless the autotuner chose a lead) runs every CDC
  * before any AEQ.  In effect for 0 < lead_channels < channels when the other
@@ -293,9 +300,10 @@ typedef struct fnt_plan_timing {
                                0 without a lead) */
     uint64_t aeq_blocks;    /* 16-symbol AEQ blocks of the channels aeq_ms covers */
     uint64_t aeq_lead_blocks;  /* 16-symbol AEQ blocks of the channels aeq_lead_ms covers */
-    float aeq_top_ms;       /* the first level's AEQ launch on the third stream (0 if none) */
+    float aeq_top_ms;       /* the first level's AEQ launch on the third stream (0 if none, or
+                               if it runs inside the lead's launch) */
     int32_t reserved;
-    uint64_t aeq_top_blocks;   /* 16-symbol AEQ blocks of the first level */
+    uint64_t aeq_top_blocks;   /* 16-symbol AEQ blocks of the first level's own launch */
 } fnt_plan_timing;
 /* Run every channel once, as fnt_plan_run does, but launch the sequence
  * directly (never the graph) with HIP events around every launch on the stream

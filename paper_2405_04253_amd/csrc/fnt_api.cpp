@@ -340,10 +340,22 @@ static hipError_t plan_aeq_range(fnt_plan *p, int first, int nl, int count, hipS
 // first level's channels among them (0: one level).
 static size_t plan_top(const fnt_plan *p) { return p->n_top > 0 && p->n_top < p->n_lead ? p->n_top : 0; }
 
+// AEQ forms of the lead after its first level, and of the first level
+static int lead_form_of(const fnt_plan *p) { return p->lead_form >= 0 ? p->lead_form : p->wpp_long; }
+static int top_form_of(const fnt_plan *p) { return p->top_form >= 0 ? p->top_form : p->wpp_long; }
+
+// A first level whose form pairs with the lead's in one split launch runs inside
+// the lead's launch (no CDC segment, stream or launch of its own).
+static bool plan_top_fused(const fnt_plan *p) {
+    return plan_top(p) > 0 && p->variant == 0 && aeq_split_fusable(top_form_of(p), lead_form_of(p));
+}
+// The first level's own CDC segment (0 when there is none or it is fused).
+static size_t plan_cdc_top(const fnt_plan *p) { return plan_top_fused(p) ? 0 : plan_top(p); }
+
 static size_t plan_lead(const fnt_plan *p) {
     const size_t n = p->aeq_host.size();
     if (p->n_lead == 0 || p->n_lead >= n || p->seg_lead != p->n_lead ||
-        p->seg_top != plan_top(p) || !p->cdc_seg_dev)
+        p->seg_top != plan_cdc_top(p) || !p->cdc_seg_dev)
         return 0;
     const size_t rest_long = p->n_long > p->n_lead ? p->n_long - p->n_lead : 0;
     return plan_aeq_one_launch(p, (int)rest_long, (int)(n - p->n_lead)) ? p->n_lead : 0;
@@ -388,7 +400,8 @@ static int plan_launch(fnt_plan *p, hipStream_t s, hipStream_t side, hipStream_t
     auto rec = [&](int i, hipStream_t st) { return ev ? hipEventRecord(ev[i], st) : hipSuccess; };
     hipError_t e = rec(0, s);
     const size_t lead = plan_lead(p);
-    const size_t top = lead ? plan_top(p) : 0;
+    const bool fused = lead && plan_top_fused(p);
+    const size_t top = lead && !fused ? plan_top(p) : 0;      // a first level of its own
     if (lead == 0) {
         int rc = e == hipSuccess ? plan_launch_cdc(p, s) : hip_fail(e, "plan: timing event");
         if (!rc && (e = rec(1, s)) != hipSuccess) rc = hip_fail(e, "plan: timing event");
@@ -416,14 +429,24 @@ static int plan_launch(fnt_plan *p, hipStream_t s, hipStream_t side, hipStream_t
         if (r == hipSuccess) r = rec(ev0 + 1, st);
         return r;
     };
-    const int lf = p->lead_form >= 0 ? p->lead_form : p->wpp_long;
-    const int tf = p->top_form >= 0 ? p->top_form : p->wpp_long;
+    const int lf = lead_form_of(p);
+    const int tf = top_form_of(p);
     if (top) {
         if (e == hipSuccess) e = seg_cdc(0, top);
         if (e == hipSuccess) e = seg_aeq(0, top, tf, side2, p->fork2, 6);
     }
     if (e == hipSuccess) e = seg_cdc(top, lead);
-    if (e == hipSuccess) e = seg_aeq(top, lead, lf, side, p->fork, 2);
+    if (fused) {
+        // the first level's chains first in the lead's own split launch
+        if (e == hipSuccess) e = hipEventRecord(p->fork, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(side, p->fork, 0);
+        if (e == hipSuccess) e = rec(2, side);
+        if (e == hipSuccess)
+            e = launch_aeq_split(p->aeq_dev, (int)plan_top(p), (int)lead, tf, lf, p->err, side, true);
+        if (e == hipSuccess) e = rec(3, side);
+    } else if (e == hipSuccess) {
+        e = seg_aeq(top, lead, lf, side, p->fork, 2);
+    }
     if (e == hipSuccess) e = seg_cdc(lead, n);
     if (e == hipSuccess) e = rec(1, s);
     if (e == hipSuccess) e = plan_aeq_range(p, (int)lead, rest_long, (int)(n - lead), s);
@@ -588,10 +611,11 @@ static void tune_cache_store(const char *path, const std::string &key, int wpg, 
 // polarisation half over more waves to shorten the serial chain.
 // AEQ forms of a plan (the `waves per half` value): 0 = one transform per lane
 // (two channels per wave), 3 = two lanes per transform (one channel per wave),
-// 1 / 2 / 4 = split by output polarisation with that many waves per half.
+// 1 / 2 / 4 = split by output polarisation with that many waves per half, 5 =
+// split by output polarisation with both halves in one workgroup.
 // Cost per block rises, and the serial latency per block falls, in this order.
-static bool valid_form(int f) { return f == 0 || f == 1 || f == 2 || f == 3 || f == 4; }
-static int form_rank(int f) { return f == 0 ? 0 : f == 3 ? 1 : f == 1 ? 2 : f == 2 ? 3 : 4; }
+static bool valid_form(int f) { return f >= 0 && f <= 5; }
+static int form_rank(int f) { return f == 0 ? 0 : f == 3 ? 1 : (f == 1 || f == 5) ? 2 : f == 2 ? 3 : 4; }
 static int default_wpp(size_t nch) { return nch >= 512 ? 3 : (nch >= 128 ? 2 : 4); }
 
 static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
@@ -723,7 +747,6 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
             struct LCand { size_t lead, nl; int q, ql, lf; size_t top; int tf; double ms; };
             std::vector<LCand> leads;
             auto time_lead = [&](const LCand &c) -> double {
-                if (plan_build_segments(p, c.top, c.lead, s)) return 1e30;
                 p->n_lead = c.lead;
                 p->n_top = c.top;
                 p->n_long = c.nl;
@@ -731,6 +754,7 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
                 p->wpp_long = c.ql;
                 p->lead_form = c.lf;
                 p->top_form = c.tf;
+                if (plan_build_segments(p, plan_cdc_top(p), c.lead, s)) return 1e30;
                 if (plan_lead(p) != c.lead || plan_top(p) != c.top) return 1e30;
                 return time_it([&] { return plan_launch(p, s, p->side, p->side2) ? hipErrorUnknown : hipSuccess; });
             };
@@ -762,22 +786,42 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
                 return cs.front();
             };
             leads.push_back({0, bnl, bq, bql, -1, 0, -1, 0});   // the choice above, without a lead
-            for (size_t lead : {128, 256, 512, 768, 1024, 1536})
+            std::vector<int> lfs = {bql}, qls = {bql};
+            for (int f : {2, 5})
+                if (f != bql) lfs.push_back(f);
+            for (int f : {3, 5})
+                if (f != bql) qls.push_back(f);
+            for (size_t lead : {256, 512, 1024, 1536})
                 for (size_t extra : {0, 512, 1024})
                     for (int q : {0, 3})
-                        for (int lf : {bql, 2})
-                            for (int ql : {bql, 3}) {
+                        for (int lf : lfs)
+                            for (int ql : qls) {
                                 const size_t nl = lead + extra;
                                 if (lead >= nch || nl > nch) continue;
-                                if (lf == 2 && bql == 2) continue;
                                 if (extra == 0 && ql != bql) continue;  // no latency form after the lead
                                 if (extra > 0 && form_rank(q) >= form_rank(ql)) continue;
                                 leads.push_back({lead, nl, q, ql, lf, 0, -1, 0});
                             }
-            // (a first lead level of its own is not among the candidates: single
-            // passes sometimes timed it faster, steady runs slower, 130 against
-            // 106 ms on the 4096-channel batch)
-            const LCand best = best_of(leads);
+            // (a first lead level on a stream of its own is not among the
+            // candidates: single passes sometimes timed it faster, steady runs
+            // slower, 130 against 106 ms on the 4096-channel batch)
+            LCand best = best_of(leads);
+            // the very longest chains of the lead on two waves per half, first in
+            // the lead's own launch (form 2 with the rest of the lead in form 5);
+            // tried only when the lead already runs in form 5 (as a lead, form 5
+            // timed 124 against 105 ms for form 1 on the 4096-channel batch)
+            if (best.lead > 0 && best.lf == 5) {
+                std::vector<LCand> tops = {best};
+                for (size_t top : {32, 64, 128, 256})
+                    if (top < best.lead) {
+                        LCand c = best;
+                        c.top = top;
+                        c.tf = 2;
+                        c.lf = 5;
+                        tops.push_back(c);
+                    }
+                if (tops.size() > 1) best = best_of(tops);
+            }
             p->info.tune_run_ms = best.ms;
             // the CDC's waves per workgroup were chosen on the CDC alone; with a
             // lead the CDC shares the chip with the lead's AEQ, so the best
@@ -949,7 +993,7 @@ int fnt_plan_create(fnt_plan **out, const fnt_channel_desc *ch, size_t nch, cons
             return rc;
         }
     }
-    if ((rc = plan_build_segments(p, p->n_top, p->n_lead, s))) {
+    if ((rc = plan_build_segments(p, plan_cdc_top(p), p->n_lead, s))) {
         fnt_plan_destroy(p);
         return rc;
     }
@@ -1024,12 +1068,12 @@ int fnt_plan_set_lead(fnt_plan *p, uint64_t lead, int lead_form, uint64_t top, i
     // the segmented table may be read by runs still in flight on any stream
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "plan: set lead");
-    int rc = plan_build_segments(p, t, l, nullptr);
-    if (rc) return rc;
     p->n_lead = l;
     p->n_top = t;
     p->lead_form = lead_form;
     p->top_form = top_form;
+    int rc = plan_build_segments(p, plan_cdc_top(p), l, nullptr);
+    if (rc) return rc;
     if (p->exec) return plan_capture(p, nullptr);
     return FNT_OK;
 }
@@ -1044,7 +1088,7 @@ int fnt_plan_run_timed(fnt_plan *p, fnt_plan_timing *t, void *stream) {
         if (!p->tev[i]) e = hipEventCreate(&p->tev[i]);
     if (e != hipSuccess) return hip_fail(e, "plan: timing events");
     const size_t lead = plan_lead(p);
-    const size_t top = lead ? plan_top(p) : 0;
+    const size_t top = lead && !plan_top_fused(p) ? plan_top(p) : 0;   // a launch of its own
     int rc = plan_launch(p, s, p->side, p->side2, p->tev);
     if (rc) return rc;
     e = hipEventSynchronize(p->tev[5]);

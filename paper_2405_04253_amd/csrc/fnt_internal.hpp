@@ -69,13 +69,16 @@ hipError_t launch_cdc(const CdcItem *items, int nitems, const CdcItem &single,
                       int waves_per_group, int blocks_per_wave, bool with_z, int *err,
                       hipStream_t s);
 // One launch for the split of a longest-first table: items [0, nlong) in form
-// form_long at raised wave priority (dispatched first), the rest in form_rest.
-// Fusable pairs: long form 1, 2 or 4 with rest 0 or 3, and (3, 0).
+// form_long at raised wave priority (dispatched first), the rest in form_rest
+// (at raised priority too with rest_high_priority).
+// Fusable pairs: long form 1, 2, 4 or 5 with rest 0 or 3, (3, 0) and (2, 5).
 hipError_t launch_aeq_split(const AeqItem *items, int nlong, int nitems, int form_long, int form_rest,
-                           int *err, hipStream_t s);
+                           int *err, hipStream_t s, bool rest_high_priority = false);
 bool aeq_split_fusable(int form_long, int form_rest);
-// variant 0: Fermat-domain AEQ split by output polarisation, waves_per_pol in
-// {1, 2, 4}; 1: direct time-domain comparator; 2: Fermat-domain, one wave per channel.
+// variant 0: Fermat-domain AEQ in form waves_per_pol (0 lane, 3 duo, 1 / 2 / 4
+// split by output polarisation with that many waves per half, 5 split by output
+// polarisation with both halves in one workgroup); 1: direct time-domain
+// comparator; 2: Fermat-domain, one wave per channel.
 hipError_t launch_aeq(const AeqItem *items, int nitems, const AeqItem &single, int variant,
                       int waves_per_pol, int *err, hipStream_t s,
                       bool high_priority = false);

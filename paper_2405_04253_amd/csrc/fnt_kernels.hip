@@ -1319,10 +1319,14 @@ __device__ __forceinline__ uint32_t aeq_sym(const AeqItem &it, int64_t i) {
 // whose 16-bit pieces both write, then cross HBM once.
 __host__ __device__ constexpr unsigned pol_blocks(int n) { return 16u * (unsigned)((n + 7) / 8); }
 
-template <int LPT>
+// IW = 1: one half per workgroup, the halves paired on XCDs as above.  IW = 2
+// (one wave per half only): both halves of a channel in one workgroup of two
+// independent waves (wave v runs polarisation v), one workgroup per channel.
+template <int LPT, int IW = 1>
 __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const AeqItem &single, int *err,
                                              int prio, unsigned bid) {
-    const unsigned ch = (bid >> 4) * 8 + (bid & 7);
+    static_assert(IW == 1 || (IW == 2 && LPT == 4), "paired halves need one wave per half");
+    const unsigned ch = IW == 1 ? (bid >> 4) * 8 + (bid & 7) : bid;
     if (ch >= (unsigned)(items ? n : 1)) return;       // padding of the last run of 16
     // latency-critical chains (the longest of a batch) issue ahead of the
     // throughput work that shares their SIMDs
@@ -1331,16 +1335,17 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const 
     constexpr int PPL = 32 / LPT;                      // bins per lane
     constexpr int NT = 16 / LPT;                       // taps owned per lane (= PPL / 2)
     const AeqItem it = items ? items[ch] : single;
-    const int pol = (bid >> 3) & 1;
     const int tid = threadIdx.x;
     const int v = tid >> 6, lane = tid & 63;
+    const int vh = v % WPP;                            // wave within its half
+    const int pol = IW == 1 ? (int)((bid >> 3) & 1) : v;
     const int pos = lane & 31;
     // transform role: filter (tS1 -> 2 pol + tS2l), digit td, lane t of LPT; the
     // lane also owns the taps k = t + LPT i (i < NT) of that filter
     const int tr = lane / LPT, t = lane_pos(lane % LPT);
     const int ts = tr & 1, tS2l = (tr >> 1) & 1;
-    const int td = WPP == 1 ? (tr >> 2) & 1 : (v & 1);
-    const int tg = WPP == 1 ? (tr >> 3) : WPP == 2 ? (tr >> 2) & 1 : (v >> 1);
+    const int td = WPP == 1 ? (tr >> 2) & 1 : (vh & 1);
+    const int tg = WPP == 1 ? (tr >> 3) : WPP == 2 ? (tr >> 2) & 1 : (vh >> 1);
     const int tS1 = 2 * tg + ts;
     const int tS2 = 2 * pol + tS2l;
     // output / error role (lanes 0..31 of every wave): symbol om, stream 2 pol + oS2l
@@ -1349,16 +1354,17 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const 
 
     // rows padded to 33 words: lanes reading the same position of different
     // rows hit different LDS banks
-    __shared__ int32_t aspec_s[WPP][4][33];            // per wave: input spectra by position
-    // [block parity][g*2+d][m*2+S2l], shared by the waves; double-buffered so a
-    // wave that runs ahead (one barrier per block) never overwrites partials
-    // another wave is still reading
-    __shared__ int32_t part_s[2][4][33];
-    __shared__ uint32_t epsw_s[WPP][8];                // per wave: bytes [S2l][m]
-    __shared__ uint32_t winw_s[WPP][36];               // per wave: bytes [S1][32] + pad
+    __shared__ int32_t aspec_s[WPP * IW][4][33];       // per wave: input spectra by position
+    // per half: [block parity][g*2+d][m*2+S2l], shared by the half's waves;
+    // double-buffered so a wave that runs ahead (one barrier per block) never
+    // overwrites partials another wave is still reading
+    __shared__ int32_t part_s[IW][2][4][33];
+    __shared__ uint32_t epsw_s[WPP * IW][8];           // per wave: bytes [S2l][m]
+    __shared__ uint32_t winw_s[WPP * IW][36];          // per wave: bytes [S1][32] + pad
     int32_t(*aspec)[33] = aspec_s[v];
     uint32_t *epsw = epsw_s[v];
     uint32_t *winw = winw_s[v];
+    int32_t(*part_h)[4][33] = part_s[v / WPP];
 
     int16_t *const wrow = it.taps + (tS1 * 4 + tS2) * 16;
     int32_t w[NT];
@@ -1369,9 +1375,9 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const 
         w[i] = clamp32(val, -8192, 8191);
     }
     const uint64_t M = it.m;
-    const bool writer = v == 0;                        // stores the outputs
+    const bool writer = vh == 0;                       // stores the outputs
     const bool tap_owner = td == 0;                    // one of the two digit copies stores taps
-    const bool hist_owner = pol == 0 && v == 0;
+    const bool hist_owner = pol == 0 && vh == 0;
     auto finish = [&]() {
         if (tap_owner) {
 #pragma unroll
@@ -1469,12 +1475,12 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const 
         if (ts == 0) {
 #pragma unroll
             for (int j = PPL / 2; j < PPL; ++j)
-                part_s[b & 1][tg * 2 + td][(t + LPT * (j - PPL / 2)) * 2 + tS2l] = lift_loose(Y[j]);
+                part_h[b & 1][tg * 2 + td][(t + LPT * (j - PPL / 2)) * 2 + tS2l] = lift_loose(Y[j]);
         }
         if (WPP > 1) __syncthreads(); else wave_lds_sync();
         // symbol om, stream 2 pol + oS2l: y = 2^7 (high-digit sums) + (low-digit sums)
         const int pi = lane & 31;
-        const int32_t(*part)[33] = part_s[b & 1];
+        const int32_t(*part)[33] = part_h[b & 1];
         const int32_t y = 128 * (part[0][pi] + part[2][pi]) + part[1][pi] + part[3][pi];
         const int32_t yh = clamp32(rs32(y, it.out_shift), -32768, 32767);
         const bool valid = lane < 32 && om < left;
@@ -1517,10 +1523,10 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const 
     finish();
 }
 
-template <int LPT>
-__global__ __launch_bounds__(64 * (LPT / 4)) void aeq_pol_kernel(const AeqItem *items, int n, AeqItem single,
-                                                                 int *err, int prio) {
-    aeq_pol_body<LPT>(items, n, single, err, prio, blockIdx.x);
+template <int LPT, int IW = 1>
+__global__ __launch_bounds__(64 * (LPT / 4) * IW) void aeq_pol_kernel(const AeqItem *items, int n,
+                                                                      AeqItem single, int *err, int prio) {
+    aeq_pol_body<LPT, IW>(items, n, single, err, prio, blockIdx.x);
 }
 
 // ------------------------------------------------------------------------
@@ -2108,24 +2114,28 @@ __global__ __launch_bounds__(64 * WPG) void aeq_duo_kernel(const AeqItem *items,
 // of the table in form RF, with WPG waves per workgroup throughout.  Forms:
 // 0 (one transform per lane, 2 channels per wave), 3 (two lanes per transform,
 // 1 channel per wave), 1 / 2 / 4 (split by polarisation with 1 / 2 / 4 waves per
-// half: one workgroup per half, so WPG = 1 / 2 / 4).
+// half: one workgroup per half, so WPG = 1 / 2 / 4), 5 (split by polarisation,
+// one wave per half, both halves in one workgroup: WPG = 2).
 __host__ __device__ constexpr unsigned aeq_form_blocks(int form, int n, int wpg) {
     return form == 0 ? (unsigned)((n + 2 * wpg - 1) / (2 * wpg))
-         : form == 3 ? (unsigned)((n + wpg - 1) / wpg) : pol_blocks(n);
+         : form == 3 ? (unsigned)((n + wpg - 1) / wpg) : form == 5 ? (unsigned)n : pol_blocks(n);
 }
 template <int F, int WPG>
 __device__ __forceinline__ void aeq_form_body(const AeqItem *items, int n, int *err, int prio, unsigned bid) {
     const AeqItem none{};
     if constexpr (F == 0) aeq_lane_body<WPG>(items, n, none, err, prio, bid);
     else if constexpr (F == 3) aeq_duo_body<WPG>(items, n, none, err, prio, bid);
-    else aeq_pol_body<4 * WPG>(items, n, none, err, prio, bid);
+    else if constexpr (F == 5) {
+        static_assert(WPG == 2, "form 5 runs two waves per workgroup");
+        aeq_pol_body<4, 2>(items, n, none, err, prio, bid);
+    } else aeq_pol_body<4 * WPG>(items, n, none, err, prio, bid);
 }
 template <int LF, int RF, int WPG>
 __global__ __launch_bounds__(64 * WPG) void aeq_split_kernel(const AeqItem *items, int nlong, int nitems,
-                                                             int *err) {
+                                                             int *err, int rest_prio) {
     const unsigned nbl = aeq_form_blocks(LF, nlong, WPG);
     if (blockIdx.x < nbl) aeq_form_body<LF, WPG>(items, nlong, err, 1, blockIdx.x);
-    else aeq_form_body<RF, WPG>(items + nlong, nitems - nlong, err, 0, blockIdx.x - nbl);
+    else aeq_form_body<RF, WPG>(items + nlong, nitems - nlong, err, rest_prio, blockIdx.x - nbl);
 }
 
 // Direct comparator: y by integer dot products in the time domain, same RDE.
@@ -2308,27 +2318,29 @@ hipError_t launch_cdc(const CdcItem *items, int nitems, const CdcItem &single,
     return hipGetLastError();
 }
 
-static int split_wpg(int form_long) { return form_long == 2 ? 2 : form_long == 4 ? 4 : 1; }
+static int split_wpg(int form_long) { return (form_long == 2 || form_long == 5) ? 2 : form_long == 4 ? 4 : 1; }
 
 hipError_t launch_aeq_split(const AeqItem *items, int nlong, int nitems, int form_long, int form_rest,
-                           int *err, hipStream_t s) {
+                           int *err, hipStream_t s, bool rest_high_priority) {
     if (!items || nlong <= 0 || nlong >= nitems || nitems > (1 << 26)) return hipErrorInvalidValue;
     const int wpg = split_wpg(form_long);
     const unsigned grid = aeq_form_blocks(form_long, nlong, wpg) + aeq_form_blocks(form_rest, nitems - nlong, wpg);
 #define FNT_SPLIT(L, R, W)                                                                     \
     if (form_long == L && form_rest == R) {                                                    \
-        aeq_split_kernel<L, R, W><<<grid, 64 * W, 0, s>>>(items, nlong, nitems, err);           \
+        aeq_split_kernel<L, R, W><<<grid, 64 * W, 0, s>>>(items, nlong, nitems, err, rest_high_priority ? 1 : 0);           \
         return hipGetLastError();                                                              \
     }
     FNT_SPLIT(1, 0, 1) FNT_SPLIT(1, 3, 1) FNT_SPLIT(3, 0, 1)
     FNT_SPLIT(2, 0, 2) FNT_SPLIT(2, 3, 2) FNT_SPLIT(4, 0, 4) FNT_SPLIT(4, 3, 4)
+    FNT_SPLIT(5, 0, 2) FNT_SPLIT(5, 3, 2) FNT_SPLIT(2, 5, 2)
 #undef FNT_SPLIT
     return hipErrorInvalidValue;
 }
 
 bool aeq_split_fusable(int form_long, int form_rest) {
-    return ((form_long == 1 || form_long == 2 || form_long == 4) && (form_rest == 0 || form_rest == 3)) ||
-           (form_long == 3 && form_rest == 0);
+    return ((form_long == 1 || form_long == 2 || form_long == 4 || form_long == 5) &&
+            (form_rest == 0 || form_rest == 3)) ||
+           (form_long == 3 && form_rest == 0) || (form_long == 2 && form_rest == 5);
 }
 
 hipError_t launch_aeq(const AeqItem *items, int nitems, const AeqItem &single, int variant,
@@ -2348,6 +2360,8 @@ hipError_t launch_aeq(const AeqItem *items, int nitems, const AeqItem &single, i
             aeq_pol_kernel<8><<<pol_blocks(n), 128, 0, s>>>(items, n, single, err, prio);
         else if (waves_per_pol == 4)
             aeq_pol_kernel<16><<<pol_blocks(n), 256, 0, s>>>(items, n, single, err, prio);
+        else if (waves_per_pol == 5)
+            aeq_pol_kernel<4, 2><<<n, 128, 0, s>>>(items, n, single, err, prio);
         else
             return hipErrorInvalidValue;
     } else if (variant == 1) {

@@ -409,9 +409,9 @@ int fnt_session_create(fnt_session **out, const fnt_session_config *cfg) {
         delete s;
         return fail(FNT_E_INVAL, "session: chunk_blocks %u > 4096", cfg->chunk_blocks);
     }
-    if (cfg->aeq_form < -1 || cfg->aeq_form > 4) {
+    if (cfg->aeq_form < -1 || cfg->aeq_form > 5) {
         delete s;
-        return fail(FNT_E_INVAL, "session: aeq_form %d outside [-1, 4]", cfg->aeq_form);
+        return fail(FNT_E_INVAL, "session: aeq_form %d outside [-1, 5]", cfg->aeq_form);
     }
     if (s->cfg.max_active == 0 || s->cfg.max_active > s->cfg.max_channels)
         s->cfg.max_active = s->cfg.max_channels;

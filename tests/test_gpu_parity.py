@@ -265,7 +265,7 @@ def _plan_channels(torch, dev, chans, rng):
     return out
 
 
-@pytest.mark.parametrize("variant,wpp", [(0, 0), (0, 3), (0, 1), (0, 2), (0, 4), (1, 1), (2, 1)])
+@pytest.mark.parametrize("variant,wpp", [(0, 0), (0, 3), (0, 1), (0, 2), (0, 4), (0, 5), (1, 1), (2, 1)])
 def test_plan_batched_vs_oracle(torch_dev, variant, wpp):
     torch, dev = torch_dev
     chans = _batch(40, 6, 11, seed=variant)
@@ -316,7 +316,7 @@ EXTREME_AEQ = [dict(out_shift=24, err_shift=62, mu_shift=40, const_unit=4096, up
                dict(out_shift=9, err_shift=12, mu_shift=1, const_unit=33, update_enable=0)]
 
 
-@pytest.mark.parametrize("wpp", [0, 3, 1])
+@pytest.mark.parametrize("wpp", [0, 3, 1, 5])
 def test_plan_extreme_aeq_params(torch_dev, wpp):
     """Shift and constant extremes (saturating taps and errors) on the batched kernels."""
     torch, dev = torch_dev
@@ -394,6 +394,11 @@ def test_plan_direct_cdc_comparator(torch_dev, aeq_variant):
     fnt.fnt_check()
 
 
+def _fusable(long_form, rest_form):
+    """Form pairs that run as one split launch (mirrors the library's table)."""
+    return ((long_form in (1, 2, 4, 5) and rest_form in (0, 3)) or (long_form, rest_form) in ((3, 0), (2, 5)))
+
+
 def test_plan_determinism_across_schedules(torch_dev):
     """Race check: identical outputs for every launch schedule and wave split."""
     torch, dev = torch_dev
@@ -404,7 +409,7 @@ def test_plan_determinism_across_schedules(torch_dev):
     ref = None
     for wpg, bpw, wpp, variant in [(4, 0, 1, 0), (4, 1, 1, 0), (1, 1, 2, 0), (2, 3, 4, 0), (4, 64, 1, 0),
                                    (1, 7, 2, 0), (1, 0, 2, 0), (2, 0, 4, 0), (4, 0, 0, 0), (4, 0, 3, 0),
-                                   (2, 2, 1, 1), (4, 5, 1, 2)]:
+                                   (2, 2, 1, 1), (4, 5, 1, 2), (1, 0, 5, 0)]:
         plan.set_cdc_schedule(wpg, bpw)
         plan.set_aeq_waves(wpp)
         plan.set_aeq_variant(variant)
@@ -427,7 +432,7 @@ def test_plan_determinism_across_schedules(torch_dev):
     # longest chains in their own concurrent launch
     plan.set_aeq_variant(0)
     for nl, wl, ws in [(5, 4, 1), (12, 2, 1), (1, 4, 2), (24, 4, 1), (3, 4, 0), (8, 2, 0), (23, 4, 0),
-                       (6, 3, 0), (9, 1, 3), (2, 4, 3)]:
+                       (6, 3, 0), (9, 1, 3), (2, 4, 3), (7, 5, 0), (10, 5, 3), (4, 2, 5), (1, 2, 5), (23, 2, 5)]:
         plan.set_aeq_split(nl, wl, ws)
         for c in pc:
             c["taps"].copy_(to_dev(torch, dev, c["w0"]))
@@ -448,11 +453,15 @@ def test_plan_determinism_across_schedules(torch_dev):
             (n, -1, 0, -1, 3, 1, 0, False), (0, 2, 0, -1, 3, 1, 0, False),
             # two levels: the first level's CDC first and its AEQ on a third stream
             (6, -1, 2, 2, 9, 1, 0, True), (12, 1, 1, -1, 12, 1, 3, True), (n - 1, 3, 5, 4, n, 2, 0, True),
-            (4, -1, 4, 2, 4, 1, 0, True), (5, -1, 2, 1, 12, 2, 1, False)]:
+            (4, -1, 4, 2, 4, 1, 0, True), (5, -1, 2, 1, 12, 2, 1, False),
+            # a first level that pairs with the lead's form runs inside the lead's launch
+            (6, 5, 2, 2, 9, 1, 0, True), (8, 5, 3, -1, 8, 2, 0, True), (n - 1, 5, 7, 2, n, 1, 3, True)]:
         plan.set_aeq_split(nl, wl, ws)
         plan.set_lead(lead, lf, top, tf)
         info = plan.info()
         top_eff = top if active and top < lead else 0
+        lf_e, tf_e = (wl if lf == -1 else lf), (wl if tf == -1 else tf)
+        own_top = top_eff > 0 and not _fusable(tf_e, lf_e)
         assert info["lead_channels"] == (lead if active else 0)
         assert info["lead_form"] == (wl if lf == -1 else lf)
         assert info["top_channels"] == top_eff and info["top_form"] == (wl if tf == -1 else tf)
@@ -466,7 +475,7 @@ def test_plan_determinism_across_schedules(torch_dev):
             elif mode == "timed":
                 t = plan.run_timed()
                 assert t["step_ms"] > 0 and t["cdc_ms"] > 0 and t["aeq_ms"] > 0
-                assert (t["aeq_lead_ms"] > 0) == active and (t["aeq_top_ms"] > 0) == (top_eff > 0)
+                assert (t["aeq_lead_ms"] > 0) == active and (t["aeq_top_ms"] > 0) == own_top
                 assert t["aeq_blocks"] + t["aeq_lead_blocks"] + t["aeq_top_blocks"] == \
                     sum((c["out"].shape[0] + 15) // 16 for c in pc)
             else:
@@ -475,7 +484,7 @@ def test_plan_determinism_across_schedules(torch_dev):
             for c, (o, w) in zip(pc, ref):
                 assert np.array_equal(c["out"].cpu().numpy(), o) and np.array_equal(c["taps"].cpu().numpy(), w)
     with pytest.raises(fnt.FntError):
-        plan.set_lead(2, 5)
+        plan.set_lead(2, 6)
     with pytest.raises(fnt.FntError):
         plan.set_lead(4, 1, 2, 7)
     plan.set_aeq_waves(1)
@@ -553,7 +562,7 @@ def _oracle_stream(ch, w0=None):
     return outr, wr
 
 
-@pytest.mark.parametrize("form", [-1, 0, 3, 1, 2, 4])
+@pytest.mark.parametrize("form", [-1, 0, 3, 1, 2, 4, 5])
 def test_session_streams_vs_oracle(torch_dev, form):
     """Tick after tick through every AEQ form: taps, CDC tail and AEQ tail carry over."""
     torch, dev = torch_dev
