@@ -179,9 +179,9 @@ def bench_single(args, torch, dev):
                 "us_per_block": round(aeq_ms * 1e3 / blocks_aeq, 4)},
     }
     achieved = aeq_ops / (aeq_ms / 1e3) / 1e9
-    roof = {"kernel": "aeq_pol_kernel<16>", "bound": "alu", "achieved": round(achieved, 3),
+    roof = {"kernel": "aeq_pol_kernel<16, 1>", "bound": "alu", "achieved": round(achieved, 3),
             "peak": PEAK_ALU_GOPS, "unit": "Gops/s", "frac": round(achieved / PEAK_ALU_GOPS, 6),
-            "traffic": load_traffic("aeq_pol_kernel<16>", "single", blocks_aeq),
+            "traffic": load_traffic("aeq_pol_kernel<16, 1>", "single", blocks_aeq),
             "algorithmic_ops_per_launch": aeq_ops}
     res = {
         "value": round(n / (ms / 1e3) / 1e9, 6), "unit": "Gsamples/s",
@@ -210,8 +210,8 @@ def _time_events(torch, fn, reps, stream):
     return float(np.mean([a.elapsed_time(b) for a, b in evs]))
 
 
-AEQ_FORM_KERNEL = {0: "aeq_lane_kernel<1>", 3: "aeq_duo_kernel<1>", 1: "aeq_pol_kernel<4>",
-                   2: "aeq_pol_kernel<8>", 4: "aeq_pol_kernel<16>", 5: "aeq_pol_kernel<4, 2>"}
+AEQ_FORM_KERNEL = {0: "aeq_lane_kernel<1>", 3: "aeq_duo_kernel<1>", 1: "aeq_pol_kernel<4, 1>",
+                   2: "aeq_pol_kernel<8, 1>", 4: "aeq_pol_kernel<16, 1>", 5: "aeq_pol_kernel<4, 2>"}
 SPLIT_WPG = {1: 1, 3: 1, 2: 2, 4: 4, 5: 2}
 
 
@@ -227,7 +227,6 @@ def split_name(long_form: int, rest_form: int) -> str:
 def aeq_kernel_name(info) -> str:
     """Kernel of the AEQ launch on the launch stream (the channels after a
     pipelined lead, or every channel)."""
-    lpt = {1: 4, 2: 8, 4: 16}
     form = AEQ_FORM_KERNEL
     if info["aeq_variant"] == 0:
         wl, ws = info["aeq_waves_long"], info["aeq_waves_per_pol"]
@@ -243,12 +242,7 @@ def aeq_kernel_name(info) -> str:
         return k
     if info["aeq_variant"] == 1:
         return "aeq_direct_kernel"
-    if info["aeq_variant"] == 2:
-        return "aeq_fnt_kernel"
-    k = "aeq_pol_kernel<%d>" % lpt[info["aeq_waves_per_pol"]]
-    if info["aeq_long_channels"]:
-        k = "aeq_pol_kernel<%d>+" % lpt[info["aeq_waves_long"]] + k
-    return k
+    return "aeq_fnt_kernel"                                             # variant 2
 
 
 def cpu_baseline_batched(chans, prms, budget_s: float):
