@@ -161,3 +161,25 @@ def aeq_block_digits(windows, w, t: int = 4, counter=None):
                 scale = 128 if d == 0 else 1
                 y[s2] = [y[s2][n] + scale * part[n] for n in range(N)]
     return y
+
+
+def aeq_gradient_fnt(eps, window, t: int = 4):
+    """The RDE gradient of one AEQ block in the Fermat domain (a variant the
+    block update of Eq. (6) admits; the kernels compute it directly).
+
+    ``eps``: the 16 error terms of output stream S2 in the block (8-bit);
+    ``window``: the 32-symbol input window of stream S1 (oldest first, the block's
+    own symbols at 16..31).  G[k] = sum_m eps[m] x[16 b + m - k] for k < 16 is a
+    correlation: with the reversed, zero-padded error e'[n] = eps[15 - n], the
+    cyclic convolution c = IFNT(FNT(window) FNT(e')) (N = 32, alpha = 2) holds
+    c[31 - k] = G[k] with no wrap-around (the largest index used is 31).  Every
+    true value is at most 16 * 128 * 16 = 32768 = (F - 1) / 2 (Eq. (5)), so the
+    centred lift is exact.  Returns G[0..15]."""
+    F = fermat(t)
+    N = 32
+    e = [eps[15 - n] for n in range(16)] + [0] * 16
+    X = fnt([v % F for v in window], 2, F)
+    E = fnt([v % F for v in e], 2, F)
+    c = [lift(v, F) for v in ifnt([X[k] * E[k] % F for k in range(N)], 2, F)]
+    return [c[N - 1 - k] for k in range(16)]
+

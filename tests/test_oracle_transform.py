@@ -226,6 +226,27 @@ def test_aeq_digit_split_block_worst_case():
         assert [row[16:] for row in y] == _aeq_brute(win, w)
 
 
+def _gradient_direct(eps, win):
+    # G[k] = sum_m eps[m] x[16 b + m - k], the block's symbols at window positions 16..31
+    return [sum(eps[m] * win[16 + m - k] for m in range(16)) for k in range(16)]
+
+
+def test_aeq_gradient_in_the_fermat_domain_is_exact():
+    # The correlation through FNT32 equals the direct sum for random blocks and at the
+    # Eq. (5) extreme (|eps| = 128 against |x| = 16 everywhere: 16 * 128 * 16 = 32768).
+    rng = random.Random(17)
+    for trial in range(200):
+        eps = [rng.randint(-128, 127) for _ in range(16)]
+        win = [rng.randint(-16, 15) for _ in range(32)]
+        assert R.aeq_gradient_fnt(eps, win) == _gradient_direct(eps, win), trial
+    for e0, x0 in ((-128, -16), (-128, 15), (127, -16)):
+        eps, win = [e0] * 16, [x0] * 32
+        assert R.aeq_gradient_fnt(eps, win) == _gradient_direct(eps, win)
+    # past the bound (a 9-bit error, 16 * 256 * 16 = 65536) the lift wraps
+    eps, win = [-256] * 16, [-16] * 32
+    assert R.aeq_gradient_fnt(eps, win) != _gradient_direct(eps, win)
+
+
 def test_table1_product_counts():
     # Tab. 1: FNT-CDC 8 and FNT-AEQ 64 real multiplications.  Per CDC block of one
     # polarisation: 2 spectra x 64 bins for 32 new instants; both polarisations -> 8
