@@ -557,17 +557,21 @@ def measured_peaks(torch, dev):
                     "grid-stride copy of 1 GiB (read + write bytes)"}
 
 
-def bench_served(args, torch, dev):
-    """Poisson arrivals of stream segments into a session; p50/p99 latency."""
+def bench_served(args, torch, dev, host: bool = False):
+    """Poisson arrivals of stream segments into a session; p50/p99 latency.
+    host=True: the payloads and outputs live in pinned host memory and every
+    request is staged through the session's HBM pool (host-to-device and back
+    inside the measured latency), over a shorter window."""
     import oracle as O
     from paper_2405_04253_amd import fnt, synth
     rng = np.random.default_rng(12345)
     nch = args.served_channels
+    window = args.h2d_window if host else args.window
     # arrivals over the window, each to a uniformly random channel
     times, t = [], 0.0
     while True:
         t += rng.exponential(1.0 / args.rate)
-        if t > args.window:
+        if t > window:
             break
         times.append(t)
     seg_sym = [16 * max(1, int(2 ** rng.uniform(13, 18)) // 16) for _ in times]
@@ -592,7 +596,11 @@ def bench_served(args, torch, dev):
         prm = dict(synth.AEQ_DEFAULTS, const_unit=unit)
         params[c] = (taps, sh, prm)
         sess.add_channel(c, fnt.cdc_params(taps, sh), fnt.aeq_params(**prm))
-    outs = {c: torch.zeros((streams[c].shape[0] // 2, 4), dtype=torch.int16, device=dev) for c in range(nch)}
+    if host:
+        streams = {c: q.cpu().pin_memory() for c, q in streams.items()}
+        outs = {c: torch.zeros((streams[c].shape[0] // 2, 4), dtype=torch.int16).pin_memory() for c in range(nch)}
+    else:
+        outs = {c: torch.zeros((streams[c].shape[0] // 2, 4), dtype=torch.int16, device=dev) for c in range(nch)}
     reqs, offs = [], [0] * nch
     for i in range(len(times)):
         c = int(owner[i])
@@ -602,8 +610,8 @@ def bench_served(args, torch, dev):
         offs[c] += n
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t0
-    progress(f"served: replaying {len(reqs)} arrivals over {args.window} s")
-    sess.replay(reqs)
+    progress(f"served{' (host buffers)' if host else ''}: replaying {len(reqs)} arrivals over {window} s")
+    sess.replay(reqs, host=host)
     t_end = time.perf_counter()
     while sess.stats()["completed"] < len(reqs):
         time.sleep(1.0)
@@ -622,12 +630,14 @@ def bench_served(args, torch, dev):
         if not np.array_equal(outs[c][: n // 2].cpu().numpy(), outr):
             raise SystemExit(f"served parity failure on channel {c}")
     inst = sum(2 * x for x in seg_sym)
-    return {"value": round(st["gsamples_per_s"], 4), "unit": "Gsamples/s",
+    what = ("payloads and outputs in pinned host memory, staged through the session's HBM pool "
+            "(PCIe both ways inside the latency)" if host else "payloads resident in HBM")
+    return {"value": round(st["gsamples_per_s"], 4), "unit": "Gsamples/s", "buffers": what,
             "p50_us": round(st["p50_us"], 1), "p99_us": round(st["p99_us"], 1),
             "mean_us": round(st["mean_us"], 1), "max_us": round(st["max_us"], 1),
             "requests": int(st["completed"]), "ticks": int(st["ticks"]),
-            "offered_gsamples_per_s": round(inst / args.window / 1e9, 3),
-            "workload": f"{nch} channels, Poisson {args.rate:.0f} req/s for {args.window} s, segments "
+            "offered_gsamples_per_s": round(inst / window / 1e9, 3),
+            "workload": f"{nch} channels, Poisson {args.rate:.0f} req/s for {window} s, segments "
                         f"log-uniform 2^13..2^18 symbols, chunk {args.chunk} blocks/tick, "
                         f"AEQ form {args.served_form}",
             "parity": f"bit-exact vs oracle on channels {busiest} (whole streams)", "gen_s": round(gen_s, 1)}
@@ -655,6 +665,8 @@ def main():
     ap.add_argument("--rate", type=float, default=20000.0)
     ap.add_argument("--window", type=float, default=0.5)
     ap.add_argument("--chunk", type=int, default=512)
+    ap.add_argument("--h2d-window", type=float, default=0.25,
+                    help="arrival window of the served leg with host buffers (0: skip it)")
     ap.add_argument("--served-form", type=int, default=-1,
                     help="AEQ form of the session ticks (0, 3, 1, 2, 4; -1: automatic)")
     ap.add_argument("--tune-cache", default=None,
@@ -706,6 +718,10 @@ def main():
         progress("served")
         res["served"] = bench_served(args, torch, dev)
         progress(f"served done: {res['served']['value']}")
+        if args.h2d_window > 0:
+            progress("served with host buffers")
+            res["served_h2d"] = bench_served(args, torch, dev, host=True)
+            progress(f"served with host buffers done: {res['served_h2d']['value']}")
     print(json.dumps(res), flush=True)
 
 

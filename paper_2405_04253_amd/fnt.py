@@ -374,11 +374,13 @@ class Session:
         _ok(lib().fnt_session_submit(self._h, ch, pin, n, pout, flags, arrival_ns, ctypes.byref(tk)))
         return tk.value
 
-    def replay(self, reqs):
-        """reqs: list of (ch, samples, out, at_ns) with GPU tensors; returns tickets."""
+    def replay(self, reqs, host: bool = False):
+        """reqs: list of (ch, samples, out, at_ns) with GPU tensors, or with host
+        (preferably pinned) CPU tensors when host=True; returns tickets."""
         arr = (Request * max(1, len(reqs)))()
+        flags = FNT_SUBMIT_HOST if host else 0
         for i, (ch, x, o, at) in enumerate(reqs):
-            arr[i] = Request(ch, 0, x.data_ptr(), o.data_ptr(), x.shape[0], int(at))
+            arr[i] = Request(ch, flags, x.data_ptr(), o.data_ptr(), x.shape[0], int(at))
         tks = (ctypes.c_uint64 * max(1, len(reqs)))()
         _ok(lib().fnt_session_replay(self._h, arr, len(reqs), tks))
         return list(tks)[: len(reqs)]
