@@ -12,7 +12,9 @@
 // stream and the state record carries the history.  A completion thread
 // retires ticks in order and stamps request latencies.  Host-buffer requests
 // are staged through a first-fit pool inside the session's HBM budget; a
-// request that does not fit waits (admission by footprint).
+// request that does not fit waits (admission by footprint).  Their PCIe copies
+// run on two copy streams of their own, so a tick's input upload and the
+// previous tick's result download overlap the kernels in between.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -121,7 +123,9 @@ struct TickSlot {
     CdcItem *cdc_dev = nullptr;
     AeqItem *aeq_dev = nullptr;
     int8_t *scratch = nullptr;      // decimated symbols, max_active * chunk * 64 bytes
-    hipEvent_t done = nullptr;
+    hipEvent_t done = nullptr;      // kernels and result downloads of the tick finished
+    hipEvent_t staged = nullptr;    // input uploads of requests admitted in the tick finished
+    hipEvent_t computed = nullptr;  // kernels of the tick finished
     bool busy = false;
     std::vector<uint64_t> finishing;   // tickets whose last block is in this tick
     uint64_t seq = 0;
@@ -134,7 +138,9 @@ constexpr int kSlots = 3;
 struct fnt_session {
     fnt_session_config cfg{};
     int device = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;      // tick kernels, in order
+    hipStream_t copy_in = nullptr;     // host-to-device staging of admitted requests
+    hipStream_t copy_out = nullptr;    // device-to-host results of finished requests
     DevState *dstate = nullptr;
     int8_t *pool_base = nullptr;
     Pool pool;
@@ -183,7 +189,10 @@ uint64_t staging_bytes(uint64_t n) { return ((n * 4 + 255) & ~255ull) + n * 4; }
 
 // Build one tick's work (called with the lock held).  Channels served in this
 // tick move behind the ones that were not, so every channel makes progress.
-int build_tick(fnt_session *s, TickSlot &slot) {
+// Input uploads of newly admitted host-buffer requests are queued on the
+// upload stream; *uploads tells whether there were any.
+int build_tick(fnt_session *s, TickSlot &slot, bool *uploads) {
+    *uploads = false;
     const uint32_t chunk = s->cfg.chunk_blocks;
     const uint32_t cap = s->cfg.max_active;
     int nitems = 0;
@@ -217,9 +226,10 @@ int build_tick(fnt_session *s, TickSlot &slot) {
                 r.in = s->pool_base + off;
                 r.out = reinterpret_cast<int16_t *>(s->pool_base + off + ((r.n * 4 + 255) & ~255ull));
                 hipError_t e = hipMemcpyAsync((void *)r.in, r.host_in, r.n * 4, hipMemcpyHostToDevice,
-                                              s->stream);
+                                              s->copy_in);
                 if (e != hipSuccess) set_fatal(s, "session: stage input", e);
                 r.staged = true;
+                *uploads = true;
             }
             r.status = ACTIVE;
         }
@@ -291,7 +301,8 @@ void scheduler_main(fnt_session *s) {
             continue;
         }
         TickSlot &slot = s->slots[slot_idx];
-        int nitems = build_tick(s, slot);
+        bool uploads = false;
+        int nitems = build_tick(s, slot, &uploads);
         if (nitems == 0) {
             s->cv_work.wait_for(lk, std::chrono::microseconds(200));
             continue;
@@ -306,7 +317,12 @@ void scheduler_main(fnt_session *s) {
         }
         lk.unlock();
         hipStream_t st = s->stream;
-        hipError_t e = hipMemcpyAsync(slot.cdc_dev, slot.cdc_host, nitems * sizeof(CdcItem),
+        hipError_t e = hipSuccess;
+        if (uploads) {   // the tick's kernels read the inputs just queued for upload
+            e = hipEventRecord(slot.staged, s->copy_in);
+            if (e == hipSuccess) e = hipStreamWaitEvent(st, slot.staged, 0);
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(slot.cdc_dev, slot.cdc_host, nitems * sizeof(CdcItem),
                                       hipMemcpyHostToDevice, st);
         if (e == hipSuccess)
             e = hipMemcpyAsync(slot.aeq_dev, slot.aeq_host, nitems * sizeof(AeqItem),
@@ -325,10 +341,17 @@ void scheduler_main(fnt_session *s) {
             const int form = s->cfg.aeq_form >= 0 ? s->cfg.aeq_form : tick_form(nitems);
             e = launch_aeq(slot.aeq_dev, nitems, AeqItem{}, 0, form, s->err, st);
         }
-        for (auto &c : d2h)
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(c.first, c.second.first, c.second.second, hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipEventRecord(slot.done, st);
+        if (d2h.empty()) {
+            if (e == hipSuccess) e = hipEventRecord(slot.done, st);
+        } else {         // downloads wait for this tick's kernels only, not for later ticks
+            if (e == hipSuccess) e = hipEventRecord(slot.computed, st);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s->copy_out, slot.computed, 0);
+            for (auto &c : d2h)
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(c.first, c.second.first, c.second.second, hipMemcpyDeviceToHost,
+                                       s->copy_out);
+            if (e == hipSuccess) e = hipEventRecord(slot.done, s->copy_out);
+        }
         lk.lock();
         if (e != hipSuccess) set_fatal(s, "session: tick launch", e);
         s->st.ticks++;
@@ -384,10 +407,14 @@ void free_session(fnt_session *s) {
         if (sl.aeq_dev) (void)hipFree(sl.aeq_dev);
         if (sl.scratch) (void)hipFree(sl.scratch);
         if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.staged) (void)hipEventDestroy(sl.staged);
+        if (sl.computed) (void)hipEventDestroy(sl.computed);
     }
     if (s->dstate) (void)hipFree(s->dstate);
     if (s->pool_base) (void)hipFree(s->pool_base);
     if (s->stream) (void)hipStreamDestroy(s->stream);
+    if (s->copy_in) (void)hipStreamDestroy(s->copy_in);
+    if (s->copy_out) (void)hipStreamDestroy(s->copy_out);
     delete s;
 }
 
@@ -434,6 +461,8 @@ int fnt_session_create(fnt_session **out, const fnt_session_config *cfg) {
                     (unsigned long long)cfg->hbm_budget_bytes, (unsigned long long)fixed);
     }
     e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->copy_in, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->copy_out, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMalloc(&s->dstate, (size_t)s->cfg.max_channels * sizeof(DevState));
     const uint64_t pool = cfg->hbm_budget_bytes - fixed;
     if (e == hipSuccess && pool) e = hipMalloc(&s->pool_base, pool);
@@ -446,6 +475,8 @@ int fnt_session_create(fnt_session **out, const fnt_session_config *cfg) {
         if (e == hipSuccess) e = hipMalloc(&sl.aeq_dev, ni * sizeof(AeqItem));
         if (e == hipSuccess) e = hipMalloc(&sl.scratch, scratch_bytes);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.staged, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.computed, hipEventDisableTiming);
     }
     if (e != hipSuccess) {
         free_session(s);
@@ -696,7 +727,9 @@ int fnt_session_destroy(fnt_session *s) {
     }
     if (s->sched.joinable()) s->sched.join();
     if (s->compl_.joinable()) s->compl_.join();
+    (void)hipStreamSynchronize(s->copy_in);
     (void)hipStreamSynchronize(s->stream);
+    (void)hipStreamSynchronize(s->copy_out);
     free_session(s);
     return rc;
 }
