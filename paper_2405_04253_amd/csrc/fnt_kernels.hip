@@ -1195,13 +1195,46 @@ __device__ __forceinline__ int32_t xor_h(int32_t v) { return xor_lane<H>(v); }
 // and a select).
 __device__ __forceinline__ int32_t mul_sign(int32_t x, int32_t s) { return sext24(x) * sext24(opq(s)); }
 
+// One butterfly of a cross-lane stage at distance H with its twiddle folded in:
+// fold16(x a + p b), p the partner lane's value, for per-lane constants a, b
+// that give the lower and the upper lane of a pair their own outputs.  Two
+// 24-bit multiplies (the partner's value enters the first through DPP) and one
+// fold.  Needs |x|, |p| < 2^23 and |x a| + |p b| < 2^31; the result has
+// magnitude < 2^16 + 2^15.  The partner product passes through opq so that it
+// stays a multiply of its own (which takes the DPP operand) instead of being
+// merged into the multiply-add.
+template <int H>
+__device__ __forceinline__ int32_t xbfly(int32_t x, int32_t a, int32_t b) {
+    const int32_t q = opq(sext24(xor_pos<H>(x)) * sext24(b));
+    return fold16(sext24(x) * sext24(a) + q);
+}
+
+// Per-lane constants (a, b) of xbfly for the cross-lane stages of one
+// transform lane, computed once outside the block loop.  DIF stage at
+// distance h: lower lane x + p, upper lane (p - x) 2^e.  DIT stage: lower lane
+// x + w p, upper lane p - w x with w = 2^-e (= -2^(16-e), or 1 for e = 0).
+// The values pass through opq: the compiler must not see powers of two and
+// rewrite the multiplies.
+struct XbCoef { int32_t a, b; };
+__device__ __forceinline__ XbCoef xb_dif(int t, int h) {
+    const bool up = (t & h) != 0;
+    const int32_t c = 1 << ((16 / h) * (t & (h - 1)));
+    return {opq(up ? -c : 1), opq(up ? c : 1)};
+}
+__device__ __forceinline__ XbCoef xb_dit(int t, int h) {
+    const bool up = (t & h) != 0;
+    const int e = (16 / h) * (t & (h - 1));
+    const int32_t w = e ? -(1 << (16 - e)) : 1;
+    return {opq(up ? -w : 1), opq(up ? 1 : w)};
+}
+
 // In-register and cross-lane DIF of 16 tap-digit positions zero-padded to 32.
-// In: |x| <= 2^17; out: |X| <= 2^21; register j of lane t holds bin bitrev5(t + LPT j).
+// In: |x| <= 2^17; out: |X| < 2^18; register j of lane t holds bin bitrev5(t + LPT j).
 // Twiddles are powers of two: exponents up to 14 for every lane take the
 // shift form (mul_pow2), the register whose exponent reaches 15 in some lane
 // takes mulmod, and the last cross-lane stage (twiddle 1) is a signed sum.
 template <int LPT>
-__device__ __forceinline__ void tap_fnt_lpt(int32_t (&x)[32 / LPT], int t) {
+__device__ __forceinline__ void tap_fnt_lpt(int32_t (&x)[32 / LPT], int t, XbCoef k2) {
     constexpr int PPL = 32 / LPT;
 #pragma unroll
     for (int h = 16; h >= LPT; h >>= 1) {
@@ -1222,18 +1255,26 @@ __device__ __forceinline__ void tap_fnt_lpt(int32_t (&x)[32 / LPT], int t) {
             }
         }
     }
-    // across lanes: lower lane x + p, upper lane (p - x) * 2^e, e <= 14
+    // across lanes: lower lane x + p, upper lane (p - x) * 2^e, e <= 14.  At
+    // distance 2 (e <= 8, |x| <= 2^19) as one butterfly x a + p b with
+    // (a, b) = (1, 1) or (-2^e, 2^e); the wider stages keep the shift form, as
+    // digit sums of up to 2^18 times 2^12 leave no headroom there.
 #pragma unroll
     for (int h = LPT / 2; h >= 2; h >>= 1) {
         const bool up = (t & h) != 0;
         const int e = (16 / h) * (t & (h - 1));
+        if (h == 2) {
 #pragma unroll
-        for (int j = 0; j < PPL; ++j) {
-            int32_t p = h == 8 ? xor_pos<8>(x[j]) : h == 4 ? xor_pos<4>(x[j]) : xor_pos<2>(x[j]);
-            x[j] = blend(up, mul_pow2(p - x[j], e), x[j] + p);
+            for (int j = 0; j < PPL; ++j) x[j] = xbfly<2>(x[j], k2.a, k2.b);   // k2 = xb_dif(t, 2)
+        } else {
+#pragma unroll
+            for (int j = 0; j < PPL; ++j) {
+                int32_t p = h == 8 ? xor_pos<8>(x[j]) : xor_pos<4>(x[j]);
+                x[j] = blend(up, mul_pow2(p - x[j], e), x[j] + p);
+            }
         }
     }
-    {   // distance 1, twiddle 1: lower lane p + x, upper lane p - x  (|x| <= 2^20)
+    {   // distance 1, twiddle 1: lower lane p + x, upper lane p - x  (|x| < 2^17)
         const int32_t sg = (t & 1) ? -1 : 1;
 #pragma unroll
         for (int j = 0; j < PPL; ++j) x[j] = xor_pos<1>(x[j]) + mul_sign(x[j], sg);
@@ -1246,29 +1287,23 @@ __device__ __forceinline__ int32_t inv_pow2(int e) { return e ? -(1 << (16 - e))
 // DIT inverse (unnormalised) keeping positions 16..31 (registers PPL/2..PPL-1).
 // In: |x| < 2^18; out: |x| < 2^21.
 template <int LPT>
-__device__ __forceinline__ void ifnt_upper_lpt(int32_t (&x)[32 / LPT], int t) {
+__device__ __forceinline__ void ifnt_upper_lpt(int32_t (&x)[32 / LPT], int t, const XbCoef (&k)[3]) {
     constexpr int PPL = 32 / LPT;
     {   // distance 1, twiddle 1: lower lane x + p, upper lane p - x  (|x| < 2^18)
         const int32_t sg = (t & 1) ? -1 : 1;
 #pragma unroll
         for (int j = 0; j < PPL; ++j) x[j] = xor_pos<1>(x[j]) + mul_sign(x[j], sg);
     }
-    // across lanes: the upper lane twiddles its value by 2^-e first (2^-e =
-    // -2^(16-e), 16 - e <= 14 for e > 0; the other lanes fold theirs), then
-    // lower = own + partner, upper = partner - own
+    // across lanes: the upper lane's value carries the twiddle w = 2^-e
+    // (= -2^(16-e), 16 - e in [2, 14], or 1 for e = 0): lower = own + w partner,
+    // upper = partner - w own, as one butterfly x a + p b with (a, b) = (1, w)
+    // or (-w, 1).  Inputs |x| < 2^19 at distance 2 (|w| <= 2^8), then < 2^17.
 #pragma unroll
-    for (int h = 2; h < LPT; h <<= 1) {
-        const bool up = (t & h) != 0;
-        const int e = (16 / h) * (t & (h - 1));
-        const bool tw = up && e != 0;
-        const int sh = tw ? 16 - e : 0;
-        const int32_t sg_in = tw ? -1 : 1, sg_out = up ? -1 : 1;
+    for (int h = 2, hi = 0; h < LPT; h <<= 1, ++hi) {       // k[hi] = xb_dit(t, h)
+        const int32_t a = k[hi].a, b = k[hi].b;
 #pragma unroll
-        for (int j = 0; j < PPL; ++j) {
-            int32_t tt = mul_pow2(mul_sign(x[j], sg_in), sh);                  // |.| < 2^17
-            int32_t p = h == 8 ? xor_pos<8>(tt) : h == 4 ? xor_pos<4>(tt) : xor_pos<2>(tt);
-            x[j] = p + mul_sign(tt, sg_out);
-        }
+        for (int j = 0; j < PPL; ++j)
+            x[j] = h == 8 ? xbfly<8>(x[j], a, b) : h == 4 ? xbfly<4>(x[j], a, b) : xbfly<2>(x[j], a, b);
     }
 #pragma unroll
     for (int h = LPT; h <= 16; h <<= 1) {
@@ -1405,6 +1440,16 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const 
     }
     if (lane < 4) winw[32 + lane] = 0u;
 
+    // lane constants of the cross-lane butterflies: tap transform, inverse,
+    // input spectra (lane position kp of the 16-lane spectrum groups)
+    const XbCoef ktap = xb_dif(t, 2);
+    XbCoef kinv[3], kspec[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        kinv[i] = xb_dit(t, 2 << i);
+        kspec[i] = xb_dif(lane_pos(kk), 8 >> i);
+    }
+
     // tap-digit spectra of this lane's filter and digit, N^-1 = -2048 folded in
     int32_t W[PPL];
     auto transform_taps = [&]() {
@@ -1418,7 +1463,7 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const 
                 W[j] = 0;                             // zero padding 16 -> 32
             }
         }
-        tap_fnt_lpt<LPT>(W, t);
+        tap_fnt_lpt<LPT>(W, t, ktap);
     };
     transform_taps();
 
@@ -1447,21 +1492,29 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const 
             int32_t x0 = wb[kp], x1 = wb[kp + 16];
             int32_t u0 = x0 + x1;
             int32_t u1 = fold16(opq((x0 - x1) << kp));   // |x0 - x1| <= 31: no overflow
+            // lower lane u + p, upper lane (p - u) 2^e as one butterfly u a + p b
+            // with (a, b) = (1, 1) or (-2^e, 2^e); u1 (|u1| < 2^16 + 15) keeps the
+            // shift form at distance 8, where 2^e reaches 2^14
 #pragma unroll
-            for (int h = 8; h >= 2; h >>= 1) {
-                const bool up = (kp & h) != 0;
-                const int e = (16 / h) * (kp & (h - 1));   // <= 14
-                int32_t p0 = h == 8 ? xor_pos<8>(u0) : h == 4 ? xor_pos<4>(u0) : xor_pos<2>(u0);
-                int32_t p1 = h == 8 ? xor_pos<8>(u1) : h == 4 ? xor_pos<4>(u1) : xor_pos<2>(u1);
-                u0 = blend(up, mul_pow2(p0 - u0, e), u0 + p0);
-                u1 = blend(up, mul_pow2(p1 - u1, e), u1 + p1);
+            for (int h = 8, hi = 0; h >= 2; h >>= 1, ++hi) {
+                const int32_t a = kspec[hi].a, b = kspec[hi].b;      // xb_dif(kp, h)
+                if (h == 8) {
+                    const bool up = (kp & 8) != 0;
+                    const int e = 2 * (kp & 7);              // <= 14
+                    int32_t p1 = xor_pos<8>(u1);
+                    u0 = xbfly<8>(u0, a, b);                // |u0| <= 32
+                    u1 = blend(up, mul_pow2(p1 - u1, e), u1 + p1);
+                } else {                                    // |u| < 2^17.01, 2^e <= 2^12
+                    u0 = h == 4 ? xbfly<4>(u0, a, b) : xbfly<2>(u0, a, b);
+                    u1 = h == 4 ? xbfly<4>(u1, a, b) : xbfly<2>(u1, a, b);
+                }
             }
             {   // distance 1, twiddle 1
                 const int32_t sg = (kp & 1) ? -1 : 1;
                 u0 = xor_pos<1>(u0) + mul_sign(u0, sg);
                 u1 = xor_pos<1>(u1) + mul_sign(u1, sg);
             }
-            aspec[lane >> 4][kp] = u0;                  // |.| <= 2^21
+            aspec[lane >> 4][kp] = u0;                  // |.| < 2^18
             aspec[lane >> 4][kp + 16] = u1;
         }
         wave_lds_sync();
@@ -1471,7 +1524,7 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const 
             int32_t P = mulmod(aspec[tS1][t + LPT * j], W[j]);
             Y[j] = P + xor_lpt_lane<LPT>(P);            // pair sum over S1 = 2g, 2g+1
         }
-        ifnt_upper_lpt<LPT>(Y, t);
+        ifnt_upper_lpt<LPT>(Y, t, kinv);
         if (ts == 0) {
 #pragma unroll
             for (int j = PPL / 2; j < PPL; ++j)
