@@ -199,6 +199,16 @@ __device__ __forceinline__ int32_t xor_pos(int32_t v) {
     return xor_lane<X>(v);
 }
 
+// Global-address-space view of a device pointer.  Loads and stores through it
+// are global_* instructions, which count only against the vector-memory
+// counter; through a generic pointer they are flat_* instructions, which also
+// count against the LDS counter, so every wait for an LDS result would wait for
+// them as well.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gptr(T *p) {
+    return (__attribute__((address_space(1))) T *)p;
+}
+
 // Range-violation bits latched into the per-device flag.
 enum : int { RANGE_SAMPLE = 1, RANGE_TAP = 2, RANGE_RESIDUE = 4, RANGE_SYMBOL = 8 };
 

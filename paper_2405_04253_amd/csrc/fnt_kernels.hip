@@ -851,7 +851,7 @@ __device__ __forceinline__ uint32_t aeq_load(const AeqItem &it, int64_t i, int *
     if (i < 0) {
         w = it.hist_in ? reinterpret_cast<const uint32_t *>(it.hist_in)[16 + i] : 0u;
     } else {
-        w = (uint64_t)i < it.m ? reinterpret_cast<const uint32_t *>(it.a)[i] : 0u;
+        w = (uint64_t)i < it.m ? gptr(reinterpret_cast<const uint32_t *>(it.a))[i] : 0u;
     }
     if (!bytes_5bit(w)) flag(err, RANGE_SYMBOL);
     return w;
@@ -1132,7 +1132,7 @@ __global__ __launch_bounds__(64) void aeq_fnt_kernel(const AeqItem *items, AeqIt
         const int32_t yh = (int32_t)clamp64(rs64((int64_t)y, it.out_shift), -32768, 32767);
         const int64_t m = 16 * b + om;
         const bool valid = (uint64_t)m < M;
-        if (valid) it.out[m * 4 + oS2] = (int16_t)yh;
+        if (valid) gptr(it.out)[m * 4 + oS2] = (int16_t)yh;
         if (it.update_enable) {
             // RDE error of this symbol's polarisation and the 8-bit error term
             const int32_t yp = xor_lane<1>(yh);
@@ -1473,8 +1473,8 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const 
     uint32_t win = aeq_sym(it, -16 + pos);
     bad |= !bytes_5bit(win);
     // running pointers: next window symbols and this block's outputs
-    const uint32_t *asym = reinterpret_cast<const uint32_t *>(it.a) + pos;
-    int16_t *outp = it.out + 4 * om + 2 * pol + oS2l;
+    auto asym = gptr(reinterpret_cast<const uint32_t *>(it.a) + pos);
+    auto outp = gptr(it.out + 4 * om + 2 * pol + oS2l);
     int64_t left = (int64_t)M;                         // symbols from 16 b on
 
     for (uint32_t b = 0; b < nblocks; ++b, asym += 16, outp += 64, left -= 16) {
@@ -1742,7 +1742,7 @@ __device__ __forceinline__ void aeq_lane_body(const AeqItem *items, int nitems, 
                     if (i < 0) {
                         if (hist_in) v = reinterpret_cast<const uint32_t *>(hist_in)[16 + i];
                     } else if ((uint64_t)i < M) {
-                        v = reinterpret_cast<const uint32_t *>(ain)[i];
+                        v = gptr(reinterpret_cast<const uint32_t *>(ain))[i];
                         bad |= v ^ (v << 1);
                     }
                     uint8_t *ab = reinterpret_cast<uint8_t *>(&abytes[0][0]);
@@ -1811,7 +1811,7 @@ __device__ __forceinline__ void aeq_lane_body(const AeqItem *items, int nitems, 
         const int32_t hi_ = clamp32((yi + ((1 << out_shift) >> 1)) >> out_shift, -32768, 32767);
         const int32_t hq_ = clamp32((yq + ((1 << out_shift) >> 1)) >> out_shift, -32768, 32767);
         if (valid)
-            reinterpret_cast<uint32_t *>(outp)[2 * m + opol] = ((uint32_t)hi_ & 0xFFFFu) | ((uint32_t)hq_ << 16);
+            gptr(reinterpret_cast<uint32_t *>(outp))[2 * m + opol] = ((uint32_t)hi_ & 0xFFFFu) | ((uint32_t)hq_ << 16);
         if (__ballot(upd && live)) {
             const int64_t r2 = (int64_t)hi_ * hi_ + (int64_t)hq_ * hq_;
             const int64_t R2 = r2 < 6 * c2 ? 2 * c2 : (r2 < 14 * c2 ? 10 * c2 : 18 * c2);
@@ -2028,7 +2028,7 @@ __device__ __forceinline__ void aeq_duo_body(const AeqItem *items, int nitems, c
                     if (i < 0) {
                         if (hist_in) v = reinterpret_cast<const uint32_t *>(hist_in)[16 + i];
                     } else if ((uint64_t)i < M) {
-                        v = reinterpret_cast<const uint32_t *>(ain)[i];
+                        v = gptr(reinterpret_cast<const uint32_t *>(ain))[i];
                         bad |= v ^ (v << 1);
                     }
                     uint8_t *ab = reinterpret_cast<uint8_t *>(&abytes[0][0]);
@@ -2103,7 +2103,7 @@ __device__ __forceinline__ void aeq_duo_body(const AeqItem *items, int nitems, c
         const int32_t hi_ = clamp32((yi + ((1 << out_shift) >> 1)) >> out_shift, -32768, 32767);
         const int32_t hq_ = clamp32((yq + ((1 << out_shift) >> 1)) >> out_shift, -32768, 32767);
         if (valid)
-            reinterpret_cast<uint32_t *>(outp)[2 * m + opol] = ((uint32_t)hi_ & 0xFFFFu) | ((uint32_t)hq_ << 16);
+            gptr(reinterpret_cast<uint32_t *>(outp))[2 * m + opol] = ((uint32_t)hi_ & 0xFFFFu) | ((uint32_t)hq_ << 16);
         if (upd) {
             const int64_t r2 = (int64_t)hi_ * hi_ + (int64_t)hq_ * hq_;
             const int64_t R2 = r2 < 6 * c2 ? 2 * c2 : (r2 < 14 * c2 ? 10 * c2 : 18 * c2);
@@ -2250,7 +2250,7 @@ __global__ __launch_bounds__(64) void aeq_direct_kernel(const AeqItem *items, Ae
             uint2 o;
             o.x = ((uint32_t)ys[0] & 0xFFFFu) | ((uint32_t)ys[1] << 16);
             o.y = ((uint32_t)ys[2] & 0xFFFFu) | ((uint32_t)ys[3] << 16);
-            reinterpret_cast<uint2 *>(it.out)[m] = o;
+            gptr(reinterpret_cast<uint64_t *>(it.out))[m] = (uint64_t)o.x | ((uint64_t)o.y << 32);
         }
         if (it.update_enable) {
             uint32_t epack = 0;

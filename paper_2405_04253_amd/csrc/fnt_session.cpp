@@ -272,7 +272,7 @@ int build_tick(fnt_session *s, TickSlot &slot, bool *uploads) {
 // 70 % efficiency).
 int tick_form(int nitems) {
     struct Form { int code; double lat_us, instr; };
-    static const Form forms[] = {{4, 0.88, 1904}, {2, 1.03, 1336}, {1, 1.38, 998}, {3, 2.09, 740}, {0, 2.69, 600}};
+    static const Form forms[] = {{4, 0.81, 1536}, {2, 0.91, 1100}, {1, 1.21, 860}, {3, 2.08, 740}, {0, 2.69, 600}};
     int best = 4;
     double best_t = 1e30;
     for (const Form &f : forms) {
