@@ -535,7 +535,7 @@ static int plan_capture(fnt_plan *p, hipStream_t s) {
     return FNT_OK;
 }
 
-constexpr int kTuneVersion = 6;
+constexpr int kTuneVersion = 7;
 
 static std::string tune_key(const fnt_plan *p) {
     // length histogram (log2 buckets of instants) + channel count + variant
@@ -786,14 +786,16 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
                 return cs.front();
             };
             leads.push_back({0, bnl, bq, bql, -1, 0, -1, 0});   // the choice above, without a lead
-            std::vector<int> lfs = {bql}, qls = {bql};
-            for (int f : {2, 5})
-                if (f != bql) lfs.push_back(f);
-            for (int f : {3, 5})
+            // lead forms: one, two and four waves per half (form 5 pairs the
+            // halves in a workgroup); following latency chains: the sweep's
+            // choice, two lanes per transform, or the pol forms; the rest: one
+            // lane or two lanes per transform, or one wave per half
+            std::vector<int> lfs = {1, 5, 2}, qls = {bql}, qs = {0, 3, 1};
+            for (int f : {3, 1, 5})
                 if (f != bql) qls.push_back(f);
             for (size_t lead : {256, 512, 1024, 1536})
                 for (size_t extra : {0, 512, 1024})
-                    for (int q : {0, 3})
+                    for (int q : qs)
                         for (int lf : lfs)
                             for (int ql : qls) {
                                 const size_t nl = lead + extra;

@@ -105,6 +105,9 @@ __device__ __forceinline__ int64_t rs64(int64_t v, int s) {
 __device__ __forceinline__ int32_t rs32(int32_t v, int s) {
     return s > 0 ? (int32_t)(((int64_t)v + ((int64_t)1 << (s - 1))) >> s) : v;
 }
+// rs32 in 32-bit arithmetic, given the rounding term r = 2^(s-1) (0 for s = 0)
+// and |v| + r < 2^31.
+__device__ __forceinline__ int32_t rs32r(int32_t v, int s, int32_t r) { return (v + r) >> s; }
 __device__ __forceinline__ int64_t clamp64(int64_t v, int64_t lo, int64_t hi) {
     return v < lo ? lo : (v > hi ? hi : v);
 }
@@ -157,9 +160,9 @@ __device__ __forceinline__ int32_t blend(bool c, int32_t a, int32_t b) {
     return c ? a : b;                                  // -> v_cndmask_b32
 }
 
-// Centred representative in [-32768, 32768] of a loose residue with |r| < 2^30.
+// Centred representative in [-32768, 32768] of a loose residue (any int32).
 __device__ __forceinline__ int32_t lift_loose(int32_t r) {
-    int32_t f = (int32_t)((uint32_t)r & 0xFFFFu) - (r >> 16);   // in [-2^14, 2^16 + 2^14)
+    int32_t f = (int32_t)((uint32_t)r & 0xFFFFu) - (r >> 16);   // in [-32767, 98303]
     f = f > 32768 ? f - 65537 : f;
     return f < -32768 ? f + 65537 : f;
 }

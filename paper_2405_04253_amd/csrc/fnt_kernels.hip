@@ -1184,16 +1184,18 @@ __global__ __launch_bounds__(64) void aeq_fnt_kernel(const AeqItem *items, AeqIt
 //     stream pairs (XI,XQ) / (YI,YQ); the waves then meet once per block to sum
 //     their partial outputs.
 // ------------------------------------------------------------------------
+// The same bin of the partner transform (S1 = 2g + 1 for S1 = 2g), LPT lanes
+// further on.  For LPT = 4 the lanes that keep the pair sum (even transforms:
+// lanes 0-3 and 8-11 of every row of 16) read lane + 4 by a DPP row rotation;
+// the odd transforms' sums are discarded.
 template <int LPT>
-__device__ __forceinline__ int32_t xor_lpt_lane(int32_t v) { return xor_lane<LPT>(v); }
+__device__ __forceinline__ int32_t s1_partner(int32_t v) {
+    if constexpr (LPT == 4) return __builtin_amdgcn_update_dpp(0, v, 0x12C, 0xF, 0xF, true);   // row_ror:12
+    else return xor_lane<LPT>(v);
+}
 
 template <int H>
 __device__ __forceinline__ int32_t xor_h(int32_t v) { return xor_lane<H>(v); }
-
-// x * s for |x| < 2^23 and a lane constant s = +-1: one 24-bit multiply (the
-// sign passes through opq, or the compiler turns the product into a negate
-// and a select).
-__device__ __forceinline__ int32_t mul_sign(int32_t x, int32_t s) { return sext24(x) * sext24(opq(s)); }
 
 // One butterfly of a cross-lane stage at distance H with its twiddle folded in:
 // fold16(x a + p b), p the partner lane's value, for per-lane constants a, b
@@ -1210,11 +1212,9 @@ __device__ __forceinline__ int32_t xbfly(int32_t x, int32_t a, int32_t b) {
 }
 
 // Per-lane constants (a, b) of xbfly for the cross-lane stages of one
-// transform lane, computed once outside the block loop.  DIF stage at
-// distance h: lower lane x + p, upper lane (p - x) 2^e.  DIT stage: lower lane
-// x + w p, upper lane p - w x with w = 2^-e (= -2^(16-e), or 1 for e = 0).
-// The values pass through opq: the compiler must not see powers of two and
-// rewrite the multiplies.
+// transform lane.  DIF stage at distance h: lower lane x + p, upper lane
+// (p - x) 2^e.  DIT stage: lower lane x + w p, upper lane p - w x with
+// w = 2^-e (= -2^(16-e), or 1 for e = 0).
 struct XbCoef { int32_t a, b; };
 __device__ __forceinline__ XbCoef xb_dif(int t, int h) {
     const bool up = (t & h) != 0;
@@ -1228,45 +1228,89 @@ __device__ __forceinline__ XbCoef xb_dit(int t, int h) {
     return {opq(up ? -w : 1), opq(up ? 1 : w)};
 }
 
-// In-register and cross-lane DIF of 16 tap-digit positions zero-padded to 32.
-// In: |x| <= 2^17; out: |X| < 2^18; register j of lane t holds bin bitrev5(t + LPT j).
-// Twiddles are powers of two: exponents up to 14 for every lane take the
-// shift form (mul_pow2), the register whose exponent reaches 15 in some lane
-// takes mulmod, and the last cross-lane stage (twiddle 1) is a signed sum.
+// 2^-e (mod 65537) as a small signed constant, 0 <= e < 16.
+__device__ __forceinline__ int32_t inv_pow2(int e) { return e ? -(1 << (16 - e)) : 1; }
+
+// -2048 2^e (mod 65537) as a small signed constant, 0 <= e < 16: -2^(11+e)
+// for e <= 4, 2^(e-5) above (2^16 = -1).
+__device__ __forceinline__ int32_t ninv32_pow2(int e) { return e <= 4 ? -(1 << (11 + e)) : 1 << (e - 5); }
+
+// Every twiddle and sign a lane of the polarisation-split AEQ applies, computed
+// once before the block loop (lane position t of its transform, kp of its
+// input-spectrum group).  The values pass through opq: the compiler must not
+// see powers of two and rewrite the multiplies into longer shift sequences.
 template <int LPT>
-__device__ __forceinline__ void tap_fnt_lpt(int32_t (&x)[32 / LPT], int t, XbCoef k2) {
-    constexpr int PPL = 32 / LPT;
+struct PolLaneK {
+    static constexpr int NT = 16 / LPT;
+    XbCoef tap2;               // tap transform, distance 2
+    XbCoef inv[3];             // inverse, distances 2, 4, 8
+    XbCoef spec[3];            // input spectra, distances 8, 4, 2
+    int32_t sg, sgk;           // +-1 by t & 1 and by kp & 1 (distance-1 stages)
+    int32_t h16[NT];           // tap transform, first stage: -2048 2^(t + LPT j)
+    int32_t n2048;             // -2048 = 32^-1
+    int32_t iw_first;          // inverse, first in-register stage (h = LPT < 16): 2^-(16/LPT) t
+    int32_t iw_second;         // inverse, h = 2 LPT < 16, j even: 2^-(8/LPT) t
+    int32_t iw_last;           // inverse, h = 16, j = 0: 2^-t
+    __device__ __forceinline__ PolLaneK(int t, int kp) {
+        tap2 = xb_dif(t, 2);
 #pragma unroll
-    for (int h = 16; h >= LPT; h >>= 1) {
+        for (int i = 0; i < 3; ++i) {
+            inv[i] = xb_dit(t, 2 << i);
+            spec[i] = xb_dif(kp, 8 >> i);
+        }
+        sg = opq((t & 1) ? -1 : 1);
+        sgk = opq((kp & 1) ? -1 : 1);
+#pragma unroll
+        for (int j = 0; j < NT; ++j) h16[j] = opq(ninv32_pow2(t + LPT * j));
+        n2048 = opq(-2048);
+        iw_first = opq(inv_pow2((16 / LPT) * t));
+        iw_second = opq(inv_pow2(((16 / (2 * LPT)) * t) & 15));
+        iw_last = opq(inv_pow2(t));
+    }
+};
+
+// x * s for |x| < 2^23 and a lane constant s (24-bit product).
+__device__ __forceinline__ int32_t mul24k(int32_t x, int32_t s) { return sext24(x) * sext24(s); }
+
+// In-register and cross-lane DIF of 16 tap digits zero-padded to 32, times
+// 32^-1 = -2048 (so the inverse needs no scaling).  In: digits |d| <= 64 in
+// x[0 .. NT-1]; out: |X| < 2^18; register j of lane t holds bin bitrev5(t + LPT j).
+// The first stage (partner zero padding) is one 24-bit multiply per output:
+// d (-2048), and d (-2048) 2^e as a small constant; later in-register twiddles
+// are shifts (mul_pow2, every lane's exponent <= 14); distance 2 across lanes is
+// xbfly, distance 4 and 8 keep the shift form (digit sums of up to 2^18 times
+// 2^12 leave no headroom there), distance 1 is a signed sum.
+template <int LPT>
+__device__ __forceinline__ void tap_fnt_lpt(int32_t (&x)[32 / LPT], int t, const PolLaneK<LPT> &k) {
+    constexpr int PPL = 32 / LPT;
+    constexpr int NT = PPL / 2;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {              // h = 16: |d 2^(11+e)| <= 2^21
+        x[j + NT] = mul24k(x[j], k.h16[j]);
+        x[j] = mul24k(x[j], k.n2048);             // |.| <= 2^17
+    }
+#pragma unroll
+    for (int h = 8; h >= LPT; h >>= 1) {
         const int jd = h / LPT;
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
             if (j & jd) continue;
             const int jp = j & (jd - 1);
-            const int e = (16 / h) * t + (16 * LPT / h) * jp;               // < 16
-            const bool shift_ok = (16 / h) * (LPT - 1) + (16 * LPT / h) * jp <= 14;   // every lane
-            if (h == 16) {
-                // the partner is zero padding
-                x[j + jd] = shift_ok ? mul_pow2(x[j], e) : mulmod(x[j], opq(1 << e));
-            } else {
-                int32_t a = x[j], b = x[j + jd];
-                x[j] = a + b;
-                x[j + jd] = shift_ok ? mul_pow2(a - b, e) : mulmod(a - b, opq(1 << e));
-            }
+            const int e = (16 / h) * t + (16 * LPT / h) * jp;               // <= 14
+            int32_t a = x[j], b = x[j + jd];
+            x[j] = a + b;
+            x[j + jd] = mul_pow2(a - b, e);
         }
     }
-    // across lanes: lower lane x + p, upper lane (p - x) * 2^e, e <= 14.  At
-    // distance 2 (e <= 8, |x| <= 2^19) as one butterfly x a + p b with
-    // (a, b) = (1, 1) or (-2^e, 2^e); the wider stages keep the shift form, as
-    // digit sums of up to 2^18 times 2^12 leave no headroom there.
+    // across lanes: lower lane x + p, upper lane (p - x) * 2^e, e <= 14
 #pragma unroll
     for (int h = LPT / 2; h >= 2; h >>= 1) {
-        const bool up = (t & h) != 0;
-        const int e = (16 / h) * (t & (h - 1));
         if (h == 2) {
 #pragma unroll
-            for (int j = 0; j < PPL; ++j) x[j] = xbfly<2>(x[j], k2.a, k2.b);   // k2 = xb_dif(t, 2)
+            for (int j = 0; j < PPL; ++j) x[j] = xbfly<2>(x[j], k.tap2.a, k.tap2.b);
         } else {
+            const bool up = (t & h) != 0;
+            const int e = (16 / h) * (t & (h - 1));
 #pragma unroll
             for (int j = 0; j < PPL; ++j) {
                 int32_t p = h == 8 ? xor_pos<8>(x[j]) : xor_pos<4>(x[j]);
@@ -1274,36 +1318,31 @@ __device__ __forceinline__ void tap_fnt_lpt(int32_t (&x)[32 / LPT], int t, XbCoe
             }
         }
     }
-    {   // distance 1, twiddle 1: lower lane p + x, upper lane p - x  (|x| < 2^17)
-        const int32_t sg = (t & 1) ? -1 : 1;
+    // distance 1, twiddle 1: lower lane p + x, upper lane p - x  (|x| < 2^17)
 #pragma unroll
-        for (int j = 0; j < PPL; ++j) x[j] = xor_pos<1>(x[j]) + mul_sign(x[j], sg);
-    }
+    for (int j = 0; j < PPL; ++j) x[j] = xor_pos<1>(x[j]) + mul24k(x[j], k.sg);
 }
 
-// 2^-e (mod 65537) as a small signed constant, 0 <= e < 16.
-__device__ __forceinline__ int32_t inv_pow2(int e) { return e ? -(1 << (16 - e)) : 1; }
-
 // DIT inverse (unnormalised) keeping positions 16..31 (registers PPL/2..PPL-1).
-// In: |x| < 2^18; out: |x| < 2^21.
+// In: |x| < 2^18; out: any int32 (a loose residue for lift_loose).
+// Distance 1 is a signed sum; the other cross-lane stages are xbfly (outputs
+// < 2^16.6).  The first in-register stage multiplies by w = 2^-e directly
+// (|w| <= 2^14, outputs < 2^30.6); at h = 2 LPT < 16 the registers whose
+// exponent can be 0 fold the operand and multiply likewise (outputs < 2^31),
+// the others take the shift form; at h = 16 the exponent can be 1 (w = -2^15)
+// in the first register: mulmod on the folded operand, shift form elsewhere.
 template <int LPT>
-__device__ __forceinline__ void ifnt_upper_lpt(int32_t (&x)[32 / LPT], int t, const XbCoef (&k)[3]) {
+__device__ __forceinline__ void ifnt_upper_lpt(int32_t (&x)[32 / LPT], int t, const PolLaneK<LPT> &k) {
     constexpr int PPL = 32 / LPT;
-    {   // distance 1, twiddle 1: lower lane x + p, upper lane p - x  (|x| < 2^18)
-        const int32_t sg = (t & 1) ? -1 : 1;
 #pragma unroll
-        for (int j = 0; j < PPL; ++j) x[j] = xor_pos<1>(x[j]) + mul_sign(x[j], sg);
-    }
-    // across lanes: the upper lane's value carries the twiddle w = 2^-e
-    // (= -2^(16-e), 16 - e in [2, 14], or 1 for e = 0): lower = own + w partner,
-    // upper = partner - w own, as one butterfly x a + p b with (a, b) = (1, w)
-    // or (-w, 1).  Inputs |x| < 2^19 at distance 2 (|w| <= 2^8), then < 2^17.
+    for (int j = 0; j < PPL; ++j) x[j] = xor_pos<1>(x[j]) + mul24k(x[j], k.sg);     // |.| < 2^18.4
 #pragma unroll
-    for (int h = 2, hi = 0; h < LPT; h <<= 1, ++hi) {       // k[hi] = xb_dit(t, h)
-        const int32_t a = k[hi].a, b = k[hi].b;
+    for (int h = 2, hi = 0; h < LPT; h <<= 1, ++hi) {
 #pragma unroll
         for (int j = 0; j < PPL; ++j)
-            x[j] = h == 8 ? xbfly<8>(x[j], a, b) : h == 4 ? xbfly<4>(x[j], a, b) : xbfly<2>(x[j], a, b);
+            x[j] = h == 8 ? xbfly<8>(x[j], k.inv[hi].a, k.inv[hi].b)
+                 : h == 4 ? xbfly<4>(x[j], k.inv[hi].a, k.inv[hi].b)
+                          : xbfly<2>(x[j], k.inv[hi].a, k.inv[hi].b);
     }
 #pragma unroll
     for (int h = LPT; h <= 16; h <<= 1) {
@@ -1314,7 +1353,13 @@ __device__ __forceinline__ void ifnt_upper_lpt(int32_t (&x)[32 / LPT], int t, co
             const int jp = j & (jd - 1);
             const int e = (16 / h) * t + (16 * LPT / h) * jp;
             const int32_t a = x[j];
-            if ((16 * LPT / h) * jp >= 2) {
+            if (h < 16 && (h == LPT || jp == 0)) {
+                // tt = b w: |b| < 2^16.6 (first stage) or folded, |w| <= 2^14
+                const int32_t b = h == LPT ? x[j + jd] : fold16(x[j + jd]);
+                const int32_t tt = mul24k(b, h == LPT ? k.iw_first : k.iw_second);
+                x[j] = a + tt;
+                x[j + jd] = a - tt;
+            } else if ((16 * LPT / h) * jp >= 2) {
                 // every lane has 2 <= e: tt = -m with m = x 2^(16-e), 16 - e <= 14
                 const int32_t m = mul_pow2(x[j + jd], 16 - e);
                 if (h == 16) {
@@ -1323,14 +1368,9 @@ __device__ __forceinline__ void ifnt_upper_lpt(int32_t (&x)[32 / LPT], int t, co
                     x[j] = a - m;
                     x[j + jd] = a + m;
                 }
-            } else {
-                const int32_t tt = mulmod(x[j + jd], opq(inv_pow2(e)));
-                if (h == 16) {
-                    x[j + jd] = a - tt;
-                } else {
-                    x[j] = a + tt;
-                    x[j + jd] = a - tt;
-                }
+            } else {                                  // h = 16, j = 0: w = 2^-t
+                const int32_t b = h == LPT ? x[j + jd] : fold16(x[j + jd]);
+                x[j + jd] = a - mulmod(b, k.iw_last);
             }
         }
     }
@@ -1440,51 +1480,51 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const 
     }
     if (lane < 4) winw[32 + lane] = 0u;
 
-    // lane constants of the cross-lane butterflies: tap transform, inverse,
-    // input spectra (lane position kp of the 16-lane spectrum groups)
-    const XbCoef ktap = xb_dif(t, 2);
-    XbCoef kinv[3], kspec[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        kinv[i] = xb_dit(t, 2 << i);
-        kspec[i] = xb_dif(lane_pos(kk), 8 >> i);
-    }
+    // twiddles and signs of this lane's transforms (position t) and of its
+    // input-spectrum group (position lane_pos(kk))
+    const PolLaneK<LPT> K(t, lane_pos(kk));
 
     // tap-digit spectra of this lane's filter and digit, N^-1 = -2048 folded in
     int32_t W[PPL];
     auto transform_taps = [&]() {
 #pragma unroll
-        for (int j = 0; j < PPL; ++j) {
-            if (j < NT) {
-                int32_t lo = ((w[j] + 64) & 127) - 64;
-                int32_t hi = (w[j] - lo) >> 7;
-                W[j] = (td ? lo : hi) * -2048;        // |.| <= 2^17
-            } else {
-                W[j] = 0;                             // zero padding 16 -> 32
-            }
+        for (int j = 0; j < NT; ++j) {
+            int32_t lo = ((w[j] + 64) & 127) - 64;
+            int32_t hi = (w[j] - lo) >> 7;
+            W[j] = td ? lo : hi;                      // |.| <= 64; W[NT..] is the padding
         }
-        tap_fnt_lpt<LPT>(W, t, ktap);
+        tap_fnt_lpt<LPT>(W, t, K);
     };
     transform_taps();
 
     const uint32_t nblocks = (uint32_t)((M + 15) / 16);
     const int c2 = it.const_unit * it.const_unit;
+    // 32-bit rounding shifts: |y| < 2^24 with out_shift <= 24; |G| <= 16 * 128 * 16
+    // = 2^15, so every mu_shift above 17 rounds G to 0 exactly as 17 does
+    const int out_s = it.out_shift, mu_s = min(it.mu_shift, 17);
+    const int32_t out_r = out_s ? 1 << (out_s - 1) : 0, mu_r = mu_s ? 1 << (mu_s - 1) : 0;
     bool bad = false;                                  // range violations, flagged once at the end
-    uint32_t win = aeq_sym(it, -16 + pos);
-    bad |= !bytes_5bit(win);
-    // running pointers: next window symbols and this block's outputs
-    auto asym = gptr(reinterpret_cast<const uint32_t *>(it.a) + pos);
-    auto outp = gptr(it.out + 4 * om + 2 * pol + oS2l);
-    int64_t left = (int64_t)M;                         // symbols from 16 b on
+    // windows: lane pos holds symbol 16 b - 16 + pos of block b.  Block b loads
+    // the symbols of block b + 2's window into the register its own window came
+    // in, two blocks ahead of use (even and odd blocks alternate between two
+    // registers), so load latency in a busy memory system stays off the chain.
+    // The load itself is unconditional (index clamped into the input) and the
+    // zeros past the end are applied when the window is used, so no wait for it
+    // is placed before then.
+    const auto abase = gptr(reinterpret_cast<const uint32_t *>(it.a));
+    const auto obase = gptr(it.out + 4 * om + 2 * pol + oS2l);
+    uint32_t win_even = aeq_sym(it, -16 + pos), win_odd = aeq_sym(it, pos);   // blocks 0 and 1
 
-    for (uint32_t b = 0; b < nblocks; ++b, asym += 16, outp += 64, left -= 16) {
-        uint32_t nxt = pos < left ? *asym : 0u;        // used by lanes pos >= 16
-        bad |= !bytes_5bit(nxt);
+    auto block = [&](uint32_t b, uint32_t &win) {
+        const int64_t left = (int64_t)M - 16 * (int64_t)b;         // symbols from 16 b on
+        if (pos - 16 >= left) win = 0u;                             // past the end
+        bad |= !bytes_5bit(win);
         if (lane < 32) {
             uint8_t *wb = reinterpret_cast<uint8_t *>(winw);
 #pragma unroll
             for (int c = 0; c < 4; ++c) wb[c * 32 + pos] = (uint8_t)(win >> (8 * c));
         }
+        win = abase[min<uint64_t>(16 * (uint64_t)b + 16 + pos, M - 1)];   // symbol 16 b + 16 + pos
         wave_lds_sync();
         {   // input spectra of the 4 streams: lane (S1 = lane / 16, k) holds positions k, k + 16
             const int kp = lane_pos(kk);                 // position index of this lane
@@ -1497,7 +1537,7 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const 
             // shift form at distance 8, where 2^e reaches 2^14
 #pragma unroll
             for (int h = 8, hi = 0; h >= 2; h >>= 1, ++hi) {
-                const int32_t a = kspec[hi].a, b = kspec[hi].b;      // xb_dif(kp, h)
+                const int32_t a = K.spec[hi].a, b = K.spec[hi].b;    // xb_dif(kp, h)
                 if (h == 8) {
                     const bool up = (kp & 8) != 0;
                     const int e = 2 * (kp & 7);              // <= 14
@@ -1509,11 +1549,9 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const 
                     u1 = h == 4 ? xbfly<4>(u1, a, b) : xbfly<2>(u1, a, b);
                 }
             }
-            {   // distance 1, twiddle 1
-                const int32_t sg = (kp & 1) ? -1 : 1;
-                u0 = xor_pos<1>(u0) + mul_sign(u0, sg);
-                u1 = xor_pos<1>(u1) + mul_sign(u1, sg);
-            }
+            // distance 1, twiddle 1
+            u0 = xor_pos<1>(u0) + mul24k(u0, K.sgk);
+            u1 = xor_pos<1>(u1) + mul24k(u1, K.sgk);
             aspec[lane >> 4][kp] = u0;                  // |.| < 2^18
             aspec[lane >> 4][kp + 16] = u1;
         }
@@ -1522,9 +1560,9 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const 
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
             int32_t P = mulmod(aspec[tS1][t + LPT * j], W[j]);
-            Y[j] = P + xor_lpt_lane<LPT>(P);            // pair sum over S1 = 2g, 2g+1
+            Y[j] = P + s1_partner<LPT>(P);              // pair sum over S1 = 2g, 2g+1
         }
-        ifnt_upper_lpt<LPT>(Y, t, kinv);
+        ifnt_upper_lpt<LPT>(Y, t, K);
         if (ts == 0) {
 #pragma unroll
             for (int j = PPL / 2; j < PPL; ++j)
@@ -1535,9 +1573,9 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const 
         const int pi = lane & 31;
         const int32_t(*part)[33] = part_h[b & 1];
         const int32_t y = 128 * (part[0][pi] + part[2][pi]) + part[1][pi] + part[3][pi];
-        const int32_t yh = clamp32(rs32(y, it.out_shift), -32768, 32767);
+        const int32_t yh = clamp32(rs32r(y, out_s, out_r), -32768, 32767);
         const bool valid = lane < 32 && om < left;
-        if (writer && valid) *outp = (int16_t)yh;
+        if (writer && valid) obase[64 * (uint64_t)b] = (int16_t)yh;
         if (it.update_enable) {
             const int32_t yp = xor_h<1>(yh);
             const int64_t r2 = (int64_t)yh * yh + (int64_t)yp * yp;
@@ -1562,15 +1600,17 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const 
                     gsum = __builtin_amdgcn_sdot4((int)e4[q],
                                                   (int)__builtin_amdgcn_alignbyte(dd[q + 1], dd[q], off & 3),
                                                   gsum, false);
-                w[i] = clamp32(w[i] + (int32_t)rs64((int64_t)gsum, it.mu_shift), -8192, 8191);
+                w[i] = clamp32(w[i] + rs32r(gsum, mu_s, mu_r), -8192, 8191);
             }
             transform_taps();
         }
         // the next block reuses this wave's window and error bytes: keep the LDS
         // reads above in front of the writes that follow
         wave_lds_sync();
-        uint32_t slid = (uint32_t)__shfl((int)win, (lane & 32) | ((pos + 16) & 31));
-        win = pos < 16 ? slid : nxt;
+    };
+    for (uint32_t b = 0; b < nblocks; b += 2) {
+        block(b, win_even);
+        if (b + 1 < nblocks) block(b + 1, win_odd);
     }
     if (bad) flag(err, RANGE_SYMBOL);
     finish();
