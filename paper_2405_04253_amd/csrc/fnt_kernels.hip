@@ -1414,7 +1414,6 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const 
     const int v = tid >> 6, lane = tid & 63;
     const int vh = v % WPP;                            // wave within its half
     const int pol = IW == 1 ? (int)((bid >> 3) & 1) : v;
-    const int pos = lane & 31;
     // transform role: filter (tS1 -> 2 pol + tS2l), digit td, lane t of LPT; the
     // lane also owns the taps k = t + LPT i (i < NT) of that filter
     const int tr = lane / LPT, t = lane_pos(lane % LPT);
@@ -1504,7 +1503,10 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const 
     const int out_s = it.out_shift, mu_s = min(it.mu_shift, 17);
     const int32_t out_r = out_s ? 1 << (out_s - 1) : 0, mu_r = mu_s ? 1 << (mu_s - 1) : 0;
     bool bad = false;                                  // range violations, flagged once at the end
-    // windows: lane pos holds symbol 16 b - 16 + pos of block b.  Block b loads
+    // windows: lane wpos of each half-wave holds window position wpos =
+    // (lane & 16) | lane_pos(lane & 15), symbol 16 b - 16 + wpos of block b (the
+    // order the input-spectrum lanes use, so a row swap hands every lane its
+    // two positions without LDS).  Block b loads
     // the symbols of block b + 2's window into the register its own window came
     // in, two blocks ahead of use (even and odd blocks alternate between two
     // registers), so load latency in a busy memory system stays off the chain.
@@ -1513,23 +1515,27 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const 
     // is placed before then.
     const auto abase = gptr(reinterpret_cast<const uint32_t *>(it.a));
     const auto obase = gptr(it.out + 4 * om + 2 * pol + oS2l);
-    uint32_t win_even = aeq_sym(it, -16 + pos), win_odd = aeq_sym(it, pos);   // blocks 0 and 1
+    const int wpos = (lane & 16) | lane_pos(lane & 15);
+    uint32_t win_even = aeq_sym(it, -16 + wpos), win_odd = aeq_sym(it, wpos);   // blocks 0 and 1
 
     auto block = [&](uint32_t b, uint32_t &win) {
         const int64_t left = (int64_t)M - 16 * (int64_t)b;         // symbols from 16 b on
-        if (pos - 16 >= left) win = 0u;                             // past the end
+        if (wpos - 16 >= left) win = 0u;                            // past the end
         bad |= !bytes_5bit(win);
-        if (lane < 32) {
+        // rows 0, 2 hold positions lane_pos(l), rows 1, 3 positions 16 + lane_pos(l):
+        // swapping odd rows of one copy with even rows of the other gives every
+        // lane both (sw[0]: position kp, sw[1]: position kp + 16)
+        const auto sw = __builtin_amdgcn_permlane16_swap(win, win, false, false);
+        if (lane < 32) {       // window bytes by stream for the tap update
             uint8_t *wb = reinterpret_cast<uint8_t *>(winw);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) wb[c * 32 + pos] = (uint8_t)(win >> (8 * c));
+            for (int c = 0; c < 4; ++c) wb[c * 32 + wpos] = (uint8_t)(win >> (8 * c));
         }
-        win = abase[min<uint64_t>(16 * (uint64_t)b + 16 + pos, M - 1)];   // symbol 16 b + 16 + pos
-        wave_lds_sync();
-        {   // input spectra of the 4 streams: lane (S1 = lane / 16, k) holds positions k, k + 16
+        win = abase[min<uint64_t>(16 * (uint64_t)b + 16 + wpos, M - 1)];  // symbol 16 b + 16 + wpos
+        {   // input spectra of the 4 streams: lane (S1 = lane / 16, k) holds positions kp, kp + 16
             const int kp = lane_pos(kk);                 // position index of this lane
-            const int8_t *wb = reinterpret_cast<const int8_t *>(winw) + (lane >> 4) * 32;
-            int32_t x0 = wb[kp], x1 = wb[kp + 16];
+            const int sh = 8 * (lane >> 4);              // byte of stream S1
+            int32_t x0 = (int32_t)(int8_t)((uint32_t)sw[0] >> sh), x1 = (int32_t)(int8_t)((uint32_t)sw[1] >> sh);
             int32_t u0 = x0 + x1;
             int32_t u1 = fold16(opq((x0 - x1) << kp));   // |x0 - x1| <= 31: no overflow
             // lower lane u + p, upper lane (p - u) 2^e as one butterfly u a + p b
