@@ -82,21 +82,27 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel: str, workload: str, blocks: int | None = None):
+def load_traffic(kernel: str, workload: str, blocks: int | None = None, per_block: bool = False):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
-    taken on the current kernel source (and, given `blocks`, on a launch of the
-    same number of AEQ blocks); else None."""
+    taken on the current kernel source, and where it comes from; (None, reason)
+    otherwise.  Given `blocks`, a launch of another number of AEQ blocks gets the
+    profiled bytes per block times its blocks if `per_block`, else None."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         d = json.load(open(p))
     except Exception:
-        return None
+        return None, "no counter summary"
     e = d.get(workload, {}).get(kernel)
     if not e or e.get("source_hash") != kernel_source_hash():
-        return None
-    if blocks is not None and e.get("aeq_blocks") not in (None, blocks):
-        return None
-    return e.get("bytes_per_launch")
+        return None, "no counters taken on the current kernel source"
+    nb = e.get("aeq_blocks")
+    if blocks is None or nb in (None, blocks):
+        return e.get("bytes_per_launch"), "rocprofv3 FETCH_SIZE + WRITE_SIZE of this launch, copy-calibrated"
+    if per_block and nb:
+        return (round(e["bytes_per_launch"] * blocks / nb),
+                f"rocprofv3 FETCH_SIZE + WRITE_SIZE per block of a profiled {nb}-block launch of this kernel, "
+                f"times {blocks} blocks")
+    return None, "profiled launch had another block count"
 
 
 def cpu_baseline_single(ch, prm, budget_s: float):
@@ -181,7 +187,7 @@ def bench_single(args, torch, dev):
     achieved = aeq_ops / (aeq_ms / 1e3) / 1e9
     roof = {"kernel": "aeq_pol_kernel<16, 1>", "bound": "alu", "achieved": round(achieved, 3),
             "peak": PEAK_ALU_GOPS, "unit": "Gops/s", "frac": round(achieved / PEAK_ALU_GOPS, 6),
-            "traffic": load_traffic("aeq_pol_kernel<16, 1>", "single", blocks_aeq),
+            "traffic": load_traffic("aeq_pol_kernel<16, 1>", "single", blocks_aeq)[0],
             "algorithmic_ops_per_launch": aeq_ops}
     res = {
         "value": round(n / (ms / 1e3) / 1e9, 6), "unit": "Gsamples/s",
@@ -427,9 +433,10 @@ def bench_batched(args, torch, dev):
     dom_blocks, dom_name, dom_ms, dom_key, dom_where = max(launches, key=lambda x: x[0])
     dom_ops = AEQ_OPS_PER_BLOCK * dom_blocks
     dom_achieved = dom_ops / (dom_ms / 1e3) / 1e9
+    dom_traffic, traffic_basis = load_traffic(dom_key, "batched", dom_blocks, per_block=True)
     roof = {"kernel": dom_name, "bound": "alu", "achieved": round(dom_achieved, 1), "peak": PEAK_ALU_GOPS,
             "unit": "Gops/s", "frac": round(dom_achieved / PEAK_ALU_GOPS, 5),
-            "traffic": load_traffic(dom_key, "batched", dom_blocks),
+            "traffic": dom_traffic, "traffic_basis": traffic_basis,
             "algorithmic_ops_per_launch": dom_ops,
             "launch": dom_where,
             "hbm_algorithmic_gbs": round(dom_blocks * 16 * AEQ_BYTES_PER_SYMBOL / dom_ms / 1e6, 1),
