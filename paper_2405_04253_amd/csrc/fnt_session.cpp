@@ -272,7 +272,7 @@ int build_tick(fnt_session *s, TickSlot &slot, bool *uploads) {
 // 70 % efficiency).
 int tick_form(int nitems) {
     struct Form { int code; double lat_us, instr; };
-    static const Form forms[] = {{4, 0.81, 1536}, {2, 0.91, 1100}, {1, 1.21, 860}, {3, 2.08, 740}, {0, 2.69, 600}};
+    static const Form forms[] = {{4, 0.70, 1472}, {2, 0.84, 1020}, {1, 1.08, 774}, {3, 2.05, 740}, {0, 2.70, 600}};
     int best = 4;
     double best_t = 1e30;
     for (const Form &f : forms) {
