@@ -316,6 +316,31 @@ EXTREME_AEQ = [dict(out_shift=24, err_shift=62, mu_shift=40, const_unit=4096, up
                dict(out_shift=9, err_shift=12, mu_shift=1, const_unit=33, update_enable=0)]
 
 
+
+@pytest.mark.parametrize("wpp", [1, 2, 4, 5])
+def test_plan_short_chains_pol_forms(torch_dev, wpp):
+    """Chains of 1 to 5 blocks with ragged ends on the polarisation-split forms: the
+    window symbols two blocks ahead are loaded from a clamped index and the zeros
+    past the end applied when the window is used."""
+    torch, dev = torch_dev
+    lengths = [1, 2, 15, 16, 17, 31, 32, 33, 47, 48, 49, 63, 64, 65, 80]
+    chans = [synth.gen_channel(m, 20.0 + m % 50, 20.0, seed=100 + m) for m in lengths]
+    pc = _plan_channels(torch, dev, chans, np.random.default_rng(1))
+    refs = [O.cdc_aeq(c["ch"].samples, c["ch"].taps, c["ch"].requant_shift, c["w0"], O.params(**c["prm"]))
+            for c in pc]
+    plan = fnt.Plan([(c["x"], c["out"], c["taps"], fnt.cdc_params(c["ch"].taps, c["ch"].requant_shift),
+                      fnt.aeq_params(**c["prm"])) for c in pc], autotune=False, use_graph=False)
+    plan.set_aeq_waves(wpp)
+    note(f"short chains, form {wpp}")
+    plan.run()
+    torch.cuda.synchronize()
+    fnt.fnt_check()
+    for m, c, (outr, wr, _) in zip(lengths, pc, refs):
+        assert np.array_equal(c["out"].cpu().numpy(), outr), m
+        assert np.array_equal(c["taps"].cpu().numpy(), wr), m
+    plan.close()
+
+
 @pytest.mark.parametrize("wpp", [0, 3, 1, 5])
 def test_plan_extreme_aeq_params(torch_dev, wpp):
     """Shift and constant extremes (saturating taps and errors) on the batched kernels."""
