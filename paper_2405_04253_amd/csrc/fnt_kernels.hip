@@ -1503,16 +1503,15 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const 
     const int out_s = it.out_shift, mu_s = min(it.mu_shift, 17);
     const int32_t out_r = out_s ? 1 << (out_s - 1) : 0, mu_r = mu_s ? 1 << (mu_s - 1) : 0;
     bool bad = false;                                  // range violations, flagged once at the end
-    // windows: lane wpos of each half-wave holds window position wpos =
-    // (lane & 16) | lane_pos(lane & 15), symbol 16 b - 16 + wpos of block b (the
-    // order the input-spectrum lanes use, so a row swap hands every lane its
-    // two positions without LDS).  Block b loads
-    // the symbols of block b + 2's window into the register its own window came
-    // in, two blocks ahead of use (even and odd blocks alternate between two
-    // registers), so load latency in a busy memory system stays off the chain.
-    // The load itself is unconditional (index clamped into the input) and the
-    // zeros past the end are applied when the window is used, so no wait for it
-    // is placed before then.
+    // Windows: the lane holds window position wpos = (lane & 16) | lane_pos(lane &
+    // 15), symbol 16 b - 16 + wpos of block b (the order the input-spectrum lanes
+    // use, so a row swap hands every lane its two positions without LDS).  Block
+    // b loads the symbols of block b + 2's window into the register its own
+    // window came in, two blocks ahead of use (even and odd blocks alternate
+    // between two registers), so load latency in a busy memory system stays off
+    // the chain.  The load itself is unconditional (index clamped into the
+    // input) and the zeros past the end are applied when the window is used, so
+    // no wait for it is placed before then.
     const auto abase = gptr(reinterpret_cast<const uint32_t *>(it.a));
     const auto obase = gptr(it.out + 4 * om + 2 * pol + oS2l);
     const int wpos = (lane & 16) | lane_pos(lane & 15);
