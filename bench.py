@@ -344,6 +344,7 @@ def bench_batched(args, torch, dev):
     lead_ms = float(np.mean([t["aeq_lead_ms"] for t in times]))
     top_ms = float(np.mean([t["aeq_top_ms"] for t in times]))
     event_step_ms = float(np.mean([t["step_ms"] for t in times]))
+    event_step_med = float(np.median([t["step_ms"] for t in times]))
     ms = wall / max(args.steps, 1) * 1e3
     progress(f"batched: {ms:.1f} ms per step (events {event_step_ms:.1f}: cdc {cdc_ms:.1f} ms, "
              f"aeq {aeq_ms:.1f} ms, lead aeq {lead_ms:.1f} ms, first-level aeq {top_ms:.1f} ms)")
@@ -480,6 +481,7 @@ def bench_batched(args, torch, dev):
         "kernels": kernels,
         "plan_run_ms": round(run_ms, 3),
         "event_ms_per_step": round(event_step_ms, 3),
+        "event_ms_per_step_median": round(event_step_med, 3),
         "direct_comparator": {
             "value": round(inst / (d_step / 1e3) / 1e9, 4), "unit": "Gsamples/s",
             "cdc_ms": round(d_cdc, 3), "aeq_ms": round(d_aeq, 3), "step_ms": round(d_step, 3),
@@ -653,8 +655,8 @@ def bench_served(args, torch, dev, host: bool = False):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--log2-symbols", type=int, default=24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--single-cpu-baseline", action="store_true",
