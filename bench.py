@@ -672,7 +672,7 @@ def main():
     ap.add_argument("--log2-max", type=int, default=20)
     ap.add_argument("--served-channels", type=int, default=1024)
     ap.add_argument("--rate", type=float, default=20000.0)
-    ap.add_argument("--window", type=float, default=0.5)
+    ap.add_argument("--window", type=float, default=1.0)
     ap.add_argument("--chunk", type=int, default=512)
     ap.add_argument("--h2d-window", type=float, default=0.25,
                     help="arrival window of the served leg with host buffers (0: skip it)")
