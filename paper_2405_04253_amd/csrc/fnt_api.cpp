@@ -535,7 +535,7 @@ static int plan_capture(fnt_plan *p, hipStream_t s) {
     return FNT_OK;
 }
 
-constexpr int kTuneVersion = 7;
+constexpr int kTuneVersion = 8;
 
 static std::string tune_key(const fnt_plan *p) {
     // length histogram (log2 buckets of instants) + channel count + variant
@@ -794,7 +794,7 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
             for (int f : {3, 1, 5})
                 if (f != bql) qls.push_back(f);
             for (size_t lead : {256, 512, 1024, 1536})
-                for (size_t extra : {0, 512, 1024})
+                for (size_t extra : {0, 512, 1024, 1536})
                     for (int q : qs)
                         for (int lf : lfs)
                             for (int ql : qls) {
