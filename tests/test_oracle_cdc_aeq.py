@@ -162,6 +162,82 @@ def test_aeq_hand_worked_two_blocks():
     assert np.array_equal(wf, want_w)
 
 
+def test_aeq_hand_worked_rings_lags_cross_pol():
+    # One block of 16 symbols, two of them nonzero, with c_y = 64 (c^2 = 4096):
+    # thresholds 6c^2 = 24576 and 14c^2 = 57344, radii R2 = 2c^2 = 8192,
+    # 10c^2 = 40960, 18c^2 = 73728.  Neither threshold is a sum of two integer
+    # squares (3 and 7 appear to an odd power), so r2 never ties with one; the
+    # symbols below sit 31 below / 4 and 13 above them.  s_o = 0 (yhat = y),
+    # s_e = 15, s_mu = 0 (w += G).  Lag-0 taps only: t = (16, 11, 39, 17) on
+    # S1 == S2, so yhat_S[m] = t_S a_S[m].
+    #   a[0] = (4, 13, -2, -8)   a[1] = (12, 13, -6, -3)
+    #   m=0 X: yhat (64, 143)    r2 = 4096 + 20449  = 24545 < 6c^2    -> R2 =  8192, e_X = -16353
+    #   m=0 Y: yhat (-78, -136)  r2 = 6084 + 18496  = 24580 >= 6c^2   -> R2 = 40960, e_Y = +16380
+    #   m=1 X: yhat (192, 143)   r2 = 36864 + 20449 = 57313 < 14c^2   -> R2 = 40960, e_X = -16353
+    #   m=1 Y: yhat (-234, -51)  r2 = 54756 + 2601  = 57357 >= 14c^2  -> R2 = 73728, e_Y = +16371
+    # eps_S2 = sat8(rs(e_pol(S2) yhat_S2, 15)), e.g. rs(-16353 * 64, 15) = floor(-31.94 + 0.5) = -32:
+    #   eps[0] = (-32, -71, -39, -68)    eps[1] = (-96, -71, -117, -25)
+    # G[S1][S2][0] = eps_S2[0] a_S1[0] + eps_S2[1] a_S1[1];  G[S1][S2][1] = eps_S2[1] a_S1[0]
+    # (lag 1 reaches a_S1[0] from m = 1; a[-1] is zero history), e.g.
+    #   G[XI][XI][0] = -32*4 + -96*12 = -1280 -> w = 16 - 1280 = -1264;  G[XI][XI][1] = -96*4 = -384
+    #   G[YI][XQ][0] = -71*-2 + -71*-6 = 568 (cross-polarisation: S2 = XQ uses e_X);  G[YI][XQ][1] = 142
+    #   G[XQ][YI][0] = -39*13 + -117*13 = -2028 (S2 = YI uses e_Y);  G[XQ][YI][1] = -117*13 = -1521
+    a = np.zeros((16, 4), np.int8)
+    a[0] = (4, 13, -2, -8)
+    a[1] = (12, 13, -6, -3)
+    w = np.zeros((4, 4, 16), np.int16)
+    for s, t in enumerate((16, 11, 39, 17)):
+        w[s, s, 0] = t
+    prm = O.params(out_shift=0, err_shift=15, mu_shift=0, const_unit=64, update_enable=1)
+    out, wf = O.aeq(a, w, prm)
+    want_out = np.zeros((16, 4), np.int16)
+    want_out[0] = (64, 143, -78, -136)
+    want_out[1] = (192, 143, -234, -51)
+    assert np.array_equal(out, want_out)
+    # final taps (lag 0, lag 1) for S1 (rows) x S2 = XI, XQ, YI, YQ (columns)
+    want = {0: [(-1264, -384), (-1136, -284), (-1560, -468), (-572, -100)],
+            1: [(-1664, -1248), (-1835, -923), (-2028, -1521), (-1209, -325)],
+            2: [(640, 192), (568, 142), (819, 234), (286, 50)],
+            3: [(544, 768), (781, 568), (663, 936), (636, 200)]}
+    want_w = np.zeros((4, 4, 16), np.int16)
+    for s1, row in want.items():
+        for s2, (k0, k1) in enumerate(row):
+            want_w[s1, s2, 0], want_w[s1, s2, 1] = k0, k1
+    assert np.array_equal(wf, want_w)
+
+
+def test_aeq_hand_worked_saturation_and_long_lags():
+    # s_o = 10, s_e = 0, s_mu = 0, c_y = 64.  Taps: w[YI][XI][3] = 8150 (near the
+    # 14-bit top), w[XQ][XQ][0] = -8000 (near the bottom), all others 0.
+    # Input: a_YI[0] = 1, a_XQ[1] = 2, every other sample 0.
+    #   y_XQ[1] = -8000 * 2 = -16000 -> yhat = rs(-16000, 10) = floor(-15.625 + 0.5) = -16
+    #   y_XI[3] = 8150 * a_YI[0] = 8150 -> yhat = rs(8150, 10) = floor(7.959 + 0.5) = 8
+    #   m=1 X: r2 = 256 < 6c^2 -> e = 8192 - 256 = 7936, eps_XQ = sat8(7936 * -16 = -126976) = -128
+    #   m=3 X: r2 = 64         -> e = 8192 - 64 = 8128,  eps_XI = sat8(8128 * 8 = 65024) = 127
+    #   every other yhat is 0, so every other eps is 0.
+    # G[S1][XI][k] = 127 a_S1[3 - k]: G[YI][XI][3] = 127, G[XQ][XI][2] = 254
+    # G[S1][XQ][k] = -128 a_S1[1 - k]: G[XQ][XQ][0] = -256, G[YI][XQ][1] = -128
+    # w[YI][XI][3] = sat14(8150 + 127 = 8277) = 8191; w[XQ][XQ][0] = sat14(-8256) = -8192.
+    a = np.zeros((16, 4), np.int8)
+    a[0, 2] = 1
+    a[1, 1] = 2
+    w = np.zeros((4, 4, 16), np.int16)
+    w[2, 0, 3] = 8150
+    w[1, 1, 0] = -8000
+    prm = O.params(out_shift=10, err_shift=0, mu_shift=0, const_unit=64, update_enable=1)
+    out, wf = O.aeq(a, w, prm)
+    want_out = np.zeros((16, 4), np.int16)
+    want_out[1, 1] = -16
+    want_out[3, 0] = 8
+    assert np.array_equal(out, want_out)
+    want_w = np.zeros((4, 4, 16), np.int16)
+    want_w[2, 0, 3] = 8191
+    want_w[1, 0, 2] = 254
+    want_w[1, 1, 0] = -8192
+    want_w[2, 1, 1] = -128
+    assert np.array_equal(wf, want_w)
+
+
 def test_aeq_update_invariants(aeq_defaults):
     ch = synth.single_channel(1 << 10)
     _, a = O.cdc(ch.samples, ch.taps, ch.requant_shift)
