@@ -71,6 +71,14 @@ struct Channel {
     fnt_aeq_params aeq{};
     std::deque<uint64_t> queue;     // tickets in submission order (queued or active)
     uint64_t position = 0;
+    // The AEQ history has two device copies: a tick reads one and writes the
+    // other, so no workgroup of a tick can read a history that another
+    // workgroup of the same tick has already replaced (the two polarisation
+    // halves of a channel may run as separate workgroups).  tail_sel names the
+    // copy holding the current history: 0 = DevState::aeq_tail, 1 = the
+    // session's aeq_tail_alt record of the channel.
+    int tail_sel = 0;
+    uint64_t last_seq = 0;          // last tick that advanced the channel
 };
 
 // First-fit allocator over [0, size) with coalescing.
@@ -142,6 +150,7 @@ struct fnt_session {
     hipStream_t copy_in = nullptr;     // host-to-device staging of admitted requests
     hipStream_t copy_out = nullptr;    // device-to-host results of finished requests
     DevState *dstate = nullptr;
+    int8_t *aeq_tail_alt = nullptr;    // [max_channels][64]: second copy of each AEQ history
     int8_t *pool_base = nullptr;
     Pool pool;
     int *err = nullptr;
@@ -151,6 +160,7 @@ struct fnt_session {
     TickSlot slots[kSlots];
     uint64_t next_ticket = 1;
     uint64_t tick_seq = 0;
+    uint64_t retired_seq = 0;          // ticks retire in launch order: every seq <= this has ended
     std::deque<int> inflight;          // slot indices in launch order
 
     std::mutex mu;
@@ -245,8 +255,11 @@ int build_tick(fnt_session *s, TickSlot &slot, bool *uploads) {
         chunk0 += cdc_chunks(ci.n);
         AeqItem &ai = slot.aeq_host[nitems];
         fill_aeq_item(ai, ci.a_out, nb * 16, st->taps, &ch.aeq, r.out + r.issued * 16 * 4);
-        ai.hist_in = st->aeq_tail;
-        ai.hist_out = st->aeq_tail;
+        int8_t *tails[2] = {st->aeq_tail, s->aeq_tail_alt + (uint64_t)c * 64};
+        ai.hist_in = tails[ch.tail_sel];
+        ai.hist_out = tails[ch.tail_sel ^ 1];
+        ch.tail_sel ^= 1;
+        ch.last_seq = s->tick_seq + 1;   // the seq this tick receives when it is issued
         ai.cdc_in = ci.in;
         ai.cdc_n = ci.n;
         ai.cdc_tail = st->cdc_tail;
@@ -374,6 +387,7 @@ void completion_main(fnt_session *s) {
         lk.lock();
         if (e != hipSuccess) set_fatal(s, "session: tick completion", e);
         s->inflight.pop_front();
+        s->retired_seq = slot.seq;
         for (uint64_t tk : slot.finishing) {
             auto it = s->reqs.find(tk);
             if (it == s->reqs.end()) continue;
@@ -399,6 +413,26 @@ int check_fatal(fnt_session *s) {
     return FNT_OK;
 }
 
+// Wait (lock held through lk) until the last tick that advanced channel ch has
+// retired, so its kernels no longer read or write the channel's state.  A
+// request leaves its channel's queue when its last block is placed in a tick,
+// before that tick runs, so an empty queue alone does not make the state free.
+int wait_channel_ticks(fnt_session *s, std::unique_lock<std::mutex> &lk, uint32_t ch) {
+    while (s->retired_seq < s->chans[ch].last_seq) {
+        if (s->fatal) return check_fatal(s);
+        s->cv_done.wait_for(lk, std::chrono::milliseconds(5));
+    }
+    return FNT_OK;
+}
+
+bool channel_idle(fnt_session *s, uint32_t ch) {
+    for (uint64_t t : s->chans[ch].queue) {
+        auto it = s->reqs.find(t);
+        if (it != s->reqs.end() && (it->second.status == QUEUED || it->second.status == ACTIVE)) return false;
+    }
+    return true;
+}
+
 void free_session(fnt_session *s) {
     for (auto &sl : s->slots) {
         if (sl.cdc_host) (void)hipHostFree(sl.cdc_host);
@@ -411,6 +445,7 @@ void free_session(fnt_session *s) {
         if (sl.computed) (void)hipEventDestroy(sl.computed);
     }
     if (s->dstate) (void)hipFree(s->dstate);
+    if (s->aeq_tail_alt) (void)hipFree(s->aeq_tail_alt);
     if (s->pool_base) (void)hipFree(s->pool_base);
     if (s->stream) (void)hipStreamDestroy(s->stream);
     if (s->copy_in) (void)hipStreamDestroy(s->copy_in);
@@ -454,7 +489,7 @@ int fnt_session_create(fnt_session **out, const fnt_session_config *cfg) {
         return rc;
     }
     const uint64_t scratch_bytes = (uint64_t)s->cfg.max_active * s->cfg.chunk_blocks * 64;
-    const uint64_t fixed = (uint64_t)kSlots * scratch_bytes + (uint64_t)s->cfg.max_channels * sizeof(DevState);
+    const uint64_t fixed = (uint64_t)kSlots * scratch_bytes + (uint64_t)s->cfg.max_channels * (sizeof(DevState) + 64);
     if (cfg->hbm_budget_bytes < fixed) {
         delete s;
         return fail(FNT_E_NOMEM, "session: budget %llu below the fixed %llu bytes",
@@ -464,6 +499,7 @@ int fnt_session_create(fnt_session **out, const fnt_session_config *cfg) {
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->copy_in, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->copy_out, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMalloc(&s->dstate, (size_t)s->cfg.max_channels * sizeof(DevState));
+    if (e == hipSuccess) e = hipMalloc(&s->aeq_tail_alt, (size_t)s->cfg.max_channels * 64);
     const uint64_t pool = cfg->hbm_budget_bytes - fixed;
     if (e == hipSuccess && pool) e = hipMalloc(&s->pool_base, pool);
     for (int k = 0; k < kSlots && e == hipSuccess; ++k) {
@@ -511,12 +547,14 @@ int fnt_session_add_channel(fnt_session *s, uint32_t ch, const fnt_cdc_params *c
         for (int d = 0; d < 4; ++d) h.taps[(d * 4 + d) * 16 + 8] = 4096;
     }
     std::unique_lock<std::mutex> lk(s->mu);
+    if (!channel_idle(s, ch)) return fail(FNT_E_STATE, "session: channel %u busy", ch);
+    if ((rc = wait_channel_ticks(s, lk, ch))) return rc;
     Channel &c = s->chans[ch];
-    if (!c.queue.empty()) return fail(FNT_E_STATE, "session: channel %u busy", ch);
     c.registered = true;
     c.cdc = *cp;
     c.aeq = *ap;
     c.position = 0;
+    c.tail_sel = 0;
     lk.unlock();
     hipError_t e = hipMemcpy(s->dstate + ch, &h, sizeof h, hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "session: upload channel state");
@@ -639,14 +677,6 @@ int fnt_session_cancel(fnt_session *s, uint64_t ticket) {
     return FNT_OK;
 }
 
-static bool channel_idle(fnt_session *s, uint32_t ch) {
-    for (uint64_t t : s->chans[ch].queue) {
-        auto it = s->reqs.find(t);
-        if (it != s->reqs.end() && (it->second.status == QUEUED || it->second.status == ACTIVE)) return false;
-    }
-    return true;
-}
-
 int fnt_session_get_state(fnt_session *s, uint32_t ch, void *host_buf, size_t *size) {
     if (!s || !size) return fail(FNT_E_INVAL, "session: NULL");
     if (!host_buf || *size < FNT_STATE_BYTES) {
@@ -657,11 +687,15 @@ int fnt_session_get_state(fnt_session *s, uint32_t ch, void *host_buf, size_t *s
     if (ch >= s->cfg.max_channels || !s->chans[ch].registered)
         return fail(FNT_E_STATE, "session: channel %u not registered", ch);
     if (!channel_idle(s, ch)) return fail(FNT_E_STATE, "session: channel %u busy", ch);
-    uint64_t pos = s->chans[ch].position;
-    while (!s->inflight.empty()) s->cv_done.wait_for(lk, std::chrono::milliseconds(5));
+    int rc = wait_channel_ticks(s, lk, ch);
+    if (rc) return rc;
+    const uint64_t pos = s->chans[ch].position;
+    const int sel = s->chans[ch].tail_sel;
     lk.unlock();
     DevState h;
     hipError_t e = hipMemcpy(&h, s->dstate + ch, sizeof h, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && sel)   // the current AEQ history is in the second copy
+        e = hipMemcpy(h.aeq_tail, s->aeq_tail_alt + (uint64_t)ch * 64, 64, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "session: read state");
     h.position = pos;
     std::memcpy(host_buf, &h, sizeof h);
@@ -684,8 +718,10 @@ int fnt_session_set_state(fnt_session *s, uint32_t ch, const void *host_buf, siz
     if (ch >= s->cfg.max_channels || !s->chans[ch].registered)
         return fail(FNT_E_STATE, "session: channel %u not registered", ch);
     if (!channel_idle(s, ch)) return fail(FNT_E_STATE, "session: channel %u busy", ch);
-    while (!s->inflight.empty()) s->cv_done.wait_for(lk, std::chrono::milliseconds(5));
+    int rc = wait_channel_ticks(s, lk, ch);
+    if (rc) return rc;
     s->chans[ch].position = h.position;
+    s->chans[ch].tail_sel = 0;         // the imported history goes to DevState::aeq_tail
     lk.unlock();
     hipError_t e = hipMemcpy(s->dstate + ch, &h, sizeof h, hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "session: write state");

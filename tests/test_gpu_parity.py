@@ -646,6 +646,118 @@ def test_session_state_export_import(torch_dev):
     fnt.fnt_check()
 
 
+@pytest.mark.parametrize("form", [1, 2, 4])
+def test_session_history_after_each_segment(torch_dev, form):
+    """After every request the exported state holds the oracle's histories.
+
+    The polarisation-split forms run a channel's two halves as separate
+    workgroups; a tick reads one copy of the AEQ history and writes the other,
+    so the exported AEQ tail must be the last 16 symbols of the 1-sps stream
+    and the CDC tail the last 32 instants, segment after segment."""
+    torch, dev = torch_dev
+    ch = synth.gen_channel(16 * 70, 60.0, 22.0, seed=91)
+    x = to_dev(torch, dev, ch.samples)
+    out = torch.zeros((ch.n // 2, 4), dtype=torch.int16, device=dev)
+    cp, ap = fnt.cdc_params(ch.taps, ch.requant_shift), fnt.aeq_params(**synth.aeq_params_for(ch))
+    s = fnt.Session(max_channels=2, hbm_budget_bytes=16 << 20, chunk_blocks=4, aeq_form=form)
+    s.add_channel(0, cp, ap)
+    _, a_ref = O.cdc(ch.samples, ch.taps, ch.requant_shift)
+    outr, _ = _oracle_stream(ch)
+    off = 0
+    for k, nb in enumerate([5, 1, 8, 3, 2, 4]):        # blocks of 32 instants; odd and even tick counts
+        n = 32 * nb
+        note(f"session history form {form} segment {k} n={n}")
+        s.wait(s.submit(0, x[off:off + n], out[off // 2:(off + n) // 2]))
+        off += n
+        st = s.get_state(0)
+        cdc_tail = np.frombuffer(st[512:640], np.int8).reshape(32, 4)
+        aeq_tail = np.frombuffer(st[640:704], np.int8).reshape(16, 4)
+        assert np.array_equal(cdc_tail, ch.samples[off - 32:off]), k
+        assert np.array_equal(aeq_tail, a_ref[off // 2 - 16:off // 2]), k
+    assert np.array_equal(out[:off // 2].cpu().numpy(), outr[:off // 2])
+    s.close()
+    fnt.fnt_check()
+
+
+def test_session_reregister_right_after_submit(torch_dev):
+    """Registering a channel again waits for the ticks still running on it."""
+    torch, dev = torch_dev
+    ch = synth.gen_channel(16 * 48, 40.0, 22.0, seed=92)
+    x = to_dev(torch, dev, ch.samples)
+    cp, ap = fnt.cdc_params(ch.taps, ch.requant_shift), fnt.aeq_params(**synth.aeq_params_for(ch))
+    outr, _ = _oracle_stream(ch)
+    s = fnt.Session(max_channels=1, hbm_budget_bytes=16 << 20, chunk_blocks=48)
+    for rep in range(3):
+        s.add_channel(0, cp, ap)
+        out = torch.zeros((ch.n // 2, 4), dtype=torch.int16, device=dev)
+        note(f"session re-register rep {rep}")
+        tk = s.submit(0, x, out)
+        # the request leaves the queue when its last block is placed in a tick;
+        # from then on add_channel succeeds, after that tick has retired
+        while True:
+            try:
+                s.add_channel(0, cp, ap)
+                break
+            except fnt.FntError as e:
+                assert e.code == fnt.FNT_E_STATE
+        assert s.poll(tk)
+        assert np.array_equal(out.cpu().numpy(), outr), rep
+    s.close()
+    fnt.fnt_check()
+
+
+def test_session_cancel_and_destroy_in_flight(torch_dev):
+    """Cancelled requests never run; closing a session with work queued drains it."""
+    torch, dev = torch_dev
+    ch = synth.gen_channel(16 * 64, 50.0, 22.0, seed=93)
+    x = to_dev(torch, dev, ch.samples)
+    cp, ap = fnt.cdc_params(ch.taps, ch.requant_shift), fnt.aeq_params(**synth.aeq_params_for(ch))
+    outr, _ = _oracle_stream(ch)
+    s = fnt.Session(max_channels=1, hbm_budget_bytes=16 << 20, chunk_blocks=2)
+    s.add_channel(0, cp, ap)
+    out = torch.full((ch.n // 2, 4), 777, dtype=torch.int16, device=dev)
+    segs = [(i * 256, 256) for i in range(ch.n // 256)]           # 8 blocks each
+    note("session cancel: submit segments")
+    tks = [s.submit(0, x[o:o + n], out[o // 2:(o + n) // 2]) for o, n in segs]
+    # the last segments are still queued behind the first: cancel them
+    cancelled = []
+    for tk in reversed(tks[2:]):
+        try:
+            s.cancel(tk)
+            cancelled.append(tk)
+        except fnt.FntError as e:
+            assert e.code == fnt.FNT_E_STATE            # already started
+            break
+    assert cancelled, "nothing was left to cancel"
+    with pytest.raises(fnt.FntError) as e:
+        s.cancel(cancelled[0])                          # not queued any more
+    assert e.value.code == fnt.FNT_E_STATE
+    with pytest.raises(fnt.FntError) as e:
+        s.cancel(10 ** 9)
+    assert e.value.code == fnt.FNT_E_STATE
+    s.drain()
+    ran = [tk for tk in tks if tk not in cancelled]
+    assert all(s.poll(tk) for tk in tks)
+    done_inst = 256 * len(ran)                       # the requests that ran form a prefix
+    o = out.cpu().numpy()
+    assert np.array_equal(o[:done_inst // 2], outr[:done_inst // 2])
+    assert (o[done_inst // 2:] == 777).all()         # cancelled outputs never written
+    st = s.stats()
+    assert st["cancelled"] == len(cancelled) and st["completed"] == len(ran)
+    # destroy with requests still queued: close drains them first
+    s2 = fnt.Session(max_channels=1, hbm_budget_bytes=16 << 20, chunk_blocks=1)
+    s2.add_channel(0, cp, ap)
+    out2 = torch.zeros((ch.n // 2, 4), dtype=torch.int16, device=dev)
+    note("session destroy with requests in flight")
+    for o0, n in segs:
+        s2.submit(0, x[o0:o0 + n], out2[o0 // 2:(o0 + n) // 2])
+    s2.close()
+    torch.cuda.synchronize()
+    assert np.array_equal(out2.cpu().numpy(), outr)
+    s.close()
+    fnt.fnt_check()
+
+
 def test_session_alone_equals_in_mix(torch_dev):
     torch, dev = torch_dev
     chans = _session_channels(12, 60, seed=5)
