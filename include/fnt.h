@@ -65,7 +65,9 @@ int fnt_version(void);
 
 /* Synchronise `stream`, then report and clear the per-device range flag of the
  * current device: FNT_E_RANGE if any kernel launched since the previous check
- * saw an out-of-range input, else FNT_OK. */
+ * saw an out-of-range input; FNT_E_DEVICE if a bounded wait inside a fused
+ * launch (fnt_cdc_aeq, fused plans) gave up, which a correct launch never does
+ * (that launch's outputs are then unspecified); else FNT_OK. */
 int fnt_check(void *stream);
 
 /* ------------------------------------------------------------------------
@@ -150,10 +152,14 @@ int fnt_cdc(const int8_t *in, uint64_t n, const fnt_cdc_params *p, int32_t *out_
 int fnt_aeq(const int8_t *in_1sps, uint64_t m, int16_t *taps, const fnt_aeq_params *p,
             int16_t *out, void *stream);
 
-/* The receiver chain on one channel: fnt_cdc (to 1 sample/symbol) then fnt_aeq.
- * out int16[M][4] with M = (n + 1 - decim_phase) / 2.  The 1-sample/symbol
- * stream lives in a stream-ordered scratch of M*4 bytes (hipMallocAsync and
- * hipFreeAsync on `stream`). */
+/* The receiver chain on one channel (experimental section: CDC, resampling to
+ * 1 sample/symbol, then the AEQ; Figs. 2 and 3): the same results as fnt_cdc to
+ * the 1-sample/symbol stream followed by fnt_aeq, in ONE kernel launch that
+ * allocates nothing.  Inside the launch one wave computes the CDC 64 blocks at a
+ * time into a ring in on-chip memory (LDS) while the AEQ chain consumes it, so
+ * the 1-sample/symbol stream never goes to device memory.
+ *   in   int8[n][4] device;  taps as for fnt_aeq (in/out);
+ *   out  int16[M][4] device with M = (n + 1 - decim_phase) / 2. */
 int fnt_cdc_aeq(const int8_t *in, uint64_t n, const fnt_cdc_params *cp, int16_t *taps,
                 const fnt_aeq_params *ap, int16_t *out, void *stream);
 
@@ -201,6 +207,11 @@ typedef struct fnt_plan_info {
     int32_t top_form;      /* AEQ form of the first level */
     double tune_run_ms;    /* whole-run time (CDC + AEQ) of the chosen schedule during autotune,
                               ms (0 if none) */
+    int32_t fused_lpt;     /* 0: the staged / lead schedule above; 4, 8, 16: every run is one launch
+                              of the fused kernel with that many AEQ lanes per transform (see
+                              fnt_plan_set_fused) */
+    int32_t fused_grid;    /* workgroups of the fused launch (0 when not fused) */
+    uint64_t fused_prio_channels;  /* longest channels at raised wave priority in the fused launch */
 } fnt_plan_info;
 
 typedef struct fnt_plan fnt_plan;
@@ -270,7 +281,9 @@ int fnt_plan_set_cdc_schedule(fnt_plan *plan, int waves_per_group, int blocks_pe
  * or the long chains' form for -1; at raised wave priority) then starts on the
  * plan's side stream while the CDC and the AEQ of the other channels run on the
  * launch stream, so the longest serial chains do not wait for the whole batch's
- * CDC.  With 0 < top_channels < lead_channels the lead has two levels: the
+ * CDC.  lead_form 6: the lead channels' CDC and AEQ run together as one launch
+ * of the fused kernel (see fnt_plan_set_fused; one wave per half) on the side
+ * stream from the start, with no CDC launch of their own (no first level).  With 0 < top_channels < lead_channels the lead has two levels: the
  * `top_channels` longest run in form `top_form` (-1 as above).  If that form
  * pairs with the lead's in one split launch (see fnt_plan_set_aeq_split; e.g.
  * 2 with 5) they are the first workgroups of the lead's own launch; otherwise
@@ -291,6 +304,20 @@ int fnt_plan_set_cdc_schedule(fnt_plan *plan, int waves_per_group, int blocks_pe
 int fnt_plan_set_lead(fnt_plan *plan, uint64_t lead_channels, int lead_form, uint64_t top_channels,
                       int top_form);
 
+/* Fused persistent schedule: every fnt_plan_run is ONE launch of the fused
+ * kernel (the receiver chain of the experimental section, Figs. 2 and 3):
+ * each workgroup takes channels longest chain first from a work counter; per
+ * channel one wave computes the CDC 64 blocks at a time into a ring in LDS
+ * while the AEQ waves consume it, so the 1-sample/symbol stream never goes to
+ * device memory and the longest chains start at once.  lpt = 4, 8 or 16 AEQ
+ * lanes per transform (one, two or four waves per polarisation half; 4 suits
+ * large batches, 16 the shortest serial latency), 0 switches the fused
+ * schedule off (the staged / lead schedule applies again).  The
+ * `prio_channels` longest channels run at raised wave priority.  Any other
+ * schedule setter (fnt_plan_set_aeq_waves, _aeq_split, _lead, the variants)
+ * switches it off.  Results never depend on it.  FNT_E_INVAL for another lpt. */
+int fnt_plan_set_fused(fnt_plan *plan, int lpt, uint64_t prio_channels);
+
 typedef struct fnt_plan_timing {
     float step_ms;          /* first launch to the end of the last, on the launch stream */
     float cdc_ms;           /* the CDC launches, back to back on the launch stream */
@@ -302,7 +329,7 @@ typedef struct fnt_plan_timing {
     uint64_t aeq_lead_blocks;  /* 16-symbol AEQ blocks of the channels aeq_lead_ms covers */
     float aeq_top_ms;       /* the first level's AEQ launch on the third stream (0 if none, or
                                if it runs inside the lead's launch) */
-    int32_t reserved;
+    int32_t fused;          /* 1: the run was one fused launch (aeq_ms is that launch, cdc_ms 0) */
     uint64_t aeq_top_blocks;   /* 16-symbol AEQ blocks of the first level's own launch */
 } fnt_plan_timing;
 /* Run every channel once, as fnt_plan_run does, but launch the sequence

@@ -160,6 +160,8 @@ int fnt_check(void *stream) {
     if (h) {
         e = hipMemset(d, 0, sizeof(int));
         if (e != hipSuccess) return hip_fail(e, "hipMemset(range flag)");
+        if (h & kFlagStall)
+            return fail(FNT_E_DEVICE, "a bounded wait of a fused launch gave up (flags 0x%x)", h);
         return fail(FNT_E_RANGE, "input value outside its declared width (flags 0x%x)", h);
     }
     return FNT_OK;
@@ -234,6 +236,9 @@ int fnt_aeq(const int8_t *in_1sps, uint64_t m, int16_t *taps, const fnt_aeq_para
     return FNT_OK;
 }
 
+// AEQ lanes per transform of the single-stream fused launch.
+constexpr int kSingleLpt = 16;
+
 int fnt_cdc_aeq(const int8_t *in, uint64_t n, const fnt_cdc_params *cp, int16_t *taps,
                 const fnt_aeq_params *ap, int16_t *out, void *stream) {
     int rc = validate_cdc(cp);
@@ -241,33 +246,20 @@ int fnt_cdc_aeq(const int8_t *in, uint64_t n, const fnt_cdc_params *cp, int16_t 
     if ((rc = validate_aeq(ap))) return rc;
     if (!taps) return fail(FNT_E_INVAL, "fnt_cdc_aeq: NULL taps");
     const uint64_t M = n_symbols(n, cp->decim_phase);
-    if (n > 0 && (!in || !out)) return fail(FNT_E_INVAL, "fnt_cdc_aeq: NULL buffer");
+    if ((n > 0 && !in) || (M > 0 && !out)) return fail(FNT_E_INVAL, "fnt_cdc_aeq: NULL buffer");
     if (!aligned(in, 4) || !aligned(out, 8) || !aligned(taps, 2))
         return fail(FNT_E_INVAL, "fnt_cdc_aeq: misaligned buffer");
     int *err = nullptr;
     if ((rc = device_err_flag(&err))) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    int8_t *abuf = nullptr;
-    if (M > 0) {
-        hipError_t e = hipMallocAsync((void **)&abuf, M * 4, s);
-        if (e != hipSuccess) return fail(FNT_E_NOMEM, "hipMallocAsync(%llu): %s",
-                                         (unsigned long long)(M * 4), hipGetErrorString(e));
-        CdcItem ci;
-        fill_cdc_item(ci, in, n, cp);
-        ci.a_out = abuf;
-        int wpg, bpw;
-        default_cdc_schedule(cdc_blocks(n), &wpg, &bpw);
-        e = run_cdc(nullptr, 0, ci, cdc_blocks(n), cdc_chunks(n), wpg, bpw, false, err, s);
-        if (e != hipSuccess) {
-            (void)hipFreeAsync(abuf, s);
-            return hip_fail(e, "fnt_cdc_aeq: cdc launch");
-        }
-    }
+    // one launch of the fused kernel with one workgroup: a producer wave runs
+    // the CDC chunk by chunk into LDS while four waves per polarisation half run
+    // the AEQ chain (the shortest serial latency per block on an idle GPU)
+    CdcItem ci;
+    fill_cdc_item(ci, in, n, cp);
     AeqItem ai;
-    fill_aeq_item(ai, abuf, M, taps, ap, out);
-    hipError_t e = launch_aeq(nullptr, 0, ai, 0, 4, err, s);
-    if (abuf) (void)hipFreeAsync(abuf, s);
-    if (e != hipSuccess) return hip_fail(e, "fnt_cdc_aeq: aeq launch");
+    fill_aeq_item(ai, nullptr, M, taps, ap, out);
+    hipError_t e = launch_fused(nullptr, nullptr, 1, ci, ai, kSingleLpt, nullptr, 1, 1, err, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "fnt_cdc_aeq: launch");
     return FNT_OK;
 }
 
@@ -306,6 +298,13 @@ struct fnt_plan {
     bool use_graph = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // fused persistent CDC + AEQ (one launch per run; fused_lpt = 0: off): AEQ
+    // lanes per transform, channels at raised priority, workgroups, and the two
+    // work-counter words the kernel takes channels from (zero between launches)
+    int fused_lpt = 0;
+    size_t fused_prio = 0;
+    unsigned fused_grid = 0;
+    uint32_t *queue = nullptr;
 };
 
 // The CDC of the table `tab` (nitems items whose block0 / chunk0 start at 0).
@@ -338,22 +337,32 @@ static hipError_t plan_aeq_range(fnt_plan *p, int first, int nl, int count, hipS
 
 // Lead channels in effect for the plan's current schedule (0: none), and the
 // first level's channels among them (0: one level).
-static size_t plan_top(const fnt_plan *p) { return p->n_top > 0 && p->n_top < p->n_lead ? p->n_top : 0; }
+// Lead form kFusedLead: the lead channels run as one launch of the fused CDC +
+// AEQ kernel (one wave per half) on the side stream, with no CDC of their own
+// before it, so their chains start at once.
+constexpr int kFusedLead = 6;
+
+static size_t plan_top(const fnt_plan *p) {
+    if (p->variant == 0 && p->lead_form == kFusedLead) return 0;   // a fused lead has no first level
+    return p->n_top > 0 && p->n_top < p->n_lead ? p->n_top : 0;
+}
 
 // AEQ forms of the lead after its first level, and of the first level
 static int lead_form_of(const fnt_plan *p) { return p->lead_form >= 0 ? p->lead_form : p->wpp_long; }
+static bool lead_is_fused(const fnt_plan *p) { return p->variant == 0 && lead_form_of(p) == kFusedLead; }
 static int top_form_of(const fnt_plan *p) { return p->top_form >= 0 ? p->top_form : p->wpp_long; }
 
 // A first level whose form pairs with the lead's in one split launch runs inside
 // the lead's launch (no CDC segment, stream or launch of its own).
 static bool plan_top_fused(const fnt_plan *p) {
-    return plan_top(p) > 0 && p->variant == 0 && aeq_split_fusable(top_form_of(p), lead_form_of(p));
+    return plan_top(p) > 0 && p->variant == 0 && !lead_is_fused(p) && aeq_split_fusable(top_form_of(p), lead_form_of(p));
 }
 // The first level's own CDC segment (0 when there is none or it is fused).
 static size_t plan_cdc_top(const fnt_plan *p) { return plan_top_fused(p) ? 0 : plan_top(p); }
 
 static size_t plan_lead(const fnt_plan *p) {
     const size_t n = p->aeq_host.size();
+    if (p->fused_lpt) return 0;                        // the fused kernel runs every channel
     if (p->n_lead == 0 || p->n_lead >= n || p->seg_lead != p->n_lead ||
         p->seg_top != plan_cdc_top(p) || !p->cdc_seg_dev)
         return 0;
@@ -395,10 +404,27 @@ static int plan_launch_aeq(fnt_plan *p, hipStream_t s, hipStream_t side) {
 // Fork / join are events, which a graph capture turns into parallel branches.
 // `ev` (timing, direct launches only) receives start, CDC end, lead AEQ start,
 // lead AEQ end, AEQ end, done, first-level AEQ start and end.
+static unsigned plan_fused_grid(const fnt_plan *p, int lpt) {
+    const size_t n = p->aeq_host.size();
+    const int cap = fused_capacity(lpt);
+    return (unsigned)std::min<size_t>(n, cap > 0 ? (size_t)cap : 1024);
+}
+
 static int plan_launch(fnt_plan *p, hipStream_t s, hipStream_t side, hipStream_t side2,
                        hipEvent_t *ev = nullptr) {
     auto rec = [&](int i, hipStream_t st) { return ev ? hipEventRecord(ev[i], st) : hipSuccess; };
     hipError_t e = rec(0, s);
+    if (p->fused_lpt) {
+        // one launch: every channel's CDC and AEQ in the fused persistent kernel
+        if (e == hipSuccess) e = rec(1, s);
+        if (e == hipSuccess)
+            e = launch_fused(p->cdc_dev, p->aeq_dev, (int)p->aeq_host.size(), CdcItem{}, AeqItem{}, p->fused_lpt,
+                             p->queue, p->fused_grid, (int)std::min<size_t>(p->fused_prio, 1u << 26), p->err, s);
+        if (e == hipSuccess) e = rec(4, s);
+        if (e == hipSuccess) e = rec(5, s);
+        if (e != hipSuccess) return hip_fail(e, "plan: fused launch");
+        return FNT_OK;
+    }
     const size_t lead = plan_lead(p);
     const bool fused = lead && plan_top_fused(p);
     const size_t top = lead && !fused ? plan_top(p) : 0;      // a first level of its own
@@ -435,8 +461,21 @@ static int plan_launch(fnt_plan *p, hipStream_t s, hipStream_t side, hipStream_t
         if (e == hipSuccess) e = seg_cdc(0, top);
         if (e == hipSuccess) e = seg_aeq(0, top, tf, side2, p->fork2, 6);
     }
-    if (e == hipSuccess) e = seg_cdc(top, lead);
-    if (fused) {
+    if (lead_is_fused(p)) {
+        // the lead's CDC and AEQ in one fused launch on the side stream, at once
+        if (e == hipSuccess) e = hipEventRecord(p->fork, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(side, p->fork, 0);
+        if (e == hipSuccess) e = rec(2, side);
+        if (e == hipSuccess)
+            e = launch_fused(p->cdc_dev, p->aeq_dev, (int)lead, CdcItem{}, AeqItem{}, 4, p->queue,
+                             (unsigned)std::min<size_t>(lead, std::max(1, fused_capacity(4))), (int)lead, p->err,
+                             side);
+        if (e == hipSuccess) e = rec(3, side);
+    } else if (e == hipSuccess) {
+        e = seg_cdc(top, lead);
+    }
+    if (lead_is_fused(p)) {
+    } else if (fused) {
         // the first level's chains first in the lead's own split launch
         if (e == hipSuccess) e = hipEventRecord(p->fork, s);
         if (e == hipSuccess) e = hipStreamWaitEvent(side, p->fork, 0);
@@ -535,7 +574,7 @@ static int plan_capture(fnt_plan *p, hipStream_t s) {
     return FNT_OK;
 }
 
-constexpr int kTuneVersion = 8;
+constexpr int kTuneVersion = 9;
 
 static std::string tune_key(const fnt_plan *p) {
     // length histogram (log2 buckets of instants) + channel count + variant
@@ -559,7 +598,7 @@ static std::string tune_key(const fnt_plan *p) {
 // The last entry for `key`; the values are range-checked by the caller.
 static bool tune_cache_lookup(const char *path, const std::string &key, int *wpg, int *bpw, int *wpp,
                               int *wpp_long, long long *n_long, long long *n_lead, int *lead_form,
-                              long long *n_top, int *top_form) {
+                              long long *n_top, int *top_form, int *fused_lpt, long long *fused_prio) {
     if (!path) return false;
     std::ifstream f(path);
     std::string line;
@@ -579,9 +618,13 @@ static bool tune_cache_lookup(const char *path, const std::string &key, int *wpg
         size_t pl = line.find("\"wpp_long\": "), pn = line.find("\"n_long\": "),
                pd = line.find("\"n_lead\": "), pf = line.find("\"lead_form\": "),
                pt = line.find("\"n_top\": "), ptf = line.find("\"top_form\": ");
+        size_t pfl = line.find("\"fused_lpt\": "), pfp = line.find("\"fused_prio\": ");
         if (pl == std::string::npos || pn == std::string::npos || pd == std::string::npos ||
-            pf == std::string::npos || pt == std::string::npos || ptf == std::string::npos)
+            pf == std::string::npos || pt == std::string::npos || ptf == std::string::npos ||
+            pfl == std::string::npos || pfp == std::string::npos)
             continue;
+        *fused_lpt = std::atoi(line.c_str() + pfl + 13);
+        *fused_prio = std::atoll(line.c_str() + pfp + 14);
         *wpg = w;
         *bpw = bb;
         *wpp = pp;
@@ -598,13 +641,13 @@ static bool tune_cache_lookup(const char *path, const std::string &key, int *wpg
 
 static void tune_cache_store(const char *path, const std::string &key, int wpg, int bpw, int wpp,
                              int wpp_long, long long n_long, long long n_lead, int lead_form, long long n_top,
-                             int top_form, double ms) {
+                             int top_form, int fused_lpt, long long fused_prio, double ms) {
     if (!path) return;
     std::ofstream f(path, std::ios::app);
     f << "{\"key\": \"" << key << "\", \"wpg\": " << wpg << ", \"bpw\": " << bpw << ", \"wpp\": " << wpp
       << ", \"wpp_long\": " << wpp_long << ", \"n_long\": " << n_long << ", \"n_lead\": " << n_lead
       << ", \"lead_form\": " << lead_form << ", \"n_top\": " << n_top << ", \"top_form\": " << top_form
-      << ", \"ms\": " << ms << "}\n";
+      << ", \"fused_lpt\": " << fused_lpt << ", \"fused_prio\": " << fused_prio << ", \"ms\": " << ms << "}\n";
 }
 
 // Default AEQ schedule: with few channels the chip is idle, so spread each
@@ -620,12 +663,17 @@ static int default_wpp(size_t nch) { return nch >= 512 ? 3 : (nch >= 128 ? 2 : 4
 
 static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
     std::string key = tune_key(p);
-    int w, b, q, ql, lf, tf;
-    long long nl, nd, nt;
-    if (tune_cache_lookup(cache, key, &w, &b, &q, &ql, &nl, &nd, &lf, &nt, &tf) && (w == 1 || w == 2 || w == 4) &&
+    int w, b, q, ql, lf, tf, fl;
+    long long nl, nd, nt, fp;
+    if (tune_cache_lookup(cache, key, &w, &b, &q, &ql, &nl, &nd, &lf, &nt, &tf, &fl, &fp) &&
+        (w == 1 || w == 2 || w == 4) &&
         b >= 0 && b <= 1024 && valid_form(q) && valid_form(ql) && nl >= 0 && nd >= 0 &&
-        (size_t)nd < std::max<size_t>(1, p->aeq_host.size()) && (lf == -1 || valid_form(lf)) && nt >= 0 &&
-        (nt == 0 || nt < nd) && (tf == -1 || valid_form(tf))) {
+        (size_t)nd < std::max<size_t>(1, p->aeq_host.size()) && (lf == -1 || lf == kFusedLead || valid_form(lf)) && nt >= 0 &&
+        (nt == 0 || nt < nd) && (tf == -1 || valid_form(tf)) && (fl == 0 || fl == 4 || fl == 8 || fl == 16) &&
+        fp >= 0) {
+        p->fused_lpt = fl;
+        p->fused_prio = (size_t)fp;
+        if (fl) p->fused_grid = plan_fused_grid(p, fl);
         p->wpg = w;
         p->bpw = b;
         p->wpp = q;
@@ -676,8 +724,8 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
     AeqItem *tdev = nullptr;
     double best_aeq = 1e30;
     int bq = p->wpp, bql = p->wpp_long;
-    size_t bnl = p->n_long, bnd = 0, btop = 0;
-    int blf = -1, btf = -1;
+    size_t bnl = p->n_long, bnd = 0, btop = 0, bfp = 0;
+    int blf = -1, btf = -1, bfl = 0;
     if (p->variant == 0 && hipMalloc(&tscratch, nch * 256 * sizeof(int16_t)) == hipSuccess &&
         hipMalloc(&tdev, nch * sizeof(AeqItem)) == hipSuccess) {
         std::vector<AeqItem> tab = p->aeq_host;
@@ -790,10 +838,10 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
             // halves in a workgroup); following latency chains: the sweep's
             // choice, two lanes per transform, or the pol forms; the rest: one
             // lane or two lanes per transform, or one wave per half
-            std::vector<int> lfs = {1, 5, 2}, qls = {bql}, qs = {0, 3, 1};
+            std::vector<int> lfs = {1, 5, 2, kFusedLead}, qls = {bql}, qs = {0, 3, 1};
             for (int f : {3, 1, 5})
                 if (f != bql) qls.push_back(f);
-            for (size_t lead : {256, 512, 1024, 1536})
+            for (size_t lead : {256, 512, 1024, 1536, 2048})
                 for (size_t extra : {0, 512, 1024, 1536})
                     for (int q : qs)
                         for (int lf : lfs)
@@ -855,6 +903,46 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
             blf = best.lf;
             btop = best.top;
             btf = best.tf;
+            // the fused persistent kernel (one launch, the 1-sps stream kept in LDS):
+            // one wave per half for any batch; two or four waves per half only when
+            // every channel is resident at once; channels at raised priority from
+            // none to the first 2048.  One pass, then the median of three for the
+            // best two, against the staged or lead schedule's median
+            {
+                struct FCand { int lpt; size_t prio; double ms; };
+                std::vector<FCand> fc;
+                for (int lpt : {4, 8, 16}) {
+                    const int cap = fused_capacity(lpt);
+                    if (cap <= 0 || (lpt != 4 && nch > (size_t)cap)) continue;
+                    for (size_t prio : {0, 256, 512, 1024, 2048})
+                        if (prio == 0 || prio < nch) fc.push_back({lpt, prio, 0});
+                }
+                auto time_fused = [&](const FCand &c) {
+                    p->fused_lpt = c.lpt;
+                    p->fused_prio = c.prio;
+                    p->fused_grid = plan_fused_grid(p, c.lpt);
+                    double ms = time_it([&] { return plan_launch(p, s, p->side, p->side2) ? hipErrorUnknown : hipSuccess; });
+                    if (tlog.is_open())
+                        tlog << "fused lpt " << c.lpt << " prio " << c.prio << " grid " << p->fused_grid << " ms " << ms
+                             << "\n";
+                    return ms;
+                };
+                for (FCand &c : fc) c.ms = time_fused(c);
+                std::sort(fc.begin(), fc.end(), [](const FCand &x, const FCand &y) { return x.ms < y.ms; });
+                FCand fbest{0, 0, 1e30};
+                for (size_t i = 0; i < fc.size() && i < 2; ++i) {
+                    double r[3];
+                    for (double &v : r) v = time_fused(fc[i]);
+                    std::sort(r, r + 3);
+                    if (r[1] < fbest.ms) fbest = {fc[i].lpt, fc[i].prio, r[1]};
+                }
+                p->fused_lpt = 0;
+                if (fbest.lpt && fbest.ms < p->info.tune_run_ms) {
+                    bfl = fbest.lpt;
+                    bfp = fbest.prio;
+                    p->info.tune_run_ms = fbest.ms;
+                }
+            }
             p->n_lead = p->n_top = 0;
             p->lead_form = p->top_form = -1;
             p->seg_lead = p->seg_top = 0;
@@ -874,9 +962,12 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
     p->lead_form = blf;
     p->n_top = btop;
     p->top_form = btf;
+    p->fused_lpt = bfl;
+    p->fused_prio = bfp;
+    if (bfl) p->fused_grid = plan_fused_grid(p, bfl);
     p->info.tune_ms = best_aeq < 1e29 ? best_aeq : best_cdc;
-    tune_cache_store(cache, key, bw, bb, bq, bql, (long long)bnl, (long long)bnd, blf, (long long)btop, btf,
-                     p->info.tune_ms);
+    tune_cache_store(cache, key, bw, bb, bq, bql, (long long)bnl, (long long)bnd, blf, (long long)btop, btf, bfl,
+                     (long long)bfp, p->info.tune_ms);
     return FNT_OK;
 }
 
@@ -913,7 +1004,8 @@ int fnt_plan_create(fnt_plan **out, const fnt_channel_desc *ch, size_t nch, cons
             delete p;
             return fail(rc, "plan: channel %zu: %s", i, fnt_last_error());
         }
-        if (!d.taps || (d.n > 0 && (!d.in || !d.out)) || !aligned(d.in, 4) || !aligned(d.out, 8) ||
+        if (!d.taps || (d.n > 0 && !d.in) || (n_symbols(d.n, d.cdc.decim_phase) > 0 && !d.out) ||
+            !aligned(d.in, 4) || !aligned(d.out, 8) ||
             !aligned(d.taps, 2)) {
             delete p;
             return fail(FNT_E_INVAL, "plan: channel %zu: NULL or misaligned buffer", i);
@@ -971,6 +1063,18 @@ int fnt_plan_create(fnt_plan **out, const fnt_channel_desc *ch, size_t nch, cons
         if (e != hipSuccess) {
             fnt_plan_destroy(p);
             return hip_fail(e, "plan: upload tables");
+        }
+    }
+    if (nch > 0) {
+        hipError_t eq = hipMalloc(&p->queue, 2 * sizeof(uint32_t));
+        if (eq != hipSuccess) {
+            fnt_plan_destroy(p);
+            return fail(FNT_E_NOMEM, "plan: work counter: %s", hipGetErrorString(eq));
+        }
+        eq = hipMemset(p->queue, 0, 2 * sizeof(uint32_t));
+        if (eq != hipSuccess) {
+            fnt_plan_destroy(p);
+            return hip_fail(eq, "plan: clear work counter");
         }
     }
     default_cdc_schedule(blocks, &p->wpg, &p->bpw);
@@ -1057,12 +1161,28 @@ int fnt_plan_get_info(const fnt_plan *p, fnt_plan_info *info) {
     info->lead_form = p->lead_form >= 0 ? p->lead_form : p->wpp_long;
     info->top_channels = lead ? (int32_t)plan_top(p) : 0;
     info->top_form = p->top_form >= 0 ? p->top_form : p->wpp_long;
+    info->fused_lpt = p->fused_lpt;
+    info->fused_grid = p->fused_lpt ? (int32_t)p->fused_grid : 0;
+    info->fused_prio_channels = p->fused_lpt ? std::min(p->fused_prio, p->aeq_host.size()) : 0;
+    return FNT_OK;
+}
+
+int fnt_plan_set_fused(fnt_plan *p, int lpt, uint64_t prio_channels) {
+    if (!p) return fail(FNT_E_INVAL, "plan: NULL");
+    if (lpt != 0 && lpt != 4 && lpt != 8 && lpt != 16)
+        return fail(FNT_E_INVAL, "plan: fused lanes per transform %d (0, 4, 8 or 16)", lpt);
+    p->fused_lpt = lpt;
+    p->fused_prio = (size_t)std::min<uint64_t>(prio_channels, p->aeq_host.size());
+    p->fused_grid = lpt ? plan_fused_grid(p, lpt) : 0;
+    if (p->exec) return plan_capture(p, nullptr);
     return FNT_OK;
 }
 
 int fnt_plan_set_lead(fnt_plan *p, uint64_t lead, int lead_form, uint64_t top, int top_form) {
     if (!p) return fail(FNT_E_INVAL, "plan: NULL");
-    if (lead_form != -1 && !valid_form(lead_form)) return fail(FNT_E_INVAL, "plan: lead form %d", lead_form);
+    p->fused_lpt = 0;                                // another schedule: the fused kernel is off
+    if (lead_form != -1 && lead_form != kFusedLead && !valid_form(lead_form))
+        return fail(FNT_E_INVAL, "plan: lead form %d", lead_form);
     if (top_form != -1 && !valid_form(top_form)) return fail(FNT_E_INVAL, "plan: first-level form %d", top_form);
     const size_t n = p->aeq_host.size();
     const size_t l = lead < n ? (size_t)lead : 0;
@@ -1108,11 +1228,13 @@ int fnt_plan_run_timed(fnt_plan *p, fnt_plan_timing *t, void *stream) {
     t->aeq_top_blocks = aeq_blocks_of(p, 0, top);
     t->aeq_lead_blocks = aeq_blocks_of(p, top, lead);
     t->aeq_blocks = aeq_blocks_of(p, lead, p->aeq_host.size());
+    t->fused = p->fused_lpt ? 1 : 0;
     return FNT_OK;
 }
 
 int fnt_plan_set_aeq_variant(fnt_plan *p, int variant) {
     if (!p) return fail(FNT_E_INVAL, "plan: NULL");
+    p->fused_lpt = 0;                                // another schedule: the fused kernel is off
     if (variant < 0 || variant > 2) return fail(FNT_E_INVAL, "plan: variant %d", variant);
     p->variant = variant;
     if (p->exec) return plan_capture(p, nullptr);
@@ -1121,6 +1243,7 @@ int fnt_plan_set_aeq_variant(fnt_plan *p, int variant) {
 
 int fnt_plan_set_cdc_variant(fnt_plan *p, int variant) {
     if (!p) return fail(FNT_E_INVAL, "plan: NULL");
+    p->fused_lpt = 0;                                // another schedule: the fused kernel is off
     if (variant != 0 && variant != 1) return fail(FNT_E_INVAL, "plan: CDC variant %d", variant);
     p->cdc_variant = variant;
     if (p->exec) return plan_capture(p, nullptr);
@@ -1129,6 +1252,7 @@ int fnt_plan_set_cdc_variant(fnt_plan *p, int variant) {
 
 int fnt_plan_set_aeq_waves(fnt_plan *p, int wpp) {
     if (!p) return fail(FNT_E_INVAL, "plan: NULL");
+    p->fused_lpt = 0;                                // another schedule: the fused kernel is off
     if (!valid_form(wpp)) return fail(FNT_E_INVAL, "plan: AEQ form %d", wpp);
     p->wpp = wpp;
     p->n_long = 0;
@@ -1139,6 +1263,7 @@ int fnt_plan_set_aeq_waves(fnt_plan *p, int wpp) {
 
 int fnt_plan_set_aeq_split(fnt_plan *p, uint64_t long_channels, int wpp_long, int wpp) {
     if (!p) return fail(FNT_E_INVAL, "plan: NULL");
+    p->fused_lpt = 0;                                // another schedule: the fused kernel is off
     if (!valid_form(wpp_long) || !valid_form(wpp))
         return fail(FNT_E_INVAL, "plan: waves per half %d / %d", wpp_long, wpp);
     p->n_long = (size_t)std::min<uint64_t>(long_channels, p->aeq_host.size());
@@ -1171,6 +1296,7 @@ int fnt_plan_destroy(fnt_plan *p) {
     if (p->cdc_dev) (void)hipFree(p->cdc_dev);
     if (p->aeq_dev) (void)hipFree(p->aeq_dev);
     if (p->abuf) (void)hipFree(p->abuf);
+    if (p->queue) (void)hipFree(p->queue);
     delete p;
     return FNT_OK;
 }

@@ -213,6 +213,8 @@ __device__ __forceinline__ __attribute__((address_space(1))) T *gptr(T *p) {
 }
 
 // Range-violation bits latched into the per-device flag.
-enum : int { RANGE_SAMPLE = 1, RANGE_TAP = 2, RANGE_RESIDUE = 4, RANGE_SYMBOL = 8 };
+// RANGE_STALL is not a range violation: a bounded wait of the fused kernel gave
+// up (its outputs are then unspecified).
+enum : int { RANGE_SAMPLE = 1, RANGE_TAP = 2, RANGE_RESIDUE = 4, RANGE_SYMBOL = 8, RANGE_STALL = 16 };
 
 }  // namespace fntd

@@ -54,6 +54,12 @@ __host__ __device__ inline uint64_t n_symbols(uint64_t n, int phase) {
     return n + 1 > (uint64_t)phase ? (n + 1 - (uint64_t)phase) / 2 : 0;
 }
 
+// Bit of the per-device error flag latched when a bounded wait of the fused
+// kernel gave up (the other bits are range violations).
+constexpr int kFlagStall = 16;
+// Polls a fused-kernel wait makes before it gives up (seconds of waiting).
+constexpr uint32_t kFusedSpinLimit = 1u << 22;
+
 // Launchers (fnt_kernels.hip).  `items` is a device table or nullptr, in which
 // case `single` is used (passed by value in the kernel arguments).
 hipError_t launch_transform(const uint32_t *x, uint32_t *X, size_t batch, int t, int log2n,
@@ -79,6 +85,20 @@ bool aeq_split_fusable(int form_long, int form_rest);
 // split by output polarisation with that many waves per half, 5 split by output
 // polarisation with both halves in one workgroup); 1: direct time-domain
 // comparator; 2: Fermat-domain, one wave per channel.
+// Fused persistent CDC + AEQ in one launch (cdc_aeq_fused_kernel), AEQ in the
+// polarisation-split form with lpt lanes per transform (4, 8 or 16: one, two or
+// four waves per half) and one CDC producer wave per workgroup.  Tables
+// citems / aitems: the same channels in the same order (longest chains first),
+// aitems[i].m = n_symbols(citems[i].n, phase); or both nullptr and the single
+// items cs / as.  With queue (two device words, zero before the first launch;
+// every launch leaves them zero) grid <= channels workgroups take channels in
+// table order; without, grid = channels and workgroup w runs channel w.
+// Channels [0, nprio) run at raised wave priority.
+hipError_t launch_fused(const CdcItem *citems, const AeqItem *aitems, int n, const CdcItem &cs,
+                        const AeqItem &as, int lpt, uint32_t *queue, unsigned grid, int nprio, int *err,
+                        hipStream_t s, uint32_t spin_limit = kFusedSpinLimit);
+// Workgroups of the fused kernel resident at once on the current device (0 on error).
+int fused_capacity(int lpt);
 hipError_t launch_aeq(const AeqItem *items, int nitems, const AeqItem &single, int variant,
                       int waves_per_pol, int *err, hipStream_t s,
                       bool high_priority = false);

@@ -15,6 +15,10 @@
 //    block tap update, in forms from throughput (one transform per lane) to
 //    latency (a channel's polarisation halves over several waves), and a split
 //    launch of two forms.
+//  * cdc_aeq_fused_kernel : the whole chain (CDC, resampling, AEQ) in one
+//    persistent launch: per channel a producer wave runs the lane-per-block CDC
+//    64 blocks at a time into a ring in LDS and the polarisation-split AEQ waves
+//    consume it; workgroups take channels longest first from a work counter.
 //  * aeq_fnt_kernel       : the same AEQ with one wave64 per channel.
 //  * cdc_direct_kernel, aeq_direct_kernel : the same CDC and AEQ by time-domain
 //    integer dot products, comparators with bit-identical output.
@@ -547,53 +551,39 @@ __device__ __forceinline__ int32_t requant5(int32_t z, int s) {
     return r < -16 ? -16 : (r > 15 ? 15 : r);
 }
 
-template <int WPG>
-__global__ __launch_bounds__(64 * WPG) void cdc_lane_kernel(const CdcItem *items, int nitems,
-                                                            CdcItem single, uint64_t total_chunks,
-                                                            int *err) {
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    __shared__ int32_t hs_s[WPG][2][64];               // per wave: H+, H- by register index
-    __shared__ __align__(16) uint32_t edge_s[WPG][2][64];  // per wave: windows of edge blocks
-    int32_t(*hs)[64] = hs_s[wv];
-
-    const uint64_t chunk = (uint64_t)blockIdx.x * WPG + wv;
-    if (chunk >= total_chunks) return;
-    int idx = 0;
-    if (items) {                                        // last item whose chunk range starts <= chunk
-        int lo = 0, hi = nitems - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (items[mid].chunk0 <= chunk) lo = mid; else hi = mid - 1;
-        }
-        idx = lo;
+// Tap spectra of item ip for the lane-per-block CDC, bin k = lane:
+// H+- = sum_n (h_r[n] +- 2^8 h_i[n]) alpha^(n k), into hs[0] / hs[1] at the
+// register index of bin k (LDS; one wave writes all 64 bins).
+__device__ __forceinline__ void cdc_lane_spectra(const CdcItem *ip, int lane, int32_t (*hs)[64]) {
+    const int ntaps = ip->ntaps < 32 ? ip->ntaps : 32;
+    const int8_t *tp = &ip->taps[0][0];
+    const int32_t ak = kAlphaPow.v[lane];
+    int32_t a = 1, sr = 0, si = 0;                      // |sums| < 32 * 32 * 2^16.6
+    for (int k = 0; k < ntaps; ++k) {
+        sr += (int32_t)tp[2 * k] * sext24(a);
+        si += (int32_t)tp[2 * k + 1] * sext24(a);
+        a = mulmod(a, ak);
     }
-    const CdcItem *ip = items ? &items[idx] : &single;
+    const int32_t r = fold16(sr), i8 = mul_pow2(si, 8);
+    const int reg = bitrev(lane, 6);
+    hs[0][reg] = r + i8;                               // |.| < 2^17.6
+    hs[1][reg] = r - i8;
+}
+
+// Overlap-save FNT-CDC of the blocks lb0 + lane of item ip, one whole block per
+// lane (hs: the item's tap spectra from cdc_lane_spectra; edge: 2 x 64 words of
+// LDS for the windows of edge blocks, private to the wave).  o[q] receives the
+// q-th 1-sample/symbol output of the lane's block as 4 packed 5-bit bytes
+// {XI, XQ, YI, YQ} (symbol 16 (lb0 + lane) + q).  Returns whether the lane's
+// block lies inside the item; lanes past its end compute on zeros.
+__device__ __forceinline__ bool cdc_lane_blocks(const CdcItem *ip, uint64_t lb0, int lane,
+                                                const int32_t (*hs)[64], uint32_t (*edge)[64],
+                                                int *err, uint32_t (&o)[16]) {
     const uint64_t n = ip->n;
     const uint64_t nb = fnti::cdc_blocks(n);
-    const uint64_t lb0 = (chunk - (items ? ip->chunk0 : 0)) * fnti::CDC_CHUNK;
-    if (lb0 >= nb) return;                              // a table that does not cover the chunk
-    const int ntaps = ip->ntaps < 32 ? ip->ntaps : 32;
     const int shift = ip->shift, phase = ip->phase;
     const int8_t *in = ip->in;
     const int8_t *hist = ip->hist;
-    int8_t *a_out = ip->a_out;
-
-    {   // tap spectra, bin k = lane: H+- = sum_n (h_r[n] +- 2^8 h_i[n]) alpha^(n k)
-        const int8_t *tp = &ip->taps[0][0];
-        const int32_t ak = kAlphaPow.v[lane];
-        int32_t a = 1, sr = 0, si = 0;                  // |sums| < 32 * 32 * 2^16.6
-        for (int k = 0; k < ntaps; ++k) {
-            sr += (int32_t)tp[2 * k] * sext24(a);
-            si += (int32_t)tp[2 * k + 1] * sext24(a);
-            a = mulmod(a, ak);
-        }
-        const int32_t r = fold16(sr), i8 = mul_pow2(si, 8);
-        const int reg = bitrev(lane, 6);
-        hs[0][reg] = r + i8;                           // |.| < 2^17.6
-        hs[1][reg] = r - i8;
-    }
-    wave_lds_sync();
 
     const uint64_t lb = lb0 + (uint64_t)lane;
     const bool active = lb < nb;                        // lanes past the channel's end idle
@@ -618,12 +608,12 @@ __global__ __launch_bounds__(64 * WPG) void cdc_lane_kernel(const CdcItem *items
             w = reinterpret_cast<const uint32_t *>(in)[i];
             if (lane >= 32) bad |= w ^ (w << 1);        // new word of block lb0 + L
         }
-        edge_s[wv][k][lane] = w;
+        edge[k][lane] = w;
     }
     wave_lds_sync();
     // this lane's 64 window words, through a flat pointer into global memory or LDS
     const uint32_t *wp = interior ? reinterpret_cast<const uint32_t *>(in) + i0
-                                  : &edge_s[wv][(active && lane == e1 && e1 != e0) ? 1 : 0][0];
+                                  : &edge[(active && lane == e1 && e1 != e0) ? 1 : 0][0];
     const bool vec = ((uintptr_t)in & 15u) == 0u;       // uniform: 16-byte loads possible
     if (interior) {                                     // range check of the 32 new words
         if (vec) {
@@ -638,12 +628,8 @@ __global__ __launch_bounds__(64 * WPG) void cdc_lane_kernel(const CdcItem *items
             for (int q = 32; q < 64; ++q) bad |= wp[q] ^ (wp[q] << 1);
         }
     }
-    const uint64_t M = fnti::n_symbols(n, phase);
-    const int64_t m0 = 16 * (int64_t)lb;                // first symbol of the block
-    uint32_t o[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) o[q] = 0u;
-
 #pragma unroll 1
     for (int pol = 0; pol < 2; ++pol) {
         int32_t ys[32], yd[32];
@@ -721,7 +707,41 @@ __global__ __launch_bounds__(64 * WPG) void cdc_lane_kernel(const CdcItem *items
         }
     }
     if ((bad & 0xE0E0E0E0u) != 0u) flag(err, RANGE_SAMPLE);
+    return active;
+}
+
+template <int WPG>
+__global__ __launch_bounds__(64 * WPG) void cdc_lane_kernel(const CdcItem *items, int nitems,
+                                                            CdcItem single, uint64_t total_chunks,
+                                                            int *err) {
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    __shared__ int32_t hs_s[WPG][2][64];               // per wave: H+, H- by register index
+    __shared__ __align__(16) uint32_t edge_s[WPG][2][64];  // per wave: windows of edge blocks
+
+    const uint64_t chunk = (uint64_t)blockIdx.x * WPG + wv;
+    if (chunk >= total_chunks) return;
+    int idx = 0;
+    if (items) {                                        // last item whose chunk range starts <= chunk
+        int lo = 0, hi = nitems - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (items[mid].chunk0 <= chunk) lo = mid; else hi = mid - 1;
+        }
+        idx = lo;
+    }
+    const CdcItem *ip = items ? &items[idx] : &single;
+    const uint64_t nb = fnti::cdc_blocks(ip->n);
+    const uint64_t lb0 = (chunk - (items ? ip->chunk0 : 0)) * fnti::CDC_CHUNK;
+    if (lb0 >= nb) return;                              // a table that does not cover the chunk
+    cdc_lane_spectra(ip, lane, hs_s[wv]);
+    wave_lds_sync();
+    uint32_t o[16];
+    const bool active = cdc_lane_blocks(ip, lb0, lane, hs_s[wv], edge_s[wv], err, o);
+    int8_t *a_out = ip->a_out;
     if (a_out == nullptr || !active) return;
+    const uint64_t M = fnti::n_symbols(ip->n, ip->phase);
+    const int64_t m0 = 16 * (int64_t)(lb0 + (uint64_t)lane);   // first symbol of the block
     uint32_t *dst = reinterpret_cast<uint32_t *>(a_out) + m0;
     if ((uint64_t)(m0 + 16) <= M && ((uintptr_t)dst & 15u) == 0u) {
         uint4 *d4 = reinterpret_cast<uint4 *>(dst);
@@ -1394,26 +1414,126 @@ __device__ __forceinline__ uint32_t aeq_sym(const AeqItem &it, int64_t i) {
 // whose 16-bit pieces both write, then cross HBM once.
 __host__ __device__ constexpr unsigned pol_blocks(int n) { return 16u * (unsigned)((n + 7) / 8); }
 
-// IW = 1: one half per workgroup, the halves paired on XCDs as above.  IW = 2
-// (one wave per half only): both halves of a channel in one workgroup of two
-// independent waves (wave v runs polarisation v), one workgroup per channel.
-template <int LPT, int IW = 1>
-__device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const AeqItem &single, int *err,
-                                             int prio, unsigned bid) {
-    static_assert(IW == 1 || (IW == 2 && LPT == 4), "paired halves need one wave per half");
-    const unsigned ch = IW == 1 ? (bid >> 4) * 8 + (bid & 7) : bid;
-    if (ch >= (unsigned)(items ? n : 1)) return;       // padding of the last run of 16
-    // latency-critical chains (the longest of a batch) issue ahead of the
-    // throughput work that shares their SIMDs
-    if (prio) __builtin_amdgcn_s_setprio(3);
+// Where the polarisation-split AEQ reads its 1-sample/symbol input.  Every
+// source gives symbol i of the channel's stream (history before 0, zeros past
+// M) for the two window loads before the first block (first), the window of
+// block b + 2 loaded during block b (ahead: symbols 16 b + 16 .. 16 b + 47,
+// index clamped to M - 1), and hears when the wave has finished block b (done).
+struct AeqSrcGlobal {          // the stream in device memory
+    const AeqItem *it;
+    __attribute__((address_space(1))) const uint32_t *base;
+    uint64_t M;
+    __device__ __forceinline__ void prime() {}
+    __device__ __forceinline__ uint32_t first(int64_t i) const { return aeq_sym(*it, i); }
+    __device__ __forceinline__ uint32_t ahead(uint32_t b, int wpos) {
+        return base[min<uint64_t>(16 * (uint64_t)b + 16 + wpos, M - 1)];
+    }
+    __device__ __forceinline__ void done(uint32_t) {}
+};
+
+// Counters of the fused kernel's hand-offs live in LDS and are read and
+// written with workgroup-scope atomics (on gfx950: plain LDS loads and stores
+// with lgkmcnt waits).  A wait polls with s_sleep between reads and gives up
+// after `limit` polls, or at once when another wave of the workgroup has given
+// up (the workgroup's `stall` word): it then latches RANGE_STALL, sets `stall`
+// and reports false, and no wave of the workgroup waits again for the rest of
+// the launch, so every wave still ends.  Polls sleep about 64 * SLEEP cycles
+// each; with the limits the launchers pass a give-up takes seconds, far beyond
+// any legitimate wait (a chunk of CDC or a few blocks of AEQ, microseconds).
+__device__ __forceinline__ uint32_t lds_load_acq(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_store_rel(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <int SLEEP>
+__device__ __forceinline__ bool wait_at_least(const uint32_t *p, uint32_t target, uint32_t limit, int *err,
+                                              uint32_t *stall, uint32_t *seen = nullptr) {
+    uint32_t polls = 0, v;
+    while ((v = lds_load_acq(p)) < target) {
+        if (++polls > limit || __hip_atomic_load(stall, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0u) {
+            flag(err, RANGE_STALL);
+            __hip_atomic_store(stall, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            return false;
+        }
+        if constexpr (SLEEP > 0) __builtin_amdgcn_s_sleep(SLEEP);
+    }
+    if (seen) *seen = v;
+    return true;
+}
+
+// Ring of CDC output in LDS: FUSED_RING chunks of 64 CDC blocks (1024 symbols,
+// 4 KB) each; symbol i of the channel sits at word i mod FUSED_RING_WORDS.
+constexpr int FUSED_RING = 4;
+constexpr int FUSED_CHUNK_SYMS = 16 * fnti::CDC_CHUNK;
+constexpr int FUSED_RING_WORDS = FUSED_RING * FUSED_CHUNK_SYMS;
+
+struct AeqSrcRing {            // the CDC output ring of the fused kernel
+    const AeqItem *it;
+    const uint32_t *ring;      // LDS, FUSED_RING_WORDS words
+    const uint32_t *produced;  // LDS: chunks the producer wave has written
+    uint32_t *mine;            // LDS: blocks this wave has finished
+    uint32_t *stall;           // LDS: set once a wait of the workgroup gave up
+    uint64_t M;
+    uint32_t limit;
+    int *err;
+    uint32_t have;             // chunks known to be written (wave-uniform)
+    bool live;                 // false once a wait gave up
+    __device__ __forceinline__ void need(uint32_t chunk) {
+        if (chunk < have || !live) return;
+        uint32_t v = 0;
+        live = wait_at_least<2>(produced, chunk + 1, limit, err, stall, &v);
+        have = v;
+    }
+    __device__ __forceinline__ void prime() { need(0); }
+    __device__ __forceinline__ uint32_t first(int64_t i) const {
+        if (i < 0) return aeq_sym(*it, i);
+        return (uint64_t)i < M ? ring[i & (FUSED_RING_WORDS - 1)] : 0u;
+    }
+    __device__ __forceinline__ uint32_t ahead(uint32_t b, int wpos) {
+        const uint64_t last = M - 1;
+        need((uint32_t)(min<uint64_t>(16 * (uint64_t)b + 47, last) / FUSED_CHUNK_SYMS));
+        return ring[min<uint64_t>(16 * (uint64_t)b + 16 + wpos, last) & (FUSED_RING_WORDS - 1)];
+    }
+    // published every 16 blocks: the producer waits for whole chunks of 64
+    __device__ __forceinline__ void done(uint32_t b) {
+        if (((b + 1) & 15) == 0 && (threadIdx.x & 63) == 0) lds_store_rel(mine, b + 1);
+    }
+};
+
+// Barrier of the WPP waves of one polarisation half, once per block.  Plain
+// launches use the workgroup barrier (a workgroup is one half); the fused
+// kernel holds both halves and the producer wave, so its halves count arrivals
+// in LDS instead (every wave of the half adds one per block and waits for all).
+struct HalfSyncWg {
+    __device__ __forceinline__ void block(uint32_t) { __syncthreads(); }
+};
+template <int WPP>
+struct HalfSyncLds {
+    uint32_t *count;           // LDS, zeroed before the channel starts
+    uint32_t *stall;           // LDS: set once a wait of the workgroup gave up
+    uint32_t limit;
+    int *err;
+    bool live;
+    __device__ __forceinline__ void block(uint32_t b) {
+        if ((threadIdx.x & 63) == 0)                   // after the wave's partial-output writes
+            __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (live) live = wait_at_least<0>(count, (uint32_t)WPP * (b + 1), limit, err, stall);
+    }
+};
+
+// The AEQ of one channel in the polarisation-split form: this wave is wave vh
+// of the WPP = LPT / 4 waves of half `pol`.  LDS of the wave: aspec (input
+// spectra), epsw (error bytes), winw (window bytes); of the half: part_h
+// (partial outputs, by block parity).  Reads its input through src and meets
+// the other waves of its half through hsync once per block.
+template <int LPT, class Src, class Sync>
+__device__ __forceinline__ void aeq_pol_run(const AeqItem &it, int pol, int vh, int lane, int *err,
+                                            int32_t (*aspec)[33], int32_t (*part_h)[4][33], uint32_t *epsw,
+                                            uint32_t *winw, Src &src, Sync &hsync) {
     constexpr int WPP = LPT / 4;                       // waves per polarisation half
     constexpr int PPL = 32 / LPT;                      // bins per lane
     constexpr int NT = 16 / LPT;                       // taps owned per lane (= PPL / 2)
-    const AeqItem it = items ? items[ch] : single;
-    const int tid = threadIdx.x;
-    const int v = tid >> 6, lane = tid & 63;
-    const int vh = v % WPP;                            // wave within its half
-    const int pol = IW == 1 ? (int)((bid >> 3) & 1) : v;
     // transform role: filter (tS1 -> 2 pol + tS2l), digit td, lane t of LPT; the
     // lane also owns the taps k = t + LPT i (i < NT) of that filter
     const int tr = lane / LPT, t = lane_pos(lane % LPT);
@@ -1425,20 +1545,6 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const 
     // output / error role (lanes 0..31 of every wave): symbol om, stream 2 pol + oS2l
     const int om = (lane >> 1) & 15, oS2l = lane & 1;
     const int kk = lane & 15;
-
-    // rows padded to 33 words: lanes reading the same position of different
-    // rows hit different LDS banks
-    __shared__ int32_t aspec_s[WPP * IW][4][33];       // per wave: input spectra by position
-    // per half: [block parity][g*2+d][m*2+S2l], shared by the half's waves;
-    // double-buffered so a wave that runs ahead (one barrier per block) never
-    // overwrites partials another wave is still reading
-    __shared__ int32_t part_s[IW][2][4][33];
-    __shared__ uint32_t epsw_s[WPP * IW][8];           // per wave: bytes [S2l][m]
-    __shared__ uint32_t winw_s[WPP * IW][36];          // per wave: bytes [S1][32] + pad
-    int32_t(*aspec)[33] = aspec_s[v];
-    uint32_t *epsw = epsw_s[v];
-    uint32_t *winw = winw_s[v];
-    int32_t(*part_h)[4][33] = part_s[v / WPP];
 
     int16_t *const wrow = it.taps + (tS1 * 4 + tS2) * 16;
     int32_t w[NT];
@@ -1459,7 +1565,7 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const 
         }
         if (hist_owner) {
             if (it.hist_out) {
-                uint32_t h = (lane < 16) ? aeq_sym(it, (int64_t)M - 16 + lane) : 0u;
+                uint32_t h = (lane < 16) ? src.first((int64_t)M - 16 + lane) : 0u;
                 if (lane < 16) reinterpret_cast<uint32_t *>(it.hist_out)[lane] = h;
             }
             if (it.cdc_tail) {
@@ -1512,10 +1618,10 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const 
     // the chain.  The load itself is unconditional (index clamped into the
     // input) and the zeros past the end are applied when the window is used, so
     // no wait for it is placed before then.
-    const auto abase = gptr(reinterpret_cast<const uint32_t *>(it.a));
     const auto obase = gptr(it.out + 4 * om + 2 * pol + oS2l);
     const int wpos = (lane & 16) | lane_pos(lane & 15);
-    uint32_t win_even = aeq_sym(it, -16 + wpos), win_odd = aeq_sym(it, wpos);   // blocks 0 and 1
+    src.prime();
+    uint32_t win_even = src.first(-16 + wpos), win_odd = src.first(wpos);   // blocks 0 and 1
 
     auto block = [&](uint32_t b, uint32_t &win) {
         const int64_t left = (int64_t)M - 16 * (int64_t)b;         // symbols from 16 b on
@@ -1530,7 +1636,7 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const 
 #pragma unroll
             for (int c = 0; c < 4; ++c) wb[c * 32 + wpos] = (uint8_t)(win >> (8 * c));
         }
-        win = abase[min<uint64_t>(16 * (uint64_t)b + 16 + wpos, M - 1)];  // symbol 16 b + 16 + wpos
+        win = src.ahead(b, wpos);                                   // symbol 16 b + 16 + wpos
         {   // input spectra of the 4 streams: lane (S1 = lane / 16, k) holds positions kp, kp + 16
             const int kp = lane_pos(kk);                 // position index of this lane
             const int sh = 8 * (lane >> 4);              // byte of stream S1
@@ -1573,7 +1679,7 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const 
             for (int j = PPL / 2; j < PPL; ++j)
                 part_h[b & 1][tg * 2 + td][(t + LPT * (j - PPL / 2)) * 2 + tS2l] = lift_loose(Y[j]);
         }
-        if (WPP > 1) __syncthreads(); else wave_lds_sync();
+        if (WPP > 1) hsync.block(b); else wave_lds_sync();
         // symbol om, stream 2 pol + oS2l: y = 2^7 (high-digit sums) + (low-digit sums)
         const int pi = lane & 31;
         const int32_t(*part)[33] = part_h[b & 1];
@@ -1612,6 +1718,7 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const 
         // the next block reuses this wave's window and error bytes: keep the LDS
         // reads above in front of the writes that follow
         wave_lds_sync();
+        src.done(b);
     };
     for (uint32_t b = 0; b < nblocks; b += 2) {
         block(b, win_even);
@@ -1621,10 +1728,159 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const 
     finish();
 }
 
+// IW = 1: one half per workgroup, the halves paired on XCDs as above.  IW = 2
+// (one wave per half only): both halves of a channel in one workgroup of two
+// independent waves (wave v runs polarisation v), one workgroup per channel.
+template <int LPT, int IW = 1>
+__device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const AeqItem &single, int *err,
+                                             int prio, unsigned bid) {
+    static_assert(IW == 1 || (IW == 2 && LPT == 4), "paired halves need one wave per half");
+    const unsigned ch = IW == 1 ? (bid >> 4) * 8 + (bid & 7) : bid;
+    if (ch >= (unsigned)(items ? n : 1)) return;       // padding of the last run of 16
+    // latency-critical chains (the longest of a batch) issue ahead of the
+    // throughput work that shares their SIMDs
+    if (prio) __builtin_amdgcn_s_setprio(3);
+    constexpr int WPP = LPT / 4;                       // waves per polarisation half
+    const AeqItem it = items ? items[ch] : single;
+    const int tid = threadIdx.x;
+    const int v = tid >> 6, lane = tid & 63;
+    const int vh = v % WPP;                            // wave within its half
+    const int pol = IW == 1 ? (int)((bid >> 3) & 1) : v;
+
+    // rows padded to 33 words: lanes reading the same position of different
+    // rows hit different LDS banks
+    __shared__ int32_t aspec_s[WPP * IW][4][33];       // per wave: input spectra by position
+    // per half: [block parity][g*2+d][m*2+S2l], shared by the half's waves;
+    // double-buffered so a wave that runs ahead (one barrier per block) never
+    // overwrites partials another wave is still reading
+    __shared__ int32_t part_s[IW][2][4][33];
+    __shared__ uint32_t epsw_s[WPP * IW][8];           // per wave: bytes [S2l][m]
+    __shared__ uint32_t winw_s[WPP * IW][36];          // per wave: bytes [S1][32] + pad
+    AeqSrcGlobal src{&it, gptr(reinterpret_cast<const uint32_t *>(it.a)), it.m};
+    HalfSyncWg hs;
+    aeq_pol_run<LPT>(it, pol, vh, lane, err, aspec_s[v], part_s[v / WPP], epsw_s[v], winw_s[v], src, hs);
+}
+
 template <int LPT, int IW = 1>
 __global__ __launch_bounds__(64 * (LPT / 4) * IW) void aeq_pol_kernel(const AeqItem *items, int n,
                                                                       AeqItem single, int *err, int prio) {
     aeq_pol_body<LPT, IW>(items, n, single, err, prio, blockIdx.x);
+}
+
+// ------------------------------------------------------------------------
+// Fused persistent FNT-CDC + FNT-AEQ (the receiver chain of the experimental
+// section: CDC, resampling to 1 sample/symbol, AEQ) in one launch.
+//
+// A workgroup runs one channel at a time: 2 WPP consumer waves run the two
+// polarisation halves of the AEQ (aeq_pol_run), and one producer wave runs the
+// lane-per-block CDC (cdc_lane_blocks) chunk by chunk, 64 blocks per chunk,
+// into a ring of FUSED_RING chunks in LDS.  The 1-sample/symbol stream never
+// leaves the CU.  Hand-offs, all in LDS:
+//   * produced: chunks written; a consumer loading the window of block b + 2
+//     needs chunk min(16 b + 47, M - 1) / 1024;
+//   * cons[v]: blocks finished by consumer wave v, published every 16 blocks;
+//     after block b a wave never reads a symbol below 16 (b + 1) + 16 again, so
+//     the producer may rewrite the slot of chunk c - FUSED_RING once every wave
+//     has published 64 (c - FUSED_RING + 1) - 1 blocks.
+// Neither side waits for more than the other can supply with the ring's
+// FUSED_RING >= 2 chunks, so the waits end; each also gives up after a bound
+// (RANGE_STALL).  Channels come from a work counter (queue[0]) in table order
+// (longest chains first), so the longest chains start at once on the first
+// workgroups and the others fill in as workgroups free up; the last workgroup
+// to find the table empty resets the counters (queue[0], queue[1]) for the
+// next launch.  Without a counter (queue = nullptr) workgroup w runs channel w
+// once.  Channels with index < nprio run at raised wave priority.
+// ------------------------------------------------------------------------
+template <int LPT>
+__global__ __launch_bounds__(64 * (2 * (LPT / 4) + 1)) __attribute__((amdgpu_waves_per_eu(3))) void cdc_aeq_fused_kernel(
+    const CdcItem *citems, const AeqItem *aitems, int n, CdcItem csingle, AeqItem asingle,
+    uint32_t *queue, int nprio, int *err, uint32_t spin_limit) {
+    constexpr int WPP = LPT / 4;
+    constexpr int NC = 2 * WPP;                        // consumer waves
+    const int v = threadIdx.x >> 6, lane = threadIdx.x & 63;
+
+    __shared__ __align__(16) uint32_t ring_s[FUSED_RING_WORDS];
+    __shared__ uint32_t produced_s, cons_s[NC], half_s[2], next_s, stall_s;
+    __shared__ int32_t hs_s[2][64];
+    __shared__ __align__(16) uint32_t edge_s[2][64];
+    __shared__ int32_t aspec_s[NC][4][33];
+    __shared__ int32_t part_s[2][2][4][33];
+    __shared__ uint32_t epsw_s[NC][8];
+    __shared__ uint32_t winw_s[NC][36];
+
+    const int total = citems ? n : 1;
+    // Both roles run the same sequence of workgroup barriers, two per channel,
+    // in loops of their own (so that neither role's loop-invariant lane
+    // constants stay live through the other role's code).  Thread 0 (consumer
+    // wave 0) takes the next channel and clears the hand-off counters.
+    auto next_channel = [&](uint32_t iter) -> uint32_t {
+        if (threadIdx.x == 0) {
+            // with a work counter: the next channel of the table; without: channel
+            // blockIdx.x, once
+            next_s = queue ? atomicAdd(&queue[0], 1u) : (iter == 0 ? blockIdx.x : 0xFFFFFFFFu);
+            produced_s = 0;
+            half_s[0] = half_s[1] = 0;
+            if (iter == 0) stall_s = 0;
+        }
+        if (threadIdx.x < NC) cons_s[threadIdx.x] = 0;
+        __syncthreads();
+        return next_s;
+    };
+    if (v == NC) {                                     // producer: the CDC of each channel
+        for (uint32_t iter = 0;; ++iter) {
+            const uint32_t chn = next_channel(iter);
+            if (chn >= (uint32_t)total) break;
+            // one level below the channel's AEQ waves: the CDC runs up to
+            // FUSED_RING chunks ahead and only has to keep ahead of the chain
+            if ((int)chn < nprio) __builtin_amdgcn_s_setprio(2); else __builtin_amdgcn_s_setprio(0);
+            const CdcItem *ip = citems ? &citems[chn] : &csingle;
+            const uint64_t nb = fnti::cdc_blocks(ip->n);
+            const uint32_t nchunks = (uint32_t)((nb + fnti::CDC_CHUNK - 1) / fnti::CDC_CHUNK);
+            cdc_lane_spectra(ip, lane, hs_s);
+            wave_lds_sync();
+            bool live = true;
+            for (uint32_t c = 0; c < nchunks; ++c) {
+                if (c >= (uint32_t)FUSED_RING && live) {   // slot of chunk c - FUSED_RING free?
+                    const uint32_t need = (uint32_t)fnti::CDC_CHUNK * (c - FUSED_RING + 1) - 1;
+#pragma unroll
+                    for (int k = 0; k < NC; ++k)
+                        if (live) live = wait_at_least<32>(&cons_s[k], need, spin_limit, err, &stall_s);
+                }
+                uint32_t o[16];
+                cdc_lane_blocks(ip, (uint64_t)c * fnti::CDC_CHUNK, lane, hs_s, edge_s, err, o);
+                uint4 *dst = reinterpret_cast<uint4 *>(
+                    &ring_s[(c % FUSED_RING) * FUSED_CHUNK_SYMS + 16 * lane]);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) dst[q] = make_uint4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
+                if (lane == 0) lds_store_rel(&produced_s, c + 1);   // after the wave's ring writes
+                wave_lds_sync();
+            }
+            __syncthreads();                           // the channel is done; LDS is free again
+        }
+    } else {                                           // consumers: the AEQ halves of each channel
+        const int pol = v / WPP, vh = v % WPP;
+        for (uint32_t iter = 0;; ++iter) {
+            const uint32_t chn = next_channel(iter);
+            if (chn >= (uint32_t)total) break;
+            if ((int)chn < nprio) __builtin_amdgcn_s_setprio(3); else __builtin_amdgcn_s_setprio(1);
+            const AeqItem it = aitems ? aitems[chn] : asingle;
+            AeqSrcRing src{&it, ring_s, &produced_s, &cons_s[v], &stall_s, it.m, spin_limit, err, 0u, true};
+            if constexpr (WPP == 1) {
+                HalfSyncWg unused;
+                aeq_pol_run<LPT>(it, pol, vh, lane, err, aspec_s[v], part_s[pol], epsw_s[v], winw_s[v], src, unused);
+            } else {
+                HalfSyncLds<WPP> hsync{&half_s[pol], &stall_s, spin_limit, err, true};
+                aeq_pol_run<LPT>(it, pol, vh, lane, err, aspec_s[v], part_s[pol], epsw_s[v], winw_s[v], src, hsync);
+            }
+            __syncthreads();                           // the channel is done; LDS is free again
+        }
+    }
+    if (queue && threadIdx.x == 0) {                   // the last workgroup out resets the counters
+        if (atomicAdd(&queue[1], 1u) == gridDim.x - 1) {
+            __hip_atomic_store(&queue[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&queue[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
 }
 
 // ------------------------------------------------------------------------
@@ -2343,6 +2599,39 @@ __global__ __launch_bounds__(64) void aeq_direct_kernel(const AeqItem *items, Ae
 }  // namespace
 
 namespace fnti {
+
+static_assert(RANGE_STALL == kFlagStall, "stall flag bit");
+
+template <int LPT>
+static hipError_t fused_kernel_caps(int *per_cu) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, cdc_aeq_fused_kernel<LPT>,
+                                                        64 * (2 * (LPT / 4) + 1), 0);
+}
+
+int fused_capacity(int lpt) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    hipError_t e = lpt == 4 ? fused_kernel_caps<4>(&per) : lpt == 8 ? fused_kernel_caps<8>(&per)
+                 : lpt == 16 ? fused_kernel_caps<16>(&per) : hipErrorInvalidValue;
+    return e == hipSuccess ? per * cus : 0;
+}
+
+hipError_t launch_fused(const CdcItem *citems, const AeqItem *aitems, int n, const CdcItem &cs,
+                        const AeqItem &as, int lpt, uint32_t *queue, unsigned grid, int nprio, int *err,
+                        hipStream_t s, uint32_t spin_limit) {
+    const int total = citems ? n : 1;
+    if (total <= 0) return hipSuccess;
+    if ((citems == nullptr) != (aitems == nullptr) || n > (1 << 26) || grid == 0) return hipErrorInvalidValue;
+    if (queue ? grid > (unsigned)total : grid != (unsigned)total) return hipErrorInvalidValue;
+    switch (lpt) {
+    case 4: cdc_aeq_fused_kernel<4><<<grid, 192, 0, s>>>(citems, aitems, n, cs, as, queue, nprio, err, spin_limit); break;
+    case 8: cdc_aeq_fused_kernel<8><<<grid, 320, 0, s>>>(citems, aitems, n, cs, as, queue, nprio, err, spin_limit); break;
+    case 16: cdc_aeq_fused_kernel<16><<<grid, 576, 0, s>>>(citems, aitems, n, cs, as, queue, nprio, err, spin_limit); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_transform(const uint32_t *x, uint32_t *X, size_t batch, int t, int log2n,
                             int alpha_kind, bool inverse, int *err, hipStream_t s) {

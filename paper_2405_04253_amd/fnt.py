@@ -66,14 +66,15 @@ class PlanInfo(ctypes.Structure):
                 ("aeq_long_channels", ctypes.c_uint64), ("cdc_variant", ctypes.c_int32),
                 ("lead_channels", ctypes.c_int32), ("lead_form", ctypes.c_int32),
                 ("top_channels", ctypes.c_int32), ("top_form", ctypes.c_int32),
-                ("tune_run_ms", ctypes.c_double)]
+                ("tune_run_ms", ctypes.c_double), ("fused_lpt", ctypes.c_int32),
+                ("fused_grid", ctypes.c_int32), ("fused_prio_channels", ctypes.c_uint64)]
 
 
 class PlanTiming(ctypes.Structure):
     _fields_ = [("step_ms", ctypes.c_float), ("cdc_ms", ctypes.c_float), ("aeq_ms", ctypes.c_float),
                 ("aeq_lead_ms", ctypes.c_float), ("aeq_blocks", ctypes.c_uint64),
                 ("aeq_lead_blocks", ctypes.c_uint64), ("aeq_top_ms", ctypes.c_float),
-                ("reserved", ctypes.c_int32), ("aeq_top_blocks", ctypes.c_uint64)]
+                ("fused", ctypes.c_int32), ("aeq_top_blocks", ctypes.c_uint64)]
 
 
 class SessionConfig(ctypes.Structure):
@@ -119,6 +120,7 @@ SIGNATURES = {
     "fnt_plan_set_cdc_schedule": (_i32, [_vp, _i32, _i32]),
     "fnt_plan_set_aeq_split": (_i32, [_vp, _u64, _i32, _i32]),
     "fnt_plan_set_lead": (_i32, [_vp, _u64, _i32, _u64, _i32]),
+    "fnt_plan_set_fused": (_i32, [_vp, _i32, _u64]),
     "fnt_plan_run_timed": (_i32, [_vp, ctypes.POINTER(PlanTiming), _vp]),
     "fnt_plan_destroy": (_i32, [_vp]),
     "fnt_now_ns": (_u64, []),
@@ -321,6 +323,10 @@ class Plan:
     def set_lead(self, lead_channels: int, lead_form: int = -1, top_channels: int = 0, top_form: int = -1):
         _ok(lib().fnt_plan_set_lead(self._h, int(lead_channels), int(lead_form), int(top_channels),
                                     int(top_form)))
+
+    def set_fused(self, lanes_per_transform: int, prio_channels: int = 0):
+        """Every run as one launch of the fused CDC + AEQ kernel (0: off)."""
+        _ok(lib().fnt_plan_set_fused(self._h, int(lanes_per_transform), int(prio_channels)))
 
     def run_timed(self, stream=None) -> dict:
         """One run launched directly with events around every launch; blocks
