@@ -212,6 +212,8 @@ typedef struct fnt_plan_info {
                               fnt_plan_set_fused) */
     int32_t fused_grid;    /* workgroups of the fused launch (0 when not fused) */
     uint64_t fused_prio_channels;  /* longest channels at raised wave priority in the fused launch */
+    int32_t fused_split;   /* 1: the fused launch runs one workgroup per polarisation half */
+    int32_t reserved2;
 } fnt_plan_info;
 
 typedef struct fnt_plan fnt_plan;
@@ -315,8 +317,13 @@ int fnt_plan_set_lead(fnt_plan *plan, uint64_t lead_channels, int lead_form, uin
  * schedule off (the staged / lead schedule applies again).  The
  * `prio_channels` longest channels run at raised wave priority.  Any other
  * schedule setter (fnt_plan_set_aeq_waves, _aeq_split, _lead, the variants)
- * switches it off.  Results never depend on it.  FNT_E_INVAL for another lpt. */
-int fnt_plan_set_fused(fnt_plan *plan, int lpt, uint64_t prio_channels);
+ * switches it off.  split_halves = 1: one workgroup per polarisation half of
+ * every channel, each computing the channel's CDC itself (twice the CDC work,
+ * but each half's AEQ waves get a CU of their own: the shortest chains for a
+ * few channels on an otherwise idle GPU); 0: both halves and one CDC per
+ * workgroup, channels from a work counter.  Results never depend on it.
+ * FNT_E_INVAL for another lpt or split_halves. */
+int fnt_plan_set_fused(fnt_plan *plan, int lpt, uint64_t prio_channels, int split_halves);
 
 typedef struct fnt_plan_timing {
     float step_ms;          /* first launch to the end of the last, on the launch stream */

@@ -251,14 +251,16 @@ int fnt_cdc_aeq(const int8_t *in, uint64_t n, const fnt_cdc_params *cp, int16_t 
         return fail(FNT_E_INVAL, "fnt_cdc_aeq: misaligned buffer");
     int *err = nullptr;
     if ((rc = device_err_flag(&err))) return rc;
-    // one launch of the fused kernel with one workgroup: a producer wave runs
-    // the CDC chunk by chunk into LDS while four waves per polarisation half run
-    // the AEQ chain (the shortest serial latency per block on an idle GPU)
+    // one launch of the fused kernel, one workgroup per polarisation half: in
+    // each, producer waves run the CDC chunk by chunk into LDS while four waves
+    // run the half's AEQ chain (the shortest serial latency per block on an
+    // otherwise idle GPU)
     CdcItem ci;
     fill_cdc_item(ci, in, n, cp);
     AeqItem ai;
     fill_aeq_item(ai, nullptr, M, taps, ap, out);
-    hipError_t e = launch_fused(nullptr, nullptr, 1, ci, ai, kSingleLpt, nullptr, 1, 1, err, (hipStream_t)stream);
+    hipError_t e = launch_fused(nullptr, nullptr, 1, ci, ai, kSingleLpt, nullptr, fused_split_grid(1), 1, err,
+                                (hipStream_t)stream, true);
     if (e != hipSuccess) return hip_fail(e, "fnt_cdc_aeq: launch");
     return FNT_OK;
 }
@@ -302,6 +304,7 @@ struct fnt_plan {
     // lanes per transform, channels at raised priority, workgroups, and the two
     // work-counter words the kernel takes channels from (zero between launches)
     int fused_lpt = 0;
+    bool fused_split = false;        // one workgroup per polarisation half
     size_t fused_prio = 0;
     unsigned fused_grid = 0;
     uint32_t *queue = nullptr;
@@ -404,8 +407,9 @@ static int plan_launch_aeq(fnt_plan *p, hipStream_t s, hipStream_t side) {
 // Fork / join are events, which a graph capture turns into parallel branches.
 // `ev` (timing, direct launches only) receives start, CDC end, lead AEQ start,
 // lead AEQ end, AEQ end, done, first-level AEQ start and end.
-static unsigned plan_fused_grid(const fnt_plan *p, int lpt) {
+static unsigned plan_fused_grid(const fnt_plan *p, int lpt, bool split) {
     const size_t n = p->aeq_host.size();
+    if (split) return fused_split_grid((int)n);
     const int cap = fused_capacity(lpt);
     return (unsigned)std::min<size_t>(n, cap > 0 ? (size_t)cap : 1024);
 }
@@ -419,7 +423,8 @@ static int plan_launch(fnt_plan *p, hipStream_t s, hipStream_t side, hipStream_t
         if (e == hipSuccess) e = rec(1, s);
         if (e == hipSuccess)
             e = launch_fused(p->cdc_dev, p->aeq_dev, (int)p->aeq_host.size(), CdcItem{}, AeqItem{}, p->fused_lpt,
-                             p->queue, p->fused_grid, (int)std::min<size_t>(p->fused_prio, 1u << 26), p->err, s);
+                             p->fused_split ? nullptr : p->queue, p->fused_grid,
+                             (int)std::min<size_t>(p->fused_prio, 1u << 26), p->err, s, p->fused_split);
         if (e == hipSuccess) e = rec(4, s);
         if (e == hipSuccess) e = rec(5, s);
         if (e != hipSuccess) return hip_fail(e, "plan: fused launch");
@@ -669,11 +674,12 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
         (w == 1 || w == 2 || w == 4) &&
         b >= 0 && b <= 1024 && valid_form(q) && valid_form(ql) && nl >= 0 && nd >= 0 &&
         (size_t)nd < std::max<size_t>(1, p->aeq_host.size()) && (lf == -1 || lf == kFusedLead || valid_form(lf)) && nt >= 0 &&
-        (nt == 0 || nt < nd) && (tf == -1 || valid_form(tf)) && (fl == 0 || fl == 4 || fl == 8 || fl == 16) &&
-        fp >= 0) {
-        p->fused_lpt = fl;
+        (nt == 0 || nt < nd) && (tf == -1 || valid_form(tf)) &&
+        (fl == 0 || std::abs(fl) == 4 || std::abs(fl) == 8 || std::abs(fl) == 16) && fp >= 0) {
+        p->fused_lpt = std::abs(fl);
+        p->fused_split = fl < 0;
         p->fused_prio = (size_t)fp;
-        if (fl) p->fused_grid = plan_fused_grid(p, fl);
+        if (fl) p->fused_grid = plan_fused_grid(p, fl, p->fused_split);
         p->wpg = w;
         p->bpw = b;
         p->wpp = q;
@@ -726,6 +732,7 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
     int bq = p->wpp, bql = p->wpp_long;
     size_t bnl = p->n_long, bnd = 0, btop = 0, bfp = 0;
     int blf = -1, btf = -1, bfl = 0;
+    bool bfs = false;
     if (p->variant == 0 && hipMalloc(&tscratch, nch * 256 * sizeof(int16_t)) == hipSuccess &&
         hipMalloc(&tdev, nch * sizeof(AeqItem)) == hipSuccess) {
         std::vector<AeqItem> tab = p->aeq_host;
@@ -909,36 +916,42 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
             // none to the first 2048.  One pass, then the median of three for the
             // best two, against the staged or lead schedule's median
             {
-                struct FCand { int lpt; size_t prio; double ms; };
+                struct FCand { int lpt; bool split; size_t prio; double ms; };
                 std::vector<FCand> fc;
                 for (int lpt : {4, 8, 16}) {
                     const int cap = fused_capacity(lpt);
-                    if (cap <= 0 || (lpt != 4 && nch > (size_t)cap)) continue;
-                    for (size_t prio : {0, 256, 512, 1024, 2048})
-                        if (prio == 0 || prio < nch) fc.push_back({lpt, prio, 0});
+                    if (cap <= 0) continue;
+                    if (lpt == 4 || nch <= (size_t)cap)
+                        for (size_t prio : {0, 256, 512, 1024, 2048})
+                            if (prio == 0 || prio < nch) fc.push_back({lpt, false, prio, 0});
+                    // a workgroup per half when the halves of every channel fit at once
+                    if (2 * nch <= (size_t)cap) fc.push_back({lpt, true, nch, 0});
                 }
                 auto time_fused = [&](const FCand &c) {
                     p->fused_lpt = c.lpt;
+                    p->fused_split = c.split;
                     p->fused_prio = c.prio;
-                    p->fused_grid = plan_fused_grid(p, c.lpt);
+                    p->fused_grid = plan_fused_grid(p, c.lpt, c.split);
                     double ms = time_it([&] { return plan_launch(p, s, p->side, p->side2) ? hipErrorUnknown : hipSuccess; });
                     if (tlog.is_open())
-                        tlog << "fused lpt " << c.lpt << " prio " << c.prio << " grid " << p->fused_grid << " ms " << ms
-                             << "\n";
+                        tlog << "fused lpt " << c.lpt << " split " << c.split << " prio " << c.prio << " grid "
+                             << p->fused_grid << " ms " << ms << "\n";
                     return ms;
                 };
                 for (FCand &c : fc) c.ms = time_fused(c);
                 std::sort(fc.begin(), fc.end(), [](const FCand &x, const FCand &y) { return x.ms < y.ms; });
-                FCand fbest{0, 0, 1e30};
+                FCand fbest{0, false, 0, 1e30};
                 for (size_t i = 0; i < fc.size() && i < 2; ++i) {
                     double r[3];
                     for (double &v : r) v = time_fused(fc[i]);
                     std::sort(r, r + 3);
-                    if (r[1] < fbest.ms) fbest = {fc[i].lpt, fc[i].prio, r[1]};
+                    if (r[1] < fbest.ms) fbest = {fc[i].lpt, fc[i].split, fc[i].prio, r[1]};
                 }
                 p->fused_lpt = 0;
+                p->fused_split = false;
                 if (fbest.lpt && fbest.ms < p->info.tune_run_ms) {
                     bfl = fbest.lpt;
+                    bfs = fbest.split;
                     bfp = fbest.prio;
                     p->info.tune_run_ms = fbest.ms;
                 }
@@ -963,11 +976,13 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
     p->n_top = btop;
     p->top_form = btf;
     p->fused_lpt = bfl;
+    p->fused_split = bfs;
     p->fused_prio = bfp;
-    if (bfl) p->fused_grid = plan_fused_grid(p, bfl);
+    if (bfl) p->fused_grid = plan_fused_grid(p, bfl, p->fused_split);
     p->info.tune_ms = best_aeq < 1e29 ? best_aeq : best_cdc;
-    tune_cache_store(cache, key, bw, bb, bq, bql, (long long)bnl, (long long)bnd, blf, (long long)btop, btf, bfl,
-                     (long long)bfp, p->info.tune_ms);
+    // the cache keeps a split fused schedule as a negative lane count
+    tune_cache_store(cache, key, bw, bb, bq, bql, (long long)bnl, (long long)bnd, blf, (long long)btop, btf,
+                     bfs ? -bfl : bfl, (long long)bfp, p->info.tune_ms);
     return FNT_OK;
 }
 
@@ -1164,16 +1179,19 @@ int fnt_plan_get_info(const fnt_plan *p, fnt_plan_info *info) {
     info->fused_lpt = p->fused_lpt;
     info->fused_grid = p->fused_lpt ? (int32_t)p->fused_grid : 0;
     info->fused_prio_channels = p->fused_lpt ? std::min(p->fused_prio, p->aeq_host.size()) : 0;
+    info->fused_split = p->fused_lpt && p->fused_split ? 1 : 0;
     return FNT_OK;
 }
 
-int fnt_plan_set_fused(fnt_plan *p, int lpt, uint64_t prio_channels) {
+int fnt_plan_set_fused(fnt_plan *p, int lpt, uint64_t prio_channels, int split_halves) {
     if (!p) return fail(FNT_E_INVAL, "plan: NULL");
     if (lpt != 0 && lpt != 4 && lpt != 8 && lpt != 16)
         return fail(FNT_E_INVAL, "plan: fused lanes per transform %d (0, 4, 8 or 16)", lpt);
+    if (split_halves != 0 && split_halves != 1) return fail(FNT_E_INVAL, "plan: split_halves %d", split_halves);
     p->fused_lpt = lpt;
+    p->fused_split = split_halves != 0;
     p->fused_prio = (size_t)std::min<uint64_t>(prio_channels, p->aeq_host.size());
-    p->fused_grid = lpt ? plan_fused_grid(p, lpt) : 0;
+    p->fused_grid = lpt ? plan_fused_grid(p, lpt, p->fused_split) : 0;
     if (p->exec) return plan_capture(p, nullptr);
     return FNT_OK;
 }

@@ -93,10 +93,14 @@ bool aeq_split_fusable(int form_long, int form_rest);
 // items cs / as.  With queue (two device words, zero before the first launch;
 // every launch leaves them zero) grid <= channels workgroups take channels in
 // table order; without, grid = channels and workgroup w runs channel w.
-// Channels [0, nprio) run at raised wave priority.
+// Channels [0, nprio) run at raised wave priority.  split_halves: one
+// workgroup per polarisation half, each computing the CDC itself (for idle
+// GPUs: the halves' waves get a CU each), grid = fused_split_grid(channels),
+// no queue.
 hipError_t launch_fused(const CdcItem *citems, const AeqItem *aitems, int n, const CdcItem &cs,
                         const AeqItem &as, int lpt, uint32_t *queue, unsigned grid, int nprio, int *err,
-                        hipStream_t s, uint32_t spin_limit = kFusedSpinLimit);
+                        hipStream_t s, bool split_halves = false, uint32_t spin_limit = kFusedSpinLimit);
+unsigned fused_split_grid(int n);
 // Workgroups of the fused kernel resident at once on the current device (0 on error).
 int fused_capacity(int lpt);
 hipError_t launch_aeq(const AeqItem *items, int nitems, const AeqItem &single, int variant,

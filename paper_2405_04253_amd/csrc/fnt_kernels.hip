@@ -576,9 +576,12 @@ __device__ __forceinline__ void cdc_lane_spectra(const CdcItem *ip, int lane, in
 // q-th 1-sample/symbol output of the lane's block as 4 packed 5-bit bytes
 // {XI, XQ, YI, YQ} (symbol 16 (lb0 + lane) + q).  Returns whether the lane's
 // block lies inside the item; lanes past its end compute on zeros.
+// With ring16 (an LDS pointer), polarisation p's two output bytes of symbol q
+// go straight to ring16[2 (16 lane + q) + p] as each polarisation finishes, and
+// o is left untouched (fewer registers live across the two polarisations).
 __device__ __forceinline__ bool cdc_lane_blocks(const CdcItem *ip, uint64_t lb0, int lane,
                                                 const int32_t (*hs)[64], uint32_t (*edge)[64],
-                                                int *err, uint32_t (&o)[16]) {
+                                                int *err, uint32_t (&o)[16], uint16_t *ring16 = nullptr) {
     const uint64_t n = ip->n;
     const uint64_t nb = fnti::cdc_blocks(n);
     const int shift = ip->shift, phase = ip->phase;
@@ -703,7 +706,11 @@ __device__ __forceinline__ bool cdc_lane_blocks(const CdcItem *ip, uint64_t lb0,
             const int32_t zi = lift_z(sext24(yd[16 + q]) * -2);
             const uint32_t b2 = ((uint32_t)requant5(zr, shift) & 0xFFu) |
                                 (((uint32_t)requant5(zi, shift) & 0xFFu) << 8);
-            o[q] |= b2 << (16 * pol);
+            if (ring16) {
+                ((__attribute__((address_space(3))) uint16_t *)ring16)[2 * (16 * lane + q) + pol] = (uint16_t)b2;
+            } else {
+                o[q] |= b2 << (16 * pol);
+            }
         }
     }
     if ((bad & 0xE0E0E0E0u) != 0u) flag(err, RANGE_SAMPLE);
@@ -1434,8 +1441,8 @@ struct AeqSrcGlobal {          // the stream in device memory
 // Counters of the fused kernel's hand-offs live in LDS and are read and
 // written with workgroup-scope atomics (on gfx950: plain LDS loads and stores
 // with lgkmcnt waits).  A wait polls with s_sleep between reads and gives up
-// after `limit` polls, or at once when another wave of the workgroup has given
-// up (the workgroup's `stall` word): it then latches RANGE_STALL, sets `stall`
+// after `limit` polls, or when another wave of the workgroup has given up (the
+// workgroup's `stall` word, looked at every 64 polls): it then latches RANGE_STALL, sets `stall`
 // and reports false, and no wave of the workgroup waits again for the rest of
 // the launch, so every wave still ends.  Polls sleep about 64 * SLEEP cycles
 // each; with the limits the launchers pass a give-up takes seconds, far beyond
@@ -1451,7 +1458,8 @@ __device__ __forceinline__ bool wait_at_least(const uint32_t *p, uint32_t target
                                               uint32_t *stall, uint32_t *seen = nullptr) {
     uint32_t polls = 0, v;
     while ((v = lds_load_acq(p)) < target) {
-        if (++polls > limit || __hip_atomic_load(stall, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0u) {
+        if ((++polls & 63) == 0 &&
+            (polls > limit || __hip_atomic_load(stall, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0u)) {
             flag(err, RANGE_STALL);
             __hip_atomic_store(stall, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             return false;
@@ -1462,38 +1470,41 @@ __device__ __forceinline__ bool wait_at_least(const uint32_t *p, uint32_t target
     return true;
 }
 
-// Ring of CDC output in LDS: FUSED_RING chunks of 64 CDC blocks (1024 symbols,
-// 4 KB) each; symbol i of the channel sits at word i mod FUSED_RING_WORDS.
-constexpr int FUSED_RING = 4;
+// Ring of CDC output in LDS: RING chunks of 64 CDC blocks (1024 symbols, 4 KB)
+// each; symbol i of the channel sits at word i mod (RING * 1024).  Word s of
+// `slots` holds 1 + the index of the chunk slot s contains (0: none yet).
 constexpr int FUSED_CHUNK_SYMS = 16 * fnti::CDC_CHUNK;
-constexpr int FUSED_RING_WORDS = FUSED_RING * FUSED_CHUNK_SYMS;
 
+template <int RING>
 struct AeqSrcRing {            // the CDC output ring of the fused kernel
+    static constexpr uint32_t WORDS = RING * FUSED_CHUNK_SYMS;
     const AeqItem *it;
-    const uint32_t *ring;      // LDS, FUSED_RING_WORDS words
-    const uint32_t *produced;  // LDS: chunks the producer wave has written
+    const uint32_t *ring;      // LDS, WORDS words
+    const uint32_t *slots;     // LDS, RING words
     uint32_t *mine;            // LDS: blocks this wave has finished
     uint32_t *stall;           // LDS: set once a wait of the workgroup gave up
     uint64_t M;
     uint32_t limit;
     int *err;
-    uint32_t have;             // chunks known to be written (wave-uniform)
+    uint32_t have;             // chunks [0, have) known to be written (wave-uniform)
     bool live;                 // false once a wait gave up
+    // chunks complete out of order when several producer waves share them out,
+    // so each is checked in its own slot, in order
     __device__ __forceinline__ void need(uint32_t chunk) {
-        if (chunk < have || !live) return;
-        uint32_t v = 0;
-        live = wait_at_least<2>(produced, chunk + 1, limit, err, stall, &v);
-        have = v;
+        while (have <= chunk && live) {
+            live = wait_at_least<2>(&slots[have % RING], have + 1, limit, err, stall);
+            ++have;
+        }
     }
     __device__ __forceinline__ void prime() { need(0); }
     __device__ __forceinline__ uint32_t first(int64_t i) const {
         if (i < 0) return aeq_sym(*it, i);
-        return (uint64_t)i < M ? ring[i & (FUSED_RING_WORDS - 1)] : 0u;
+        return (uint64_t)i < M ? ring[i & (WORDS - 1)] : 0u;
     }
     __device__ __forceinline__ uint32_t ahead(uint32_t b, int wpos) {
         const uint64_t last = M - 1;
         need((uint32_t)(min<uint64_t>(16 * (uint64_t)b + 47, last) / FUSED_CHUNK_SYMS));
-        return ring[min<uint64_t>(16 * (uint64_t)b + 16 + wpos, last) & (FUSED_RING_WORDS - 1)];
+        return ring[min<uint64_t>(16 * (uint64_t)b + 16 + wpos, last) & (WORDS - 1)];
     }
     // published every 16 blocks: the producer waits for whole chunks of 64
     __device__ __forceinline__ void done(uint32_t b) {
@@ -1503,22 +1514,48 @@ struct AeqSrcRing {            // the CDC output ring of the fused kernel
 
 // Barrier of the WPP waves of one polarisation half, once per block.  Plain
 // launches use the workgroup barrier (a workgroup is one half); the fused
-// kernel holds both halves and the producer wave, so its halves count arrivals
-// in LDS instead (every wave of the half adds one per block and waits for all).
+// kernel holds both halves and the producer waves, so a half's waves meet in
+// LDS instead: wave vh writes 1 + the block it finished into its own word of
+// the half (after its partial outputs) and waits until every word of the half
+// has reached that block (one LDS load of all WPP words per poll).
 struct HalfSyncWg {
     __device__ __forceinline__ void block(uint32_t) { __syncthreads(); }
 };
 template <int WPP>
 struct HalfSyncLds {
-    uint32_t *count;           // LDS, zeroed before the channel starts
+    uint32_t *arrive;          // LDS, WPP words of this half, zeroed before the channel
     uint32_t *stall;           // LDS: set once a wait of the workgroup gave up
     uint32_t limit;
     int *err;
+    int vh;
     bool live;
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    // one LDS load of the half's words (the pointer is cast to the LDS address
+    // space: through a generic pointer a volatile load would be a flat load)
+    __device__ __forceinline__ uint32_t slowest() const {
+        if constexpr (WPP == 2) {
+            const u32x2 a = *(const volatile __attribute__((address_space(3))) u32x2 *)arrive;
+            return min(a.x, a.y);
+        } else {
+            const u32x4 a = *(const volatile __attribute__((address_space(3))) u32x4 *)arrive;
+            return min(min(a.x, a.y), min(a.z, a.w));
+        }
+    }
     __device__ __forceinline__ void block(uint32_t b) {
-        if ((threadIdx.x & 63) == 0)                   // after the wave's partial-output writes
-            __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (live) live = wait_at_least<0>(count, (uint32_t)WPP * (b + 1), limit, err, stall);
+        if ((threadIdx.x & 63) == 0) lds_store_rel(&arrive[vh], b + 1);   // after the partial outputs
+        if (!live) return;
+        uint32_t polls = 0;
+        while (slowest() < b + 1) {
+            if ((++polls & 63) == 0 &&
+                (polls > limit || __hip_atomic_load(stall, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0u)) {
+                flag(err, RANGE_STALL);
+                __hip_atomic_store(stall, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                live = false;
+                return;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");   // the partial outputs after the words
     }
 };
 
@@ -1772,39 +1809,56 @@ __global__ __launch_bounds__(64 * (LPT / 4) * IW) void aeq_pol_kernel(const AeqI
 // section: CDC, resampling to 1 sample/symbol, AEQ) in one launch.
 //
 // A workgroup runs one channel at a time: 2 WPP consumer waves run the two
-// polarisation halves of the AEQ (aeq_pol_run), and one producer wave runs the
-// lane-per-block CDC (cdc_lane_blocks) chunk by chunk, 64 blocks per chunk,
-// into a ring of FUSED_RING chunks in LDS.  The 1-sample/symbol stream never
-// leaves the CU.  Hand-offs, all in LDS:
-//   * produced: chunks written; a consumer loading the window of block b + 2
-//     needs chunk min(16 b + 47, M - 1) / 1024;
+// polarisation halves of the AEQ (aeq_pol_run), and NP producer waves run the
+// lane-per-block CDC (cdc_lane_blocks) 64 blocks (one chunk) at a time into a
+// ring of RING chunks in LDS, producer p taking the chunks c = p mod NP (so
+// that the CDC spreads over the SIMDs the consumers run on).  The
+// 1-sample/symbol stream never leaves the CU.  Hand-offs, all in LDS:
+//   * slots[s]: 1 + the chunk slot s holds, written after the chunk; a consumer
+//     loading the window of block b + 2 needs chunk min(16 b + 47, M - 1) / 1024;
 //   * cons[v]: blocks finished by consumer wave v, published every 16 blocks;
 //     after block b a wave never reads a symbol below 16 (b + 1) + 16 again, so
-//     the producer may rewrite the slot of chunk c - FUSED_RING once every wave
-//     has published 64 (c - FUSED_RING + 1) - 1 blocks.
-// Neither side waits for more than the other can supply with the ring's
-// FUSED_RING >= 2 chunks, so the waits end; each also gives up after a bound
-// (RANGE_STALL).  Channels come from a work counter (queue[0]) in table order
-// (longest chains first), so the longest chains start at once on the first
-// workgroups and the others fill in as workgroups free up; the last workgroup
-// to find the table empty resets the counters (queue[0], queue[1]) for the
-// next launch.  Without a counter (queue = nullptr) workgroup w runs channel w
-// once.  Channels with index < nprio run at raised wave priority.
+//     a producer may rewrite the slot of chunk c - RING once every wave has
+//     published 64 (c - RING + 1) - 1 blocks.
+// Neither side waits for more than the other can supply with RING >= 4 chunks,
+// so the waits end; each also gives up after a bound (RANGE_STALL).  Channels
+// come from a work counter (queue[0]) in table order (longest chains first), so
+// the longest chains start at once on the first workgroups and the others fill
+// in as workgroups free up; the last workgroup to find the table empty resets
+// the counters (queue[0], queue[1]) for the next launch.  Without a counter
+// (queue = nullptr) workgroup w runs channel w once.  Channels with index <
+// nprio run at raised wave priority (the producers one level below their
+// consumers: they run up to RING chunks ahead and only have to keep ahead).
 // ------------------------------------------------------------------------
-template <int LPT>
-__global__ __launch_bounds__(64 * (2 * (LPT / 4) + 1)) __attribute__((amdgpu_waves_per_eu(3))) void cdc_aeq_fused_kernel(
+// HALVES = 2: a workgroup runs both halves of its channel (2 WPP consumer
+// waves, one producer set); HALVES = 1: a workgroup runs one half and has its
+// own producers (the CDC is computed once per half), the halves of a channel
+// in the two workgroups of a pair 8 indices apart (one XCD, as for the plain
+// polarisation-split AEQ), for the shortest serial latency when the GPU is
+// otherwise idle.  HALVES = 1 takes no work counter.
+template <int LPT, int NP, int HALVES>
+__global__ __launch_bounds__(64 * (HALVES * (LPT / 4) + NP)) __attribute__((amdgpu_waves_per_eu(3))) void cdc_aeq_fused_kernel(
     const CdcItem *citems, const AeqItem *aitems, int n, CdcItem csingle, AeqItem asingle,
     uint32_t *queue, int nprio, int *err, uint32_t spin_limit) {
     constexpr int WPP = LPT / 4;
-    constexpr int NC = 2 * WPP;                        // consumer waves
+    constexpr int NC = HALVES * WPP;                   // consumer waves
+    constexpr int RING = NP >= 4 ? 8 : 4;              // a power of two, >= 2 NP
+    static_assert(NP == 1 || NP == 2 || NP == 4, "producer waves");
+    static_assert(HALVES == 1 || HALVES == 2, "halves per workgroup");
     const int v = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // HALVES = 1: workgroup bid runs half (bid >> 3) & 1 of channel (bid >> 4) * 8 + (bid & 7)
+    const unsigned bid = blockIdx.x;
+    const int my_pol = HALVES == 1 ? (int)((bid >> 3) & 1) : 0;
+    const unsigned my_ch = HALVES == 1 ? (bid >> 4) * 8 + (bid & 7) : bid;
 
-    __shared__ __align__(16) uint32_t ring_s[FUSED_RING_WORDS];
-    __shared__ uint32_t produced_s, cons_s[NC], half_s[2], next_s, stall_s;
-    __shared__ int32_t hs_s[2][64];
-    __shared__ __align__(16) uint32_t edge_s[2][64];
+
+    __shared__ __align__(16) uint32_t ring_s[RING * FUSED_CHUNK_SYMS];
+    __shared__ uint32_t slot_s[RING], cons_s[NC], next_s, stall_s;
+    __shared__ __align__(16) uint32_t arrive_s[HALVES][WPP < 2 ? 2 : WPP];
+    __shared__ int32_t hs_s[NP][2][64];
+    __shared__ __align__(16) uint32_t edge_s[NP][2][64];
     __shared__ int32_t aspec_s[NC][4][33];
-    __shared__ int32_t part_s[2][2][4][33];
+    __shared__ int32_t part_s[HALVES][2][4][33];
     __shared__ uint32_t epsw_s[NC][8];
     __shared__ uint32_t winw_s[NC][36];
 
@@ -1812,65 +1866,65 @@ __global__ __launch_bounds__(64 * (2 * (LPT / 4) + 1)) __attribute__((amdgpu_wav
     // Both roles run the same sequence of workgroup barriers, two per channel,
     // in loops of their own (so that neither role's loop-invariant lane
     // constants stay live through the other role's code).  Thread 0 (consumer
-    // wave 0) takes the next channel and clears the hand-off counters.
+    // wave 0) takes the next channel; consumer wave 0 clears the hand-off words.
     auto next_channel = [&](uint32_t iter) -> uint32_t {
         if (threadIdx.x == 0) {
             // with a work counter: the next channel of the table; without: channel
             // blockIdx.x, once
-            next_s = queue ? atomicAdd(&queue[0], 1u) : (iter == 0 ? blockIdx.x : 0xFFFFFFFFu);
-            produced_s = 0;
-            half_s[0] = half_s[1] = 0;
+            next_s = queue ? atomicAdd(&queue[0], 1u) : (iter == 0 ? my_ch : 0xFFFFFFFFu);
             if (iter == 0) stall_s = 0;
         }
-        if (threadIdx.x < NC) cons_s[threadIdx.x] = 0;
+        if (threadIdx.x < NC) {
+            cons_s[threadIdx.x] = 0;
+            arrive_s[threadIdx.x / WPP][threadIdx.x % WPP] = 0;
+        }
+        if (threadIdx.x < RING) slot_s[threadIdx.x] = 0;
         __syncthreads();
         return next_s;
     };
-    if (v == NC) {                                     // producer: the CDC of each channel
+    if (v >= NC) {                                     // producers: the CDC of each channel
+        const int pv = v - NC;
         for (uint32_t iter = 0;; ++iter) {
             const uint32_t chn = next_channel(iter);
             if (chn >= (uint32_t)total) break;
-            // one level below the channel's AEQ waves: the CDC runs up to
-            // FUSED_RING chunks ahead and only has to keep ahead of the chain
             if ((int)chn < nprio) __builtin_amdgcn_s_setprio(2); else __builtin_amdgcn_s_setprio(0);
             const CdcItem *ip = citems ? &citems[chn] : &csingle;
             const uint64_t nb = fnti::cdc_blocks(ip->n);
             const uint32_t nchunks = (uint32_t)((nb + fnti::CDC_CHUNK - 1) / fnti::CDC_CHUNK);
-            cdc_lane_spectra(ip, lane, hs_s);
+            cdc_lane_spectra(ip, lane, hs_s[pv]);
             wave_lds_sync();
             bool live = true;
-            for (uint32_t c = 0; c < nchunks; ++c) {
-                if (c >= (uint32_t)FUSED_RING && live) {   // slot of chunk c - FUSED_RING free?
-                    const uint32_t need = (uint32_t)fnti::CDC_CHUNK * (c - FUSED_RING + 1) - 1;
+            for (uint32_t c = pv; c < nchunks; c += NP) {
+                if (c >= (uint32_t)RING && live) {     // slot of chunk c - RING free?
+                    const uint32_t need = (uint32_t)fnti::CDC_CHUNK * (c - RING + 1) - 1;
 #pragma unroll
                     for (int k = 0; k < NC; ++k)
                         if (live) live = wait_at_least<32>(&cons_s[k], need, spin_limit, err, &stall_s);
                 }
                 uint32_t o[16];
-                cdc_lane_blocks(ip, (uint64_t)c * fnti::CDC_CHUNK, lane, hs_s, edge_s, err, o);
-                uint4 *dst = reinterpret_cast<uint4 *>(
-                    &ring_s[(c % FUSED_RING) * FUSED_CHUNK_SYMS + 16 * lane]);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) dst[q] = make_uint4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
-                if (lane == 0) lds_store_rel(&produced_s, c + 1);   // after the wave's ring writes
+                cdc_lane_blocks(ip, (uint64_t)c * fnti::CDC_CHUNK, lane, hs_s[pv], edge_s[pv], err, o,
+                                reinterpret_cast<uint16_t *>(&ring_s[(c % RING) * FUSED_CHUNK_SYMS]));
+                if (lane == 0) lds_store_rel(&slot_s[c % RING], c + 1);   // after the wave's ring writes
                 wave_lds_sync();
             }
             __syncthreads();                           // the channel is done; LDS is free again
         }
     } else {                                           // consumers: the AEQ halves of each channel
-        const int pol = v / WPP, vh = v % WPP;
+        const int pol = HALVES == 2 ? v / WPP : my_pol, vh = v % WPP;
         for (uint32_t iter = 0;; ++iter) {
             const uint32_t chn = next_channel(iter);
             if (chn >= (uint32_t)total) break;
             if ((int)chn < nprio) __builtin_amdgcn_s_setprio(3); else __builtin_amdgcn_s_setprio(1);
             const AeqItem it = aitems ? aitems[chn] : asingle;
-            AeqSrcRing src{&it, ring_s, &produced_s, &cons_s[v], &stall_s, it.m, spin_limit, err, 0u, true};
+            AeqSrcRing<RING> src{&it, ring_s, slot_s, &cons_s[v], &stall_s, it.m, spin_limit, err, 0u, true};
             if constexpr (WPP == 1) {
                 HalfSyncWg unused;
-                aeq_pol_run<LPT>(it, pol, vh, lane, err, aspec_s[v], part_s[pol], epsw_s[v], winw_s[v], src, unused);
+                aeq_pol_run<LPT>(it, pol, vh, lane, err, aspec_s[v], part_s[v / WPP], epsw_s[v], winw_s[v], src,
+                                 unused);
             } else {
-                HalfSyncLds<WPP> hsync{&half_s[pol], &stall_s, spin_limit, err, true};
-                aeq_pol_run<LPT>(it, pol, vh, lane, err, aspec_s[v], part_s[pol], epsw_s[v], winw_s[v], src, hsync);
+                HalfSyncLds<WPP> hsync{arrive_s[v / WPP], &stall_s, spin_limit, err, vh, true};
+                aeq_pol_run<LPT>(it, pol, vh, lane, err, aspec_s[v], part_s[v / WPP], epsw_s[v], winw_s[v], src,
+                                 hsync);
             }
             __syncthreads();                           // the channel is done; LDS is free again
         }
@@ -2602,10 +2656,12 @@ namespace fnti {
 
 static_assert(RANGE_STALL == kFlagStall, "stall flag bit");
 
+// Producer waves of the fused kernel per AEQ form: as many as waves per
+// polarisation half, one per SIMD the consumers run on.
 template <int LPT>
 static hipError_t fused_kernel_caps(int *per_cu) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, cdc_aeq_fused_kernel<LPT>,
-                                                        64 * (2 * (LPT / 4) + 1), 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, cdc_aeq_fused_kernel<LPT, LPT / 4, 2>,
+                                                        64 * (3 * (LPT / 4)), 0);
 }
 
 int fused_capacity(int lpt) {
@@ -2617,17 +2673,30 @@ int fused_capacity(int lpt) {
     return e == hipSuccess ? per * cus : 0;
 }
 
+unsigned fused_split_grid(int n) { return pol_blocks(n); }
+
 hipError_t launch_fused(const CdcItem *citems, const AeqItem *aitems, int n, const CdcItem &cs,
                         const AeqItem &as, int lpt, uint32_t *queue, unsigned grid, int nprio, int *err,
-                        hipStream_t s, uint32_t spin_limit) {
+                        hipStream_t s, bool split_halves, uint32_t spin_limit) {
     const int total = citems ? n : 1;
     if (total <= 0) return hipSuccess;
     if ((citems == nullptr) != (aitems == nullptr) || n > (1 << 26) || grid == 0) return hipErrorInvalidValue;
+    if (split_halves) {
+        // one workgroup per half: the pairs of every run of 16 workgroups
+        if (queue || grid != pol_blocks(total)) return hipErrorInvalidValue;
+        switch (lpt) {
+        case 4: cdc_aeq_fused_kernel<4, 1, 1><<<grid, 128, 0, s>>>(citems, aitems, n, cs, as, nullptr, nprio, err, spin_limit); break;
+        case 8: cdc_aeq_fused_kernel<8, 2, 1><<<grid, 256, 0, s>>>(citems, aitems, n, cs, as, nullptr, nprio, err, spin_limit); break;
+        case 16: cdc_aeq_fused_kernel<16, 4, 1><<<grid, 512, 0, s>>>(citems, aitems, n, cs, as, nullptr, nprio, err, spin_limit); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     if (queue ? grid > (unsigned)total : grid != (unsigned)total) return hipErrorInvalidValue;
     switch (lpt) {
-    case 4: cdc_aeq_fused_kernel<4><<<grid, 192, 0, s>>>(citems, aitems, n, cs, as, queue, nprio, err, spin_limit); break;
-    case 8: cdc_aeq_fused_kernel<8><<<grid, 320, 0, s>>>(citems, aitems, n, cs, as, queue, nprio, err, spin_limit); break;
-    case 16: cdc_aeq_fused_kernel<16><<<grid, 576, 0, s>>>(citems, aitems, n, cs, as, queue, nprio, err, spin_limit); break;
+    case 4: cdc_aeq_fused_kernel<4, 1, 2><<<grid, 192, 0, s>>>(citems, aitems, n, cs, as, queue, nprio, err, spin_limit); break;
+    case 8: cdc_aeq_fused_kernel<8, 2, 2><<<grid, 384, 0, s>>>(citems, aitems, n, cs, as, queue, nprio, err, spin_limit); break;
+    case 16: cdc_aeq_fused_kernel<16, 4, 2><<<grid, 768, 0, s>>>(citems, aitems, n, cs, as, queue, nprio, err, spin_limit); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -67,7 +67,8 @@ class PlanInfo(ctypes.Structure):
                 ("lead_channels", ctypes.c_int32), ("lead_form", ctypes.c_int32),
                 ("top_channels", ctypes.c_int32), ("top_form", ctypes.c_int32),
                 ("tune_run_ms", ctypes.c_double), ("fused_lpt", ctypes.c_int32),
-                ("fused_grid", ctypes.c_int32), ("fused_prio_channels", ctypes.c_uint64)]
+                ("fused_grid", ctypes.c_int32), ("fused_prio_channels", ctypes.c_uint64),
+                ("fused_split", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
 
 
 class PlanTiming(ctypes.Structure):
@@ -120,7 +121,7 @@ SIGNATURES = {
     "fnt_plan_set_cdc_schedule": (_i32, [_vp, _i32, _i32]),
     "fnt_plan_set_aeq_split": (_i32, [_vp, _u64, _i32, _i32]),
     "fnt_plan_set_lead": (_i32, [_vp, _u64, _i32, _u64, _i32]),
-    "fnt_plan_set_fused": (_i32, [_vp, _i32, _u64]),
+    "fnt_plan_set_fused": (_i32, [_vp, _i32, _u64, _i32]),
     "fnt_plan_run_timed": (_i32, [_vp, ctypes.POINTER(PlanTiming), _vp]),
     "fnt_plan_destroy": (_i32, [_vp]),
     "fnt_now_ns": (_u64, []),
@@ -324,9 +325,9 @@ class Plan:
         _ok(lib().fnt_plan_set_lead(self._h, int(lead_channels), int(lead_form), int(top_channels),
                                     int(top_form)))
 
-    def set_fused(self, lanes_per_transform: int, prio_channels: int = 0):
+    def set_fused(self, lanes_per_transform: int, prio_channels: int = 0, split_halves: bool = False):
         """Every run as one launch of the fused CDC + AEQ kernel (0: off)."""
-        _ok(lib().fnt_plan_set_fused(self._h, int(lanes_per_transform), int(prio_channels)))
+        _ok(lib().fnt_plan_set_fused(self._h, int(lanes_per_transform), int(prio_channels), int(split_halves)))
 
     def run_timed(self, stream=None) -> dict:
         """One run launched directly with events around every launch; blocks

@@ -80,21 +80,23 @@ def check(chans, refs, what):
 SINGLE_N = [0, 1, 2, 31, 33, 64, 2047, 2048, 2049, 8191, 8192, 8193, 4 * 2048 + 37, 9 * 2048 + 1001]
 
 
-@pytest.mark.parametrize("lpt", [4, 8, 16])
-def test_fused_single_channel_lengths(torch_dev, lpt):
-    """One channel per plan, fused with 1, 2 or 4 waves per polarisation half."""
+@pytest.mark.parametrize("lpt,split", [(4, False), (8, False), (16, False), (4, True), (8, True), (16, True)])
+def test_fused_single_channel_lengths(torch_dev, lpt, split):
+    """One channel per plan, fused with 1, 2 or 4 waves per polarisation half,
+    both halves in one workgroup or one workgroup per half."""
     torch, dev = torch_dev
-    rng = np.random.default_rng(lpt)
+    rng = np.random.default_rng(lpt + 100 * split)
     for k, n in enumerate(SINGLE_N):
         c = rand_channel(rng, n, k % 2, k)
         ref = oracle_of(c)
         plan = fnt.Plan(plan_entries(torch, dev, [c]), autotune=False, use_graph=True)
-        plan.set_fused(lpt, k % 2)
+        plan.set_fused(lpt, k % 2, split)
         info = plan.info()
-        assert info["fused_lpt"] == lpt and info["fused_grid"] == 1 and info["graph"] == 1
+        assert info["fused_lpt"] == lpt and info["graph"] == 1 and info["fused_split"] == int(split)
+        assert info["fused_grid"] == (16 if split else 1)
         for rep in range(2):
             reset(torch, dev, [c])
-            note(f"fused single lpt={lpt} n={n} phase={c['phase']} rep={rep}")
+            note(f"fused single lpt={lpt} split={split} n={n} phase={c['phase']} rep={rep}")
             plan.run()
             torch.cuda.synchronize()
             check([c], [ref], f"lpt={lpt} rep={rep}")
@@ -163,6 +165,14 @@ def test_fused_batch_persistent(torch_dev, prio):
     t = plan.run_timed()
     assert t["fused"] == 1 and t["aeq_ms"] > 0
     check(chans, refs, "timed")
+    # one workgroup per half for every channel (no work counter)
+    plan.set_fused(8, prio, True)
+    assert plan.info()["fused_grid"] == 16 * ((len(chans) + 7) // 8)
+    reset(torch, dev, chans)
+    note("fused batch, a workgroup per half")
+    plan.run()
+    torch.cuda.synchronize()
+    check(chans, refs, "split halves")
     # switching the fused schedule off brings back the staged schedule, same results
     plan.set_fused(0)
     assert plan.info()["fused_lpt"] == 0
