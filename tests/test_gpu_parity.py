@@ -480,7 +480,9 @@ def test_plan_determinism_across_schedules(torch_dev):
             (6, -1, 2, 2, 9, 1, 0, True), (12, 1, 1, -1, 12, 1, 3, True), (n - 1, 3, 5, 4, n, 2, 0, True),
             (4, -1, 4, 2, 4, 1, 0, True), (5, -1, 2, 1, 12, 2, 1, False),
             # a first level that pairs with the lead's form runs inside the lead's launch
-            (6, 5, 2, 2, 9, 1, 0, True), (8, 5, 3, -1, 8, 2, 0, True), (n - 1, 5, 7, 2, n, 1, 3, True)]:
+            (6, 5, 2, 2, 9, 1, 0, True), (8, 5, 3, -1, 8, 2, 0, True), (n - 1, 5, 7, 2, n, 1, 3, True),
+            # a fused lead (form 6: the lead's CDC and AEQ in one fused launch; no first level)
+            (6, 6, 0, -1, 9, 1, 0, True), (n - 1, 6, 0, -1, n, 4, 0, True), (3, 6, 0, -1, 12, 2, 1, False)]:
         plan.set_aeq_split(nl, wl, ws)
         plan.set_lead(lead, lf, top, tf)
         info = plan.info()
@@ -509,7 +511,7 @@ def test_plan_determinism_across_schedules(torch_dev):
             for c, (o, w) in zip(pc, ref):
                 assert np.array_equal(c["out"].cpu().numpy(), o) and np.array_equal(c["taps"].cpu().numpy(), w)
     with pytest.raises(fnt.FntError):
-        plan.set_lead(2, 6)
+        plan.set_lead(2, 7)
     with pytest.raises(fnt.FntError):
         plan.set_lead(4, 1, 2, 7)
     plan.set_aeq_waves(1)
