@@ -347,6 +347,29 @@ typedef struct fnt_plan_timing {
 int fnt_plan_run_timed(fnt_plan *plan, fnt_plan_timing *timing, void *stream);
 
 /* ------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under hipGraph stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the fused
+ * run of fnt_plan_run (see fnt_plan_set_fused, one wave per polarisation half)
+ * over up to FNT_NOALLOC_MAX_CHANNELS channels with NO allocation of any kind.
+ * The device tables and the work counter that fnt_plan_create would allocate
+ * live instead in a fixed device array of FNT_NOALLOC_SCRATCH_BYTES inside the
+ * library, one per GPU, held until the process ends.
+ *   dev_channels  fnt_channel_desc[nch] in DEVICE memory (8-byte aligned), each
+ *                 as for fnt_plan_create (the buffers it names: device memory,
+ *                 caller-owned); read on the device, so an invalid descriptor
+ *                 is reported by fnt_check as FNT_E_INVAL and its channel is
+ *                 skipped (nothing of it is read or written), the others run;
+ *   nch           0 .. FNT_NOALLOC_MAX_CHANNELS; more returns FNT_E_INVAL.
+ * Two kernel launches on `stream` (prepare, then fused); results as
+ * fnt_plan_run's.  Every call on one GPU uses that GPU's one array and leaves
+ * it to the next: calls that overlap on one GPU (different streams with no
+ * ordering between them) race and must not be made.
+ * ------------------------------------------------------------------------ */
+#define FNT_NOALLOC_MAX_CHANNELS 4096
+#define FNT_NOALLOC_SCRATCH_BYTES (1 << 20)
+int fnt_cdc_aeq_batch_noalloc(const fnt_channel_desc *dev_channels, uint32_t nch, void *stream);
+
+/* ------------------------------------------------------------------------
  * Serving sessions: continuing per-channel streams with device-resident state.
  * ------------------------------------------------------------------------ */
 

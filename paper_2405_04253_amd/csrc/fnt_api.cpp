@@ -38,13 +38,16 @@ int hip_fail(hipError_t e, const char *what) {
     return fail(FNT_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
+// The per-device error flag is a device variable (each GPU holds its own copy,
+// zero at load), so no call ever allocates it; host code uses the address
+// hipGetSymbolAddress gives for the current device, never the variable's name.
+__device__ int g_fnt_err_flag;
+
 struct DeviceCtx {
     int *d_err = nullptr;
 };
-
 static std::mutex g_ctx_mu;
 static std::map<int, DeviceCtx> g_ctx;
-
 int device_err_flag(int **out) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -52,15 +55,15 @@ int device_err_flag(int **out) {
     std::lock_guard<std::mutex> g(g_ctx_mu);
     DeviceCtx &c = g_ctx[dev];
     if (!c.d_err) {
-        e = hipMalloc(&c.d_err, sizeof(int));
-        if (e != hipSuccess) return fail(FNT_E_NOMEM, "hipMalloc(range flag): %s", hipGetErrorString(e));
-        e = hipMemset(c.d_err, 0, sizeof(int));
-        if (e != hipSuccess) return hip_fail(e, "hipMemset(range flag)");
+        e = hipGetSymbolAddress((void **)&c.d_err, HIP_SYMBOL(g_fnt_err_flag));
+        if (e != hipSuccess) {
+            c.d_err = nullptr;
+            return hip_fail(e, "hipGetSymbolAddress(error flag)");
+        }
     }
     *out = c.d_err;
     return FNT_OK;
 }
-
 int validate_cdc(const fnt_cdc_params *p) {
     if (!p) return fail(FNT_E_INVAL, "cdc params: NULL");
     if (p->ntaps < 1 || p->ntaps > FNT_MAX_CDC_TAPS)
@@ -162,6 +165,9 @@ int fnt_check(void *stream) {
         if (e != hipSuccess) return hip_fail(e, "hipMemset(range flag)");
         if (h & kFlagStall)
             return fail(FNT_E_DEVICE, "a bounded wait of a fused launch gave up (flags 0x%x)", h);
+        if (h & kFlagParam)
+            return fail(FNT_E_INVAL, "a device-side channel descriptor was invalid; its channel was skipped "
+                                     "(flags 0x%x)", h);
         return fail(FNT_E_RANGE, "input value outside its declared width (flags 0x%x)", h);
     }
     return FNT_OK;

@@ -57,6 +57,8 @@ __host__ __device__ inline uint64_t n_symbols(uint64_t n, int phase) {
 // Bit of the per-device error flag latched when a bounded wait of the fused
 // kernel gave up (the other bits are range violations).
 constexpr int kFlagStall = 16;
+// Bit latched when a channel descriptor read on the device was invalid.
+constexpr int kFlagParam = 32;
 // Polls a fused-kernel wait makes before it gives up (seconds of waiting).
 constexpr uint32_t kFusedSpinLimit = 1u << 22;
 

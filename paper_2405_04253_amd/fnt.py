@@ -24,6 +24,7 @@ FNT_ALPHA_2, FNT_ALPHA_SQRT2 = 0, 1
 FNT_SUBMIT_HOST = 1
 FNT_STATE_BYTES = 768
 FNT_STAGE_CDC, FNT_STAGE_AEQ, FNT_STAGE_ALL = 1, 2, 3
+FNT_NOALLOC_MAX_CHANNELS = 4096
 _ERR_NAMES = {1: "FNT_E_INVAL", 2: "FNT_E_RANGE", 3: "FNT_E_NOMEM", 4: "FNT_E_DEVICE",
               5: "FNT_E_BUSY", 6: "FNT_E_STATE"}
 
@@ -124,6 +125,7 @@ SIGNATURES = {
     "fnt_plan_set_fused": (_i32, [_vp, _i32, _u64, _i32]),
     "fnt_plan_run_timed": (_i32, [_vp, ctypes.POINTER(PlanTiming), _vp]),
     "fnt_plan_destroy": (_i32, [_vp]),
+    "fnt_cdc_aeq_batch_noalloc": (_i32, [_vp, _u32, _vp]),
     "fnt_now_ns": (_u64, []),
     "fnt_session_create": (_i32, [ctypes.POINTER(_vp), ctypes.POINTER(SessionConfig)]),
     "fnt_session_add_channel": (_i32, [_vp, _u32, ctypes.POINTER(CdcParams), ctypes.POINTER(AeqParams), _vp]),
@@ -346,6 +348,21 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def channel_table(channels) -> bytes:
+    """fnt_channel_desc[] bytes for channels given as (samples, out, taps,
+    CdcParams, AeqParams) tensors, as Plan takes them."""
+    arr = (ChannelDesc * max(1, len(channels)))()
+    for i, (x, out, taps, cp, ap) in enumerate(channels):
+        arr[i] = ChannelDesc(x.data_ptr(), out.data_ptr(), taps.data_ptr(), x.shape[0], cp, ap)
+    return bytes(arr)[: ctypes.sizeof(ChannelDesc) * len(channels)]
+
+
+def fnt_cdc_aeq_batch_noalloc(dev_table, nch: int, stream=None):
+    """dev_table: uint8 device tensor holding fnt_channel_desc[nch] (channel_table)."""
+    _ok(lib().fnt_cdc_aeq_batch_noalloc(ctypes.c_void_p(dev_table.data_ptr() if nch else 0), int(nch),
+                                       _stream(stream)))
 
 
 # ------------------------------------------------------------------ sessions --
