@@ -34,37 +34,32 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0            # MI355X HBM3E
-# 32-bit VALU: the fastest forms (add, logic) issue a wave64 instruction in 2 cycles
-# per SIMD, i.e. 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 78643.2 G lane-ops/s (the
-# published fp32 vector rate, 157.3 TFLOP/s, counts an FMA as two); SDWA, shifts
-# and 24-bit multiplies take 4 cycles (half this rate)
+# 32-bit integer VALU peak from the chip's unit counts and clock: 256 CUs x 4 SIMDs
+# x 32 lanes per cycle x 2.4 GHz = 78643.2 G lane-ops/s, the published fp32 vector
+# rate (157.3 TFLOP/s) with an FMA counted as one operation.  Measured beside it
+# (measured_peaks): v_add_u32 ~57.9 T, the SDWA fold / shift / 24-bit multiply
+# forms ~37.1 T.
 PEAK_ALU_GOPS = 256 * 4 * 32 * 2.4
 
-# Algorithmic integer operations of the method, per unit:
-# a radix-2 butterfly = 3 ops (add, sub, twiddle), a Z_F product or MAC = 2 ops, etc.
-FNT32_OPS = 80 * 3
-FNT64_OPS = 192 * 3
-# CDC, per block of 32 new instants (both polarisations)
-CDC_OPS_PER_BLOCK = (2 * 2 * 64            # residue packing u, v
-                     + 4 * FNT64_OPS       # forward transforms
-                     + 2 * (128 + 128)     # products and P +- Q
-                     + 4 * FNT64_OPS       # inverse transforms
-                     + 2 * 2 * 32 * 2      # Eq. (7)/(8) scale and lift of the kept outputs
-                     + 16 * 4 * 2)         # requantise the 16 kept symbols
-# AEQ, per block of 16 symbols (= 32 instants)
-AEQ_OPS_PER_BLOCK = (4 * FNT32_OPS         # input spectra
-                     + 256 * 2 * 2         # digit split
-                     + 32 * FNT32_OPS      # tap-digit spectra
-                     + 1024 + 512          # products and pair sums
-                     + 16 * FNT32_OPS      # inverse transforms
-                     + 16 * 4 * 8          # lift + recombine
-                     + 64 * 2              # output rounding
-                     + 16 * 2 * 12         # RDE error terms
-                     + 4096 * 2            # gradient MACs
-                     + 256 * 3)            # tap update
+# Algorithmic integer operations of the method, per unit: a modular add, subtract,
+# shift, product or an integer multiply-accumulate counts one.
+FNT64_OPS = 384 + 129            # 192 butterflies (add + sub) + 129 nontrivial twiddles
+FNT32_OPS = 160 + 49             # 80 butterflies + 49 twiddles
+# CDC, per block of 32 new instants and one polarisation: packing u, v (128),
+# forward FNT64 x 2, products (128), P +- Q (128), the inverse folded to the kept
+# 1-sps outputs (two 32-point inverses of the folded spectra: 2 x (209 + 32)) and
+# scale/lift (64)
+CDC_OPS_PER_POL_BLOCK = 128 + 2 * FNT64_OPS + 128 + 128 + 2 * (FNT32_OPS + 32) + 64      # 1956
+CDC_OPS_PER_BLOCK = 2 * CDC_OPS_PER_POL_BLOCK                                             # 3912
+# AEQ, per block of 16 symbols (= 32 instants): input FNT32 x 4, tap-digit
+# re-transform 32 x FNT32, products (1024), pair sums (512) + 16 inverse FNT32,
+# RDE error (~400), gradient MACs (4096), tap update (~512)
+AEQ_OPS_PER_BLOCK = (4 * FNT32_OPS + 32 * FNT32_OPS + 1024 + (512 + 16 * FNT32_OPS)
+                     + 400 + 4096 + 512)                                                   # 17412
 METRIC = "bit-exact Gsamples/s, batched/served vs plain FNT-CDC+AEQ; p50/p99 latency"
 CDC_BYTES_PER_INSTANT = 4 + 2              # int8[4] in, int8[4] per symbol out
 AEQ_BYTES_PER_SYMBOL = 4 + 8               # int8[4] in, int16[4] out
+FUSED_BYTES_PER_INSTANT = 4 + 4            # int8[4] in, int16[4] per symbol (2 instants) out
 
 
 def kernel_source_hash() -> str:
@@ -171,6 +166,21 @@ def bench_single(args, torch, dev):
     cdc_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
     aeq_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
     ms = wall / steps * 1e3
+    # the same chain as ONE launch (fnt_cdc_aeq: the fused kernel, one workgroup per
+    # polarisation half, the 1-sps stream kept in LDS), same outputs bit for bit
+    ref_out, ref_taps = out.clone(), taps.clone()
+    out1 = torch.empty_like(out)
+
+    def one():
+        taps.copy_(w0)
+        fnt.fnt_cdc_aeq(x, cp, taps, ap, out=out1, stream=stream)
+
+    one()
+    torch.cuda.synchronize()
+    fnt.fnt_check()
+    if not (torch.equal(out1, ref_out) and torch.equal(taps, ref_taps)):
+        raise SystemExit("single stream: fnt_cdc_aeq differs from fnt_cdc + fnt_aeq")
+    one_ms = _time_events(torch, one, max(1, steps - 1), stream)
     blocks_cdc = (n + 31) // 32
     blocks_aeq = (M + 15) // 16
     aeq_ops = AEQ_OPS_PER_BLOCK * blocks_aeq
@@ -195,6 +205,10 @@ def bench_single(args, torch, dev):
         "workload": "plain single-stream FNT-CDC+AEQ (fnt_cdc then fnt_aeq), 1 channel x 2^%d "
                     "symbols/pol, 75 km, 32 taps" % args.log2_symbols,
         "instants": n, "roofline": roof, "kernels": kernels, "gen_s": round(gen_s, 1),
+        "one_launch": {"value": round(n / (one_ms / 1e3) / 1e9, 6), "unit": "Gsamples/s", "ms": round(one_ms, 3),
+                       "kernel": "cdc_aeq_fused_kernel<16, 4, 1>",
+                       "what": "fnt_cdc_aeq: CDC and AEQ in one launch, the 1-sps stream in LDS; bit-identical "
+                               "to the two launches"},
     }
     if args.single_cpu_baseline:
         progress("single: oracle CPU baseline")
@@ -406,7 +420,34 @@ def bench_batched(args, torch, dev):
     d_cdc, d_aeq, d_step = staged_runs()
     plan.set_cdc_variant(0)
     plan.set_aeq_variant(0)
-    plan.set_lead(info["lead_channels"], info["lead_form"], info["top_channels"], info["top_form"])
+    # the fused persistent schedule (one launch, hipGraph), whether or not the tuner chose it
+    progress("batched: fused persistent schedule")
+    fused = {}
+    for prio in (0, 512):
+        plan.set_fused(4, prio)
+        ts = []
+        for k in range(3):
+            taps_all.copy_(w_all)
+            ts.append(plan.run_timed(stream))
+        torch.cuda.synchronize()
+        fnt.fnt_check()
+        for i in pick:
+            if not (torch.equal(entries[i][1], ref_out[i]) and torch.equal(taps_all[i], ref_taps[i])):
+                raise SystemExit(f"fused run differs on channel {i}")
+        fms = float(np.median([t["aeq_ms"] for t in ts]))
+        if not fused or fms < fused["ms"]:
+            fused = {"ms": round(fms, 3), "value": round(inst / (fms / 1e3) / 1e9, 4), "unit": "Gsamples/s",
+                     "prio_channels": prio, "grid": plan.info()["fused_grid"],
+                     "kernel": "cdc_aeq_fused_kernel<4, 1, 2>"}
+    taps_all.copy_(w_all)
+    fused["graph_ms"] = round(_time_events(torch, plan.run, 2, stream), 3)
+    plan.set_fused(0)
+    # back to the tuned schedule
+    if info["fused_lpt"]:
+        plan.set_fused(info["fused_lpt"], info["fused_prio_channels"], info["fused_split"])
+    else:
+        plan.set_aeq_split(info["aeq_long_channels"], info["aeq_waves_long"], info["aeq_waves_per_pol"])
+        plan.set_lead(info["lead_channels"], info["lead_form"], info["top_channels"], info["top_form"])
     value = inst / (ms / 1e3) / 1e9
     aeq_blocks = times[0]["aeq_blocks"]           # the AEQ launch on the launch stream
     lead_blocks = times[0]["aeq_lead_blocks"]
@@ -425,6 +466,9 @@ def bench_batched(args, torch, dev):
     top_name = AEQ_FORM_KERNEL[info["top_form"]] if info["top_channels"] and not fused_top else None
     # the dominant kernel: the AEQ launch with the most algorithmic work (with a
     # lead, a launch on one of the plan's side streams can be the largest)
+    if times[0]["fused"]:
+        kname = "cdc_aeq_fused_kernel<%d, %d, %d>" % (info["fused_lpt"], info["fused_lpt"] // 4,
+                                                       1 if info["fused_split"] else 2)
     launches = [(aeq_blocks, kname, aeq_ms, kname, "launch stream")]
     if lead_name:
         launches.append((lead_blocks, lead_name, lead_ms, lead_name + " (lead)", "lead channels, plan side stream"))
@@ -432,25 +476,34 @@ def bench_batched(args, torch, dev):
         launches.append((top_blocks, top_name, top_ms, top_name + " (first level)",
                          "first lead level, plan third stream"))
     dom_blocks, dom_name, dom_ms, dom_key, dom_where = max(launches, key=lambda x: x[0])
-    dom_ops = AEQ_OPS_PER_BLOCK * dom_blocks
+    if times[0]["fused"]:
+        # the fused launch does every channel's CDC and AEQ: 8 B per instant of HBM
+        dom_ops = AEQ_OPS_PER_BLOCK * dom_blocks + CDC_OPS_PER_BLOCK * cdc_blocks
+        dom_bytes = inst * FUSED_BYTES_PER_INSTANT
+    else:
+        dom_ops = AEQ_OPS_PER_BLOCK * dom_blocks
+        dom_bytes = dom_blocks * 16 * AEQ_BYTES_PER_SYMBOL
     dom_achieved = dom_ops / (dom_ms / 1e3) / 1e9
     dom_traffic, traffic_basis = load_traffic(dom_key, "batched", dom_blocks, per_block=True)
     roof = {"kernel": dom_name, "bound": "alu", "achieved": round(dom_achieved, 1), "peak": PEAK_ALU_GOPS,
             "unit": "Gops/s", "frac": round(dom_achieved / PEAK_ALU_GOPS, 5),
             "traffic": dom_traffic, "traffic_basis": traffic_basis,
             "algorithmic_ops_per_launch": dom_ops,
+            "ops_per_unit": {"aeq_block_16_symbols": AEQ_OPS_PER_BLOCK, "cdc_block_32_instants": CDC_OPS_PER_BLOCK},
             "launch": dom_where,
-            "hbm_algorithmic_gbs": round(dom_blocks * 16 * AEQ_BYTES_PER_SYMBOL / dom_ms / 1e6, 1),
-            "hbm_frac": round(dom_blocks * 16 * AEQ_BYTES_PER_SYMBOL / dom_ms / 1e6 / PEAK_HBM_GBS, 5)}
+            "hbm_algorithmic_gbs": round(dom_bytes / dom_ms / 1e6, 1),
+            "hbm_frac": round(dom_bytes / dom_ms / 1e6 / PEAK_HBM_GBS, 5)}
     kernels = {
-        "cdc": {"kernel": ("cdc_lane_kernel<%d>" % info["cdc_waves_per_group"]) if info["cdc_blocks_per_wave"] == 0
-                          else "cdc_kernel<false>", "ms": round(cdc_ms, 3),
-                "gops": round(cdc_ops / cdc_ms / 1e6, 1), "frac_alu": round(cdc_ops / cdc_ms / 1e6 / PEAK_ALU_GOPS, 5),
-                "gbs": round(inst * CDC_BYTES_PER_INSTANT / cdc_ms / 1e6, 1)},
         "aeq": {"kernel": kname, "ms": round(aeq_ms, 3), "gops": round(achieved, 1), "blocks": aeq_blocks,
                 "us_per_block_per_channel_longest":
                     round(max(aeq_ms, lead_ms) * 1e3 / max(info["aeq_blocks_max"], 1), 4)},
     }
+    if not times[0]["fused"]:                      # a CDC launch of its own (not the fused schedule)
+        kernels["cdc"] = {
+            "kernel": ("cdc_lane_kernel<%d>" % info["cdc_waves_per_group"]) if info["cdc_blocks_per_wave"] == 0
+                      else "cdc_kernel<false>", "ms": round(cdc_ms, 3),
+            "gops": round(cdc_ops / cdc_ms / 1e6, 1), "frac_alu": round(cdc_ops / cdc_ms / 1e6 / PEAK_ALU_GOPS, 5),
+            "gbs": round(inst * CDC_BYTES_PER_INSTANT / cdc_ms / 1e6, 1)}
     if info["lead_channels"]:
         kernels["aeq_lead"] = {
             "kernel": lead_name, "channels": info["lead_channels"] - (info["top_channels"] if top_name else 0),
@@ -479,6 +532,7 @@ def bench_batched(args, torch, dev):
                        "sample": f"{len(sample)} random channels, fnt_cdc_aeq one after another"},
         "roofline": roof,
         "kernels": kernels,
+        "fused_schedule": fused,
         "plan_run_ms": round(run_ms, 3),
         "event_ms_per_step": round(event_step_ms, 3),
         "event_ms_per_step_median": round(event_step_med, 3),
@@ -497,7 +551,7 @@ def bench_batched(args, torch, dev):
         "plan": {k: info[k] for k in ("cdc_waves_per_group", "cdc_blocks_per_wave", "aeq_variant",
                                       "aeq_waves_per_pol", "aeq_waves_long", "aeq_long_channels",
                                       "lead_channels", "lead_form", "top_channels", "top_form", "graph",
-                                      "tune_run_ms")},
+                                      "tune_run_ms", "fused_lpt", "fused_split", "fused_prio_channels")},
         "parity": f"bit-exact vs oracle on channels {pick}", "gen_s": round(gen_s, 1),
         "autotune_s": round(tune_s, 1),
     }
@@ -712,7 +766,12 @@ def main():
         if peaks:
             res["measured_peaks"] = peaks
             if peaks["alu_gops"]:
-                res["roofline"]["frac_of_measured_peak"] = round(res["roofline"]["achieved"] / peaks["alu_gops"], 5)
+                res["roofline"]["measured_fast_gops"] = peaks["alu_gops"]
+                res["roofline"]["frac_of_measured_fast"] = round(res["roofline"]["achieved"] / peaks["alu_gops"], 5)
+            if peaks["alu_base_rate_gops"]:
+                res["roofline"]["measured_base_gops"] = peaks["alu_base_rate_gops"]
+                res["roofline"]["frac_of_measured_base"] = round(
+                    res["roofline"]["achieved"] / peaks["alu_base_rate_gops"], 5)
             progress(f"measured peaks: {peaks}")
     if not args.skip_single:
         progress("plain single stream")

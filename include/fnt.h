@@ -180,7 +180,9 @@ typedef struct fnt_plan_config {
     int32_t device;        /* HIP device ordinal the buffers live on */
     int32_t autotune;      /* 1: time the candidate schedules at create and keep the fastest */
     int32_t use_graph;     /* 1: capture the launch sequence in a hipGraph, replay it in run */
-    int32_t reserved;
+    int32_t tune_quick;    /* with autotune: 1 = a short candidate list (the lane-per-block CDC
+                              groupings, three leads, the fused schedules), for batches whose
+                              every run takes long; 0 = the full sweep */
     const char *tune_cache;/* optional JSON file remembering autotune results (NULL: none) */
 } fnt_plan_config;
 

@@ -672,8 +672,8 @@ static bool valid_form(int f) { return f >= 0 && f <= 5; }
 static int form_rank(int f) { return f == 0 ? 0 : f == 3 ? 1 : (f == 1 || f == 5) ? 2 : f == 2 ? 3 : 4; }
 static int default_wpp(size_t nch) { return nch >= 512 ? 3 : (nch >= 128 ? 2 : 4); }
 
-static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
-    std::string key = tune_key(p);
+static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache, bool quick) {
+    std::string key = tune_key(p) + (quick ? "|quick" : "");
     int w, b, q, ql, lf, tf, fl;
     long long nl, nd, nt, fp;
     if (tune_cache_lookup(cache, key, &w, &b, &q, &ql, &nl, &nd, &lf, &nt, &tf, &fl, &fp) &&
@@ -719,6 +719,7 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
     for (int wpg : {1, 2, 4})
         for (int bpw : {0, 1, 4, 16, 64}) {
             if ((uint64_t)bpw > std::max<uint64_t>(1, p->total_blocks)) continue;
+            if (quick && bpw != 0) continue;            // quick: the lane-per-block groupings only
             double ms = time_it([&] {
                 return run_cdc(p->cdc_dev, (int)p->cdc_host.size(), CdcItem{}, p->total_blocks, p->total_chunks,
                                wpg, bpw, false, p->err, s);
@@ -779,9 +780,11 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
                 });
             };
             reps = 1;                                           // one pass, then the best few again
+            if (quick) splits = {nch / 2};                      // quick: half the channels long, one pairing
             for (size_t nl : splits)
                 for (int ql : {3, 1, 2, 4})                     // long chains: latency-leaning forms
                 for (int q : {0, 3, 1, 2, 4}) {
+                    if (quick && !(ql == 1 && q == 3)) continue;
                     if (nl == 0 && ql != 4) continue;           // no split: one form for all
                     if (nl > 0 && form_rank(q) >= form_rank(ql)) continue;  // cheaper form for the rest
                     Cand c{nl, ql, q, 0};
@@ -861,6 +864,10 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
                             for (int ql : qls) {
                                 const size_t nl = lead + extra;
                                 if (lead >= nch || nl > nch) continue;
+                                // quick: three leads with the latency form after them
+                                if (quick && !(lf == 1 && q == 3 && ql == bql && extra == lead &&
+                                               (lead == 512 || lead == 1024 || lead == 2048)))
+                                    continue;
                                 if (extra == 0 && ql != bql) continue;  // no latency form after the lead
                                 if (extra > 0 && form_rank(q) >= form_rank(ql)) continue;
                                 leads.push_back({lead, nl, q, ql, lf, 0, -1, 0});
@@ -926,12 +933,13 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache) {
                 std::vector<FCand> fc;
                 for (int lpt : {4, 8, 16}) {
                     const int cap = fused_capacity(lpt);
-                    if (cap <= 0) continue;
+                    if (cap <= 0 || (quick && lpt != 4)) continue;
                     if (lpt == 4 || nch <= (size_t)cap)
                         for (size_t prio : {0, 256, 512, 1024, 2048})
-                            if (prio == 0 || prio < nch) fc.push_back({lpt, false, prio, 0});
+                            if ((prio == 0 || prio < nch) && (!quick || prio == 0 || prio == 512))
+                                fc.push_back({lpt, false, prio, 0});
                     // a workgroup per half when the halves of every channel fit at once
-                    if (2 * nch <= (size_t)cap) fc.push_back({lpt, true, nch, 0});
+                    if (2 * nch <= (size_t)cap && !quick) fc.push_back({lpt, true, nch, 0});
                 }
                 auto time_fused = [&](const FCand &c) {
                     p->fused_lpt = c.lpt;
@@ -1115,7 +1123,7 @@ int fnt_plan_create(fnt_plan **out, const fnt_channel_desc *ch, size_t nch, cons
         }
     }
     if (c.autotune && blocks > 0) {
-        if ((rc = plan_autotune(p, s, c.tune_cache))) {
+        if ((rc = plan_autotune(p, s, c.tune_cache, c.tune_quick != 0))) {
             fnt_plan_destroy(p);
             return rc;
         }

@@ -1425,7 +1425,8 @@ __host__ __device__ constexpr unsigned pol_blocks(int n) { return 16u * (unsigne
 // source gives symbol i of the channel's stream (history before 0, zeros past
 // M) for the two window loads before the first block (first), the window of
 // block b + 2 loaded during block b (ahead: symbols 16 b + 16 .. 16 b + 47,
-// index clamped to M - 1), and hears when the wave has finished block b (done).
+// index clamped to M - 1).  A segmented source is told before the blocks
+// [b0, b1) of a segment run (segment) and after (segment_done).
 struct AeqSrcGlobal {          // the stream in device memory
     const AeqItem *it;
     __attribute__((address_space(1))) const uint32_t *base;
@@ -1435,7 +1436,9 @@ struct AeqSrcGlobal {          // the stream in device memory
     __device__ __forceinline__ uint32_t ahead(uint32_t b, int wpos) {
         return base[min<uint64_t>(16 * (uint64_t)b + 16 + wpos, M - 1)];
     }
-    __device__ __forceinline__ void done(uint32_t) {}
+    static constexpr bool kSegmented = false;
+    __device__ __forceinline__ void segment(uint32_t, uint32_t) {}
+    __device__ __forceinline__ void segment_done(uint32_t) {}
 };
 
 // Counters of the fused kernel's hand-offs live in LDS and are read and
@@ -1447,8 +1450,10 @@ struct AeqSrcGlobal {          // the stream in device memory
 // the launch, so every wave still ends.  Polls sleep about 64 * SLEEP cycles
 // each; with the limits the launchers pass a give-up takes seconds, far beyond
 // any legitimate wait (a chunk of CDC or a few blocks of AEQ, microseconds).
+// The loaded word is the same for every lane; readfirstlane tells the compiler
+// so, and the waits become scalar branches instead of exec-masked loops.
 __device__ __forceinline__ uint32_t lds_load_acq(const uint32_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    return __builtin_amdgcn_readfirstlane(__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
 }
 __device__ __forceinline__ void lds_store_rel(uint32_t *p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -1459,7 +1464,8 @@ __device__ __forceinline__ bool wait_at_least(const uint32_t *p, uint32_t target
     uint32_t polls = 0, v;
     while ((v = lds_load_acq(p)) < target) {
         if ((++polls & 63) == 0 &&
-            (polls > limit || __hip_atomic_load(stall, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0u)) {
+            (polls > limit || __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                                  stall, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) != 0u)) {
             flag(err, RANGE_STALL);
             __hip_atomic_store(stall, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             return false;
@@ -1496,19 +1502,22 @@ struct AeqSrcRing {            // the CDC output ring of the fused kernel
             ++have;
         }
     }
+    static constexpr bool kSegmented = true;
     __device__ __forceinline__ void prime() { need(0); }
     __device__ __forceinline__ uint32_t first(int64_t i) const {
         if (i < 0) return aeq_sym(*it, i);
         return (uint64_t)i < M ? ring[i & (WORDS - 1)] : 0u;
     }
-    __device__ __forceinline__ uint32_t ahead(uint32_t b, int wpos) {
-        const uint64_t last = M - 1;
-        need((uint32_t)(min<uint64_t>(16 * (uint64_t)b + 47, last) / FUSED_CHUNK_SYMS));
-        return ring[min<uint64_t>(16 * (uint64_t)b + 16 + wpos, last) & (WORDS - 1)];
+    // every chunk the blocks [b0, b1) read ahead, checked once before they run
+    __device__ __forceinline__ void segment(uint32_t, uint32_t b1) {
+        need((uint32_t)(min<uint64_t>(16 * (uint64_t)(b1 - 1) + 47, M - 1) / FUSED_CHUNK_SYMS));
     }
-    // published every 16 blocks: the producer waits for whole chunks of 64
-    __device__ __forceinline__ void done(uint32_t b) {
-        if (((b + 1) & 15) == 0 && (threadIdx.x & 63) == 0) lds_store_rel(mine, b + 1);
+    __device__ __forceinline__ uint32_t ahead(uint32_t b, int wpos) const {
+        return ring[min<uint64_t>(16 * (uint64_t)b + 16 + wpos, M - 1) & (WORDS - 1)];
+    }
+    // the blocks before b1 are done: published for the producers
+    __device__ __forceinline__ void segment_done(uint32_t b1) {
+        if ((threadIdx.x & 63) == 0) lds_store_rel(mine, b1);
     }
 };
 
@@ -1536,10 +1545,10 @@ struct HalfSyncLds {
     __device__ __forceinline__ uint32_t slowest() const {
         if constexpr (WPP == 2) {
             const u32x2 a = *(const volatile __attribute__((address_space(3))) u32x2 *)arrive;
-            return min(a.x, a.y);
+            return __builtin_amdgcn_readfirstlane(min(a.x, a.y));
         } else {
             const u32x4 a = *(const volatile __attribute__((address_space(3))) u32x4 *)arrive;
-            return min(min(a.x, a.y), min(a.z, a.w));
+            return __builtin_amdgcn_readfirstlane(min(min(a.x, a.y), min(a.z, a.w)));
         }
     }
     __device__ __forceinline__ void block(uint32_t b) {
@@ -1548,7 +1557,8 @@ struct HalfSyncLds {
         uint32_t polls = 0;
         while (slowest() < b + 1) {
             if ((++polls & 63) == 0 &&
-                (polls > limit || __hip_atomic_load(stall, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0u)) {
+                (polls > limit || __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                                      stall, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) != 0u)) {
                 flag(err, RANGE_STALL);
                 __hip_atomic_store(stall, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 live = false;
@@ -1591,7 +1601,11 @@ __device__ __forceinline__ void aeq_pol_run(const AeqItem &it, int pol, int vh, 
         if (val < -8192 || val > 8191) flag(err, RANGE_TAP);
         w[i] = clamp32(val, -8192, 8191);
     }
-    const uint64_t M = it.m;
+    // M and the block count are the same for every lane; readfirstlane keeps them
+    // (and the block loop's counter) in scalar registers whatever way the item
+    // reached this wave
+    const uint64_t M = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(it.m >> 32)) << 32) |
+                       __builtin_amdgcn_readfirstlane((uint32_t)it.m);
     const bool writer = vh == 0;                       // stores the outputs
     const bool tap_owner = td == 0;                    // one of the two digit copies stores taps
     const bool hist_owner = pol == 0 && vh == 0;
@@ -1639,7 +1653,7 @@ __device__ __forceinline__ void aeq_pol_run(const AeqItem &it, int pol, int vh, 
     };
     transform_taps();
 
-    const uint32_t nblocks = (uint32_t)((M + 15) / 16);
+    const uint32_t nblocks = __builtin_amdgcn_readfirstlane((uint32_t)((M + 15) / 16));
     const int c2 = it.const_unit * it.const_unit;
     // 32-bit rounding shifts: |y| < 2^24 with out_shift <= 24; |G| <= 16 * 128 * 16
     // = 2^15, so every mu_shift above 17 rounds G to 0 exactly as 17 does
@@ -1755,11 +1769,23 @@ __device__ __forceinline__ void aeq_pol_run(const AeqItem &it, int pol, int vh, 
         // the next block reuses this wave's window and error bytes: keep the LDS
         // reads above in front of the writes that follow
         wave_lds_sync();
-        src.done(b);
     };
-    for (uint32_t b = 0; b < nblocks; b += 2) {
-        block(b, win_even);
-        if (b + 1 < nblocks) block(b + 1, win_odd);
+    if constexpr (Src::kSegmented) {
+        // segments of 64 blocks (an even count keeps each block's window register)
+        for (uint32_t b0 = 0; b0 < nblocks; b0 += 64) {
+            const uint32_t b1 = min(b0 + 64u, nblocks);
+            src.segment(b0, b1);
+            for (uint32_t b = b0; b < b1; b += 2) {
+                block(b, win_even);
+                if (b + 1 < b1) block(b + 1, win_odd);
+            }
+            src.segment_done(b1);
+        }
+    } else {
+        for (uint32_t b = 0; b < nblocks; b += 2) {
+            block(b, win_even);
+            if (b + 1 < nblocks) block(b + 1, win_odd);
+        }
     }
     if (bad) flag(err, RANGE_SYMBOL);
     finish();
@@ -1816,10 +1842,11 @@ __global__ __launch_bounds__(64 * (LPT / 4) * IW) void aeq_pol_kernel(const AeqI
 // 1-sample/symbol stream never leaves the CU.  Hand-offs, all in LDS:
 //   * slots[s]: 1 + the chunk slot s holds, written after the chunk; a consumer
 //     loading the window of block b + 2 needs chunk min(16 b + 47, M - 1) / 1024;
-//   * cons[v]: blocks finished by consumer wave v, published every 16 blocks;
-//     after block b a wave never reads a symbol below 16 (b + 1) + 16 again, so
-//     a producer may rewrite the slot of chunk c - RING once every wave has
-//     published 64 (c - RING + 1) - 1 blocks.
+//   * cons[v]: blocks finished by consumer wave v, published after every
+//     segment of 64 blocks (the chunks a segment reads ahead are checked once,
+//     before it); after block b a wave never reads a symbol below
+//     16 (b + 1) + 16 again, so a producer may rewrite the slot of chunk
+//     c - RING once every wave has published 64 (c - RING + 1) - 1 blocks.
 // Neither side waits for more than the other can supply with RING >= 4 chunks,
 // so the waits end; each also gives up after a bound (RANGE_STALL).  Channels
 // come from a work counter (queue[0]) in table order (longest chains first), so
@@ -1838,7 +1865,7 @@ __global__ __launch_bounds__(64 * (LPT / 4) * IW) void aeq_pol_kernel(const AeqI
 // otherwise idle.  HALVES = 1 takes no work counter.
 template <int LPT, int NP, int HALVES>
 __global__ __launch_bounds__(64 * (HALVES * (LPT / 4) + NP)) __attribute__((amdgpu_waves_per_eu(3))) void cdc_aeq_fused_kernel(
-    const CdcItem *citems, const AeqItem *aitems, int n, CdcItem csingle, AeqItem asingle,
+    const CdcItem *__restrict__ citems, const AeqItem *__restrict__ aitems, int n, CdcItem csingle, AeqItem asingle,
     uint32_t *queue, int nprio, int *err, uint32_t spin_limit) {
     constexpr int WPP = LPT / 4;
     constexpr int NC = HALVES * WPP;                   // consumer waves
@@ -1880,7 +1907,9 @@ __global__ __launch_bounds__(64 * (HALVES * (LPT / 4) + NP)) __attribute__((amdg
         }
         if (threadIdx.x < RING) slot_s[threadIdx.x] = 0;
         __syncthreads();
-        return next_s;
+        // the same for every lane: the channel's item and all that follows from it
+        // stay in scalar registers and branch uniformly
+        return __builtin_amdgcn_readfirstlane(next_s);
     };
     if (v >= NC) {                                     // producers: the CDC of each channel
         const int pv = v - NC;

@@ -53,7 +53,7 @@ class ChannelDesc(ctypes.Structure):
 
 class PlanConfig(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("tune_quick", ctypes.c_int32),
                 ("tune_cache", ctypes.c_char_p)]
 
 
@@ -278,7 +278,7 @@ def fnt_cdc_aeq(samples, cdc: CdcParams, taps, aeq: AeqParams, out=None, stream=
 class Plan:
     """fnt_plan_*: many independent channels, one launch sequence (optionally a hipGraph)."""
 
-    def __init__(self, channels, autotune=False, use_graph=True, tune_cache=None, stream=None):
+    def __init__(self, channels, autotune=False, use_graph=True, tune_cache=None, stream=None, tune_quick=False):
         """channels: list of (samples int8 [n,4], out int16 [M,4], taps int16 [4,4,16],
         CdcParams, AeqParams) with all tensors on the GPU."""
         import torch
@@ -290,7 +290,7 @@ class Plan:
             _need(taps, torch.int16, (4, 16), "taps")
             arr[i] = ChannelDesc(x.data_ptr(), out.data_ptr(), taps.data_ptr(), x.shape[0], cp, ap)
         dev = channels[0][0].device.index if channels else torch.cuda.current_device()
-        cfg = PlanConfig(dev or 0, int(autotune), int(use_graph), 0,
+        cfg = PlanConfig(dev or 0, int(autotune), int(use_graph), int(tune_quick),
                          tune_cache.encode() if tune_cache else None)
         h = ctypes.c_void_p()
         _ok(lib().fnt_plan_create(ctypes.byref(h), arr, len(channels), ctypes.byref(cfg), _stream(stream)))

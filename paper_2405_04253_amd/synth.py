@@ -364,3 +364,132 @@ def gen_channel_torch(nsym: int, fibre_km: float, osnr_db: float, seed: int, dev
     rms = float(torch.sqrt(torch.mean(out.double() ** 2)))
     q = torch.clamp(torch.round(out * (SAMPLE_RMS / max(rms, 1e-30))), -16, 15).to(torch.int8).contiguous()
     return q, taps, shift, unit
+
+
+# ---------------------------------------------------------------------------
+# Batched generation (large workloads): the same recipe as gen_channel_torch,
+# many channels per FFT call and no host synchronisation per channel.
+# ---------------------------------------------------------------------------
+def design_cdc_taps_many(fibre_kms, ntaps=None):
+    """design_cdc_taps for many fibre lengths at once: channels with the same tap
+    count share the least-squares matrix, so one solve with many right-hand
+    sides serves them all.  Returns a list of (taps, shift, gain)."""
+    fibre_kms = [float(z) for z in fibre_kms]
+    Ls = [cdc_tap_count(z) if ntaps is None else int(ntaps) for z in fibre_kms]
+    fs = BAUD * SPS
+    fgrid = np.linspace(-fs / 2, fs / 2, 1024, endpoint=False)
+    nu = np.abs(fgrid) / BAUD
+    lo, hi = (1 - ROLLOFF) / 2, (1 + ROLLOFF) / 2
+    rc = np.where(nu <= lo, 1.0, np.where(nu <= hi, 0.5 * (1 + np.cos(np.pi / ROLLOFF * (nu - lo))), 0.0))
+    w = np.sqrt(rc + 0.01)
+    out = [None] * len(fibre_kms)
+    for L in sorted(set(Ls)):
+        idx = [i for i, l in enumerate(Ls) if l == L]
+        n = np.arange(L) - L // 2
+        a = np.exp(-2j * np.pi * np.outer(fgrid, n) / fs)
+        ks = np.array([dispersion_beta(fibre_kms[i]) for i in idx])
+        target = np.exp(1j * np.outer(fgrid ** 2, ks))          # [1024, channels]
+        h, *_ = np.linalg.lstsq(a * w[:, None], target * w[:, None], rcond=None)
+        for j, i in enumerate(idx):
+            hj = h[:, j]
+            scale = 31.0 / max(np.abs(hj.real).max(), np.abs(hj.imag).max())
+            hq = np.stack([np.round(hj.real * scale), np.round(hj.imag * scale)], axis=1)
+            hq = np.clip(hq, -32, 31).astype(np.int8)
+            hint = hq[:, 0].astype(np.float64) + 1j * hq[:, 1].astype(np.float64)
+            resp = a @ hint
+            gain = math.sqrt(float(np.sum(rc * np.abs(resp) ** 2) / np.sum(rc)))
+            shift = int(max(0, round(math.log2(max(gain, 1.0)))))
+            out[i] = (hq, shift, gain)
+    return out
+
+
+def gen_batch_torch(specs, device, max_elems: int = 1 << 26, progress=None):
+    """Generate many channels (ChannelSpec list) with gen_channel_torch's recipe:
+    16QAM symbols, Tx RRC, CD, a Haar-random U(2) rotation, AWGN from OSNR,
+    Rx RRC, per-channel scaling to SAMPLE_RMS and rounding to 5 bit.  Channels
+    with the same power-of-two FFT length go through the FFTs together, up to
+    max_elems complex samples at a time, with no host synchronisation per
+    channel.  Every channel's samples come from its own seed (its symbols, noise
+    and rotation), independent of the others.  Returns (buffer, channels): one
+    int8 device tensor holding every channel's samples back to back (16-byte
+    aligned), and per channel (samples view [2*nsym][4], taps, requant_shift,
+    const_unit)."""
+    import torch
+    specs = list(specs)
+    designs = design_cdc_taps_many([sp.fibre_km for sp in specs])
+    offs, tot = [], 0
+    for sp in specs:
+        offs.append(tot)
+        tot += ((SPS * int(sp.nsym) * 4) + 15) // 16 * 16
+    buf = torch.empty(max(tot, 16), dtype=torch.int8, device=device)
+    views = [buf[o:o + SPS * int(sp.nsym) * 4].view(SPS * int(sp.nsym), 4) for o, sp in zip(offs, specs)]
+    groups = {}
+    for i, sp in enumerate(specs):
+        if int(sp.nsym) > 0:
+            groups.setdefault(1 << (int(sp.nsym) - 1).bit_length(), []).append(i)
+    done = 0
+    rrc_cache = {}
+    for ng in sorted(groups):
+        nfft = SPS * ng
+        if nfft not in rrc_cache:
+            rrc_cache[nfft] = _rrc_on_device(nfft, str(device))
+        rrc, p_rrc = rrc_cache[nfft]
+        fhz2 = (torch.fft.fftfreq(nfft, device=device, dtype=torch.float64) * (BAUD * SPS)) ** 2
+        idx = groups[ng]
+        per = max(1, max_elems // nfft)
+        for b0 in range(0, len(idx), per):
+            part = idx[b0:b0 + per]
+            B = len(part)
+            nsym = torch.tensor([int(specs[i].nsym) for i in part], device=device)
+            # per-channel symbols and noise from per-channel generators (seeded by the spec)
+            sym = torch.empty((B, ng, 4), dtype=torch.float32, device=device)
+            noise = torch.empty((B, 2, 2, nfft), dtype=torch.float32, device=device)
+            rots = np.empty((B, 2, 2), np.complex64)
+            for j, i in enumerate(part):
+                g = torch.Generator(device=device)
+                g.manual_seed(int(specs[i].seed) & 0x7FFFFFFFFFFFFFFF)
+                sym[j] = torch.randint(0, 4, (ng, 4), generator=g, device=device).float() * 2 - 3
+                noise[j] = torch.randn((2, 2, nfft), generator=g, device=device)
+                rots[j] = _haar_u2(np.random.default_rng(specs[i].seed))
+            sym *= (torch.arange(ng, device=device)[None, :] < nsym[:, None]).float()[:, :, None]
+            beta = torch.tensor([dispersion_beta(specs[i].fibre_km) for i in part], device=device,
+                                dtype=torch.float64)
+            cd = torch.polar(torch.ones((B, nfft), device=device, dtype=torch.float64),
+                             -beta[:, None] * fhz2[None, :]).to(torch.complex64)
+            shape = (rrc[None, :] * cd)
+            del cd
+            spec = [torch.fft.fft(torch.complex(sym[:, :, 2 * p], sym[:, :, 2 * p + 1]), dim=1).repeat(1, SPS) * shape
+                    for p in range(2)]
+            del sym, shape
+            u = torch.from_numpy(rots).to(device)
+            rot = [u[:, 0, 0, None] * spec[0] + u[:, 0, 1, None] * spec[1],
+                   u[:, 1, 0, None] * spec[0] + u[:, 1, 1, None] * spec[1]]
+            del spec
+            snr = torch.tensor([10 ** (specs[i].osnr_db / 10) * 12.5e9 / BAUD for i in part], device=device)
+            out = torch.empty((B, nfft, 4), dtype=torch.float32, device=device)
+            for p in range(2):
+                sig = rot[p] * rrc[None, :]
+                p_sig = torch.mean(sig.real ** 2 + sig.imag ** 2, dim=1) / nfft
+                sigma2 = p_sig / snr / max(p_rrc, 1e-12)
+                nz = torch.complex(noise[:, p, 0], noise[:, p, 1]) * torch.sqrt(sigma2 * nfft / 2)[:, None]
+                y = torch.fft.ifft(sig + nz * rrc[None, :], dim=1)
+                out[:, :, 2 * p] = y.real
+                out[:, :, 2 * p + 1] = y.imag
+                del sig, nz, y
+            del rot, noise
+            valid = (torch.arange(nfft, device=device)[None, :] < (SPS * nsym)[:, None]).double()
+            ms = torch.sum((out.double() ** 2).sum(dim=2) * valid, dim=1) / (4 * SPS * nsym).double()
+            scale = (SAMPLE_RMS / torch.clamp(torch.sqrt(ms), min=1e-30)).float()
+            q = torch.clamp(torch.round(out * scale[:, None, None]), -16, 15).to(torch.int8)
+            del out
+            for j, i in enumerate(part):
+                views[i].copy_(q[j, :SPS * int(specs[i].nsym)])
+            del q
+            done += B
+            if progress:
+                progress(done, len(specs))
+    chans = []
+    for i, sp in enumerate(specs):
+        taps, shift, gain = designs[i]
+        chans.append((views[i], taps, shift, const_unit_for(gain, shift)))
+    return buf, chans
