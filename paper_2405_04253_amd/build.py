@@ -58,6 +58,15 @@ def build(force: bool = True, jobs: int = 3, out: str | None = None, defines=())
     return lib
 
 
+COUNT_LIB = os.path.join(HERE, "libfnt_count.so")
+
+
+def build_counting() -> str:
+    """The test-only counting build: the same library with every Fermat-domain
+    spectral product of the CDC and AEQ kernels counted (fnt_debug_product_counts)."""
+    return build(force=True, out=COUNT_LIB, defines=("FNT_COUNT_PRODUCTS=1",))
+
+
 def build_probe() -> str:
     tmp = PROBE_LIB + ".tmp"
     _run(["hipcc", "-x", "hip", *HIP_FLAGS, "-shared", "-o", tmp, os.path.join(CSRC, PROBE_SOURCE)])

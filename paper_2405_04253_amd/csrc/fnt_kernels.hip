@@ -33,7 +33,26 @@ using namespace fntd;
 using fnti::AeqItem;
 using fnti::CdcItem;
 
+// Test-only counting build (FNT_COUNT_PRODUCTS=1, a separate library): every
+// lane adds the Fermat-domain spectral products it computes (the true
+// multiplications Tab. 1 counts) to g_fnt_products[0] (CDC) and [1] (AEQ).
+#ifndef FNT_COUNT_PRODUCTS
+#define FNT_COUNT_PRODUCTS 0
+#endif
+#if FNT_COUNT_PRODUCTS
+__device__ unsigned long long g_fnt_products[2];
+#endif
+
 namespace {
+
+__device__ __forceinline__ void count_products(int which, uint32_t n) {
+#if FNT_COUNT_PRODUCTS
+    atomicAdd(&g_fnt_products[which], (unsigned long long)n);
+#else
+    (void)which;
+    (void)n;
+#endif
+}
 
 __device__ __forceinline__ void flag(int *err, int bit) {
     if (err) atomicOr(err, bit);
@@ -714,6 +733,7 @@ __device__ __forceinline__ bool cdc_lane_blocks(const CdcItem *ip, uint64_t lb0,
         }
     }
     if ((bad & 0xE0E0E0E0u) != 0u) flag(err, RANGE_SAMPLE);
+    if (active) count_products(0, 2 * 2 * 64);         // U H+, V H- over 64 bins, both polarisations
     return active;
 }
 
@@ -1724,6 +1744,7 @@ __device__ __forceinline__ void aeq_pol_run(const AeqItem &it, int pol, int vh, 
             int32_t P = mulmod(aspec[tS1][t + LPT * j], W[j]);
             Y[j] = P + s1_partner<LPT>(P);              // pair sum over S1 = 2g, 2g+1
         }
+        count_products(1, PPL);                         // A_S1 W for this lane's bins
         ifnt_upper_lpt<LPT>(Y, t, K);
         if (ts == 0) {
 #pragma unroll
@@ -2860,3 +2881,19 @@ hipError_t launch_aeq(const AeqItem *items, int nitems, const AeqItem &single, i
 }
 
 }  // namespace fnti
+
+#if FNT_COUNT_PRODUCTS
+// Counting build only: read (and with reset, clear) the product counters.
+extern "C" int fnt_debug_product_counts(uint64_t *cdc, uint64_t *aeq, int reset) {
+    unsigned long long h[2] = {0, 0};
+    if (hipDeviceSynchronize() != hipSuccess) return FNT_E_DEVICE;
+    if (hipMemcpyFromSymbol(h, HIP_SYMBOL(g_fnt_products), sizeof h) != hipSuccess) return FNT_E_DEVICE;
+    if (cdc) *cdc = h[0];
+    if (aeq) *aeq = h[1];
+    if (reset) {
+        const unsigned long long z[2] = {0, 0};
+        if (hipMemcpyToSymbol(HIP_SYMBOL(g_fnt_products), z, sizeof z) != hipSuccess) return FNT_E_DEVICE;
+    }
+    return FNT_OK;
+}
+#endif
