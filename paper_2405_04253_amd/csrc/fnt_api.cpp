@@ -1049,6 +1049,7 @@ int fnt_plan_create(fnt_plan **out, const fnt_channel_desc *ch, size_t nch, cons
         hipError_t e = hipMalloc(&p->abuf, sym_total * 4);
         if (e != hipSuccess) {
             delete p;
+            (void)hipGetLastError();   // not left for the caller's next launch check
             return fail(FNT_E_NOMEM, "plan: scratch of %llu bytes: %s", (unsigned long long)(sym_total * 4),
                         hipGetErrorString(e));
         }
@@ -1083,6 +1084,7 @@ int fnt_plan_create(fnt_plan **out, const fnt_channel_desc *ch, size_t nch, cons
         if (e == hipSuccess) e = hipMalloc(&p->aeq_dev, nch * sizeof(AeqItem));
         if (e != hipSuccess) {
             fnt_plan_destroy(p);
+            (void)hipGetLastError();   // not left for the caller's next launch check
             return fail(FNT_E_NOMEM, "plan: tables: %s", hipGetErrorString(e));
         }
         e = hipMemcpyAsync(p->cdc_dev, p->cdc_host.data(), nch * sizeof(CdcItem), hipMemcpyHostToDevice, s);
@@ -1098,6 +1100,7 @@ int fnt_plan_create(fnt_plan **out, const fnt_channel_desc *ch, size_t nch, cons
         hipError_t eq = hipMalloc(&p->queue, 2 * sizeof(uint32_t));
         if (eq != hipSuccess) {
             fnt_plan_destroy(p);
+            (void)hipGetLastError();   // not left for the caller's next launch check
             return fail(FNT_E_NOMEM, "plan: work counter: %s", hipGetErrorString(eq));
         }
         eq = hipMemset(p->queue, 0, 2 * sizeof(uint32_t));

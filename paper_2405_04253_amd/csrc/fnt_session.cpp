@@ -516,6 +516,7 @@ int fnt_session_create(fnt_session **out, const fnt_session_config *cfg) {
     }
     if (e != hipSuccess) {
         free_session(s);
+        (void)hipGetLastError();       // the failed call must not surface in the caller's next launch check
         return fail(FNT_E_NOMEM, "session: allocation: %s", hipGetErrorString(e));
     }
     s->pool.init(pool);

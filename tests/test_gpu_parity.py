@@ -760,6 +760,34 @@ def test_session_cancel_and_destroy_in_flight(torch_dev):
     fnt.fnt_check()
 
 
+def test_allocation_failure_leaves_sessions_usable(torch_dev):
+    """A session or plan whose device memory cannot be allocated fails with
+    FNT_E_NOMEM and frees what it took; a session created before keeps working."""
+    torch, dev = torch_dev
+    ch = synth.gen_channel(16 * 40, 55.0, 22.0, seed=95)
+    x = to_dev(torch, dev, ch.samples)
+    cp, ap = fnt.cdc_params(ch.taps, ch.requant_shift), fnt.aeq_params(**synth.aeq_params_for(ch))
+    outr, _ = _oracle_stream(ch)
+    s = fnt.Session(max_channels=2, hbm_budget_bytes=16 << 20, chunk_blocks=4)
+    s.add_channel(0, cp, ap)
+    out = torch.zeros((ch.n // 2, 4), dtype=torch.int16, device=dev)
+    half = ch.n // 64 * 32
+    s.wait(s.submit(0, x[:half], out[:half // 2]))
+    free0, _ = torch.cuda.mem_get_info()
+    note("session with an HBM budget beyond the device")
+    for _ in range(2):
+        with pytest.raises(fnt.FntError) as e:
+            fnt.Session(max_channels=4, hbm_budget_bytes=1 << 50, chunk_blocks=8)
+        assert e.value.code == fnt.FNT_E_NOMEM
+    free1, _ = torch.cuda.mem_get_info()
+    assert abs(free1 - free0) < (64 << 20)       # nothing of the failed sessions is left behind
+    # the first session continues its channel's stream, bit-exact
+    s.wait(s.submit(0, x[half:], out[half // 2:]))
+    assert np.array_equal(out.cpu().numpy(), outr)
+    s.close()
+    fnt.fnt_check()
+
+
 def test_session_alone_equals_in_mix(torch_dev):
     torch, dev = torch_dev
     chans = _session_channels(12, 60, seed=5)
