@@ -137,28 +137,13 @@ __device__ __forceinline__ int32_t mulmod(int32_t v, int32_t c) {
 // A twiddle constant the compiler may not look into: powers of two would
 // otherwise be strength-reduced from the 24-bit multiply of mulmod into a
 // longer 64-bit shift sequence.  Non-volatile, so it is still hoisted.
-#ifndef FNT_OPAQUE_TWIDDLES
-#define FNT_OPAQUE_TWIDDLES 1
-#endif
-#ifndef FNT_BRANCHFREE_SELECT
-#define FNT_BRANCHFREE_SELECT 0
-#endif
 __device__ __forceinline__ int32_t opq(int32_t v) {
-#if FNT_OPAQUE_TWIDDLES
     __asm__("" : "+v"(v));
-#endif
     return v;
 }
 
-// Branch-free per-lane select (a where c, else b).  The empty asm pins the
-// computation of `a` in front of the select, so the compiler emits a
-// v_cndmask instead of sinking `a` into a divergent branch.
-__device__ __forceinline__ int32_t blend(bool c, int32_t a, int32_t b) {
-#if FNT_BRANCHFREE_SELECT
-    __asm__ volatile("" : "+v"(a));                   // a is materialised for every lane
-#endif
-    return c ? a : b;                                  // -> v_cndmask_b32
-}
+// Per-lane select (a where c, else b) -> v_cndmask_b32.
+__device__ __forceinline__ int32_t blend(bool c, int32_t a, int32_t b) { return c ? a : b; }
 
 // Centred representative in [-32768, 32768] of a loose residue (any int32).
 __device__ __forceinline__ int32_t lift_loose(int32_t r) {
@@ -184,21 +169,10 @@ __device__ __forceinline__ int32_t xor_lane(int32_t v) {
 // hold position l ^ 3, so the partner at position distance 4 is the DPP
 // row_half_mirror lane (l ^ 7) and every in-row exchange of a transform is a
 // DPP move (distance 1, 2: quad_perm; 4: row_half_mirror; 8: row_ror).
-#ifndef FNT_DPP_LANE_ORDER
-#define FNT_DPP_LANE_ORDER 1
-#endif
-__device__ __forceinline__ int lane_pos(int l) {
-#if FNT_DPP_LANE_ORDER
-    return (l & 4) ? (l ^ 3) : l;
-#else
-    return l;
-#endif
-}
+__device__ __forceinline__ int lane_pos(int l) { return (l & 4) ? (l ^ 3) : l; }
 template <int X>
 __device__ __forceinline__ int32_t xor_pos(int32_t v) {
-#if FNT_DPP_LANE_ORDER
     if constexpr (X == 4) return __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, true);  // row_half_mirror
-#endif
     return xor_lane<X>(v);
 }
 
