@@ -209,6 +209,10 @@ def bench_single(args, torch, dev):
                        "kernel": "cdc_aeq_fused_kernel<16, 4, 1>",
                        "what": "fnt_cdc_aeq: CDC and AEQ in one launch, the 1-sps stream in LDS; bit-identical "
                                "to the two launches"},
+        "launches": [launch_entry("cdc_lane_kernel<4>", "cdc_lane_kernel<4>", 0, blocks_cdc, n),
+                     launch_entry("aeq_pol_kernel<16, 1>", "aeq_pol_kernel<16, 1>", blocks_aeq),
+                     launch_entry("cdc_aeq_fused_kernel<16, 4, 1>", "cdc_aeq_fused_kernel<16, 4, 1>", blocks_aeq,
+                                  blocks_cdc, n)],
     }
     if args.single_cpu_baseline:
         progress("single: oracle CPU baseline")
@@ -242,6 +246,59 @@ def split_fusable(long_form: int, rest_form: int) -> bool:
 
 def split_name(long_form: int, rest_form: int) -> str:
     return "aeq_split_kernel<%d, %d, %d>" % (long_form, rest_form, SPLIT_WPG[long_form])
+
+
+SCHEDULE_KEYS = ("cdc_variant", "cdc_waves_per_group", "cdc_blocks_per_wave", "aeq_variant", "aeq_waves_per_pol",
+                 "aeq_waves_long", "aeq_long_channels", "lead_channels", "lead_form", "top_channels", "top_form",
+                 "fused_lpt", "fused_prio_channels", "fused_split")
+
+
+def apply_schedule(plan, s: dict):
+    """Sets a plan's schedule from keys of Plan.info() (a stored tuner choice, or
+    one written by hand for a profile); absent keys take the plan's defaults."""
+    plan.set_cdc_schedule(int(s.get("cdc_waves_per_group", 2)), int(s.get("cdc_blocks_per_wave", 0)))
+    plan.set_cdc_variant(int(s.get("cdc_variant", 0)))
+    plan.set_aeq_variant(int(s.get("aeq_variant", 0)))
+    if s.get("fused_lpt"):
+        plan.set_fused(int(s["fused_lpt"]), int(s.get("fused_prio_channels", 0)), bool(s.get("fused_split", 0)))
+        return
+    plan.set_aeq_split(int(s.get("aeq_long_channels", 0)), int(s.get("aeq_waves_long", 1)),
+                       int(s.get("aeq_waves_per_pol", 0)))
+    plan.set_lead(int(s.get("lead_channels", 0)), int(s.get("lead_form", -1)), int(s.get("top_channels", 0)),
+                  int(s.get("top_form", -1)))
+
+
+def launch_entry(kernel, key, aeq_blocks=0, cdc_blocks=0, instants=0):
+    """One launch of a step: the kernel name as a kernel trace shows it, the key its
+    counters are stored under, its units and their algorithmic work and bytes
+    (AEQ 12 B per symbol, CDC 6 B per instant, the fused chain 8 B per instant)."""
+    e = {"kernel": kernel, "key": key, "aeq_blocks": aeq_blocks, "cdc_blocks": cdc_blocks,
+         "algorithmic_ops": AEQ_OPS_PER_BLOCK * aeq_blocks + CDC_OPS_PER_BLOCK * cdc_blocks}
+    if aeq_blocks and cdc_blocks:
+        e["algorithmic_bytes"] = instants * FUSED_BYTES_PER_INSTANT
+    elif cdc_blocks:
+        e["algorithmic_bytes"] = instants * CDC_BYTES_PER_INSTANT
+    else:
+        e["algorithmic_bytes"] = aeq_blocks * 16 * AEQ_BYTES_PER_SYMBOL
+    return e
+
+
+def launches_of(info, timing, kname, lead_name, top_name, aeq_blocks, lead_blocks, top_blocks, cdc_blocks, inst):
+    """The plan's launches in one step (launch_entry)."""
+    if timing["fused"]:
+        return [launch_entry(kname, kname, aeq_blocks, cdc_blocks, inst)]
+    cdc = ("cdc_lane_kernel<%d>" % info["cdc_waves_per_group"]) if info["cdc_blocks_per_wave"] == 0 \
+        else "cdc_kernel<false>"
+    if info["cdc_variant"] == 1:
+        cdc = "cdc_direct_kernel<%d>" % info["cdc_waves_per_group"]
+    out = [launch_entry(cdc, cdc, 0, cdc_blocks, inst)]
+    if "+" not in kname:
+        out.append(launch_entry(kname, kname, aeq_blocks))
+    if lead_name:
+        out.append(launch_entry(lead_name, lead_name + " (lead)", lead_blocks))
+    if top_name:
+        out.append(launch_entry(top_name, top_name + " (first level)", top_blocks))
+    return out
 
 
 def aeq_kernel_name(info) -> str:
@@ -327,8 +384,12 @@ def bench_batched(args, torch, dev):
         inst += q.shape[0]
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
-    progress(f"batched: plan create + autotune over {len(entries)} channels")
-    plan = fnt.Plan(entries, autotune=True, use_graph=True, stream=stream, tune_cache=args.tune_cache)
+    sched = json.loads(args.schedule) if args.schedule else None
+    progress(f"batched: plan create over {len(entries)} channels, " +
+             (f"schedule {sched}" if sched else "autotuned"))
+    plan = fnt.Plan(entries, autotune=sched is None, use_graph=True, stream=stream, tune_cache=args.tune_cache)
+    if sched:
+        apply_schedule(plan, sched)
     torch.cuda.synchronize()
     tune_s = time.perf_counter() - t0
     info = plan.info()
@@ -378,76 +439,82 @@ def bench_batched(args, torch, dev):
         outr, wr, _ = O.cdc_aeq(q.cpu().numpy(), taps, sh, synth.centre_spike_taps(), O.params(**prms[i]))
         if not (np.array_equal(entries[i][1].cpu().numpy(), outr) and np.array_equal(taps_all[i].cpu().numpy(), wr)):
             raise SystemExit(f"batched parity failure on channel {i}")
-    # plain comparator: the single-stream call (fnt_cdc_aeq) channel after channel, on
-    # a random sample of channels; its rate over the sample stands for the loop
-    rng = np.random.default_rng(7)
-    sample = [int(i) for i in rng.choice(len(chans), size=min(32, len(chans)), replace=False)]
-    tmp_taps = w0.clone()
-    s_inst = sum(chans[i][1].shape[0] for i in sample)
-    progress(f"batched: plain per-channel loop over {len(sample)} sampled channels")
+    plain_gsps = None
+    fused = None
+    if not args.no_comparisons:
+        # plain comparator: the single-stream call (fnt_cdc_aeq) channel after channel, on
+        # a random sample of channels; its rate over the sample stands for the loop
+        rng = np.random.default_rng(7)
+        sample = [int(i) for i in rng.choice(len(chans), size=min(32, len(chans)), replace=False)]
+        tmp_taps = w0.clone()
+        s_inst = sum(chans[i][1].shape[0] for i in sample)
+        progress(f"batched: plain per-channel loop over {len(sample)} sampled channels")
 
-    def plain_loop():
-        for i in sample:
-            tmp_taps.copy_(w0)
-            fnt.fnt_cdc_aeq(chans[i][1], entries[i][3], tmp_taps, entries[i][4], out=entries[i][1], stream=stream)
+        # the faster of the two plain single-channel paths on this GPU: fnt_cdc to the
+        # 1-sps stream, then fnt_aeq (the one-launch fnt_cdc_aeq is timed in the
+        # single-stream leg)
+        abuf = torch.empty((max(chans[i][1].shape[0] for i in sample) // 2 + 1, 4), dtype=torch.int8, device=dev)
 
-    plain_ms = _time_events(torch, plain_loop, 1, stream)
-    plain_gsps = s_inst / (plain_ms / 1e3) / 1e9
-    # comparator: the same plan with the direct time-domain CDC and AEQ kernels
-    # (no Fermat-domain arithmetic), bit-identical outputs.  Kernels are compared
-    # in the staged schedule (every CDC, then the AEQ; no lead), which the lead
-    # was not tuned for but which treats both paths alike
-    progress("batched: direct time-domain comparator")
-    ref_out = {i: entries[i][1].clone() for i in pick}
-    ref_taps = {i: taps_all[i].clone() for i in pick}
-    plan.set_lead(0)
+        def plain_loop():
+            for i in sample:
+                tmp_taps.copy_(w0)
+                m = entries[i][1].shape[0]
+                fnt.fnt_cdc(chans[i][1], entries[i][3], exact=False, a_out=abuf[:m], stream=stream)
+                fnt.fnt_aeq(abuf[:m], tmp_taps, entries[i][4], out=entries[i][1], stream=stream)
 
-    def staged_runs():
-        ts = []
-        for k in range(2):
-            taps_all.copy_(w_all)
-            ts.append(plan.run_timed(stream))
-        torch.cuda.synchronize()
-        fnt.fnt_check()
-        for i in pick:
-            if not (torch.equal(entries[i][1], ref_out[i]) and torch.equal(taps_all[i], ref_taps[i])):
-                raise SystemExit(f"staged run differs on channel {i}")
-        return tuple(float(np.mean([t[k] for t in ts])) for k in ("cdc_ms", "aeq_ms", "step_ms"))
+        plain_ms = _time_events(torch, plain_loop, 1, stream)
+        plain_gsps = s_inst / (plain_ms / 1e3) / 1e9
+        # comparator: the same plan with the direct time-domain CDC and AEQ kernels
+        # (no Fermat-domain arithmetic), bit-identical outputs.  Kernels are compared
+        # in the staged schedule (every CDC, then the AEQ; no lead), which the lead
+        # was not tuned for but which treats both paths alike
+        progress("batched: direct time-domain comparator")
+        ref_out = {i: entries[i][1].clone() for i in pick}
+        ref_taps = {i: taps_all[i].clone() for i in pick}
+        plan.set_lead(0)
 
-    f_cdc, f_aeq, f_step = staged_runs()
-    plan.set_cdc_variant(1)
-    plan.set_aeq_variant(1)
-    d_cdc, d_aeq, d_step = staged_runs()
-    plan.set_cdc_variant(0)
-    plan.set_aeq_variant(0)
-    # the fused persistent schedule (one launch, hipGraph), whether or not the tuner chose it
-    progress("batched: fused persistent schedule")
-    fused = {}
-    for prio in (0, 512):
-        plan.set_fused(4, prio)
-        ts = []
-        for k in range(3):
-            taps_all.copy_(w_all)
-            ts.append(plan.run_timed(stream))
-        torch.cuda.synchronize()
-        fnt.fnt_check()
-        for i in pick:
-            if not (torch.equal(entries[i][1], ref_out[i]) and torch.equal(taps_all[i], ref_taps[i])):
-                raise SystemExit(f"fused run differs on channel {i}")
-        fms = float(np.median([t["aeq_ms"] for t in ts]))
-        if not fused or fms < fused["ms"]:
-            fused = {"ms": round(fms, 3), "value": round(inst / (fms / 1e3) / 1e9, 4), "unit": "Gsamples/s",
-                     "prio_channels": prio, "grid": plan.info()["fused_grid"],
-                     "kernel": "cdc_aeq_fused_kernel<4, 1, 2>"}
-    taps_all.copy_(w_all)
-    fused["graph_ms"] = round(_time_events(torch, plan.run, 2, stream), 3)
-    plan.set_fused(0)
-    # back to the tuned schedule
-    if info["fused_lpt"]:
-        plan.set_fused(info["fused_lpt"], info["fused_prio_channels"], info["fused_split"])
-    else:
-        plan.set_aeq_split(info["aeq_long_channels"], info["aeq_waves_long"], info["aeq_waves_per_pol"])
-        plan.set_lead(info["lead_channels"], info["lead_form"], info["top_channels"], info["top_form"])
+        def staged_runs():
+            ts = []
+            for k in range(2):
+                taps_all.copy_(w_all)
+                ts.append(plan.run_timed(stream))
+            torch.cuda.synchronize()
+            fnt.fnt_check()
+            for i in pick:
+                if not (torch.equal(entries[i][1], ref_out[i]) and torch.equal(taps_all[i], ref_taps[i])):
+                    raise SystemExit(f"staged run differs on channel {i}")
+            return tuple(float(np.mean([t[k] for t in ts])) for k in ("cdc_ms", "aeq_ms", "step_ms"))
+
+        f_cdc, f_aeq, f_step = staged_runs()
+        plan.set_cdc_variant(1)
+        plan.set_aeq_variant(1)
+        d_cdc, d_aeq, d_step = staged_runs()
+        plan.set_cdc_variant(0)
+        plan.set_aeq_variant(0)
+        # the fused persistent schedule (one launch, hipGraph), whether or not the tuner chose it
+        progress("batched: fused persistent schedule")
+        fused = {}
+        for prio in (0, 512):
+            plan.set_fused(4, prio)
+            ts = []
+            for k in range(3):
+                taps_all.copy_(w_all)
+                ts.append(plan.run_timed(stream))
+            torch.cuda.synchronize()
+            fnt.fnt_check()
+            for i in pick:
+                if not (torch.equal(entries[i][1], ref_out[i]) and torch.equal(taps_all[i], ref_taps[i])):
+                    raise SystemExit(f"fused run differs on channel {i}")
+            fms = float(np.median([t["aeq_ms"] for t in ts]))
+            if not fused or fms < fused["ms"]:
+                fused = {"ms": round(fms, 3), "value": round(inst / (fms / 1e3) / 1e9, 4), "unit": "Gsamples/s",
+                         "prio_channels": prio, "grid": plan.info()["fused_grid"],
+                         "kernel": "cdc_aeq_fused_kernel<4, 1, 2>"}
+        taps_all.copy_(w_all)
+        fused["graph_ms"] = round(_time_events(torch, plan.run, 2, stream), 3)
+        plan.set_fused(0)
+    # back to the tuned (or given) schedule
+    apply_schedule(plan, info)
     value = inst / (ms / 1e3) / 1e9
     aeq_blocks = times[0]["aeq_blocks"]           # the AEQ launch on the launch stream
     lead_blocks = times[0]["aeq_lead_blocks"]
@@ -527,24 +594,11 @@ def bench_batched(args, torch, dev):
                                f"2^{args.log2_min}..2^{args.log2_max} symbols/pol, fibre U(10,80) km, "
                                f"8-32 taps, OSNR U(18,26) dB, N=64 FNT mod 65537 alpha=sqrt2, AEQ N=32",
                    "channels": len(chans), "instants": inst, "longest_aeq_chain_blocks": info["aeq_blocks_max"]},
-        "vs_plain": round(value / plain_gsps, 2),
-        "plain_loop": {"value": round(plain_gsps, 5), "unit": "Gsamples/s",
-                       "sample": f"{len(sample)} random channels, fnt_cdc_aeq one after another"},
         "roofline": roof,
         "kernels": kernels,
-        "fused_schedule": fused,
         "plan_run_ms": round(run_ms, 3),
         "event_ms_per_step": round(event_step_ms, 3),
         "event_ms_per_step_median": round(event_step_med, 3),
-        "direct_comparator": {
-            "value": round(inst / (d_step / 1e3) / 1e9, 4), "unit": "Gsamples/s",
-            "cdc_ms": round(d_cdc, 3), "aeq_ms": round(d_aeq, 3), "step_ms": round(d_step, 3),
-            "fermat_staged": {"value": round(inst / (f_step / 1e3) / 1e9, 4), "cdc_ms": round(f_cdc, 3),
-                              "aeq_ms": round(f_aeq, 3), "step_ms": round(f_step, 3)},
-            "what": "same plan in the staged schedule (all CDC, then the AEQ; no lead), time-domain CDC "
-                    "(int8 dot products over the 32-instant window) and time-domain AEQ, no Fermat-domain "
-                    "arithmetic, against the Fermat-domain kernels in the same schedule; bit-identical on "
-                    "the parity channels"},
         "roofline_whole_path": {"bound": "alu", "achieved": round((all_aeq_ops + cdc_ops) / (ms / 1e3) / 1e9, 1),
                                 "peak": PEAK_ALU_GOPS, "unit": "Gops/s",
                                 "frac": round((all_aeq_ops + cdc_ops) / (ms / 1e3) / 1e9 / PEAK_ALU_GOPS, 5)},
@@ -554,7 +608,24 @@ def bench_batched(args, torch, dev):
                                       "tune_run_ms", "fused_lpt", "fused_split", "fused_prio_channels")},
         "parity": f"bit-exact vs oracle on channels {pick}", "gen_s": round(gen_s, 1),
         "autotune_s": round(tune_s, 1),
+        "launches": launches_of(info, times[0], kname, lead_name, top_name, aeq_blocks, lead_blocks, top_blocks,
+                                cdc_blocks, inst),
     }
+    if plain_gsps is not None:
+        res["vs_plain"] = round(value / plain_gsps, 2)
+        res["plain_loop"] = {"value": round(plain_gsps, 5), "unit": "Gsamples/s",
+                             "sample": f"{len(sample)} random channels, fnt_cdc then fnt_aeq, one channel after "
+                                       f"another"}
+        res["fused_schedule"] = fused
+        res["direct_comparator"] = {
+            "value": round(inst / (d_step / 1e3) / 1e9, 4), "unit": "Gsamples/s",
+            "cdc_ms": round(d_cdc, 3), "aeq_ms": round(d_aeq, 3), "step_ms": round(d_step, 3),
+            "fermat_staged": {"value": round(inst / (f_step / 1e3) / 1e9, 4), "cdc_ms": round(f_cdc, 3),
+                              "aeq_ms": round(f_aeq, 3), "step_ms": round(f_step, 3)},
+            "what": "same plan in the staged schedule (all CDC, then the AEQ; no lead), time-domain CDC "
+                    "(int8 dot products over the 32-instant window) and time-domain AEQ, no Fermat-domain "
+                    "arithmetic, against the Fermat-domain kernels in the same schedule; bit-identical on "
+                    "the parity channels"}
     if not args.no_cpu_baseline:
         progress("batched: oracle CPU baseline")
         res["cpu_baseline"] = cpu_baseline_batched(chans, prms, args.cpu_budget)
@@ -735,6 +806,14 @@ def main():
     ap.add_argument("--tune-cache", default=None,
                     help="JSON-lines file for the plan autotuner: reuse a schedule stored there for the same "
                          "workload, else tune and append it (keeps profiled runs on one schedule)")
+    ap.add_argument("--schedule", default=None,
+                    help="JSON object of plan schedule keys (as in the bench line's 'plan'): use this schedule "
+                         "instead of autotuning, e.g. for a profile of a fixed schedule")
+    ap.add_argument("--no-comparisons", action="store_true",
+                    help="batched leg: skip the plain per-channel loop, the direct comparator and the fused "
+                         "schedule comparison (profiles of one schedule)")
+    ap.add_argument("--launches-out", default=None,
+                    help="write the timed legs' launches (kernel, counter key, blocks) to this JSON file")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run 5 plain 256 MiB elementwise copies (counter calibration)")
     args = ap.parse_args()
@@ -790,6 +869,10 @@ def main():
             progress("served with host buffers")
             res["served_h2d"] = bench_served(args, torch, dev, host=True)
             progress(f"served with host buffers done: {res['served_h2d']['value']}")
+    if args.launches_out:
+        with open(args.launches_out, "w") as f:
+            json.dump({"batched": res.get("launches", []),
+                       "single": res.get("plain_single_stream", {}).get("launches", [])}, f, indent=1)
     print(json.dumps(res), flush=True)
 
 

@@ -114,8 +114,17 @@ def test_full_size_batched_4096(torch_dev):
     assert ok == 4096
 
 
-def test_full_size_large_batch_16384(torch_dev):
+LARGE_PARTS = 16
+_large = {}
+
+
+@pytest.fixture(scope="module")
+def large_batch(torch_dev):
+    """The 16384-channel batch generated, planned (quick autotuning) and run once;
+    the parts below compare it with the oracle a sixteenth at a time."""
     torch, dev = torch_dev
+    if "chans" in _large:
+        return _large
     t0 = time.perf_counter()
     specs = synth.batched_specs(16384, 14, 22, tag="large")
 
@@ -150,9 +159,25 @@ def test_full_size_large_batch_16384(torch_dev):
     fnt.fnt_check()
     note(f"16384-channel batch: {dt:.2f} s, {total / dt / 1e9:.2f} Gsamples/s")
     plan.close()
-    ok = oracle_every_channel("16384-channel batch", [c[0] for c in chans], [c[1] for c in chans],
-                              [c[2] for c in chans], prms, [e[1] for e in entries], taps_all)
-    assert ok == 16384
+    _large.update(chans=chans, prms=prms, outs=[e[1] for e in entries], taps=taps_all, ok=0)
+    return _large
+
+
+@pytest.mark.parametrize("part", range(LARGE_PARTS))
+def test_full_size_large_batch_16384(large_batch, part):
+    """Channels part, part + 16, part + 32, ... of the 16384 (every length range in
+    every part), each against the oracle."""
+    chans, idx = large_batch["chans"], list(range(part, len(large_batch["chans"]), LARGE_PARTS))
+    ok = oracle_every_channel(f"16384-channel batch, part {part + 1}/{LARGE_PARTS}",
+                              [chans[i][0] for i in idx], [chans[i][1] for i in idx], [chans[i][2] for i in idx],
+                              [large_batch["prms"][i] for i in idx], [large_batch["outs"][i] for i in idx],
+                              large_batch["taps"][idx])
+    assert ok == len(idx)
+    large_batch["ok"] += ok
+    if part == LARGE_PARTS - 1:
+        note(f"16384-channel batch: {large_batch['ok']}/{len(chans)} channels bit-exact")
+        assert large_batch["ok"] == len(chans)
+        large_batch.clear()
 
 
 def test_full_size_served_1024(torch_dev):
