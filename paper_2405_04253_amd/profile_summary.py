@@ -114,9 +114,26 @@ def calibration(fetch_dirs, write_dirs, nbytes):
             "fetch_scale": nbytes / (f[1] * 1024.0), "write_scale": nbytes / (w[1] * 1024.0)}
 
 
+def stats_table(path, include=r"aeq_|cdc_"):
+    """Rows of rocprofv3's --stats kernel_stats.csv for the kernels matching
+    `include`, with short names, as markdown."""
+    lines = ["| kernel | calls | average ms | min ms | max ms | total ms |", "|---|---|---|---|---|---|"]
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            name = short_name(r["Name"])
+            if not re.search(include, name):
+                continue
+            lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.3f} | "
+                         f"{float(r['MinNs']) / 1e6:.3f} | {float(r['MaxNs']) / 1e6:.3f} | "
+                         f"{float(r['TotalDurationNs']) / 1e6:.1f} |")
+    return lines
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("--workload", required=True)
+    ap.add_argument("--append-stats", default=None,
+                    help="only append the --stats table of this kernel_stats.csv to --md, then exit")
+    ap.add_argument("--workload", default=None)
     ap.add_argument("--title", default=None)
     ap.add_argument("--trace", action="append", default=[])
     ap.add_argument("--fetch", action="append", default=[])
@@ -137,6 +154,14 @@ def main(argv=None):
     ap.add_argument("--md", required=True)
     ap.add_argument("--traffic", default=None)
     a = ap.parse_args(argv)
+    if a.append_stats:
+        with open(a.md, "a") as f:
+            f.write("\n".join(["", "## `--kernel-trace --stats` summary of the trace run (kernels of the path)", ""]
+                              + stats_table(a.append_stats)) + "\n")
+        print(f"appended {a.append_stats} to {a.md}")
+        return
+    if not a.workload:
+        ap.error("--workload is required")
 
     sys.path.insert(0, ROOT)
     import bench  # the device-code hash the bench compares against
