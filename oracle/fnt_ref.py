@@ -10,6 +10,8 @@ equations with no fast algorithm:
 * ``sqrt2``                a square root of 2 in Z_F    (radix of the FNT-CDC, Proposed structure)
 * ``fnt`` / ``ifnt``       Eqs. (1) and (2) as O(N^2) sums
 * ``cdc_block_eq78``       one overlap-save CDC block through Eqs. (7)-(8)
+* ``cdc_block_long``       the same with N = 128 (radix of order 128) and the
+                           6-bit taps split into two balanced 3-bit digits
 * ``aeq_block_digits``     one AEQ filtering block through the 7+7-bit tap split
 
 Both block models take an optional ``counter`` dict that tallies the true
@@ -37,6 +39,15 @@ def sqrt2(t: int) -> int:
     """
     q = 1 << t
     return (pow(2, 3 * q // 4) - pow(2, q // 4)) % fermat(t)
+
+
+def sqrt_sqrt2(t: int) -> int:
+    """A radix of order 2^(t+3) modulo F_t: the smaller square root of sqrt2(t),
+    by exhaustive search (4938 for t = 4).  Its square is sqrt2(t), so its
+    order is twice that of sqrt2(t)."""
+    F = fermat(t)
+    s = sqrt2(t)
+    return min(x for x in range(F) if x * x % F == s)
 
 
 def radix(t: int, kind: str) -> int:
@@ -89,7 +100,7 @@ def cyclic_conv_fnt(x, y, alpha: int, F: int):
     return ifnt([a * b % F for a, b in zip(X, Y)], alpha, F)
 
 
-def cdc_block_eq78(win_r, win_i, h_r, h_i, t: int = 4, counter=None):
+def cdc_block_eq78(win_r, win_i, h_r, h_i, t: int = 4, counter=None, alpha=None):
     """One overlap-save CDC block by the complex packing of Eqs. (7)-(8).
 
     ``win_*``: the N-sample input window (oldest first) of one polarisation,
@@ -106,7 +117,7 @@ def cdc_block_eq78(win_r, win_i, h_r, h_i, t: int = 4, counter=None):
     """
     q = 1 << t
     F = fermat(t)
-    alpha = sqrt2(t)
+    alpha = sqrt2(t) if alpha is None else alpha
     j = pow(2, q // 2, F)
     N = len(win_r)
     Xr, Xi = fnt(win_r, alpha, F), fnt(win_i, alpha, F)
@@ -120,6 +131,32 @@ def cdc_block_eq78(win_r, win_i, h_r, h_i, t: int = 4, counter=None):
     c7 = -pow(2, q - 1)
     c8 = -pow(2, q // 2 - 1)
     return [lift(c7 * v, F) for v in zs], [lift(c8 * v, F) for v in zd]
+
+
+def split_digits3(h: int):
+    """6-bit tap -> (hi, lo) with h = 8 hi + lo, lo = ((h + 4) mod 8) - 4 in
+    [-4, 3] and hi = (h - lo) / 8 in [-4, 4]."""
+    lo = ((h + 4) % 8) - 4
+    return (h - lo) // 8, lo
+
+
+def cdc_block_long(win_r, win_i, h_r, h_i, t: int = 4, counter=None):
+    """One overlap-save CDC block of N = len(win_r) = 128 samples (64 new) for
+    up to 65 taps: longer than the N = 64 block of the paper allows (33 taps).
+
+    A 65-tap convolution of 5-bit samples with 6-bit taps reaches
+    65 * (32 * 16 + 31 * 16) = 65520 > (F - 1) / 2, outside Eq. (5), so the taps
+    are split into two balanced 3-bit digits, h = 8 hi + lo; each digit's
+    convolution stays within 65 * (4 * 16 + 4 * 16) = 8320 and goes through
+    Eqs. (7)-(8) with the radix of order 128 (sqrt_sqrt2); the two centred
+    results are combined as z = 8 z_hi + z_lo.  Returns the N circular outputs
+    (re, im); positions >= L - 1 equal the linear convolution."""
+    alpha = sqrt_sqrt2(t)
+    dr = [split_digits3(int(v)) for v in h_r]
+    di = [split_digits3(int(v)) for v in h_i]
+    zh = cdc_block_eq78(win_r, win_i, [d[0] for d in dr], [d[0] for d in di], t, counter, alpha)
+    zl = cdc_block_eq78(win_r, win_i, [d[1] for d in dr], [d[1] for d in di], t, counter, alpha)
+    return ([8 * a + b for a, b in zip(zh[0], zl[0])], [8 * a + b for a, b in zip(zh[1], zl[1])])
 
 
 def split_digits(w: int):

@@ -259,3 +259,74 @@ def test_table1_product_counts():
     cnt = {}
     R.aeq_block_digits([[0] * 32] * 4, [[[0] * 16] * 4] * 4, counter=cnt)
     assert cnt["products"] / 16 == 64
+
+
+# ---- longer CDC transform (N = 128) with 3-bit tap digits ------------------------
+def _long_window_check(xr, xi, hr, hi, model):
+    N = 128
+    L = len(hr)
+    hpr = list(hr) + [0] * (N - L)
+    hpi = list(hi) + [0] * (N - L)
+    zr, zi = model(list(xr), list(xi), hpr, hpi)
+    br, bi = _linear_complex(np.array(xr, np.int64), np.array(xi, np.int64),
+                             np.array(hr, np.int64), np.array(hi, np.int64))
+    return ([zr[n] for n in range(L - 1, N)] == [int(v) for v in br[L - 1:N]] and
+            [zi[n] for n in range(L - 1, N)] == [int(v) for v in bi[L - 1:N]])
+
+
+def test_long_radix_order_128():
+    F = 65537
+    a = R.sqrt_sqrt2(4)
+    assert a == 4938
+    assert a * a % F == R.sqrt2(4) == 4080
+    assert R.order(a, F) == 128 and pow(a, 64, F) == F - 1
+
+
+def test_long_constants_fold_n_inverse():
+    # With N = 128 (N^-1 = -512 = -2^9) the constants of Eqs. (7)-(8) times N^-1
+    # become -256 for z and -1 for z^ (2^32 = 1 and 2^16 = -1 mod F)
+    F = 65537
+    assert (128 * -512) % F == 1
+    assert (-(1 << 15) * -512 - -256) % F == 0
+    assert (-(1 << 7) * -512 - -1) % F == 0
+    # they are the inverses of 2 N and of 2 N j (j = 2^8)
+    assert (-256 * 256) % F == 1 and (-1 * 256 * 256) % F == 1
+
+
+def test_digit3_split_exhaustive():
+    for h in range(-32, 32):
+        hi, lo = R.split_digits3(h)
+        assert 8 * hi + lo == h
+        assert -4 <= lo <= 3 and -4 <= hi <= 4
+
+
+def test_long_block_random_vs_numpy():
+    rng = np.random.default_rng(11)
+    for L in (1, 33, 34, 50, 65):
+        xr, xi = rng.integers(-16, 16, 128), rng.integers(-16, 16, 128)
+        hr, hi = rng.integers(-32, 32, L), rng.integers(-32, 32, L)
+        assert _long_window_check(xr, xi, hr, hi, R.cdc_block_long)
+
+
+def test_long_eq5_worst_case_needs_the_digits():
+    # 65 taps of -32 - 32j against x = -16 - 16j: |Im z| = 65 * 1024 = 66560, far
+    # beyond (F - 1) / 2.  One transform per component wraps; the 3-bit digits keep
+    # each partial convolution within 65 * 128 = 8320 (Eq. (5)) and recombine exactly.
+    L = 65
+    for hr, hi in (([-32] * L, [-32] * L), ([-32] * L, [31] * L), ([31] * L, [-32] * L)):
+        xr, xi = [-16] * 128, [-16] * 128
+        assert _long_window_check(xr, xi, hr, hi, R.cdc_block_long)
+        undigitised = lambda a, b, c, d: R.cdc_block_eq78(a, b, c, d, alpha=R.sqrt_sqrt2(4))
+        assert not _long_window_check(xr, xi, hr, hi, undigitised)
+    # the per-digit bound itself: hi digits of -4 (h = -32) and lo digits of -4 (h = -4)
+    hi_d = [R.split_digits3(-32)[0]] * L
+    zr, zi = R.cdc_block_eq78([-16] * 128, [-16] * 128, hi_d + [0] * 63, hi_d + [0] * 63,
+                              alpha=R.sqrt_sqrt2(4))
+    assert max(abs(v) for v in zi[64:]) == 65 * 4 * 16 * 2 == 8320
+
+
+def test_long_block_product_count():
+    cnt = {}
+    z = [0] * 128
+    R.cdc_block_long(z, z, z, z, counter=cnt)
+    assert cnt["products"] == 2 * 2 * 128       # two digits x (P, Q) x 128 bins per polarisation block
