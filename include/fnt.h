@@ -195,7 +195,8 @@ typedef struct fnt_plan_info {
     int32_t cdc_waves_per_group;  /* chosen schedule */
     int32_t cdc_blocks_per_wave;  /* 0 = one block per lane (64 blocks per wave) */
     int32_t aeq_variant;   /* 0 = Fermat-domain filtering (the method), 1 = direct comparator,
-                              2 = Fermat-domain, one wave per channel */
+                              2 = Fermat-domain, one wave per channel, 3 = the same with the
+                              RDE gradient in the Fermat domain too */
     int32_t aeq_waves_per_pol;  /* variant 0: AEQ form (0, 3, 1, 5, 2, 4; see fnt_plan_set_aeq_waves) */
     int32_t graph;         /* 1 if fnt_plan_run replays a hipGraph (never while a lead is in effect) */
     int32_t aeq_waves_long;     /* AEQ form of the long chains (see fnt_plan_set_aeq_split) */
@@ -248,7 +249,11 @@ int fnt_plan_destroy(fnt_plan *plan);
 /* Select the AEQ kernel of a plan: 0 = Fermat-domain filtering split by output
  * polarisation (default, the method), 1 = direct time-domain comparator with
  * bit-identical results and no Fermat-domain arithmetic, 2 = Fermat-domain
- * filtering with one wave per channel. */
+ * filtering with one wave per channel, 3 = as 2 with the RDE gradient of the
+ * tap update (Eq. (6)) also formed in the Fermat domain: a correlation of the
+ * block's 8-bit error terms with the window through FNT32 products, exact
+ * because its magnitude stays within the Eq. (5) bound (16 * 128 * 16 =
+ * 32768); bit-identical results.  FNT_E_INVAL for another value. */
 int fnt_plan_set_aeq_variant(fnt_plan *plan, int variant);
 /* Form of AEQ variant 0 (the Fermat-domain method), from the fewest
  * instructions per block to the shortest serial latency per block:

@@ -1270,7 +1270,7 @@ int fnt_plan_run_timed(fnt_plan *p, fnt_plan_timing *t, void *stream) {
 int fnt_plan_set_aeq_variant(fnt_plan *p, int variant) {
     if (!p) return fail(FNT_E_INVAL, "plan: NULL");
     p->fused_lpt = 0;                                // another schedule: the fused kernel is off
-    if (variant < 0 || variant > 2) return fail(FNT_E_INVAL, "plan: variant %d", variant);
+    if (variant < 0 || variant > 3) return fail(FNT_E_INVAL, "plan: variant %d", variant);
     p->variant = variant;
     if (p->exec) return plan_capture(p, nullptr);
     return FNT_OK;

@@ -19,7 +19,8 @@
 //    persistent launch: per channel a producer wave runs the lane-per-block CDC
 //    64 blocks at a time into a ring in LDS and the polarisation-split AEQ waves
 //    consume it; workgroups take channels longest first from a work counter.
-//  * aeq_fnt_kernel       : the same AEQ with one wave64 per channel.
+//  * aeq_fnt_kernel       : the same AEQ with one wave64 per channel, with the RDE
+//    gradient of the tap update as dot products or in the Fermat domain.
 //  * cdc_direct_kernel, aeq_direct_kernel : the same CDC and AEQ by time-domain
 //    integer dot products, comparators with bit-identical output.
 #include <hip/hip_runtime.h>
@@ -1075,6 +1076,18 @@ __device__ __forceinline__ void ifnt32_upper(int32_t (&x)[16], int t) {
 //  * input-spectrum lanes: S1 = lane / 16, 2 of the 32 window positions each.
 //  * output / error lanes: symbol m = lane / 4, stream S2 = lane % 4.
 //  * gradient / tap-state lanes: S1 = lane / 16, tap k = lane % 16, all 4 S2.
+//
+// FDG selects how the RDE gradient of the block update (Eq. (6)) is formed:
+// false, 4-byte dot products over the window (as every other AEQ kernel);
+// true, in the Fermat domain as well.  G[k] = sum_m eps[m] x[16 b + m - k]
+// (k < 16) is a correlation of the block's 16 error terms with the 32-symbol
+// window: with e'[n] = eps[15 - n] (n < 16, zero above) the cyclic convolution
+// c = IFNT(FNT(window) FNT(e')) has c[31 - k] = G[k] with no wrap-around, and
+// every true value is within 16 * 128 * 16 = 32768 = (F - 1) / 2 (Eq. (5)), so
+// the centred lift is exact.  The window spectra are the ones the filtering
+// already computed; per block this adds four error transforms, 512 spectral
+// products and 16 inverse transforms (upper halves).
+template <bool FDG>
 __global__ __launch_bounds__(64) void aeq_fnt_kernel(const AeqItem *items, AeqItem single,
                                                      int *err) {
     const AeqItem it = items ? items[blockIdx.x] : single;
@@ -1091,6 +1104,8 @@ __global__ __launch_bounds__(64) void aeq_fnt_kernel(const AeqItem *items, AeqIt
     __shared__ int32_t part[4][64];                   // [g*2+d][m*4+S2] lifted partial outputs
     __shared__ uint32_t epsw[16];                     // bytes [S2][m]
     __shared__ uint32_t winw[36];                     // bytes [S1][32] window + zero pad
+    __shared__ int32_t espec[FDG ? 4 : 1][32];        // error spectra by position (FDG)
+    __shared__ int32_t gl[FDG ? 256 : 1];             // gradient [S1][S2][k] (FDG)
 
     int32_t w[4];
 #pragma unroll
@@ -1129,6 +1144,26 @@ __global__ __launch_bounds__(64) void aeq_fnt_kernel(const AeqItem *items, AeqIt
     const int c2 = it.const_unit * it.const_unit;
     uint32_t win = aeq_load(it, -16 + pos, err);      // lane pos: symbol 16 b - 16 + pos
 
+    // FNT32 (alpha = 2) of 16 sequences spread over 16 lanes each: lane (s1, kk)
+    // enters positions kk and kk + 16 and leaves with the bins stored at kk and
+    // kk + 16 of its row (the order the tap-digit spectra use).  |x| <= 128:
+    // out |.| <= 2^21.
+    auto spectrum = [&](int32_t x0, int32_t x1, int32_t &u0, int32_t &u1) {
+        u0 = x0 + x1;
+        u1 = mulmod(x0 - x1, 1 << kk);                // h = 16, e = kk
+#pragma unroll
+        for (int h = 8; h >= 1; h >>= 1) {
+            const bool up = (kk & h) != 0;
+            const int32_t c = 1 << ((16 / h) * (kk & (h - 1)));
+            int32_t p0 = h == 8 ? xor_lane<8>(u0) : h == 4 ? xor_lane<4>(u0)
+                       : h == 2 ? xor_lane<2>(u0) : xor_lane<1>(u0);
+            int32_t p1 = h == 8 ? xor_lane<8>(u1) : h == 4 ? xor_lane<4>(u1)
+                       : h == 2 ? xor_lane<2>(u1) : xor_lane<1>(u1);
+            u0 = blend(up, mulmod(p0 - u0, c), u0 + p0);
+            u1 = blend(up, mulmod(p1 - u1, c), u1 + p1);
+        }
+    };
+
     for (int64_t b = 0; b < nblocks; ++b) {
         uint32_t nxt = pos >= 16 ? aeq_load(it, 16 * b + pos, err) : 0u;
         if (lane < 32) {
@@ -1140,20 +1175,8 @@ __global__ __launch_bounds__(64) void aeq_fnt_kernel(const AeqItem *items, AeqIt
         // input spectra: lane (s1, kk) holds positions kk and kk + 16 of stream s1
         {
             const int8_t *wb = reinterpret_cast<const int8_t *>(winw) + s1 * 32;
-            int32_t x0 = wb[kk], x1 = wb[kk + 16];
-            int32_t u0 = x0 + x1;
-            int32_t u1 = mulmod(x0 - x1, 1 << kk);    // h = 16, e = kk
-#pragma unroll
-            for (int h = 8; h >= 1; h >>= 1) {
-                const bool up = (kk & h) != 0;
-                const int32_t c = 1 << ((16 / h) * (kk & (h - 1)));
-                int32_t p0 = h == 8 ? xor_lane<8>(u0) : h == 4 ? xor_lane<4>(u0)
-                           : h == 2 ? xor_lane<2>(u0) : xor_lane<1>(u0);
-                int32_t p1 = h == 8 ? xor_lane<8>(u1) : h == 4 ? xor_lane<4>(u1)
-                           : h == 2 ? xor_lane<2>(u1) : xor_lane<1>(u1);
-                u0 = blend(up, mulmod(p0 - u0, c), u0 + p0);
-                u1 = blend(up, mulmod(p1 - u1, c), u1 + p1);
-            }
+            int32_t u0, u1;
+            spectrum(wb[kk], wb[kk + 16], u0, u1);
             aspec[s1][kk] = u0;                        // |.| <= 2^21
             aspec[s1][kk + 16] = u1;
         }
@@ -1189,6 +1212,36 @@ __global__ __launch_bounds__(64) void aeq_fnt_kernel(const AeqItem *items, AeqIt
             if (!valid) eps = 0;
             reinterpret_cast<int8_t *>(epsw)[oS2 * 16 + om] = (int8_t)eps;
             __syncthreads();
+            if constexpr (FDG) {
+                // error spectra: lane (S2 = s1, kk) enters e'[kk] = eps_S2[15 - kk], e'[kk + 16] = 0
+                {
+                    const int8_t *eb = reinterpret_cast<const int8_t *>(epsw) + s1 * 16;
+                    int32_t u0, u1;
+                    spectrum(eb[15 - kk], 0, u0, u1);
+                    espec[s1][kk] = u0;
+                    espec[s1][kk + 16] = u1;
+                }
+                __syncthreads();
+                // filter (S1 = tS1, S2 = tS2) on the lane pair t (both digit lanes
+                // compute it; d = 0 keeps it): products |.| < 2^17, inverse upper half
+                int32_t C[16];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) C[j] = mulmod(aspec[tS1][t + 2 * j], espec[tS2][t + 2 * j]);
+                ifnt32_upper(C, t);                    // |.| < 2^21
+                if (d == 0) {
+                    // register j >= 8 holds c[16 + t + 2 (j - 8)] = G[15 - t - 2 (j - 8)]; N^-1 = -2048
+#pragma unroll
+                    for (int j = 8; j < 16; ++j)
+                        gl[(tS1 * 4 + tS2) * 16 + 15 - t - 2 * (j - 8)] = lift_loose(mulmod(C[j], -2048));
+                }
+                __syncthreads();
+#pragma unroll
+                for (int q2 = 0; q2 < 4; ++q2) {
+                    const int32_t g = gl[(s1 * 4 + q2) * 16 + kk];
+                    w[q2] = clamp32(w[q2] + (int32_t)rs64((int64_t)g, it.mu_shift), -8192, 8191);
+                }
+                transform_taps();
+            } else {
             // G[S1][S2][k] = sum_j eps_S2[j] * a_S1[16 b + j - k] as 4-byte dot products
             const int off = s1 * 32 + 16 - kk;
             uint32_t dd[5];
@@ -1206,6 +1259,7 @@ __global__ __launch_bounds__(64) void aeq_fnt_kernel(const AeqItem *items, AeqIt
                 w[q2] = clamp32(w[q2] + (int32_t)rs64((int64_t)gsum, it.mu_shift), -8192, 8191);
             }
             transform_taps();
+            }
         } else {
             __syncthreads();
         }
@@ -2873,7 +2927,9 @@ hipError_t launch_aeq(const AeqItem *items, int nitems, const AeqItem &single, i
     } else if (variant == 1) {
         aeq_direct_kernel<<<n, 64, 0, s>>>(items, single, err);
     } else if (variant == 2) {
-        aeq_fnt_kernel<<<n, 64, 0, s>>>(items, single, err);
+        aeq_fnt_kernel<false><<<n, 64, 0, s>>>(items, single, err);
+    } else if (variant == 3) {
+        aeq_fnt_kernel<true><<<n, 64, 0, s>>>(items, single, err);
     } else {
         return hipErrorInvalidValue;
     }

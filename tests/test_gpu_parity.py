@@ -265,7 +265,7 @@ def _plan_channels(torch, dev, chans, rng):
     return out
 
 
-@pytest.mark.parametrize("variant,wpp", [(0, 0), (0, 3), (0, 1), (0, 2), (0, 4), (0, 5), (1, 1), (2, 1)])
+@pytest.mark.parametrize("variant,wpp", [(0, 0), (0, 3), (0, 1), (0, 2), (0, 4), (0, 5), (1, 1), (2, 1), (3, 1)])
 def test_plan_batched_vs_oracle(torch_dev, variant, wpp):
     torch, dev = torch_dev
     chans = _batch(40, 6, 11, seed=variant)
@@ -362,6 +362,48 @@ def test_plan_extreme_aeq_params(torch_dev, wpp):
         assert np.array_equal(c["taps"].cpu().numpy(), wr), c["prm"]
     plan.close()
     fnt.fnt_check()
+
+
+def test_plan_fermat_gradient_extremes(torch_dev):
+    """AEQ variant 3 (the RDE gradient through FNT32 products) at the Eq. (5)
+    bound of the gradient: windows of -16 and errors clipped at -128 give
+    G = 16 * (-128) * (-16) = 32768 = (F - 1) / 2 in every full block (and -32512
+    with +127), next to the extreme shift settings and random channels; every
+    output and final tap equals the oracle's direct gradient."""
+    torch, dev = torch_dev
+    chans, inits, prms = [], [], []
+    extreme = dict(out_shift=0, err_shift=0, mu_shift=30, const_unit=1, update_enable=1)
+    for k, (sign, nsym) in enumerate([(-1, 16 * 40), (1, 16 * 40 + 7), (-1, 5)]):
+        x = np.full((2 * nsym, 4), -16, dtype=np.int8)
+        h = np.zeros((1, 2), dtype=np.int8)
+        h[0, 0] = 31                                    # z = 31 x: requantised to -16 with shift 0
+        chans.append((x, h, 0))
+        w0 = np.zeros((4, 4, 16), dtype=np.int16)
+        for q in range(4):
+            w0[q, q, 8] = sign * 4096                   # y = -/+ 65536: outputs saturate, eps clips
+        inits.append(w0)
+        prms.append(extreme)
+    for i, ch in enumerate(_batch(8, 6, 10, seed=91)):
+        chans.append((ch.samples, ch.taps, ch.requant_shift))
+        inits.append(synth.centre_spike_taps() if i % 2 else synth.random_aeq_taps(seed=i, lo=-300, hi=300))
+        prms.append(EXTREME_AEQ[i % len(EXTREME_AEQ)] if i < 4 else synth.aeq_params_for(ch))
+    entries, refs, outs, taps = [], [], [], []
+    for (x, h, sh), w0, prm in zip(chans, inits, prms):
+        M = O.n_symbols(x.shape[0], 0)
+        outs.append(torch.full((M, 4), 12345, dtype=torch.int16, device=dev))
+        taps.append(to_dev(torch, dev, w0))
+        entries.append((to_dev(torch, dev, x), outs[-1], taps[-1], fnt.cdc_params(h, sh), fnt.aeq_params(**prm)))
+        refs.append(O.cdc_aeq(x, h, sh, w0, O.params(**prm)))
+    plan = fnt.Plan(entries, autotune=False, use_graph=False)
+    plan.set_aeq_variant(3)
+    note("plan AEQ variant 3 (Fermat-domain gradient) at the gradient's Eq. (5) bound")
+    plan.run()
+    torch.cuda.synchronize()
+    fnt.fnt_check()
+    for i, (o, w, (outr, wr, _)) in enumerate(zip(outs, taps, refs)):
+        assert np.array_equal(o.cpu().numpy(), outr), i
+        assert np.array_equal(w.cpu().numpy(), wr), i
+    plan.close()
 
 
 @pytest.mark.parametrize("aeq_variant", [0, 1])
