@@ -220,6 +220,58 @@ def bench_single(args, torch, dev):
     return res
 
 
+# FNT128: 448 butterflies (add + sub) + 321 nontrivial twiddles (stage of span h:
+# (h - 1) N / 2h of them)
+FNT128_OPS = 896 + 321
+# CDC with N = 128 and 3-bit tap digits, per block of 64 new instants and one
+# polarisation: packing u, v (256), forward FNT128 x 2, products (2 digits x P, Q:
+# 512), P +- Q (512), four inverses, scale / lift / digit combine (4 per output: 256)
+CDC_LONG_OPS_PER_POL_BLOCK = 256 + 2 * FNT128_OPS + 512 + 512 + 4 * FNT128_OPS + 256
+CDC_LONG_OPS_PER_BLOCK = 2 * CDC_LONG_OPS_PER_POL_BLOCK                                   # 17676
+
+
+def bench_cdc_long(args, torch, dev):
+    """fnt_cdc_long (N = 128, 65 taps of 3-bit digits) on one long-fibre channel,
+    against fnt_cdc (N = 64, 32 taps) on the same samples."""
+    import oracle as O
+    from paper_2405_04253_amd import fnt, synth
+    km = 150.0
+    nsym = 1 << args.log2_symbols
+    t0 = time.perf_counter()
+    q, taps32, sh32, _ = synth.gen_channel_torch(nsym, km, 22.0, synth.seed_for(0, "cdc-long", 0), dev)
+    taps65, sh65, _ = synth.design_cdc_taps(km, 65)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    n = q.shape[0]
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name, fn in (("long", lambda: fnt.fnt_cdc_long(q, taps65, sh65, 0, exact=False, stream=stream)),
+                     ("n64", lambda: fnt.fnt_cdc(q, fnt.cdc_params(taps32, sh32), exact=False, stream=stream))):
+        fn()
+        torch.cuda.synchronize()
+        fnt.fnt_check()
+        res[name] = _time_events(torch, fn, 5, stream)
+    # parity on a prefix (causal: the first outputs depend only on the first inputs)
+    _, a = fnt.fnt_cdc_long(q, taps65, sh65, 0, exact=False, stream=stream)
+    torch.cuda.synchronize()
+    k = 1 << 17
+    _, ar = O.cdc(q[:k].cpu().numpy(), taps65, sh65, 0)
+    if not np.array_equal(a[: ar.shape[0]].cpu().numpy(), ar):
+        raise SystemExit("fnt_cdc_long parity failure")
+    blocks = (n + 63) // 64
+    ops = CDC_LONG_OPS_PER_BLOCK * blocks
+    achieved = ops / (res["long"] / 1e3) / 1e9
+    return {"value": round(n / (res["long"] / 1e3) / 1e9, 3), "unit": "Gsamples/s", "ms": round(res["long"], 3),
+            "workload": f"1 channel x 2^{args.log2_symbols} symbols/pol, {km:.0f} km, 65 taps (N = 128 FNT, "
+                        f"3-bit tap digits), to the 5-bit 1-sps stream",
+            "roofline": {"kernel": "cdc_long_kernel", "bound": "alu", "achieved": round(achieved, 1),
+                         "peak": PEAK_ALU_GOPS, "unit": "Gops/s", "frac": round(achieved / PEAK_ALU_GOPS, 5),
+                         "ops_per_unit": {"cdc_long_block_64_instants": CDC_LONG_OPS_PER_BLOCK}},
+            "n64_32_taps": {"value": round(n / (res["n64"] / 1e3) / 1e9, 3), "ms": round(res["n64"], 3),
+                            "kernel": "cdc_lane_kernel (fnt_cdc, N = 64, the 32-tap design)"},
+            "parity": f"bit-exact vs oracle on the first {k} instants", "gen_s": round(gen_s, 1)}
+
+
 def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -490,6 +542,13 @@ def bench_batched(args, torch, dev):
         plan.set_aeq_variant(1)
         d_cdc, d_aeq, d_step = staged_runs()
         plan.set_cdc_variant(0)
+        # the RDE gradient through dot products and in the Fermat domain, on the
+        # one-wave-per-channel AEQ kernel (variants 2 and 3)
+        progress("batched: Fermat-domain gradient comparator")
+        plan.set_aeq_variant(2)
+        _, g_dot, _ = staged_runs()
+        plan.set_aeq_variant(3)
+        _, g_fnt, _ = staged_runs()
         plan.set_aeq_variant(0)
         # the fused persistent schedule (one launch, hipGraph), whether or not the tuner chose it
         progress("batched: fused persistent schedule")
@@ -626,6 +685,12 @@ def bench_batched(args, torch, dev):
                     "(int8 dot products over the 32-instant window) and time-domain AEQ, no Fermat-domain "
                     "arithmetic, against the Fermat-domain kernels in the same schedule; bit-identical on "
                     "the parity channels"}
+        res["fermat_gradient"] = {
+            "aeq_ms_dot_gradient": round(g_dot, 3), "aeq_ms_fermat_gradient": round(g_fnt, 3),
+            "kernel": "aeq_fnt_kernel<false> / aeq_fnt_kernel<true>",
+            "what": "AEQ variants 2 and 3 (one wave per channel, staged schedule): the RDE gradient of the "
+                    "block update by 4-byte dot products, or through FNT32 products in the Fermat domain "
+                    "(4 error transforms, 512 products, 16 inverse transforms per block); bit-identical"}
     if not args.no_cpu_baseline:
         progress("batched: oracle CPU baseline")
         res["cpu_baseline"] = cpu_baseline_batched(chans, prms, args.cpu_budget)
@@ -792,6 +857,7 @@ def main():
     ap.add_argument("--skip-served", action="store_true")
     ap.add_argument("--skip-single", action="store_true")
     ap.add_argument("--skip-transforms", action="store_true")
+    ap.add_argument("--skip-cdc-long", action="store_true")
     ap.add_argument("--nch", type=int, default=4096)
     ap.add_argument("--log2-min", type=int, default=12)
     ap.add_argument("--log2-max", type=int, default=20)
@@ -858,6 +924,10 @@ def main():
         progress(f"single done: {res['plain_single_stream']['value']}")
         if "value" in res:
             res["vs_single_stream"] = round(res["value"] / res["plain_single_stream"]["value"], 1)
+    if not args.skip_cdc_long:
+        progress("cdc long")
+        res["cdc_long"] = bench_cdc_long(args, torch, dev)
+        progress(f"cdc long done: {res['cdc_long']['value']}")
     if not args.skip_transforms:
         progress("transforms")
         res["transforms"] = bench_transforms(args, torch, dev)

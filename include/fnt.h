@@ -52,6 +52,8 @@ enum {
 enum { FNT_ALPHA_2 = 0, FNT_ALPHA_SQRT2 = 1 };
 
 #define FNT_MAX_CDC_TAPS 32
+/* Taps of fnt_cdc_long: overlap-save with N = 128 and 64 new instants per block. */
+#define FNT_MAX_CDC_LONG_TAPS 65
 #define FNT_AEQ_TAPS 16
 #define FNT_AEQ_BLOCK 16       /* symbols per AEQ block (one tap update per block) */
 #define FNT_CDC_HOP 32         /* new instants per CDC overlap-save block */
@@ -141,6 +143,24 @@ typedef struct fnt_aeq_params {
  *             resampled to 1 sample/symbol and requantised to 5 bit. */
 int fnt_cdc(const int8_t *in, uint64_t n, const fnt_cdc_params *p, int32_t *out_exact,
             int8_t *out_1sps, void *stream);
+
+/* FNT-CDC with a longer transform, for 1 .. 65 taps (the N = 64 block of
+ * fnt_cdc holds 33): N = 128, 64 new instants per block, radix 4938 of order
+ * 128 modulo 65537 (a square root of the CDC's sqrt 2).  A 65-tap convolution
+ * leaves the Eq. (5) bound (65 * 1008 = 65520 > 32768), so the 6-bit taps are
+ * split into balanced 3-bit digits, h = 8 hi + lo (lo in [-4, 3]); each digit
+ * is convolved through the packing of Eqs. (7)-(8) (within 65 * 128 = 8320) and
+ * the centred results are combined as 8 z_hi + z_lo.  Same results as the
+ * direct convolution (zero history before in[0]).
+ *   in         int8[n][4] device
+ *   host_taps  int8[ntaps][2] host memory, (re, im) in [-32, 31]; read during the call
+ *   out_exact  int32[n][4] device or NULL (16-byte aligned)
+ *   out_1sps   int8[M][4] device or NULL, M = (n + 1 - decim_phase) / 2.
+ * FNT_E_INVAL for ntaps outside 1 .. 65, requant_shift outside 0 .. 16, a phase
+ * other than 0 or 1, a NULL or misaligned buffer; FNT_E_RANGE for a tap outside
+ * 6 bit (nothing launched); samples outside 5 bit are latched for fnt_check. */
+int fnt_cdc_long(const int8_t *in, uint64_t n, const int8_t *host_taps, int ntaps, int requant_shift,
+                 int decim_phase, int32_t *out_exact, int8_t *out_1sps, void *stream);
 
 /* FNT-AEQ of m symbols (Fig. 3 structure, Eq. (6)).
  *   in_1sps int8[m][4] device (5-bit values)

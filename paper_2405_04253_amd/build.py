@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfnt.so")
-SOURCES = ["fnt_kernels.hip", "fnt_api.cpp", "fnt_session.cpp", "fnt_noalloc.hip"]
+SOURCES = ["fnt_kernels.hip", "fnt_api.cpp", "fnt_session.cpp", "fnt_noalloc.hip", "fnt_cdc_long.hip"]
 # measured GPU ceilings for the benchmark's roofline objects (not the receiver path)
 PROBE_LIB = os.path.join(HERE, "libfntprobe.so")
 PROBE_SOURCE = "peak_probe.hip"

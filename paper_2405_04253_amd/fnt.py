@@ -109,6 +109,7 @@ SIGNATURES = {
     "fnt_forward": (_i32, [_vp, _vp, _sz, _i32, _i32, _i32, _vp]),
     "fnt_inverse": (_i32, [_vp, _vp, _sz, _i32, _i32, _i32, _vp]),
     "fnt_cdc": (_i32, [_vp, _u64, ctypes.POINTER(CdcParams), _vp, _vp, _vp]),
+    "fnt_cdc_long": (_i32, [_vp, _u64, _vp, _i32, _i32, _i32, _vp, _vp, _vp]),
     "fnt_aeq": (_i32, [_vp, _u64, _vp, ctypes.POINTER(AeqParams), _vp, _vp]),
     "fnt_cdc_aeq": (_i32, [_vp, _u64, ctypes.POINTER(CdcParams), _vp, ctypes.POINTER(AeqParams), _vp, _vp]),
     "fnt_plan_create": (_i32, [ctypes.POINTER(_vp), ctypes.POINTER(ChannelDesc), _sz,
@@ -245,6 +246,22 @@ def fnt_cdc(samples, params: CdcParams, exact: bool = True, one_sps: bool = True
         _need(a, torch.int8, (4,), "a_out")
         assert a.shape[0] == M
     _ok(lib().fnt_cdc(_ptr(samples), n, ctypes.byref(params), _ptr(z), _ptr(a), _stream(stream)))
+    return z, a
+
+
+def fnt_cdc_long(samples, taps, requant_shift: int, decim_phase: int = 0, exact: bool = True,
+                 one_sps: bool = True, stream=None):
+    """fnt_cdc_long (N = 128, up to 65 taps): samples int8 [n, 4] on the GPU, taps
+    int8 [L, 2] (host array) -> (z int32 [n, 4] or None, a int8 [M, 4] or None)."""
+    import numpy as np
+    import torch
+    _need(samples, torch.int8, (4,), "samples")
+    n = samples.shape[0]
+    h = np.ascontiguousarray(np.asarray(taps, dtype=np.int8).reshape(-1, 2))
+    z = torch.empty((n, 4), dtype=torch.int32, device=samples.device) if exact else None
+    a = torch.empty((n_symbols(n, decim_phase), 4), dtype=torch.int8, device=samples.device) if one_sps else None
+    _ok(lib().fnt_cdc_long(_ptr(samples), n, h.ctypes.data, h.shape[0], int(requant_shift), int(decim_phase),
+                           _ptr(z), _ptr(a), _stream(stream)))
     return z, a
 
 
