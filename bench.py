@@ -478,6 +478,11 @@ def bench_batched(args, torch, dev):
     # fnt_plan_run of the same plan (the graph replay when no lead is in effect), for comparison
     taps_all.copy_(w_all)
     run_ms = _time_events(torch, plan.run, 2, stream)
+    # the same schedule as a hipGraph replay (a lead's fork and join are events
+    # inside the capture); the first replay uploads the graph and is not timed
+    plan.run_graph(stream)
+    torch.cuda.synchronize()
+    graph_ms = _time_events(torch, lambda: plan.run_graph(stream), 3, stream)
     # parity on sampled channels: reset the taps, run once more, compare with the oracle
     taps_all.copy_(w_all)
     plan.run(stream)
@@ -491,6 +496,15 @@ def bench_batched(args, torch, dev):
         outr, wr, _ = O.cdc_aeq(q.cpu().numpy(), taps, sh, synth.centre_spike_taps(), O.params(**prms[i]))
         if not (np.array_equal(entries[i][1].cpu().numpy(), outr) and np.array_equal(taps_all[i].cpu().numpy(), wr)):
             raise SystemExit(f"batched parity failure on channel {i}")
+    direct_out = {i: entries[i][1].clone() for i in pick}
+    direct_taps = {i: taps_all[i].clone() for i in pick}
+    taps_all.copy_(w_all)
+    plan.run_graph(stream)
+    torch.cuda.synchronize()
+    fnt.fnt_check()
+    for i in pick:
+        if not (torch.equal(entries[i][1], direct_out[i]) and torch.equal(taps_all[i], direct_taps[i])):
+            raise SystemExit(f"graph replay differs from the direct launches on channel {i}")
     plain_gsps = None
     fused = None
     if not args.no_comparisons:
@@ -570,7 +584,9 @@ def bench_batched(args, torch, dev):
                          "prio_channels": prio, "grid": plan.info()["fused_grid"],
                          "kernel": "cdc_aeq_fused_kernel<4, 1, 2>"}
         taps_all.copy_(w_all)
-        fused["graph_ms"] = round(_time_events(torch, plan.run, 2, stream), 3)
+        plan.run(stream)                    # the first replay of the fused graph uploads it
+        torch.cuda.synchronize()
+        fused["graph_ms"] = round(_time_events(torch, plan.run, 3, stream), 3)
         plan.set_fused(0)
     # back to the tuned (or given) schedule
     apply_schedule(plan, info)
@@ -656,6 +672,7 @@ def bench_batched(args, torch, dev):
         "roofline": roof,
         "kernels": kernels,
         "plan_run_ms": round(run_ms, 3),
+        "graph_replay_ms": round(graph_ms, 3),
         "event_ms_per_step": round(event_step_ms, 3),
         "event_ms_per_step_median": round(event_step_med, 3),
         "roofline_whole_path": {"bound": "alu", "achieved": round((all_aeq_ops + cdc_ops) / (ms / 1e3) / 1e9, 1),
@@ -842,6 +859,175 @@ def bench_served(args, torch, dev, host: bool = False):
             "parity": f"bit-exact vs oracle on channels {busiest} (whole streams)", "gen_s": round(gen_s, 1)}
 
 
+def bench_large(args, torch, dev):
+    """The large batch at full HBM occupancy: 16384 channels, log-uniform
+    2^14..2^22 symbols/pol (about 2^34.5 instants, 99.5 GB in and out), every
+    channel from its own seed; one plan with quick autotuning; against the plain
+    per-channel loop on a sample; parity on sampled channels (every channel is
+    checked in the full-size GPU test)."""
+    import oracle as O
+    from paper_2405_04253_amd import fnt, synth
+    torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    specs = synth.batched_specs(16384, 14, 22, tag="large")
+    _, chans = synth.gen_batch_torch(specs, dev)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    inst = sum(c[0].shape[0] for c in chans)
+    progress(f"large: generated {inst} instants in {gen_s:.1f} s")
+    w0 = torch.from_numpy(synth.centre_spike_taps()).to(dev)
+    taps_all = w0.unsqueeze(0).repeat(len(chans), 1, 1, 1).contiguous()
+    entries, prms = [], []
+    for i, (q, taps, sh, unit) in enumerate(chans):
+        prm = dict(synth.AEQ_DEFAULTS, const_unit=unit)
+        prms.append(prm)
+        out = torch.empty((q.shape[0] // 2, 4), dtype=torch.int16, device=dev)
+        entries.append((q, out, taps_all[i], fnt.cdc_params(taps, sh), fnt.aeq_params(**prm)))
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    plan = fnt.Plan(entries, autotune=True, use_graph=True, stream=stream, tune_quick=True)
+    torch.cuda.synchronize()
+    tune_s = time.perf_counter() - t0
+    info = plan.info()
+    progress(f"large: plan ready in {tune_s:.1f} s: {info}")
+    w_all = w0.unsqueeze(0).expand_as(taps_all)
+
+    def step():
+        taps_all.copy_(w_all)
+        plan.run(stream)
+
+    step()
+    torch.cuda.synchronize()
+    fnt.fnt_check()
+    steps = max(1, args.large_steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    fnt.fnt_check()
+    order = sorted(range(len(chans)), key=lambda i: chans[i][0].shape[0])
+    pick = sorted(set([order[0], order[len(order) // 2], order[-1]]))
+    for i in pick:
+        q, taps, sh, unit = chans[i]
+        outr, wr, _ = O.cdc_aeq(q.cpu().numpy(), taps, sh, synth.centre_spike_taps(), O.params(**prms[i]))
+        if not (np.array_equal(entries[i][1].cpu().numpy(), outr) and np.array_equal(taps_all[i].cpu().numpy(), wr)):
+            raise SystemExit(f"large batch parity failure on channel {i}")
+    rng = np.random.default_rng(9)
+    sample = [int(i) for i in rng.choice(len(chans), size=16, replace=False)]
+    s_inst = sum(chans[i][0].shape[0] for i in sample)
+    abuf = torch.empty((max(chans[i][0].shape[0] for i in sample) // 2 + 1, 4), dtype=torch.int8, device=dev)
+    tmp_taps = w0.clone()
+
+    def plain_loop():
+        for i in sample:
+            tmp_taps.copy_(w0)
+            m = entries[i][1].shape[0]
+            fnt.fnt_cdc(chans[i][0], entries[i][3], exact=False, a_out=abuf[:m], stream=stream)
+            fnt.fnt_aeq(abuf[:m], tmp_taps, entries[i][4], out=entries[i][1], stream=stream)
+
+    plain_ms = _time_events(torch, plain_loop, 1, stream)
+    plain = s_inst / (plain_ms / 1e3) / 1e9
+    value = inst / (ms / 1e3) / 1e9
+    plan.close()
+    return {"value": round(value, 4), "unit": "Gsamples/s", "ms_per_step": round(ms, 3), "steps": steps,
+            "workload": "16384 channels, log-uniform 2^14..2^22 symbols/pol, fibre U(10,80) km, OSNR U(18,26) dB, "
+                        "every channel from its own seed",
+            "instants": inst, "vs_plain": round(value / plain, 2),
+            "plain_loop": {"value": round(plain, 5), "unit": "Gsamples/s",
+                           "sample": "16 random channels, fnt_cdc then fnt_aeq, one channel after another"},
+            "plan": {k: info[k] for k in ("cdc_waves_per_group", "aeq_waves_per_pol", "aeq_waves_long",
+                                          "aeq_long_channels", "lead_channels", "lead_form", "graph",
+                                          "fused_lpt", "fused_split", "fused_prio_channels")},
+            "parity": f"bit-exact vs oracle on channels {pick}", "gen_s": round(gen_s, 1),
+            "autotune_s": round(tune_s, 1)}
+
+
+def bench_served_capacity(args, torch, dev):
+    """The session's throughput ceiling: the served workload (1024 channels,
+    segments log-uniform 2^13..2^18 symbols) replayed at rising Poisson rates, a
+    fresh session per rate on the same channel streams, until the delivered rate
+    falls below 90% of the offered one or p99 exceeds 10x the first point's."""
+    from paper_2405_04253_amd import fnt, synth
+    nch = args.served_channels
+    window = args.sweep_window
+    rates = [float(r) for r in args.sweep_rates.split(",")]
+    plans = []
+    for k, rate in enumerate(rates):
+        rng = np.random.default_rng(777 + k)
+        times, t = [], 0.0
+        while True:
+            t += rng.exponential(1.0 / rate)
+            if t > window:
+                break
+            times.append(t)
+        seg = [16 * max(1, int(2 ** rng.uniform(13, 18)) // 16) for _ in times]
+        owner = rng.integers(0, nch, size=len(times))
+        plans.append((rate, times, seg, owner))
+    need = np.zeros(nch, np.int64)
+    for _, times, seg, owner in plans:
+        per = np.zeros(nch, np.int64)
+        np.add.at(per, owner, np.array(seg, np.int64))
+        need = np.maximum(need, per)
+    t0 = time.perf_counter()
+    streams, params = {}, {}
+    for c in range(nch):
+        r = np.random.default_rng(synth.seed_for(0, "served", c))
+        km, osnr = float(r.uniform(10, 80)), float(r.uniform(18, 26))
+        q, taps, sh, unit = synth.gen_channel_torch(max(int(need[c]), 16), km, osnr,
+                                                    synth.seed_for(2, "served", c), dev)
+        streams[c] = q
+        params[c] = (taps, sh, dict(synth.AEQ_DEFAULTS, const_unit=unit))
+        if c % 256 == 0:
+            torch.cuda.synchronize()
+            progress(f"served sweep: generated {c}/{nch} streams ({time.perf_counter() - t0:.1f} s)")
+    outs = {c: torch.zeros((streams[c].shape[0] // 2, 4), dtype=torch.int16, device=dev) for c in range(nch)}
+    torch.cuda.synchronize()
+    points = []
+    for rate, times, seg, owner in plans:
+        sess = fnt.Session(max_channels=nch, hbm_budget_bytes=1 << 30, chunk_blocks=args.chunk,
+                           max_active=nch, aeq_form=args.served_form)
+        for c in range(nch):
+            taps, sh, prm = params[c]
+            sess.add_channel(c, fnt.cdc_params(taps, sh), fnt.aeq_params(**prm))
+        reqs, offs = [], [0] * nch
+        for i in range(len(times)):
+            c = int(owner[i])
+            n = 2 * seg[i]
+            o = offs[c]
+            reqs.append((c, streams[c][o:o + n], outs[c][o // 2:(o + n) // 2], int(times[i] * 1e9)))
+            offs[c] += n
+        progress(f"served sweep: {rate:.0f} req/s, {len(reqs)} requests over {window} s")
+        sess.replay(reqs)
+        t_end = time.perf_counter()
+        while sess.stats()["completed"] < len(reqs):
+            time.sleep(0.5)
+            progress(f"served sweep: {sess.stats()['completed']}/{len(reqs)} done "
+                     f"({time.perf_counter() - t_end:.1f} s after the last arrival)")
+        sess.drain()
+        st = sess.stats()
+        sess.close()
+        fnt.fnt_check()
+        offered = 2 * sum(seg) / window / 1e9
+        pt = {"rate_req_s": rate, "offered_gsamples_per_s": round(offered, 3),
+              "delivered_gsamples_per_s": round(st["gsamples_per_s"], 3), "p50_us": round(st["p50_us"], 1),
+              "p99_us": round(st["p99_us"], 1), "requests": int(st["completed"]), "ticks": int(st["ticks"])}
+        points.append(pt)
+        progress(f"served sweep: {pt}")
+        if st["gsamples_per_s"] < 0.9 * offered or st["p99_us"] > 10 * points[0]["p99_us"]:
+            break
+    sustained = [p for p in points if p["delivered_gsamples_per_s"] >= 0.9 * p["offered_gsamples_per_s"]
+                 and p["p99_us"] <= 10 * points[0]["p99_us"]]
+    return {"points": points, "unit": "Gsamples/s",
+            "capacity_gsamples_per_s": max((p["delivered_gsamples_per_s"] for p in sustained), default=None),
+            "saturated_delivered_gsamples_per_s": points[-1]["delivered_gsamples_per_s"],
+            "workload": f"{nch} channels, segments log-uniform 2^13..2^18 symbols, chunk {args.chunk} blocks/tick, "
+                        f"{window} s of Poisson arrivals per rate, rates {args.sweep_rates} req/s until the "
+                        f"delivered rate drops below 90% of the offered one or p99 exceeds 10x the first point's",
+            "gen_s": round(time.perf_counter() - t0, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -858,6 +1044,8 @@ def main():
     ap.add_argument("--skip-single", action="store_true")
     ap.add_argument("--skip-transforms", action="store_true")
     ap.add_argument("--skip-cdc-long", action="store_true")
+    ap.add_argument("--skip-large", action="store_true")
+    ap.add_argument("--large-steps", type=int, default=3)
     ap.add_argument("--nch", type=int, default=4096)
     ap.add_argument("--log2-min", type=int, default=12)
     ap.add_argument("--log2-max", type=int, default=20)
@@ -867,6 +1055,10 @@ def main():
     ap.add_argument("--chunk", type=int, default=512)
     ap.add_argument("--h2d-window", type=float, default=0.25,
                     help="arrival window of the served leg with host buffers (0: skip it)")
+    ap.add_argument("--sweep-rates", default="20000,40000,80000,120000,160000,240000",
+                    help="Poisson rates (req/s) of the served capacity sweep")
+    ap.add_argument("--sweep-window", type=float, default=0.25)
+    ap.add_argument("--skip-sweep", action="store_true")
     ap.add_argument("--served-form", type=int, default=-1,
                     help="AEQ form of the session ticks (0, 3, 1, 2, 4; -1: automatic)")
     ap.add_argument("--tune-cache", default=None,
@@ -918,6 +1110,10 @@ def main():
                 res["roofline"]["frac_of_measured_base"] = round(
                     res["roofline"]["achieved"] / peaks["alu_base_rate_gops"], 5)
             progress(f"measured peaks: {peaks}")
+    if not args.skip_large:
+        progress("large batch")
+        res["large_batch"] = bench_large(args, torch, dev)
+        progress(f"large batch done: {res['large_batch']['value']}")
     if not args.skip_single:
         progress("plain single stream")
         res["plain_single_stream"] = bench_single(args, torch, dev)
@@ -939,6 +1135,10 @@ def main():
             progress("served with host buffers")
             res["served_h2d"] = bench_served(args, torch, dev, host=True)
             progress(f"served with host buffers done: {res['served_h2d']['value']}")
+        if not args.skip_sweep:
+            progress("served capacity sweep")
+            res["served_capacity"] = bench_served_capacity(args, torch, dev)
+            progress(f"served capacity sweep done: {res['served_capacity']['capacity_gsamples_per_s']}")
     if args.launches_out:
         with open(args.launches_out, "w") as f:
             json.dump({"batched": res.get("launches", []),

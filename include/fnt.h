@@ -218,7 +218,7 @@ typedef struct fnt_plan_info {
                               2 = Fermat-domain, one wave per channel, 3 = the same with the
                               RDE gradient in the Fermat domain too */
     int32_t aeq_waves_per_pol;  /* variant 0: AEQ form (0, 3, 1, 5, 2, 4; see fnt_plan_set_aeq_waves) */
-    int32_t graph;         /* 1 if fnt_plan_run replays a hipGraph (never while a lead is in effect) */
+    int32_t graph;         /* 1 if fnt_plan_run replays a hipGraph (plans created with use_graph) */
     int32_t aeq_waves_long;     /* AEQ form of the long chains (see fnt_plan_set_aeq_split) */
     double tune_ms;        /* AEQ time of the chosen schedule during autotune, ms (0 if none) */
     uint64_t aeq_long_channels; /* longest channels run in their own concurrent launch */
@@ -251,6 +251,11 @@ int fnt_plan_create(fnt_plan **plan, const fnt_channel_desc *host_channels, size
                     const fnt_plan_config *cfg, void *stream);
 /* Run every channel once (CDC + resample + AEQ), enqueued on `stream`. */
 int fnt_plan_run(fnt_plan *plan, void *stream);
+/* The run as a replay of the plan's captured hipGraph (what fnt_plan_run does
+ * for plans created with use_graph).  With a pipelined lead the graph has the
+ * lead's branch on its own stream, forked and joined by events inside the
+ * capture.  FNT_E_STATE if the plan has no graph (created without use_graph). */
+int fnt_plan_run_graph(fnt_plan *plan, void *stream);
 
 #define FNT_STAGE_CDC 1   /* CDC + resample + requantise of every channel (writes plan scratch) */
 #define FNT_STAGE_AEQ 2   /* AEQ of every channel (reads plan scratch, updates taps, writes out) */

@@ -468,6 +468,7 @@ static int plan_launch(fnt_plan *p, hipStream_t s, hipStream_t side, hipStream_t
     };
     const int lf = lead_form_of(p);
     const int tf = top_form_of(p);
+    bool cdc_enqueued = false;                 // the others' CDC segment [lead, n)
     if (top) {
         if (e == hipSuccess) e = seg_cdc(0, top);
         if (e == hipSuccess) e = seg_aeq(0, top, tf, side2, p->fork2, 6);
@@ -495,9 +496,21 @@ static int plan_launch(fnt_plan *p, hipStream_t s, hipStream_t side, hipStream_t
             e = launch_aeq_split(p->aeq_dev, (int)plan_top(p), (int)lead, tf, lf, p->err, side, true);
         if (e == hipSuccess) e = rec(3, side);
     } else if (e == hipSuccess) {
-        e = seg_aeq(top, lead, lf, side, p->fork, 2);
+        // The others' CDC is enqueued before the lead's AEQ, which waits for the
+        // lead's CDC only (the fork event is recorded before the others' CDC).
+        // Graph replays dispatch the nodes in this order; with the lead's AEQ
+        // first, its long-lived waves took the compute units ahead of the short
+        // CDC workgroups and the others' CDC ran twice as long.
+        e = hipEventRecord(p->fork, s);
+        if (e == hipSuccess) e = seg_cdc(lead, n);
+        if (e == hipSuccess) e = hipStreamWaitEvent(side, p->fork, 0);
+        if (e == hipSuccess) e = rec(2, side);
+        if (e == hipSuccess)
+            e = launch_aeq(p->aeq_dev + top, (int)(lead - top), AeqItem{}, p->variant, lf, p->err, side, true);
+        if (e == hipSuccess) e = rec(3, side);
+        cdc_enqueued = true;
     }
-    if (e == hipSuccess) e = seg_cdc(lead, n);
+    if (e == hipSuccess && !cdc_enqueued) e = seg_cdc(lead, n);
     if (e == hipSuccess) e = rec(1, s);
     if (e == hipSuccess) e = plan_aeq_range(p, (int)lead, rest_long, (int)(n - lead), s);
     if (e == hipSuccess) e = rec(4, s);
@@ -1156,14 +1169,21 @@ int fnt_plan_run(fnt_plan *p, void *stream) {
     if (!p) return fail(FNT_E_INVAL, "plan: NULL");
     if (p->cdc_host.empty()) return FNT_OK;
     hipStream_t s = (hipStream_t)stream;
-    // with a lead the sequence is launched directly: replays of its two-branch
-    // graph ran the branches with less overlap than the direct launches
-    if (p->exec && plan_lead(p) == 0) {
+    if (p->exec) {                                    // a lead's branch is forked and joined inside the graph
         hipError_t e = hipGraphLaunch(p->exec, s);
         if (e != hipSuccess) return hip_fail(e, "plan: graph launch");
         return FNT_OK;
     }
     return plan_launch(p, s, p->side, p->side2);
+}
+
+int fnt_plan_run_graph(fnt_plan *p, void *stream) {
+    if (!p) return fail(FNT_E_INVAL, "plan: NULL");
+    if (p->cdc_host.empty()) return FNT_OK;
+    if (!p->exec) return fail(FNT_E_STATE, "plan: no captured graph (created without use_graph)");
+    hipError_t e = hipGraphLaunch(p->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "plan: graph launch");
+    return FNT_OK;
 }
 
 int fnt_plan_run_stage(fnt_plan *p, int stages, void *stream) {
@@ -1186,7 +1206,7 @@ int fnt_plan_get_info(const fnt_plan *p, fnt_plan_info *info) {
     info->aeq_waves_per_pol = p->wpp;
     info->aeq_waves_long = p->wpp_long;
     info->aeq_long_channels = p->variant == 0 ? std::min(p->n_long, p->aeq_host.size()) : 0;
-    info->graph = (p->exec && plan_lead(p) == 0) ? 1 : 0;
+    info->graph = p->exec ? 1 : 0;
     info->cdc_variant = p->cdc_variant;
     const size_t lead = plan_lead(p);
     info->lead_channels = (int32_t)lead;

@@ -115,6 +115,7 @@ SIGNATURES = {
     "fnt_plan_create": (_i32, [ctypes.POINTER(_vp), ctypes.POINTER(ChannelDesc), _sz,
                                ctypes.POINTER(PlanConfig), _vp]),
     "fnt_plan_run": (_i32, [_vp, _vp]),
+    "fnt_plan_run_graph": (_i32, [_vp, _vp]),
     "fnt_plan_run_stage": (_i32, [_vp, _i32, _vp]),
     "fnt_plan_get_info": (_i32, [_vp, ctypes.POINTER(PlanInfo)]),
     "fnt_plan_set_aeq_variant": (_i32, [_vp, _i32]),
@@ -315,6 +316,10 @@ class Plan:
 
     def run(self, stream=None):
         _ok(lib().fnt_plan_run(self._h, _stream(stream)))
+
+    def run_graph(self, stream=None):
+        """Replay the captured hipGraph whatever the schedule (fnt_plan_run_graph)."""
+        _ok(lib().fnt_plan_run_graph(self._h, _stream(stream)))
 
     def run_stage(self, stages: int, stream=None):
         """Launch FNT_STAGE_CDC and/or FNT_STAGE_AEQ directly (outside the graph)."""

@@ -364,6 +364,42 @@ def test_plan_extreme_aeq_params(torch_dev, wpp):
     fnt.fnt_check()
 
 
+def test_plan_graph_replay_with_lead(torch_dev):
+    """fnt_plan_run_graph: the captured graph of a schedule with a pipelined lead
+    (the lead's branch forked and joined by events inside the capture) replayed
+    several times, with eager work and synchronisation between replays, equals
+    the direct launches and the oracle every time."""
+    torch, dev = torch_dev
+    chans = _batch(24, 6, 11, seed=41)
+    pc = _plan_channels(torch, dev, chans, None)
+    refs = [O.cdc_aeq(c["ch"].samples, c["ch"].taps, c["ch"].requant_shift, c["w0"], O.params(**c["prm"]))
+            for c in pc]
+    entries = [(c["x"], c["out"], c["taps"], fnt.cdc_params(c["ch"].taps, c["ch"].requant_shift),
+                fnt.aeq_params(**c["prm"])) for c in pc]
+    plan = fnt.Plan(entries, autotune=False, use_graph=True)
+    for lead, lf, top, tf in [(8, 1, 0, -1), (10, 2, 3, 4), (6, 6, 0, -1)]:
+        plan.set_aeq_split(12, 1, 0)
+        plan.set_lead(lead, lf, top, tf)
+        for rep in range(3):
+            for c in pc:                                # eager work between the replays
+                c["taps"].copy_(to_dev(torch, dev, c["w0"]))
+                c["out"].fill_(-7)
+            torch.cuda.synchronize()
+            note(f"graph replay with lead {lead}/{lf} top {top}/{tf}, replay {rep}")
+            plan.run_graph()
+            torch.cuda.synchronize()
+            fnt.fnt_check()
+            for c, (outr, wr, _) in zip(pc, refs):
+                assert np.array_equal(c["out"].cpu().numpy(), outr), (lead, rep, c["ch"].n)
+                assert np.array_equal(c["taps"].cpu().numpy(), wr), (lead, rep, c["ch"].n)
+    plan.close()
+    nog = fnt.Plan(entries[:3], autotune=False, use_graph=False)
+    with pytest.raises(fnt.FntError) as e:
+        nog.run_graph()
+    assert e.value.code == fnt.FNT_E_STATE
+    nog.close()
+
+
 def test_plan_fermat_gradient_extremes(torch_dev):
     """AEQ variant 3 (the RDE gradient through FNT32 products) at the Eq. (5)
     bound of the gradient: windows of -16 and errors clipped at -128 give
