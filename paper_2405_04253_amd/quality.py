@@ -198,7 +198,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--osnr", default="14,16,18,20,22,24")
     ap.add_argument("--nsym", type=int, default=1 << 18)
-    ap.add_argument("--aeq", default="16:3,14:7",
+    ap.add_argument("--aeq", default="16:4,16:5,16:3",
                     help="AEQ err_shift:mu_shift settings of the integer receiver, comma separated")
     ap.add_argument("--km", type=float, default=75.0)
     ap.add_argument("--seed", type=int, default=0)

@@ -96,16 +96,17 @@ def test_float_reference_receiver_high_osnr():
 
 @pytest.mark.gpu
 def test_fnt_receiver_converges():
-    """The integer receiver separates the polarisations and equalises: with the
-    default (fast, coarse) RDE step its SER floor at OSNR 26 dB is ~2e-2, against
-    ~0.75 for an unconverged equaliser."""
+    """The integer receiver separates the polarisations and equalises within 2^16
+    symbols: with the default RDE step (err_shift 16, mu_shift 4) its SER at
+    OSNR 26 dB is ~1e-2 (the oracle gives 8.5e-3 on this channel), against ~0.75
+    for an unconverged equaliser."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     ch = synth.gen_channel(1 << 16, 75.0, 26.0, 11)
     r = Q.align_and_count(Q.fnt_receiver(ch), ch.symbols)
     print(f"[case] FNT receiver SER at OSNR 26 dB: {r['ser']:.2e} {r['alignment']}", flush=True)
-    assert r["ser"] < 0.05
+    assert r["ser"] < 0.03
     assert {a["tx"] for a in r["alignment"]} == {0, 1}
 
 
