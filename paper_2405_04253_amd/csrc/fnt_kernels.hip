@@ -1568,6 +1568,10 @@ struct AeqSrcRing {            // the CDC output ring of the fused kernel
     int *err;
     uint32_t have;             // chunks [0, have) known to be written (wave-uniform)
     bool live;                 // false once a wait gave up
+    // the other polarisation half's progress words in the same workgroup (none
+    // when a workgroup runs one half)
+    const uint32_t *peer = nullptr;
+    int npeer = 0;
     // chunks complete out of order when several producer waves share them out,
     // so each is checked in its own slot, in order
     __device__ __forceinline__ void need(uint32_t chunk) {
@@ -1582,8 +1586,16 @@ struct AeqSrcRing {            // the CDC output ring of the fused kernel
         if (i < 0) return aeq_sym(*it, i);
         return (uint64_t)i < M ? ring[i & (WORDS - 1)] : 0u;
     }
-    // every chunk the blocks [b0, b1) read ahead, checked once before they run
-    __device__ __forceinline__ void segment(uint32_t, uint32_t b1) {
+    // Before the blocks [b0, b1): every chunk they read ahead, checked once; and
+    // the other half done with the blocks before b0, so that the halves stay
+    // within one segment of each other.  The two halves write the 16-bit pieces
+    // of the same output records: apart by up to the ring's length, partial
+    // lines left the L2 cache before the other half filled them, and the kernel
+    // wrote 1.6 times its output bytes.  The slower half never waits for the
+    // faster one, and the channel ends with the slower half anyway.
+    __device__ __forceinline__ void segment(uint32_t b0, uint32_t b1) {
+        for (int k = 0; k < npeer; ++k)
+            if (live) live = wait_at_least<2>(&peer[k], b0, limit, err, stall);
         need((uint32_t)(min<uint64_t>(16 * (uint64_t)(b1 - 1) + 47, M - 1) / FUSED_CHUNK_SYMS));
     }
     __device__ __forceinline__ uint32_t ahead(uint32_t b, int wpos) const {
@@ -2020,7 +2032,8 @@ __global__ __launch_bounds__(64 * (HALVES * (LPT / 4) + NP)) __attribute__((amdg
             if (chn >= (uint32_t)total) break;
             if ((int)chn < nprio) __builtin_amdgcn_s_setprio(3); else __builtin_amdgcn_s_setprio(1);
             const AeqItem it = aitems ? aitems[chn] : asingle;
-            AeqSrcRing<RING> src{&it, ring_s, slot_s, &cons_s[v], &stall_s, it.m, spin_limit, err, 0u, true};
+            AeqSrcRing<RING> src{&it, ring_s, slot_s, &cons_s[v], &stall_s, it.m, spin_limit, err, 0u, true,
+                                 HALVES == 2 ? &cons_s[(1 - pol) * WPP] : nullptr, HALVES == 2 ? WPP : 0};
             if constexpr (WPP == 1) {
                 HalfSyncWg unused;
                 aeq_pol_run<LPT>(it, pol, vh, lane, err, aspec_s[v], part_s[v / WPP], epsw_s[v], winw_s[v], src,
