@@ -320,12 +320,14 @@ def apply_schedule(plan, s: dict):
                   int(s.get("top_form", -1)))
 
 
-def launch_entry(kernel, key, aeq_blocks=0, cdc_blocks=0, instants=0):
+def launch_entry(kernel, key, aeq_blocks=0, cdc_blocks=0, instants=0, grid=None):
     """One launch of a step: the kernel name as a kernel trace shows it, the key its
     counters are stored under, its units and their algorithmic work and bytes
     (AEQ 12 B per symbol, CDC 6 B per instant, the fused chain 8 B per instant)."""
     e = {"kernel": kernel, "key": key, "aeq_blocks": aeq_blocks, "cdc_blocks": cdc_blocks,
          "algorithmic_ops": AEQ_OPS_PER_BLOCK * aeq_blocks + CDC_OPS_PER_BLOCK * cdc_blocks}
+    if grid is not None:
+        e["grid"] = grid                    # threads of the launch, to tell launches of one kernel apart
     if aeq_blocks and cdc_blocks:
         e["algorithmic_bytes"] = instants * FUSED_BYTES_PER_INSTANT
     elif cdc_blocks:
@@ -335,15 +337,36 @@ def launch_entry(kernel, key, aeq_blocks=0, cdc_blocks=0, instants=0):
     return e
 
 
-def launches_of(info, timing, kname, lead_name, top_name, aeq_blocks, lead_blocks, top_blocks, cdc_blocks, inst):
-    """The plan's launches in one step (launch_entry)."""
+def launches_of(info, timing, kname, lead_name, top_name, aeq_blocks, lead_blocks, top_blocks, lengths):
+    """The plan's launches in one step (launch_entry).  lengths: every channel's
+    instants; the plan orders channels longest chain first (stable), and a lead
+    runs the CDC of its segment as a launch of its own."""
+    order = sorted(range(len(lengths)), key=lambda i: -((lengths[i] + 1) // 2))
+    n = [lengths[i] for i in order]
+    blocks = [(v + 31) // 32 for v in n]
+    chunks = [(b + 63) // 64 for b in blocks]
+    inst = sum(n)
     if timing["fused"]:
-        return [launch_entry(kname, kname, aeq_blocks, cdc_blocks, inst)]
-    cdc = ("cdc_lane_kernel<%d>" % info["cdc_waves_per_group"]) if info["cdc_blocks_per_wave"] == 0 \
-        else "cdc_kernel<false>"
+        wg = 64 * (2 * (info["fused_lpt"] // 4) + info["fused_lpt"] // 4) if not info["fused_split"] else None
+        return [launch_entry(kname, kname, aeq_blocks, sum(blocks), inst,
+                             grid=info["fused_grid"] * wg if wg else None)]
+    wpg = info["cdc_waves_per_group"]
+    cdc = ("cdc_lane_kernel<%d>" % wpg) if info["cdc_blocks_per_wave"] == 0 else "cdc_kernel<false>"
     if info["cdc_variant"] == 1:
-        cdc = "cdc_direct_kernel<%d>" % info["cdc_waves_per_group"]
-    out = [launch_entry(cdc, cdc, 0, cdc_blocks, inst)]
+        cdc = "cdc_direct_kernel<%d>" % wpg
+    lane_cdc = info["cdc_blocks_per_wave"] == 0
+
+    def seg(a, b, key):
+        g = -(-sum(chunks[a:b]) // wpg) * 64 * wpg if lane_cdc else None
+        return launch_entry(cdc, key, 0, sum(blocks[a:b]), sum(n[a:b]), grid=g)
+
+    lead = info["lead_channels"]
+    top = info["top_channels"] if top_name else 0
+    if lead:
+        out = ([seg(0, top, cdc + " (first level)")] if top else []) + \
+              [seg(top, lead, cdc + " (lead)"), seg(lead, len(n), cdc)]
+    else:
+        out = [seg(0, len(n), cdc)]
     if "+" not in kname:
         out.append(launch_entry(kname, kname, aeq_blocks))
     if lead_name:
@@ -685,7 +708,7 @@ def bench_batched(args, torch, dev):
         "parity": f"bit-exact vs oracle on channels {pick}", "gen_s": round(gen_s, 1),
         "autotune_s": round(tune_s, 1),
         "launches": launches_of(info, times[0], kname, lead_name, top_name, aeq_blocks, lead_blocks, top_blocks,
-                                cdc_blocks, inst),
+                                [e[0].shape[0] for e in entries]),
     }
     if plain_gsps is not None:
         res["vs_plain"] = round(value / plain_gsps, 2)

@@ -174,7 +174,7 @@ def main(argv=None):
             for g, cs in grids.items():
                 sq.setdefault(name, {}).setdefault(g, {}).update(cs)
     cal = calibration(a.calib_fetch, a.calib_write, a.calib_bytes) if a.calib_fetch and a.calib_write else None
-    wanted, alg = [], {}
+    wanted, alg, grids = [], {}, {}
     for spec in a.kernel:
         name, rest = spec.split("=", 1)
         key, _, blocks = rest.partition(":")
@@ -183,6 +183,8 @@ def main(argv=None):
         for e in json.load(open(a.launches)).get(a.leg or a.workload, []):
             wanted.append((e["kernel"], e["key"], e.get("aeq_blocks") or None))
             alg[e["key"]] = e
+            if e.get("grid"):
+                grids[e["key"]] = int(e["grid"])
 
     lines = [f"# {a.title or a.workload}: rocprofv3 summary", ""]
     lines += a.note + ([""] if a.note else [])
@@ -196,7 +198,9 @@ def main(argv=None):
         if name not in trace:
             lines.append(f"| `{key}` | - | 0 | (not in the trace) |")
             continue
-        g, ds = _largest(trace[name])
+        # the launch's own grid when given (a kernel launched on two segments),
+        # else the kernel's largest grid (the plan's full launches)
+        g, ds = (grids[key], trace[name][grids[key]]) if grids.get(key) in trace[name] else _largest(trace[name])
         lines.append(f"| `{key}` | {g} | {len(ds)} | {_mean(ds):.3f} |")
         entries[key] = {"grid": g, "dispatches": len(ds), "avg_ms": _mean(ds)}
         if blocks is not None:
