@@ -456,22 +456,12 @@ static int plan_launch(fnt_plan *p, hipStream_t s, hipStream_t side, hipStream_t
         const uint64_t chunks = (b < n ? p->cdc_host[b].chunk0 : p->total_chunks) - ca.chunk0;
         return plan_cdc(p, p->cdc_seg_dev + a, (int)(b - a), blocks, chunks, s);
     };
-    // the AEQ of the lead segment [a, b) on stream st after its CDC
-    auto seg_aeq = [&](size_t a, size_t b, int form, hipStream_t st, hipEvent_t fk, int ev0) {
-        hipError_t r = hipEventRecord(fk, s);
-        if (r == hipSuccess) r = hipStreamWaitEvent(st, fk, 0);
-        if (r == hipSuccess) r = rec(ev0, st);
-        if (r == hipSuccess)
-            r = launch_aeq(p->aeq_dev + a, (int)(b - a), AeqItem{}, p->variant, form, p->err, st, true);
-        if (r == hipSuccess) r = rec(ev0 + 1, st);
-        return r;
-    };
     const int lf = lead_form_of(p);
     const int tf = top_form_of(p);
     bool cdc_enqueued = false;                 // the others' CDC segment [lead, n)
-    if (top) {
+    if (top) {                                 // the first level's CDC, then fork (its AEQ below)
         if (e == hipSuccess) e = seg_cdc(0, top);
-        if (e == hipSuccess) e = seg_aeq(0, top, tf, side2, p->fork2, 6);
+        if (e == hipSuccess) e = hipEventRecord(p->fork2, s);
     }
     if (lead_is_fused(p)) {
         // the lead's CDC and AEQ in one fused launch on the side stream, at once
@@ -485,6 +475,14 @@ static int plan_launch(fnt_plan *p, hipStream_t s, hipStream_t side, hipStream_t
         if (e == hipSuccess) e = rec(3, side);
     } else if (e == hipSuccess) {
         e = seg_cdc(top, lead);
+    }
+    if (top) {
+        // the first level's AEQ after the lead's CDC is enqueued (CDC workgroups
+        // dispatch ahead of the long-lived AEQ waves, as for the lead below)
+        if (e == hipSuccess) e = hipStreamWaitEvent(side2, p->fork2, 0);
+        if (e == hipSuccess) e = rec(6, side2);
+        if (e == hipSuccess) e = launch_aeq(p->aeq_dev, (int)top, AeqItem{}, p->variant, tf, p->err, side2, true);
+        if (e == hipSuccess) e = rec(7, side2);
     }
     if (lead_is_fused(p)) {
     } else if (fused) {
