@@ -663,8 +663,11 @@ __device__ __forceinline__ bool cdc_lane_blocks(const CdcItem *ip, uint64_t lb0,
             int32_t u[32], v[32];
             auto unpack = [&](auto jc, uint32_t w0, uint32_t w1) {
                 constexpr int j = decltype(jc)::value;
-                const int32_t r0 = sbyte(w0, 2 * pol), i0b = sbyte(w0, 2 * pol + 1);
-                const int32_t r1 = sbyte(w1, 2 * pol), i1b = sbyte(w1, 2 * pol + 1);
+                // one shift per word brings the polarisation's two bytes down; the
+                // byte selects then fold into the adds (SDWA)
+                const uint32_t s0 = w0 >> (16 * pol), s1 = w1 >> (16 * pol);
+                const int32_t r0 = sbyte(s0, 0), i0b = sbyte(s0, 1);
+                const int32_t r1 = sbyte(s1, 0), i1b = sbyte(s1, 1);
                 if constexpr (hf == 0) {
                     const int32_t xr = r0 + r1, xi = i0b + i1b;
                     u[j] = xr + 256 * xi;                   // |.| <= 8224
