@@ -30,7 +30,8 @@ CDC_HIST = 32
 class AeqParams(ctypes.Structure):
     _fields_ = [("out_shift", ctypes.c_int32), ("err_shift", ctypes.c_int32),
                 ("mu_shift", ctypes.c_int32), ("const_unit", ctypes.c_int32),
-                ("update_enable", ctypes.c_int32)]
+                ("update_enable", ctypes.c_int32), ("mu_shift_late", ctypes.c_int32),
+                ("gear_blocks", ctypes.c_int32), ("block0", ctypes.c_int64)]
 
 
 class _Channel(ctypes.Structure):
@@ -74,9 +75,14 @@ def _c8(a, shape_tail):
     return a
 
 
-def params(out_shift, err_shift, mu_shift, const_unit, update_enable=1) -> AeqParams:
+def params(out_shift, err_shift, mu_shift, const_unit, update_enable=1, mu_shift_late=None, gear_blocks=0,
+           block0=0) -> AeqParams:
+    """AEQ constants.  Step schedule: blocks with stream index block0 + b <
+    gear_blocks update with mu_shift, later ones with mu_shift_late (gear_blocks
+    = 0: mu_shift throughout)."""
+    late = mu_shift if mu_shift_late is None else mu_shift_late
     return AeqParams(int(out_shift), int(err_shift), int(mu_shift), int(const_unit),
-                     int(update_enable))
+                     int(update_enable), int(late), int(gear_blocks), int(block0))
 
 
 def n_symbols(n: int, phase: int = 0) -> int:

@@ -109,6 +109,12 @@ typedef struct orc_aeq_params {
     int32_t mu_shift;      /* s_mu: gradient -> tap increment (mu = 2^-(s_e+s_mu)) */
     int32_t const_unit;    /* c_y : 16QAM unit amplitude at the output */
     int32_t update_enable; /* 0: fixed filter bank */
+    /* Step schedule: the block with stream index j = block0 + (its index in this
+     * call) updates with s_mu = mu_shift while j < gear_blocks and with
+     * mu_shift_late from then on; gear_blocks = 0: mu_shift throughout. */
+    int32_t mu_shift_late;
+    int32_t gear_blocks;
+    int64_t block0;
 } orc_aeq_params;
 
 static int aeq_sample(const int8_t *a, const int8_t *hist, int64_t m, int s) {
@@ -152,6 +158,8 @@ void orc_aeq(const int8_t *a, int64_t M, int16_t *w, const orc_aeq_params *p,
             }
         }
         if (!p->update_enable) continue;
+        const int64_t j = p->block0 + b0 / ORC_AEQ_BLOCK;
+        const int mu = (p->gear_blocks > 0 && j >= p->gear_blocks) ? p->mu_shift_late : p->mu_shift;
         /* Eq. (6) summed over the block: w_{S1-S2} += mu * e_S2 * in_S1 * out_S2 */
         for (int s1 = 0; s1 < 4; ++s1)
             for (int s2 = 0; s2 < 4; ++s2)
@@ -160,7 +168,7 @@ void orc_aeq(const int8_t *a, int64_t M, int16_t *w, const orc_aeq_params *p,
                     for (int64_t m = b0; m < b1; ++m)
                         g += eps[m - b0][s2] * aeq_sample(a, hist, m - k, s1);
                     int16_t *wp = &w[(s1 * 4 + s2) * ORC_AEQ_TAPS + k];
-                    *wp = (int16_t)sat((int64_t)*wp + rs(g, p->mu_shift), 14);
+                    *wp = (int16_t)sat((int64_t)*wp + rs(g, mu), 14);
                 }
     }
 }

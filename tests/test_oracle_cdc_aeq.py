@@ -306,3 +306,71 @@ def test_chain_equals_parts_and_batch(aeq_defaults):
     assert used >= 1
     for (o, w), o2, w2 in zip(ref, outs, finals):
         assert np.array_equal(o, o2) and np.array_equal(w, w2)
+
+
+# ---- RDE step schedule (mu_shift, then mu_shift_late from stream block gear_blocks) ----
+def test_aeq_step_schedule_hand_worked():
+    # The two-block example above with s_mu = 0 for stream block 0 and s_mu = 3 from
+    # block 1 on (gear_blocks = 1):
+    #   block 0: G[XI][XI][0] = 256 -> w = 4096 + rs(256, 0) = 4352 (as before);
+    #   block 1: G[XQ][XQ][0] = -64 -> w = 4096 + rs(-64, 3) = 4096 + floor(-7.5) = 4088.
+    # With the call starting at stream block 1 (block0 = 1) both blocks are late:
+    #   block 0: rs(256, 3) = floor(32.5) = 32 -> 4128; block 1 as above -> 4088.
+    # The outputs do not depend on the step (each block's outputs precede its update
+    # and the two blocks use different filters).
+    a = np.zeros((32, 4), np.int8)
+    a[0, 0] = 8
+    a[16, 1] = -4
+    w = np.zeros((4, 4, 16), np.int16)
+    w[0, 0, 0] = 4096
+    w[1, 1, 0] = 4096
+    want_out = np.zeros((32, 4), np.int16)
+    want_out[0, 0] = 256
+    want_out[16, 1] = -128
+    base = dict(out_shift=7, err_shift=16, mu_shift=0, const_unit=64, update_enable=1, mu_shift_late=3)
+    for block0, w00, w11 in ((0, 4352, 4088), (1, 4128, 4088)):
+        out, wf = O.aeq(a, w, O.params(**base, gear_blocks=1, block0=block0))
+        assert np.array_equal(out, want_out)
+        want_w = w.copy()
+        want_w[0, 0, 0] = w00
+        want_w[1, 1, 0] = w11
+        assert np.array_equal(wf, want_w), block0
+
+
+def test_aeq_step_schedule_reductions():
+    # gear_blocks = 0, a gear beyond the stream, or mu_shift_late = mu_shift: the
+    # plain update; a late step of 40 freezes the taps at gear_blocks, after which
+    # the outputs are the fixed FIR bank of those taps (numpy, update disabled).
+    ch = synth.gen_channel(16 * 300, 40.0, 24.0, seed=42)
+    _, a = O.cdc(ch.samples, ch.taps, ch.requant_shift)
+    w0 = synth.centre_spike_taps()
+    p = dict(out_shift=7, err_shift=16, mu_shift=3, const_unit=synth.aeq_params_for(ch)["const_unit"])
+    ref_out, ref_w = O.aeq(a, w0, O.params(**p))
+    for extra in (dict(gear_blocks=0, mu_shift_late=9), dict(gear_blocks=10 ** 6, mu_shift_late=9),
+                  dict(gear_blocks=5, mu_shift_late=3), dict(gear_blocks=5, mu_shift_late=3, block0=77)):
+        out, wf = O.aeq(a, w0, O.params(**p, **extra))
+        assert np.array_equal(out, ref_out) and np.array_equal(wf, ref_w), extra
+    G = 40
+    frozen_out, frozen_w = O.aeq(a, w0, O.params(**p, gear_blocks=G, mu_shift_late=40))
+    head_out, head_w = O.aeq(a[:16 * G], w0, O.params(**p))
+    assert np.array_equal(frozen_w, head_w)
+    assert np.array_equal(frozen_out[:16 * G], head_out)
+    y = np.zeros((a.shape[0], 4), np.int64)
+    x = a.astype(np.int64)
+    for s2 in range(4):
+        for s1 in range(4):
+            y[:, s2] += np.convolve(x[:, s1], head_w[s1, s2].astype(np.int64))[: a.shape[0]]
+    yh = np.clip(np.floor((y + 64) / 128), -32768, 32767).astype(np.int16)   # rs(y, 7), sat16
+    assert np.array_equal(frozen_out[16 * G:], yh[16 * G:])
+
+
+def test_aeq_step_schedule_changes_the_result():
+    # a step that does change after gear_blocks gives other taps than either step alone
+    ch = synth.gen_channel(16 * 200, 60.0, 24.0, seed=43)
+    _, a = O.cdc(ch.samples, ch.taps, ch.requant_shift)
+    w0 = synth.centre_spike_taps()
+    p = dict(out_shift=7, err_shift=16, const_unit=synth.aeq_params_for(ch)["const_unit"])
+    _, w_a = O.aeq(a, w0, O.params(**p, mu_shift=3))
+    _, w_b = O.aeq(a, w0, O.params(**p, mu_shift=6))
+    _, w_g = O.aeq(a, w0, O.params(**p, mu_shift=3, mu_shift_late=6, gear_blocks=50))
+    assert not np.array_equal(w_g, w_a) and not np.array_equal(w_g, w_b)
