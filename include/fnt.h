@@ -121,15 +121,21 @@ typedef struct fnt_cdc_params {
  *   yhat     = sat16(rs(y, out_shift))                              -> output
  *   r2_P     = yhat_PI^2 + yhat_PQ^2,  R2 = c^2 * {2 if r2 < 6c^2, 10 if r2 < 14c^2, else 18}
  *   eps_S2   = sat8(rs((R2 - r2_pol(S2)) * yhat_S2, err_shift))
- *   w       <- sat14(w + rs(sum_m eps_S2[m] * a_S1[m - k], mu_shift))   if update_enable
- *   out_shift in [0, 24], err_shift in [0, 62], mu_shift in [0, 40],
- *   const_unit c in [1, 4096], update_enable in {0, 1}. */
+ *   w       <- sat14(w + rs(sum_m eps_S2[m] * a_S1[m - k], s_mu))   if update_enable
+ * Step schedule: s_mu = mu_shift for the blocks of a stream with index below
+ * gear_blocks (counted from the stream's first block, across session segments)
+ * and mu_shift_late from then on; gear_blocks = 0: mu_shift throughout (a
+ * large step to converge, then a small one for a low floor).
+ *   out_shift in [0, 24], err_shift in [0, 62], mu_shift and mu_shift_late in
+ *   [0, 40], const_unit c in [1, 4096], update_enable in {0, 1}. */
 typedef struct fnt_aeq_params {
     int32_t out_shift;
     int32_t err_shift;
     int32_t mu_shift;
     int32_t const_unit;
     int32_t update_enable;
+    int32_t mu_shift_late;
+    uint32_t gear_blocks;
 } fnt_aeq_params;
 
 /* ------------------------------------------------------------------------

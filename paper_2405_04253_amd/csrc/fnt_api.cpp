@@ -88,6 +88,8 @@ int validate_aeq(const fnt_aeq_params *p) {
         return fail(FNT_E_INVAL, "aeq params: err_shift %d outside [0, 62]", p->err_shift);
     if (p->mu_shift < 0 || p->mu_shift > 40)
         return fail(FNT_E_INVAL, "aeq params: mu_shift %d outside [0, 40]", p->mu_shift);
+    if (p->gear_blocks > 0 && (p->mu_shift_late < 0 || p->mu_shift_late > 40))
+        return fail(FNT_E_INVAL, "aeq params: mu_shift_late %d outside [0, 40]", p->mu_shift_late);
     if (p->const_unit < 1 || p->const_unit > 4096)
         return fail(FNT_E_INVAL, "aeq params: const_unit %d outside [1, 4096]", p->const_unit);
     if (p->update_enable != 0 && p->update_enable != 1)
@@ -120,6 +122,9 @@ void fill_aeq_item(AeqItem &it, const int8_t *a, uint64_t m, int16_t *taps, cons
     it.mu_shift = p->mu_shift;
     it.const_unit = p->const_unit;
     it.update_enable = p->update_enable;
+    it.mu_shift_late = p->gear_blocks > 0 ? p->mu_shift_late : p->mu_shift;
+    it.gear_blocks = p->gear_blocks;
+    it.block0 = 0;
 }
 
 // Default CDC schedule: the lane-per-block kernel (blocks_per_wave = 0), four

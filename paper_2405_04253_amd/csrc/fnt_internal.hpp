@@ -45,7 +45,10 @@ struct AeqItem {
     int32_t mu_shift;
     int32_t const_unit;
     int32_t update_enable;
-    int32_t pad_;
+    int32_t mu_shift_late;     // step schedule: blocks block0 + b >= gear_blocks (> 0) use mu_shift_late
+    uint32_t gear_blocks;
+    uint32_t pad_;
+    uint64_t block0;           // stream index of this run's first block (sessions: the stream position)
 };
 
 __host__ __device__ inline uint64_t cdc_blocks(uint64_t n) { return (n + 31) / 32; }

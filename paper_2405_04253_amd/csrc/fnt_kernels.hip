@@ -59,6 +59,12 @@ __device__ __forceinline__ void flag(int *err, int bit) {
     if (err) atomicOr(err, bit);
 }
 
+// s_mu of stream block j under the item's step schedule: mu_shift before block
+// gear_blocks, mu_shift_late from then on (gear_blocks = 0: mu_shift throughout).
+__device__ __forceinline__ int step_shift(const AeqItem &it, uint64_t j) {
+    return (it.gear_blocks != 0u && j >= (uint64_t)it.gear_blocks) ? it.mu_shift_late : it.mu_shift;
+}
+
 // ---------------------------------------------------------------- transforms --
 
 // Powers of the CDC radix alpha = sqrt 2 = 4080 modulo 65537, alpha^e for e < 64.
@@ -1241,7 +1247,7 @@ __global__ __launch_bounds__(64) void aeq_fnt_kernel(const AeqItem *items, AeqIt
 #pragma unroll
                 for (int q2 = 0; q2 < 4; ++q2) {
                     const int32_t g = gl[(s1 * 4 + q2) * 16 + kk];
-                    w[q2] = clamp32(w[q2] + (int32_t)rs64((int64_t)g, it.mu_shift), -8192, 8191);
+                    w[q2] = clamp32(w[q2] + (int32_t)rs64((int64_t)g, step_shift(it, it.block0 + (uint64_t)b)), -8192, 8191);
                 }
                 transform_taps();
             } else {
@@ -1259,7 +1265,7 @@ __global__ __launch_bounds__(64) void aeq_fnt_kernel(const AeqItem *items, AeqIt
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
                     gsum = __builtin_amdgcn_sdot4((int)epsw[q2 * 4 + q], (int)xs[q], gsum, false);
-                w[q2] = clamp32(w[q2] + (int32_t)rs64((int64_t)gsum, it.mu_shift), -8192, 8191);
+                w[q2] = clamp32(w[q2] + (int32_t)rs64((int64_t)gsum, step_shift(it, it.block0 + (uint64_t)b)), -8192, 8191);
             }
             transform_taps();
             }
@@ -1746,8 +1752,17 @@ __device__ __forceinline__ void aeq_pol_run(const AeqItem &it, int pol, int vh, 
     const int c2 = it.const_unit * it.const_unit;
     // 32-bit rounding shifts: |y| < 2^24 with out_shift <= 24; |G| <= 16 * 128 * 16
     // = 2^15, so every mu_shift above 17 rounds G to 0 exactly as 17 does
-    const int out_s = it.out_shift, mu_s = min(it.mu_shift, 17);
-    const int32_t out_r = out_s ? 1 << (out_s - 1) : 0, mu_r = mu_s ? 1 << (mu_s - 1) : 0;
+    const int out_s = it.out_shift;
+    const int32_t out_r = out_s ? 1 << (out_s - 1) : 0;
+    const int mu_early = __builtin_amdgcn_readfirstlane(min(it.mu_shift, 17));
+    const int mu_late = __builtin_amdgcn_readfirstlane(min(it.mu_shift_late, 17));
+    const int32_t mu_r_early = mu_early ? 1 << (mu_early - 1) : 0, mu_r_late = mu_late ? 1 << (mu_late - 1) : 0;
+    // the step changes at block gear_at of this run (never: UINT32_MAX)
+    const uint32_t gear_at = __builtin_amdgcn_readfirstlane(
+        it.gear_blocks == 0u ? 0xFFFFFFFFu
+                             : (it.block0 >= it.gear_blocks ? 0u
+                                                            : (uint32_t)min<uint64_t>(it.gear_blocks - it.block0,
+                                                                                      0xFFFFFFFFull)));
     bool bad = false;                                  // range violations, flagged once at the end
     // Windows: the lane holds window position wpos = (lane & 16) | lane_pos(lane &
     // 15), symbol 16 b - 16 + wpos of block b (the order the input-spectrum lanes
@@ -1764,6 +1779,9 @@ __device__ __forceinline__ void aeq_pol_run(const AeqItem &it, int pol, int vh, 
     uint32_t win_even = src.first(-16 + wpos), win_odd = src.first(wpos);   // blocks 0 and 1
 
     auto block = [&](uint32_t b, uint32_t &win) {
+        // the step of this block (stream block block0 + b) under the schedule
+        const int mu_s = b >= gear_at ? mu_late : mu_early;
+        const int32_t mu_r = b >= gear_at ? mu_r_late : mu_r_early;
         const int64_t left = (int64_t)M - 16 * (int64_t)b;         // symbols from 16 b on
         if (wpos - 16 >= left) win = 0u;                            // past the end
         bad |= !bytes_5bit(win);
@@ -1852,7 +1870,7 @@ __device__ __forceinline__ void aeq_pol_run(const AeqItem &it, int pol, int vh, 
                     gsum = __builtin_amdgcn_sdot4((int)e4[q],
                                                   (int)__builtin_amdgcn_alignbyte(dd[q + 1], dd[q], off & 3),
                                                   gsum, false);
-                w[i] = clamp32(w[i] + rs32r(gsum, mu_s, mu_r), -8192, 8191);
+                w[i] = clamp32(w[i] + rs32r(gsum, mu_s, mu_r), -8192, 8191);   // step of this block
             }
             transform_taps();
         }
@@ -2144,7 +2162,10 @@ __device__ __forceinline__ void aeq_lane_body(const AeqItem *items, int nitems, 
     // rs(G, s) of a gradient |G| <= 32768 is 0 for every s >= 17, so a shift
     // clamped to 20 gives the same result in 32-bit arithmetic
     const int out_shift = ip->out_shift, err_shift = ip->err_shift;
-    const int mu_shift = ip->mu_shift < 20 ? ip->mu_shift : 20;
+    const int mu_early = ip->mu_shift < 20 ? ip->mu_shift : 20;
+    const int mu_late = ip->mu_shift_late < 20 ? ip->mu_shift_late : 20;
+    const uint32_t gear = ip->gear_blocks;
+    const uint64_t blk0 = ip->block0;
     const int64_t c2 = (int64_t)ip->const_unit * ip->const_unit;
     const bool upd = has && ip->update_enable != 0;
     const uint32_t nb = (uint32_t)((M + 15) / 16);
@@ -2204,6 +2225,7 @@ __device__ __forceinline__ void aeq_lane_body(const AeqItem *items, int nitems, 
     const int om = t >> 1, opol = t & 1;                // output / error role
 
     for (uint32_t b = 0; b < nbw; ++b) {
+        const int mu_shift = (gear != 0u && blk0 + b >= (uint64_t)gear) ? mu_late : mu_early;   // step schedule
         const int j = (int)(b & 7);
         if (j == 0) {
             // stage symbols 16 b - 16 .. 16 b + 127 of the four streams as bytes
@@ -2425,7 +2447,11 @@ __device__ __forceinline__ void aeq_duo_body(const AeqItem *items, int nitems, c
     int16_t *outp = ip->out;
     int16_t *taps = ip->taps;
     const int out_shift = ip->out_shift, err_shift = ip->err_shift;
-    const int mu_shift = ip->mu_shift < 20 ? ip->mu_shift : 20;   // rs of |G| <= 2^15 is 0 from 17 on
+    // rs of |G| <= 2^15 is 0 from 17 on
+    const int mu_early = ip->mu_shift < 20 ? ip->mu_shift : 20;
+    const int mu_late = ip->mu_shift_late < 20 ? ip->mu_shift_late : 20;
+    const uint32_t gear = ip->gear_blocks;
+    const uint64_t blk0 = ip->block0;
     const int64_t c2 = (int64_t)ip->const_unit * ip->const_unit;
     const bool upd = ip->update_enable != 0;
     const uint32_t nb = (uint32_t)((M + 15) / 16);
@@ -2490,6 +2516,7 @@ __device__ __forceinline__ void aeq_duo_body(const AeqItem *items, int nitems, c
     const int32_t dscale = d ? 1 : 128;
 
     for (uint32_t b = 0; b < nb; ++b) {
+        const int mu_shift = (gear != 0u && blk0 + b >= (uint64_t)gear) ? mu_late : mu_early;   // step schedule
         const int j = (int)(b & 15);
         if (j == 0) {
             // stage symbols 16 b - 16 .. 16 b + 255 of the four streams as bytes
@@ -2760,7 +2787,7 @@ __global__ __launch_bounds__(64) void aeq_direct_kernel(const AeqItem *items, Ae
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
                     g = __builtin_amdgcn_sdot4((int)epsw[s2 * 4 + q], (int)xs[q], g, false);
-                w[s2] = clamp32(w[s2] + (int32_t)rs64((int64_t)g, it.mu_shift), -8192, 8191);
+                w[s2] = clamp32(w[s2] + (int32_t)rs64((int64_t)g, step_shift(it, it.block0 + (uint64_t)b)), -8192, 8191);
             }
         }
         __syncthreads();

@@ -49,7 +49,8 @@ __device__ bool desc_valid(const fnt_channel_desc &d) {
     for (int k = 0; k < c.ntaps; ++k)
         if (c.taps[k][0] < -32 || c.taps[k][0] > 31 || c.taps[k][1] < -32 || c.taps[k][1] > 31) return false;
     if (a.out_shift < 0 || a.out_shift > 24 || a.err_shift < 0 || a.err_shift > 62 || a.mu_shift < 0 ||
-        a.mu_shift > 40 || a.const_unit < 1 || a.const_unit > 4096 || (a.update_enable != 0 && a.update_enable != 1))
+        a.mu_shift > 40 || a.const_unit < 1 || a.const_unit > 4096 || (a.update_enable != 0 && a.update_enable != 1) ||
+        (a.gear_blocks > 0 && (a.mu_shift_late < 0 || a.mu_shift_late > 40)))
         return false;
     const uint64_t M = n_symbols(d.n, c.decim_phase);
     if (!d.taps || !aligned_dev(d.taps, 2) || (d.n > 0 && (!d.in || !aligned_dev(d.in, 4))) ||
@@ -122,6 +123,8 @@ __global__ __launch_bounds__(1024) void noalloc_prepare_kernel(const fnt_channel
             a.out_shift = d.aeq.out_shift;
             a.err_shift = d.aeq.err_shift;
             a.mu_shift = d.aeq.mu_shift;
+            a.mu_shift_late = d.aeq.gear_blocks > 0 ? d.aeq.mu_shift_late : d.aeq.mu_shift;
+            a.gear_blocks = d.aeq.gear_blocks;
             a.const_unit = d.aeq.const_unit;
             a.update_enable = d.aeq.update_enable;
         } else {

@@ -255,6 +255,7 @@ int build_tick(fnt_session *s, TickSlot &slot, bool *uploads) {
         chunk0 += cdc_chunks(ci.n);
         AeqItem &ai = slot.aeq_host[nitems];
         fill_aeq_item(ai, ci.a_out, nb * 16, st->taps, &ch.aeq, r.out + r.issued * 16 * 4);
+        ai.block0 = ch.position / 32;   // the stream's AEQ blocks so far (32 instants each)
         int8_t *tails[2] = {st->aeq_tail, s->aeq_tail_alt + (uint64_t)c * 64};
         ai.hist_in = tails[ch.tail_sel];
         ai.hist_out = tails[ch.tail_sel ^ 1];

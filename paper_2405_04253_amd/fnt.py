@@ -43,7 +43,8 @@ class CdcParams(ctypes.Structure):
 class AeqParams(ctypes.Structure):
     _fields_ = [("out_shift", ctypes.c_int32), ("err_shift", ctypes.c_int32),
                 ("mu_shift", ctypes.c_int32), ("const_unit", ctypes.c_int32),
-                ("update_enable", ctypes.c_int32)]
+                ("update_enable", ctypes.c_int32), ("mu_shift_late", ctypes.c_int32),
+                ("gear_blocks", ctypes.c_uint32)]
 
 
 class ChannelDesc(ctypes.Structure):
@@ -187,8 +188,13 @@ def cdc_params(taps, requant_shift: int, decim_phase: int = 0) -> CdcParams:
     return p
 
 
-def aeq_params(out_shift, err_shift, mu_shift, const_unit, update_enable=1) -> AeqParams:
-    return AeqParams(int(out_shift), int(err_shift), int(mu_shift), int(const_unit), int(update_enable))
+def aeq_params(out_shift, err_shift, mu_shift, const_unit, update_enable=1, mu_shift_late=None,
+               gear_blocks=0) -> AeqParams:
+    """fnt_aeq_params; the step schedule uses mu_shift_late from stream block
+    gear_blocks on (gear_blocks = 0: mu_shift throughout)."""
+    late = mu_shift if mu_shift_late is None else mu_shift_late
+    return AeqParams(int(out_shift), int(err_shift), int(mu_shift), int(const_unit), int(update_enable),
+                     int(late), int(gear_blocks))
 
 
 def n_symbols(n: int, phase: int = 0) -> int:

@@ -13,9 +13,10 @@ that comparison on the synthetic channels of ``synth``:
   per block with the radius-directed error of Eq. (6) and the same ring
   decisions), sampled at one sample per symbol;
 * ``float_5bit``: the same float receiver on the 5-bit samples;
-* ``fnt_<err_shift>_<mu_shift>``: the integer path of this library on the GPU
-  (FNT-CDC with 6-bit taps and 5-bit requantisation, FNT-AEQ with 14-bit taps in
-  two 7-bit digits), with the given RDE step shifts.
+* ``fnt_<err_shift>_<mu_shift>[_<mu_shift_late>_<gear_blocks>]``: the integer
+  path of this library on the GPU (FNT-CDC with 6-bit taps and 5-bit
+  requantisation, FNT-AEQ with 14-bit taps in two 7-bit digits), with the given
+  RDE step shifts (and step schedule).
 
 Every output stream first passes a blind carrier-phase recovery (the fourth-power
 estimator of Viterbi and Viterbi over a sliding window, unwrapped), which only
@@ -198,8 +199,9 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--osnr", default="14,16,18,20,22,24")
     ap.add_argument("--nsym", type=int, default=1 << 18)
-    ap.add_argument("--aeq", default="16:4,16:5,16:3",
-                    help="AEQ err_shift:mu_shift settings of the integer receiver, comma separated")
+    ap.add_argument("--aeq", default="16:4:6:2048,16:4,16:5,16:3",
+                    help="AEQ settings of the integer receiver, comma separated: err_shift:mu_shift "
+                         "(one step) or err_shift:mu_shift:mu_shift_late:gear_blocks (step schedule)")
     ap.add_argument("--km", type=float, default=75.0)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--target", type=float, default=1e-2)
@@ -208,10 +210,17 @@ def main(argv=None):
     ap.add_argument("--no-gpu", action="store_true", help="float receivers only")
     args = ap.parse_args(argv)
     osnrs = [float(v) for v in args.osnr.split(",")]
-    settings = [tuple(int(v) for v in a.split(":")) for a in args.aeq.split(",") if a]
+    settings = []
+    for a in args.aeq.split(","):
+        v = [int(x) for x in a.split(":")] if a else []
+        if len(v) == 2:
+            settings.append((f"fnt_{v[0]}_{v[1]}", dict(err_shift=v[0], mu_shift=v[1], gear_blocks=0)))
+        elif len(v) == 4:
+            settings.append((f"fnt_{v[0]}_{v[1]}_{v[2]}_{v[3]}",
+                             dict(err_shift=v[0], mu_shift=v[1], mu_shift_late=v[2], gear_blocks=v[3])))
     curves = {"float_ideal": [], "float_5bit": []}
-    for se, sm in settings:
-        curves[f"fnt_{se}_{sm}"] = []
+    for name, _ in settings:
+        curves[name] = []
     for o in osnrs:
         ch = synth.gen_channel(args.nsym, args.km, o, synth.seed_for(args.seed, "quality", o), keep_float=True,
                                linewidth_hz=args.linewidth)
@@ -220,8 +229,8 @@ def main(argv=None):
         outs = {"float_ideal": lambda: float_receiver(ch.float_rx, args.km, args.nsym),
                 "float_5bit": lambda: float_receiver(ch.samples, args.km, args.nsym)}
         if not args.no_gpu:
-            for se, sm in settings:
-                outs[f"fnt_{se}_{sm}"] = (lambda se=se, sm=sm: fnt_receiver(ch, err_shift=se, mu_shift=sm))
+            for name, ov in settings:
+                outs[name] = (lambda ov=ov: fnt_receiver(ch, **ov))
         for name, run in outs.items():
             r = align_and_count(cpe_4th_power(run(), args.cpe_window), ch.symbols)
             row["ser"][name], row["ber"][name] = r["ser"], r["ber"]

@@ -212,7 +212,10 @@ def gen_channel(nsym: int, fibre_km: float = 75.0, osnr_db: float = 22.0,
 # ---------------------------------------------------------------------------
 # Equaliser defaults: integer constants of the tap update (inputs, not arithmetic)
 # ---------------------------------------------------------------------------
-AEQ_DEFAULTS = dict(out_shift=7, err_shift=16, mu_shift=4, const_unit=64, update_enable=1)
+# step schedule: s_mu = 4 for the first 2048 blocks (32768 symbols) to converge,
+# then 6 for a lower floor
+AEQ_DEFAULTS = dict(out_shift=7, err_shift=16, mu_shift=4, const_unit=64, update_enable=1, mu_shift_late=6,
+                    gear_blocks=2048)
 AEQ_UNITY = 4096          # 1.0 in the 14-bit tap format
 
 

@@ -997,3 +997,104 @@ def test_full_size_single_stream(torch_dev):
         seg = ch.samples[start:start + 4096]
         zr, _ = O.cdc(seg, ch.taps, ch.requant_shift, hist=ch.samples[start - 32:start])
         assert np.array_equal(zc[start:start + 4096], zr)
+
+
+# ------------------------------------------------------- RDE step schedule --
+def _gear(prm, mu, late, gear):
+    return dict(prm, mu_shift=mu, mu_shift_late=late, gear_blocks=gear)
+
+
+def test_step_schedule_every_form(torch_dev):
+    """The step schedule (mu_shift before stream block gear_blocks, mu_shift_late
+    after) in every AEQ kernel: the batched forms and variants, the fused
+    schedules, fnt_aeq and fnt_cdc_aeq, against the oracle."""
+    torch, dev = torch_dev
+    chans = _batch(12, 6, 10, seed=123)
+    pc = _plan_channels(torch, dev, chans, None)
+    gears = [1, 7, 7, 3, 10 ** 6, 0, 7, 2, 7, 5, 40, 7]
+    for c, g in zip(pc, gears):
+        c["prm"] = _gear(c["prm"], 2, 6, g)
+    refs = [O.cdc_aeq(c["ch"].samples, c["ch"].taps, c["ch"].requant_shift, c["w0"], O.params(**c["prm"]))
+            for c in pc]
+    entries = [(c["x"], c["out"], c["taps"], fnt.cdc_params(c["ch"].taps, c["ch"].requant_shift),
+                fnt.aeq_params(**c["prm"])) for c in pc]
+    plan = fnt.Plan(entries, autotune=False, use_graph=True)
+
+    def check(what):
+        for c in pc:
+            c["taps"].copy_(to_dev(torch, dev, c["w0"]))
+            c["out"].fill_(-3)
+        note(f"step schedule: {what}")
+        plan.run()
+        torch.cuda.synchronize()
+        fnt.fnt_check()
+        for i, (c, (outr, wr, _)) in enumerate(zip(pc, refs)):
+            assert np.array_equal(c["out"].cpu().numpy(), outr), (what, i)
+            assert np.array_equal(c["taps"].cpu().numpy(), wr), (what, i)
+
+    for form in (0, 3, 1, 2, 4, 5):
+        plan.set_aeq_waves(form)
+        check(f"form {form}")
+    for variant in (1, 2, 3):
+        plan.set_aeq_variant(variant)
+        check(f"variant {variant}")
+    plan.set_aeq_variant(0)
+    for lpt, split in ((4, False), (8, False), (16, True)):
+        plan.set_fused(lpt, 2, split)
+        check(f"fused lpt {lpt} split {split}")
+    plan.close()
+    # single-channel calls
+    c = pc[1]
+    outr, wr, ar = refs[1]
+    taps = to_dev(torch, dev, c["w0"])
+    note("step schedule: fnt_cdc_aeq and fnt_aeq")
+    out = fnt.fnt_cdc_aeq(c["x"], fnt.cdc_params(c["ch"].taps, c["ch"].requant_shift), taps,
+                          fnt.aeq_params(**c["prm"]))
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), outr) and np.array_equal(taps.cpu().numpy(), wr)
+    taps.copy_(to_dev(torch, dev, c["w0"]))
+    out2 = fnt.fnt_aeq(to_dev(torch, dev, ar), taps, fnt.aeq_params(**c["prm"]))
+    torch.cuda.synchronize()
+    assert np.array_equal(out2.cpu().numpy(), outr) and np.array_equal(taps.cpu().numpy(), wr)
+    with pytest.raises(fnt.FntError) as e:
+        fnt.fnt_aeq(to_dev(torch, dev, ar), taps, fnt.aeq_params(**_gear(c["prm"], 2, 41, 3)))
+    assert e.value.code == fnt.FNT_E_INVAL
+    fnt.fnt_check()
+
+
+@pytest.mark.parametrize("form", [-1, 1, 0])
+def test_session_step_schedule_across_segments(torch_dev, form):
+    """Sessions count the step schedule's blocks over the whole stream: segments of
+    one to a few blocks cross gear_blocks mid-stream, and a state exported and
+    imported into another session continues the count."""
+    torch, dev = torch_dev
+    chans = _session_channels(4, 6, seed=9)
+    s = fnt.Session(max_channels=4, hbm_budget_bytes=64 << 20, chunk_blocks=2, aeq_form=form)
+    outs, prms = [], []
+    for c, (ch, segs) in enumerate(chans):
+        prm = _gear(synth.aeq_params_for(ch), 2, 6, 3 + 2 * c)
+        prms.append(prm)
+        s.add_channel(c, fnt.cdc_params(ch.taps, ch.requant_shift), fnt.aeq_params(**prm))
+        outs.append(torch.zeros((ch.n // 2, 4), dtype=torch.int16, device=dev))
+    xs = [to_dev(torch, dev, ch.samples) for ch, _ in chans]
+    note(f"session step schedule, AEQ form {form}")
+    for c, (ch, segs) in enumerate(chans):
+        off = 0
+        for k, n in enumerate(segs):
+            if c == 0 and k == 1:                       # move channel 0 to another session mid-stream
+                state = s.get_state(0)
+                s2 = fnt.Session(max_channels=2, hbm_budget_bytes=16 << 20, chunk_blocks=3, aeq_form=form)
+                s2.add_channel(1, fnt.cdc_params(ch.taps, ch.requant_shift), fnt.aeq_params(**prms[0]))
+                s2.set_state(1, state)
+                s2.wait(s2.submit(1, xs[c][off:off + n], outs[c][off // 2:(off + n) // 2]))
+                s.set_state(0, s2.get_state(1))
+                s2.close()
+            else:
+                s.wait(s.submit(c, xs[c][off:off + n], outs[c][off // 2:(off + n) // 2]))
+            off += n
+    s.drain()
+    for c, (ch, segs) in enumerate(chans):
+        outr, _, _ = O.cdc_aeq(ch.samples, ch.taps, ch.requant_shift, synth.centre_spike_taps(), O.params(**prms[c]))
+        assert np.array_equal(outs[c].cpu().numpy(), outr), c
+    s.close()
+    fnt.fnt_check()
