@@ -838,7 +838,7 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache, bool qui
                 if (plan_lead(p) != c.lead || plan_top(p) != c.top) return 1e30;
                 return time_it([&] { return plan_launch(p, s, p->side, p->side2) ? hipErrorUnknown : hipSuccess; });
             };
-            // one pass over all, then the best four by the median of three more;
+            // one pass over all, then the best six by the median of five more;
             // FNT_TUNE_LOG names a file that receives every timing (diagnostics)
             const char *log_path = std::getenv("FNT_TUNE_LOG");
             std::ofstream tlog;
@@ -854,14 +854,14 @@ static int plan_autotune(fnt_plan *p, hipStream_t s, const char *cache, bool qui
                     log_c("pass", c);
                 }
                 std::sort(cs.begin(), cs.end(), [](const LCand &x, const LCand &y) { return x.ms < y.ms; });
-                for (size_t i = 0; i < cs.size() && i < 4; ++i) {
-                    double r[3];
+                for (size_t i = 0; i < cs.size() && i < 6; ++i) {
+                    double r[5];
                     for (double &v : r) v = time_lead(cs[i]);
-                    std::sort(r, r + 3);
-                    cs[i].ms = r[1];
+                    std::sort(r, r + 5);
+                    cs[i].ms = r[2];
                     log_c("median", cs[i]);
                 }
-                std::sort(cs.begin(), cs.begin() + std::min<size_t>(4, cs.size()),
+                std::sort(cs.begin(), cs.begin() + std::min<size_t>(6, cs.size()),
                           [](const LCand &x, const LCand &y) { return x.ms < y.ms; });
                 return cs.front();
             };
