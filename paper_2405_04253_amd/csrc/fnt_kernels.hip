@@ -228,6 +228,17 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Wait until every vector memory operation of this wave has completed
+// (s_waitcnt vmcnt(0); expcnt and lgkmcnt fields left at their maxima), and keep
+// the compiler from moving later memory operations above the wait.
+__device__ __forceinline__ void vmem_wait_all() {
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// Blocks per group of the AEQ block loops that read device memory.
+constexpr int AEQ_GROUP = 4;
+
 
 // All bytes of w in [-16, 15]: the top four bits of each byte are equal.
 __device__ __forceinline__ bool bytes_5bit(uint32_t w) {
@@ -1666,12 +1677,13 @@ struct HalfSyncLds {
 
 // The AEQ of one channel in the polarisation-split form: this wave is wave vh
 // of the WPP = LPT / 4 waves of half `pol`.  LDS of the wave: aspec (input
-// spectra), epsw (error bytes), winw (window bytes); of the half: part_h
+// spectra, two buffers by block parity), epsw (error bytes), winw (window
+// bytes); of the half: part_h
 // (partial outputs, by block parity).  Reads its input through src and meets
 // the other waves of its half through hsync once per block.
 template <int LPT, class Src, class Sync>
 __device__ __forceinline__ void aeq_pol_run(const AeqItem &it, int pol, int vh, int lane, int *err,
-                                            int32_t (*aspec)[33], int32_t (*part_h)[4][33], uint32_t *epsw,
+                                            int32_t (*aspec)[4][33], int32_t (*part_h)[4][33], uint32_t *epsw,
                                             uint32_t *winw, Src &src, Sync &hsync) {
     constexpr int WPP = LPT / 4;                       // waves per polarisation half
     constexpr int PPL = 32 / LPT;                      // bins per lane
@@ -1766,36 +1778,22 @@ __device__ __forceinline__ void aeq_pol_run(const AeqItem &it, int pol, int vh, 
     bool bad = false;                                  // range violations, flagged once at the end
     // Windows: the lane holds window position wpos = (lane & 16) | lane_pos(lane &
     // 15), symbol 16 b - 16 + wpos of block b (the order the input-spectrum lanes
-    // use, so a row swap hands every lane its two positions without LDS).  Block
-    // b loads the symbols of block b + 2's window into the register its own
-    // window came in, two blocks ahead of use (even and odd blocks alternate
-    // between two registers), so load latency in a busy memory system stays off
-    // the chain.  The load itself is unconditional (index clamped into the
-    // input) and the zeros past the end are applied when the window is used, so
-    // no wait for it is placed before then.
+    // use, so a row swap hands every lane its two positions without LDS).  Window
+    // loads are unconditional (index clamped into the input) and the zeros past
+    // the end are applied when the window is used.
     const auto obase = gptr(it.out + 4 * om + 2 * pol + oS2l);
     const int wpos = (lane & 16) | lane_pos(lane & 15);
     src.prime();
-    uint32_t win_even = src.first(-16 + wpos), win_odd = src.first(wpos);   // blocks 0 and 1
 
-    auto block = [&](uint32_t b, uint32_t &win) {
-        // the step of this block (stream block block0 + b) under the schedule
-        const int mu_s = b >= gear_at ? mu_late : mu_early;
-        const int32_t mu_r = b >= gear_at ? mu_r_late : mu_r_early;
-        const int64_t left = (int64_t)M - 16 * (int64_t)b;         // symbols from 16 b on
-        if (wpos - 16 >= left) win = 0u;                            // past the end
-        bad |= !bytes_5bit(win);
+    // Input spectra of the 4 streams of one block from its window (zeros past
+    // the end applied): lane (S1 = lane / 16, k) writes positions kp, kp + 16 of
+    // stream S1 to dst.
+    auto spectra = [&](uint32_t win, int32_t(*dst)[33]) {
         // rows 0, 2 hold positions lane_pos(l), rows 1, 3 positions 16 + lane_pos(l):
         // swapping odd rows of one copy with even rows of the other gives every
         // lane both (sw[0]: position kp, sw[1]: position kp + 16)
         const auto sw = __builtin_amdgcn_permlane16_swap(win, win, false, false);
-        if (lane < 32) {       // window bytes by stream for the tap update
-            uint8_t *wb = reinterpret_cast<uint8_t *>(winw);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) wb[c * 32 + wpos] = (uint8_t)(win >> (8 * c));
-        }
-        win = src.ahead(b, wpos);                                   // symbol 16 b + 16 + wpos
-        {   // input spectra of the 4 streams: lane (S1 = lane / 16, k) holds positions kp, kp + 16
+        {
             const int kp = lane_pos(kk);                 // position index of this lane
             const int sh = 8 * (lane >> 4);              // byte of stream S1
             int32_t x0 = (int32_t)(int8_t)((uint32_t)sw[0] >> sh), x1 = (int32_t)(int8_t)((uint32_t)sw[1] >> sh);
@@ -1821,14 +1819,40 @@ __device__ __forceinline__ void aeq_pol_run(const AeqItem &it, int pol, int vh, 
             // distance 1, twiddle 1
             u0 = xor_pos<1>(u0) + mul24k(u0, K.sgk);
             u1 = xor_pos<1>(u1) + mul24k(u1, K.sgk);
-            aspec[lane >> 4][kp] = u0;                  // |.| < 2^18
-            aspec[lane >> 4][kp + 16] = u1;
+            dst[lane >> 4][kp] = u0;                    // |.| < 2^18
+            dst[lane >> 4][kp + 16] = u1;
         }
-        wave_lds_sync();
+    };
+
+    // One block: its window `win` and the next block's window `win_next` in, the
+    // requantised output of this lane back.  The block's input spectra were
+    // written into aspec[b & 1] during block b - 1; this block writes block b +
+    // 1's into the other buffer while it waits for the LDS reads of its tap
+    // update, off the chain from one block's taps to the next.  A segmented
+    // source (LDS) loads block b + 2's window into `win` and the output is
+    // stored here; for a source in device memory both go through the group loop
+    // below.
+    auto block = [&](uint32_t b, uint32_t &win, uint32_t win_next) -> int32_t {
+        // the step of this block (stream block block0 + b) under the schedule
+        const int mu_s = b >= gear_at ? mu_late : mu_early;
+        const int32_t mu_r = b >= gear_at ? mu_r_late : mu_r_early;
+        const int64_t left = (int64_t)M - 16 * (int64_t)b;         // symbols from 16 b on
+        if (wpos - 16 >= left) win = 0u;                            // past the end
+        bad |= !bytes_5bit(win);
+        if (lane < 32) {       // window bytes by stream for the tap update
+            uint8_t *wb = reinterpret_cast<uint8_t *>(winw);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) wb[c * 32 + wpos] = (uint8_t)(win >> (8 * c));
+        }
+        if constexpr (Src::kSegmented) win = src.ahead(b, wpos);   // symbol 16 b + 16 + wpos
+        // block b + 1's window position wpos is symbol 16 b + wpos
+        const uint32_t wn = wpos >= left ? 0u : win_next;
+        int32_t(*const spec_next)[33] = aspec[(b + 1) & 1];
+        const int32_t(*const spec)[33] = aspec[b & 1];
         int32_t Y[PPL];
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
-            int32_t P = mulmod(aspec[tS1][t + LPT * j], W[j]);
+            int32_t P = mulmod(spec[tS1][t + LPT * j], W[j]);
             Y[j] = P + s1_partner<LPT>(P);              // pair sum over S1 = 2g, 2g+1
         }
         count_products(1, PPL);                         // A_S1 W for this lane's bins
@@ -1845,7 +1869,9 @@ __device__ __forceinline__ void aeq_pol_run(const AeqItem &it, int pol, int vh, 
         const int32_t y = 128 * (part[0][pi] + part[2][pi]) + part[1][pi] + part[3][pi];
         const int32_t yh = clamp32(rs32r(y, out_s, out_r), -32768, 32767);
         const bool valid = lane < 32 && om < left;
-        if (writer && valid) obase[64 * (uint64_t)b] = (int16_t)yh;
+        if constexpr (Src::kSegmented) {
+            if (writer && valid) obase[64 * (uint64_t)b] = (int16_t)yh;
+        }
         if (it.update_enable) {
             const int32_t yp = xor_h<1>(yh);
             const int64_t r2 = (int64_t)yh * yh + (int64_t)yp * yp;
@@ -1855,45 +1881,90 @@ __device__ __forceinline__ void aeq_pol_run(const AeqItem &it, int pol, int vh, 
             if (lane < 32) reinterpret_cast<int8_t *>(epsw)[oS2l * 16 + om] = (int8_t)eps;
             wave_lds_sync();
             // G[S1][S2][k] = sum_j eps_S2[j] * a_S1[16 b + j - k] for the lane's taps
-            uint32_t e4[4];
+            // k = t + LPT i: the 4 dwords of a_S1 from byte 16 b - k on.  Tap i's
+            // dword q starts at byte base + 4 (q - S i) of the row, so the taps share
+            // the aligned dwords j = q - S i in [J0, 3]: NJ byte alignments for the
+            // NT * 4 dot products.
+            constexpr int S = LPT / 4, J0 = -S * (NT - 1), NJ = 4 - J0;
+            const int base = tS1 * 32 + 16 - t;          // byte of a_S1[16 b - t]
+            uint32_t e4[4], raw[NJ + 1];
 #pragma unroll
             for (int q = 0; q < 4; ++q) e4[q] = epsw[tS2l * 4 + q];
 #pragma unroll
-            for (int i = 0; i < NT; ++i) {
-                const int off = tS1 * 32 + 16 - (t + LPT * i);   // byte of a_S1[16 b - k]
-                uint32_t dd[5];
+            for (int r = 0; r <= NJ; ++r) raw[r] = winw[(base >> 2) + J0 + r];
+            spectra(wn, spec_next);                      // in the shadow of the reads
+            uint32_t ad[NJ];
 #pragma unroll
-                for (int r = 0; r < 5; ++r) dd[r] = winw[(off >> 2) + r];
+            for (int r = 0; r < NJ; ++r) ad[r] = __builtin_amdgcn_alignbyte(raw[r + 1], raw[r], base & 3);
+#pragma unroll
+            for (int i = 0; i < NT; ++i) {
                 int32_t gsum = 0;
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    gsum = __builtin_amdgcn_sdot4((int)e4[q],
-                                                  (int)__builtin_amdgcn_alignbyte(dd[q + 1], dd[q], off & 3),
-                                                  gsum, false);
+                    gsum = __builtin_amdgcn_sdot4((int)e4[q], (int)ad[q - S * i - J0], gsum, false);
                 w[i] = clamp32(w[i] + rs32r(gsum, mu_s, mu_r), -8192, 8191);   // step of this block
             }
             transform_taps();
+        } else {
+            spectra(wn, spec_next);
         }
         // the next block reuses this wave's window and error bytes: keep the LDS
         // reads above in front of the writes that follow
         wave_lds_sync();
+        return yh;
     };
     if constexpr (Src::kSegmented) {
-        // segments of 64 blocks (an even count keeps each block's window register)
+        // block b loads block b + 2's window into the register its own came in
+        // (even and odd blocks alternate between two); segments of 64 blocks (an
+        // even count keeps each block's window register)
+        uint32_t win_even = src.first(-16 + wpos), win_odd = src.first(wpos);   // blocks 0 and 1
+        spectra(wpos - 16 >= (int64_t)M ? 0u : win_even, aspec[0]);
+        wave_lds_sync();
         for (uint32_t b0 = 0; b0 < nblocks; b0 += 64) {
             const uint32_t b1 = min(b0 + 64u, nblocks);
             src.segment(b0, b1);
             for (uint32_t b = b0; b < b1; b += 2) {
-                block(b, win_even);
-                if (b + 1 < b1) block(b + 1, win_odd);
+                block(b, win_even, win_odd);
+                if (b + 1 < b1) block(b + 1, win_odd, win_even);
             }
             src.segment_done(b1);
         }
     } else {
-        for (uint32_t b = 0; b < nblocks; b += 2) {
-            block(b, win_even);
-            if (b + 1 < nblocks) block(b + 1, win_odd);
+        // Groups of AEQ_GROUP blocks.  Loads and stores share one counter, so a
+        // wait for a window load also waits for every store issued before it.
+        // All of a group's memory traffic therefore goes out at its start, after
+        // one wait for the previous group's: the outputs of the previous group,
+        // and the windows of the next.  Each wait then covers operations issued
+        // a whole group earlier, and load and store latency in a busy memory
+        // system stays off the chain.
+        constexpr int G = AEQ_GROUP;
+        uint32_t wcur[G];
+        int32_t yq[G];
+#pragma unroll
+        for (int i = 0; i < G; ++i) wcur[i] = src.first(16 * i - 16 + wpos);
+        spectra(wpos - 16 >= (int64_t)M ? 0u : wcur[0], aspec[0]);
+        wave_lds_sync();
+        auto store_group = [&](uint32_t g0) {
+#pragma unroll
+            for (int i = 0; i < G; ++i) {
+                const uint32_t b = g0 + i;
+                if (writer && lane < 32 && (int64_t)om < (int64_t)M - 16 * (int64_t)b)
+                    obase[64 * (uint64_t)b] = (int16_t)yq[i];
+            }
+        };
+        for (uint32_t g = 0; g < nblocks; g += G) {
+            vmem_wait_all();
+            if (g > 0) store_group(g - G);
+            uint32_t wnext[G];
+#pragma unroll
+            for (int i = 0; i < G; ++i) wnext[i] = src.ahead(g + G - 2 + i, wpos);   // window of g + G + i
+#pragma unroll
+            for (int i = 0; i < G; ++i)
+                if (g + i < nblocks) yq[i] = block(g + i, wcur[i], i + 1 < G ? wcur[i + 1] : wnext[0]);
+#pragma unroll
+            for (int i = 0; i < G; ++i) wcur[i] = wnext[i];
         }
+        store_group((nblocks - 1) / G * G);
     }
     if (bad) flag(err, RANGE_SYMBOL);
     finish();
@@ -1920,7 +1991,7 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const 
 
     // rows padded to 33 words: lanes reading the same position of different
     // rows hit different LDS banks
-    __shared__ int32_t aspec_s[WPP * IW][4][33];       // per wave: input spectra by position
+    __shared__ int32_t aspec_s[WPP * IW][2][4][33];    // per wave: input spectra by position, by block parity
     // per half: [block parity][g*2+d][m*2+S2l], shared by the half's waves;
     // double-buffered so a wave that runs ahead (one barrier per block) never
     // overwrites partials another wave is still reading
@@ -1992,7 +2063,7 @@ __global__ __launch_bounds__(64 * (HALVES * (LPT / 4) + NP)) __attribute__((amdg
     __shared__ __align__(16) uint32_t arrive_s[HALVES][WPP < 2 ? 2 : WPP];
     __shared__ int32_t hs_s[NP][2][64];
     __shared__ __align__(16) uint32_t edge_s[NP][2][64];
-    __shared__ int32_t aspec_s[NC][4][33];
+    __shared__ int32_t aspec_s[NC][2][4][33];
     __shared__ int32_t part_s[HALVES][2][4][33];
     __shared__ uint32_t epsw_s[NC][8];
     __shared__ uint32_t winw_s[NC][36];
@@ -2229,6 +2300,8 @@ __device__ __forceinline__ void aeq_lane_body(const AeqItem *items, int nitems, 
         const int j = (int)(b & 7);
         if (j == 0) {
             // stage symbols 16 b - 16 .. 16 b + 127 of the four streams as bytes
+            // (global-address loads: a generic one would make every LDS wait of
+            // the loop wait for memory too)
             wave_lds_sync();
 #pragma unroll
             for (int r = 0; r < 5; ++r) {
@@ -2237,7 +2310,7 @@ __device__ __forceinline__ void aeq_lane_body(const AeqItem *items, int nitems, 
                     const int64_t i = 16 * (int64_t)b - 16 + p;
                     uint32_t v = 0u;
                     if (i < 0) {
-                        if (hist_in) v = reinterpret_cast<const uint32_t *>(hist_in)[16 + i];
+                        if (hist_in) v = gptr(reinterpret_cast<const uint32_t *>(hist_in))[16 + i];
                     } else if ((uint64_t)i < M) {
                         v = gptr(reinterpret_cast<const uint32_t *>(ain))[i];
                         bad |= v ^ (v << 1);
@@ -2515,29 +2588,55 @@ __device__ __forceinline__ void aeq_duo_body(const AeqItem *items, int nitems, c
     const int om = (lane >> 1) & 15, opol = lane & 1;   // output / error role (lanes < 32)
     const int32_t dscale = d ? 1 : 128;
 
+    // Symbols 16 b - 16 .. 16 b + 255 of a batch of 16 blocks from b: the lane's
+    // p = lane + 64 r (r < 5, p < 272), history before 0 and zeros past M,
+    // fetched one batch ahead and waited for at the batch's start.
+    uint32_t pre[5];
+    const auto ain32 = gptr(reinterpret_cast<const uint32_t *>(ain));
+#pragma unroll
+    for (int r = 0; r < 5; ++r) {                     // the first batch, with the history
+        const int p = lane + 64 * r, i = p - 16;
+        uint32_t v = 0u;
+        if (p < 272) {
+            if (i < 0) {
+                if (hist_in) v = gptr(reinterpret_cast<const uint32_t *>(hist_in))[16 + i];
+            } else if ((uint64_t)i < M) {
+                v = ain32[i];
+            }
+        }
+        pre[r] = v;
+    }
+    // a later batch (b > 0): every index is at least 0; loads of lanes past M
+    // are skipped and their zero applied when the batch is staged
+    auto fetch = [&](uint32_t b) {
+#pragma unroll
+        for (int r = 0; r < 5; ++r) {
+            const int p = lane + 64 * r;
+            const uint64_t i = 16 * (uint64_t)b - 16 + p;
+            if (p < 272 && i < M) pre[r] = ain32[i];
+        }
+    };
+
     for (uint32_t b = 0; b < nb; ++b) {
         const int mu_shift = (gear != 0u && blk0 + b >= (uint64_t)gear) ? mu_late : mu_early;   // step schedule
         const int j = (int)(b & 15);
         if (j == 0) {
-            // stage symbols 16 b - 16 .. 16 b + 255 of the four streams as bytes
+            // stage the batch's symbols of the four streams as bytes
             wave_lds_sync();
+            vmem_wait_all();
 #pragma unroll
             for (int r = 0; r < 5; ++r) {
                 const int p = lane + 64 * r;
                 if (p < 272) {
                     const int64_t i = 16 * (int64_t)b - 16 + p;
-                    uint32_t v = 0u;
-                    if (i < 0) {
-                        if (hist_in) v = reinterpret_cast<const uint32_t *>(hist_in)[16 + i];
-                    } else if ((uint64_t)i < M) {
-                        v = gptr(reinterpret_cast<const uint32_t *>(ain))[i];
-                        bad |= v ^ (v << 1);
-                    }
+                    const uint32_t v = (uint64_t)i < M || i < 0 ? pre[r] : 0u;   // zeros past M
+                    if (i >= 0) bad |= v ^ (v << 1);
                     uint8_t *ab = reinterpret_cast<uint8_t *>(&abytes[0][0]);
 #pragma unroll
                     for (int c = 0; c < 4; ++c) ab[c * 288 + p] = (uint8_t)(v >> (8 * c));
                 }
             }
+            fetch(b + 16);                              // the next batch
             wave_lds_sync();
             {   // input spectra of the batch: stream lane % 4, block lane / 4
                 const int s1 = lane & 3, jb = lane >> 2;
