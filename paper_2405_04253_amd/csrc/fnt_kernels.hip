@@ -236,9 +236,6 @@ __device__ __forceinline__ void vmem_wait_all() {
     __builtin_amdgcn_sched_barrier(0);
 }
 
-// Blocks per group of the AEQ block loops that read device memory.
-constexpr int AEQ_GROUP = 4;
-
 
 // All bytes of w in [-16, 15]: the top four bits of each byte are equal.
 __device__ __forceinline__ bool bytes_5bit(uint32_t w) {
@@ -1824,15 +1821,13 @@ __device__ __forceinline__ void aeq_pol_run(const AeqItem &it, int pol, int vh, 
         }
     };
 
-    // One block: its window `win` and the next block's window `win_next` in, the
-    // requantised output of this lane back.  The block's input spectra were
-    // written into aspec[b & 1] during block b - 1; this block writes block b +
-    // 1's into the other buffer while it waits for the LDS reads of its tap
-    // update, off the chain from one block's taps to the next.  A segmented
-    // source (LDS) loads block b + 2's window into `win` and the output is
-    // stored here; for a source in device memory both go through the group loop
-    // below.
-    auto block = [&](uint32_t b, uint32_t &win, uint32_t win_next) -> int32_t {
+    // One block: its window `win` and the next block's window `win_next` in;
+    // block b + 2's window is loaded into `win` (two blocks ahead of use: even
+    // and odd blocks alternate between two registers).  The block's input
+    // spectra were written into aspec[b & 1] during block b - 1; this block
+    // writes block b + 1's into the other buffer while it waits for the LDS
+    // reads of its tap update, off the chain from one block's taps to the next.
+    auto block = [&](uint32_t b, uint32_t &win, uint32_t win_next) {
         // the step of this block (stream block block0 + b) under the schedule
         const int mu_s = b >= gear_at ? mu_late : mu_early;
         const int32_t mu_r = b >= gear_at ? mu_r_late : mu_r_early;
@@ -1844,7 +1839,7 @@ __device__ __forceinline__ void aeq_pol_run(const AeqItem &it, int pol, int vh, 
 #pragma unroll
             for (int c = 0; c < 4; ++c) wb[c * 32 + wpos] = (uint8_t)(win >> (8 * c));
         }
-        if constexpr (Src::kSegmented) win = src.ahead(b, wpos);   // symbol 16 b + 16 + wpos
+        win = src.ahead(b, wpos);                                   // symbol 16 b + 16 + wpos
         // block b + 1's window position wpos is symbol 16 b + wpos
         const uint32_t wn = wpos >= left ? 0u : win_next;
         int32_t(*const spec_next)[33] = aspec[(b + 1) & 1];
@@ -1869,9 +1864,7 @@ __device__ __forceinline__ void aeq_pol_run(const AeqItem &it, int pol, int vh, 
         const int32_t y = 128 * (part[0][pi] + part[2][pi]) + part[1][pi] + part[3][pi];
         const int32_t yh = clamp32(rs32r(y, out_s, out_r), -32768, 32767);
         const bool valid = lane < 32 && om < left;
-        if constexpr (Src::kSegmented) {
-            if (writer && valid) obase[64 * (uint64_t)b] = (int16_t)yh;
-        }
+        if (writer && valid) obase[64 * (uint64_t)b] = (int16_t)yh;
         if (it.update_enable) {
             const int32_t yp = xor_h<1>(yh);
             const int64_t r2 = (int64_t)yh * yh + (int64_t)yp * yp;
@@ -1911,15 +1904,12 @@ __device__ __forceinline__ void aeq_pol_run(const AeqItem &it, int pol, int vh, 
         // the next block reuses this wave's window and error bytes: keep the LDS
         // reads above in front of the writes that follow
         wave_lds_sync();
-        return yh;
     };
+    uint32_t win_even = src.first(-16 + wpos), win_odd = src.first(wpos);   // blocks 0 and 1
+    spectra(wpos - 16 >= (int64_t)M ? 0u : win_even, aspec[0]);
+    wave_lds_sync();
     if constexpr (Src::kSegmented) {
-        // block b loads block b + 2's window into the register its own came in
-        // (even and odd blocks alternate between two); segments of 64 blocks (an
-        // even count keeps each block's window register)
-        uint32_t win_even = src.first(-16 + wpos), win_odd = src.first(wpos);   // blocks 0 and 1
-        spectra(wpos - 16 >= (int64_t)M ? 0u : win_even, aspec[0]);
-        wave_lds_sync();
+        // segments of 64 blocks (an even count keeps each block's window register)
         for (uint32_t b0 = 0; b0 < nblocks; b0 += 64) {
             const uint32_t b1 = min(b0 + 64u, nblocks);
             src.segment(b0, b1);
@@ -1930,41 +1920,10 @@ __device__ __forceinline__ void aeq_pol_run(const AeqItem &it, int pol, int vh, 
             src.segment_done(b1);
         }
     } else {
-        // Groups of AEQ_GROUP blocks.  Loads and stores share one counter, so a
-        // wait for a window load also waits for every store issued before it.
-        // All of a group's memory traffic therefore goes out at its start, after
-        // one wait for the previous group's: the outputs of the previous group,
-        // and the windows of the next.  Each wait then covers operations issued
-        // a whole group earlier, and load and store latency in a busy memory
-        // system stays off the chain.
-        constexpr int G = AEQ_GROUP;
-        uint32_t wcur[G];
-        int32_t yq[G];
-#pragma unroll
-        for (int i = 0; i < G; ++i) wcur[i] = src.first(16 * i - 16 + wpos);
-        spectra(wpos - 16 >= (int64_t)M ? 0u : wcur[0], aspec[0]);
-        wave_lds_sync();
-        auto store_group = [&](uint32_t g0) {
-#pragma unroll
-            for (int i = 0; i < G; ++i) {
-                const uint32_t b = g0 + i;
-                if (writer && lane < 32 && (int64_t)om < (int64_t)M - 16 * (int64_t)b)
-                    obase[64 * (uint64_t)b] = (int16_t)yq[i];
-            }
-        };
-        for (uint32_t g = 0; g < nblocks; g += G) {
-            vmem_wait_all();
-            if (g > 0) store_group(g - G);
-            uint32_t wnext[G];
-#pragma unroll
-            for (int i = 0; i < G; ++i) wnext[i] = src.ahead(g + G - 2 + i, wpos);   // window of g + G + i
-#pragma unroll
-            for (int i = 0; i < G; ++i)
-                if (g + i < nblocks) yq[i] = block(g + i, wcur[i], i + 1 < G ? wcur[i + 1] : wnext[0]);
-#pragma unroll
-            for (int i = 0; i < G; ++i) wcur[i] = wnext[i];
+        for (uint32_t b = 0; b < nblocks; b += 2) {
+            block(b, win_even, win_odd);
+            if (b + 1 < nblocks) block(b + 1, win_odd, win_even);
         }
-        store_group((nblocks - 1) / G * G);
     }
     if (bad) flag(err, RANGE_SYMBOL);
     finish();
