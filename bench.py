@@ -34,11 +34,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0            # MI355X HBM3E
-# 32-bit integer VALU peak from the chip's unit counts and clock: 256 CUs x 4 SIMDs
-# x 32 lanes per cycle x 2.4 GHz = 78643.2 G lane-ops/s, the published fp32 vector
-# rate (157.3 TFLOP/s) with an FMA counted as one operation.  Measured beside it
+# Vector ALU peak from the chip's unit counts and clock: the published fp32 vector
+# rate (157.3 TFLOP/s) with an FMA counted as one operation, 256 CUs x 4 SIMDs x 32
+# lane-operations per cycle x 2.4 GHz = 78643.2 G lane-ops/s.  That rate is reached
+# by packed (two-wide) fp32 instructions on 16-lane SIMDs; 32-bit integer
+# instructions have no packed form, so the chip's own rates are set beside it
 # (measured_peaks): v_add_u32 ~57.9 T, the SDWA fold / shift / 24-bit multiply
-# forms ~37.1 T.
+# forms ~37.1 T (16 lanes per cycle).
 PEAK_ALU_GOPS = 256 * 4 * 32 * 2.4
 
 # Algorithmic integer operations of the method, per unit: a modular add, subtract,

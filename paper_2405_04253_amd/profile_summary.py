@@ -207,7 +207,7 @@ def main(argv=None):
             entries[key]["aeq_blocks"] = blocks
     if alg:
         lines += ["", "## Against the roofline: algorithmic work per launch / average duration", "",
-                  f"Integer VALU peak {bench.PEAK_ALU_GOPS:.1f} Gops/s (256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz); "
+                  f"Vector ALU peak {bench.PEAK_ALU_GOPS:.1f} Gops/s (the fp32 vector rate with an FMA as one operation: 256 CUs x 4 SIMDs x 32 lane-ops per cycle x 2.4 GHz); "
                   f"algorithmic ops per unit: {bench.AEQ_OPS_PER_BLOCK} per 16-symbol AEQ block, "
                   f"{bench.CDC_OPS_PER_BLOCK} per 32-instant CDC block (both polarisations).", "",
                   "| kernel | AEQ blocks | CDC blocks | algorithmic ops | Gops/s | frac of peak | algorithmic bytes |",
