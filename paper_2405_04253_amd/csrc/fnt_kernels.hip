@@ -228,6 +228,19 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// The polarisation-split AEQ: words per stream row of its input spectra (rows
+// 16-byte aligned for the batched stores); blocks per batch and bytes per
+// stream row of a batch's staged window symbols (144 used, the tail zero).
+constexpr int kSpecRow = 36;
+constexpr int kBatch = 8;
+constexpr int kStgRow = 160;
+typedef int32_t v16i __attribute__((ext_vector_type(16)));
+
+// The 5-bit reversal of p.
+__device__ __forceinline__ int bitrev5(int p) {
+    return ((p & 1) << 4) | ((p & 2) << 2) | (p & 4) | ((p & 8) >> 2) | ((p & 16) >> 4);
+}
+
 // Wait until every vector memory operation of this wave has completed
 // (s_waitcnt vmcnt(0); expcnt and lgkmcnt fields left at their maxima), and keep
 // the compiler from moving later memory operations above the wait.
@@ -1680,7 +1693,7 @@ struct HalfSyncLds {
 // the other waves of its half through hsync once per block.
 template <int LPT, class Src, class Sync>
 __device__ __forceinline__ void aeq_pol_run(const AeqItem &it, int pol, int vh, int lane, int *err,
-                                            int32_t (*aspec)[4][33], int32_t (*part_h)[4][33], uint32_t *epsw,
+                                            int32_t (*aspec)[4][kSpecRow], int32_t (*part_h)[4][33], uint32_t *epsw,
                                             uint32_t *winw, Src &src, Sync &hsync) {
     constexpr int WPP = LPT / 4;                       // waves per polarisation half
     constexpr int PPL = 32 / LPT;                      // bins per lane
@@ -1738,8 +1751,6 @@ __device__ __forceinline__ void aeq_pol_run(const AeqItem &it, int pol, int vh, 
         finish();
         return;
     }
-    if (lane < 4) winw[32 + lane] = 0u;
-
     // twiddles and signs of this lane's transforms (position t) and of its
     // input-spectrum group (position lane_pos(kk))
     const PolLaneK<LPT> K(t, lane_pos(kk));
@@ -1785,7 +1796,7 @@ __device__ __forceinline__ void aeq_pol_run(const AeqItem &it, int pol, int vh, 
     // Input spectra of the 4 streams of one block from its window (zeros past
     // the end applied): lane (S1 = lane / 16, k) writes positions kp, kp + 16 of
     // stream S1 to dst.
-    auto spectra = [&](uint32_t win, int32_t(*dst)[33]) {
+    auto spectra = [&](uint32_t win, int32_t(*dst)[kSpecRow]) {
         // rows 0, 2 hold positions lane_pos(l), rows 1, 3 positions 16 + lane_pos(l):
         // swapping odd rows of one copy with even rows of the other gives every
         // lane both (sw[0]: position kp, sw[1]: position kp + 16)
@@ -1821,29 +1832,17 @@ __device__ __forceinline__ void aeq_pol_run(const AeqItem &it, int pol, int vh, 
         }
     };
 
-    // One block: its window `win` and the next block's window `win_next` in;
-    // block b + 2's window is loaded into `win` (two blocks ahead of use: even
-    // and odd blocks alternate between two registers).  The block's input
-    // spectra were written into aspec[b & 1] during block b - 1; this block
-    // writes block b + 1's into the other buffer while it waits for the LDS
-    // reads of its tap update, off the chain from one block's taps to the next.
-    auto block = [&](uint32_t b, uint32_t &win, uint32_t win_next) {
+    // One block from its input spectra `spec` (position order, rows of kSpecRow
+    // words by stream) and the window bytes `wbw` (rows of `row` bytes by
+    // stream; the block's symbol 16 b at byte `woff` of each row).  `shadow` runs
+    // in the shadow of the tap update's LDS reads, or in its place when the
+    // update is off.
+    auto block_core = [&](uint32_t b, const int32_t(*spec)[kSpecRow], const uint32_t *wbw, int row, int woff,
+                          auto &&shadow) {
         // the step of this block (stream block block0 + b) under the schedule
         const int mu_s = b >= gear_at ? mu_late : mu_early;
         const int32_t mu_r = b >= gear_at ? mu_r_late : mu_r_early;
         const int64_t left = (int64_t)M - 16 * (int64_t)b;         // symbols from 16 b on
-        if (wpos - 16 >= left) win = 0u;                            // past the end
-        bad |= !bytes_5bit(win);
-        if (lane < 32) {       // window bytes by stream for the tap update
-            uint8_t *wb = reinterpret_cast<uint8_t *>(winw);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) wb[c * 32 + wpos] = (uint8_t)(win >> (8 * c));
-        }
-        win = src.ahead(b, wpos);                                   // symbol 16 b + 16 + wpos
-        // block b + 1's window position wpos is symbol 16 b + wpos
-        const uint32_t wn = wpos >= left ? 0u : win_next;
-        int32_t(*const spec_next)[33] = aspec[(b + 1) & 1];
-        const int32_t(*const spec)[33] = aspec[b & 1];
         int32_t Y[PPL];
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
@@ -1879,13 +1878,13 @@ __device__ __forceinline__ void aeq_pol_run(const AeqItem &it, int pol, int vh, 
             // the aligned dwords j = q - S i in [J0, 3]: NJ byte alignments for the
             // NT * 4 dot products.
             constexpr int S = LPT / 4, J0 = -S * (NT - 1), NJ = 4 - J0;
-            const int base = tS1 * 32 + 16 - t;          // byte of a_S1[16 b - t]
+            const int base = tS1 * row + woff - t;       // byte of a_S1[16 b - t]
             uint32_t e4[4], raw[NJ + 1];
 #pragma unroll
             for (int q = 0; q < 4; ++q) e4[q] = epsw[tS2l * 4 + q];
 #pragma unroll
-            for (int r = 0; r <= NJ; ++r) raw[r] = winw[(base >> 2) + J0 + r];
-            spectra(wn, spec_next);                      // in the shadow of the reads
+            for (int r = 0; r <= NJ; ++r) raw[r] = wbw[(base >> 2) + J0 + r];
+            shadow();                                    // in the shadow of the reads
             uint32_t ad[NJ];
 #pragma unroll
             for (int r = 0; r < NJ; ++r) ad[r] = __builtin_amdgcn_alignbyte(raw[r + 1], raw[r], base & 3);
@@ -1899,16 +1898,37 @@ __device__ __forceinline__ void aeq_pol_run(const AeqItem &it, int pol, int vh, 
             }
             transform_taps();
         } else {
-            spectra(wn, spec_next);
+            shadow();
         }
         // the next block reuses this wave's window and error bytes: keep the LDS
         // reads above in front of the writes that follow
         wave_lds_sync();
     };
-    uint32_t win_even = src.first(-16 + wpos), win_odd = src.first(wpos);   // blocks 0 and 1
-    spectra(wpos - 16 >= (int64_t)M ? 0u : win_even, aspec[0]);
-    wave_lds_sync();
+
     if constexpr (Src::kSegmented) {
+        // The window of block b + 2 is loaded during block b into the register
+        // block b's came in (even and odd blocks alternate between two); block b
+        // computes block b + 1's input spectra into the other of two buffers while
+        // it waits for the LDS reads of its tap update, off the chain from one
+        // block's taps to the next.  Window bytes: rows of 32 (+ 4 zero) bytes.
+        if (lane < 4) winw[32 + lane] = 0u;
+        auto block = [&](uint32_t b, uint32_t &win, uint32_t win_next) {
+            const int64_t left = (int64_t)M - 16 * (int64_t)b;
+            if (wpos - 16 >= left) win = 0u;                        // past the end
+            bad |= !bytes_5bit(win);
+            if (lane < 32) {       // window bytes by stream for the tap update
+                uint8_t *wb = reinterpret_cast<uint8_t *>(winw);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) wb[c * 32 + wpos] = (uint8_t)(win >> (8 * c));
+            }
+            win = src.ahead(b, wpos);                               // symbol 16 b + 16 + wpos
+            // block b + 1's window position wpos is symbol 16 b + wpos
+            const uint32_t wn = wpos >= left ? 0u : win_next;
+            block_core(b, aspec[b & 1], winw, 32, 16, [&] { spectra(wn, aspec[(b + 1) & 1]); });
+        };
+        uint32_t win_even = src.first(-16 + wpos), win_odd = src.first(wpos);   // blocks 0 and 1
+        spectra(wpos - 16 >= (int64_t)M ? 0u : win_even, aspec[0]);
+        wave_lds_sync();
         // segments of 64 blocks (an even count keeps each block's window register)
         for (uint32_t b0 = 0; b0 < nblocks; b0 += 64) {
             const uint32_t b1 = min(b0 + 64u, nblocks);
@@ -1920,9 +1940,94 @@ __device__ __forceinline__ void aeq_pol_run(const AeqItem &it, int pol, int vh, 
             src.segment_done(b1);
         }
     } else {
-        for (uint32_t b = 0; b < nblocks; b += 2) {
-            block(b, win_even, win_odd);
-            if (b + 1 < nblocks) block(b + 1, win_odd, win_even);
+        // Batches of kBatch blocks.  A batch's 144 window symbols (16 b0 - 16 ..
+        // 16 b0 + 127, history before 0, zeros past M) are fetched one batch
+        // ahead, three per lane, and staged as bytes by stream (rows of kStgRow
+        // bytes, the tail zero); the input spectra of its 4 streams x kBatch
+        // blocks are then the matrix product of Eq. (1)'s transform matrix (rows
+        // in position order, bin bitrev5(p) at position p) with the 32-symbol
+        // windows, on the matrix cores in 8-bit digits: each entry 2^(nk) mod F
+        // is a signed power of two, written as 256 hi + lo with int8 hi, lo
+        // (2^15 as -32769 = 256 (-128) - 1, congruent modulo F).  Four
+        // v_mfma_i32_32x32x16_i8: hi digits over positions 0-15 and 16-31, the
+        // accumulator times 256, then lo.  |sum| <= 32 * 128 * 16 (257) < 2^24.1,
+        // one fold, |X| < 2^17.
+        uint8_t *const stgb = reinterpret_cast<uint8_t *>(winw);
+        if (lane < 16) winw[(lane >> 2) * (kStgRow / 4) + 36 + (lane & 3)] = 0u;   // row tails: bytes 144..159
+        const int mp = lane & 31, mkb = bitrev5(mp), mnh = 8 * (lane >> 5);
+        uint64_t a_hi[2], a_lo[2];
+#pragma unroll
+        for (int kh = 0; kh < 2; ++kh) {
+            uint64_t hi = 0, lo = 0;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int m = (mkb * (16 * kh + mnh + e)) & 31;
+                const int pw = m & 15, neg = m & 16;
+                int dh, dl;
+                if (pw <= 6) { dh = 0; dl = neg ? -(1 << pw) : (1 << pw); }
+                else if (pw == 7) { dh = neg ? 0 : 1; dl = -128; }
+                else if (pw <= 14) { dh = neg ? -(1 << (pw - 8)) : (1 << (pw - 8)); dl = 0; }
+                else { dh = -128; dl = neg ? 0 : -1; }
+                hi |= (uint64_t)(uint8_t)dh << (8 * e);
+                lo |= (uint64_t)(uint8_t)dl << (8 * e);
+            }
+            a_hi[kh] = hi;
+            a_lo[kh] = lo;
+        }
+        const auto a32 = src.base;
+        const auto h32 = gptr(reinterpret_cast<const uint32_t *>(it.hist_in));
+        uint32_t pre[3];
+        auto fetch = [&](uint32_t b0) {
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const int q = lane + 64 * r;
+                const int64_t i = 16 * (int64_t)b0 - 16 + q;
+                uint32_t v = 0u;
+                if (q < 144) {
+                    if (i < 0) {
+                        if (it.hist_in != nullptr) v = h32[16 + i];
+                    } else if ((uint64_t)i < M) {
+                        v = a32[i];
+                    }
+                }
+                pre[r] = v;
+            }
+        };
+        fetch(0);
+        const int mj = lane & 31, mjb = mj >> 2, ms = mj & 3;   // this lane's column: block mjb, stream ms
+        for (uint32_t b0 = 0; b0 < nblocks; b0 += kBatch) {
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const int q = lane + 64 * r;
+                if (q < 144) {
+                    const uint32_t v = pre[r];
+                    bad |= !bytes_5bit(v);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) stgb[c * kStgRow + q] = (uint8_t)(v >> (8 * c));
+                }
+            }
+            fetch(b0 + kBatch);                          // the next batch
+            wave_lds_sync();
+            const uint8_t *col = stgb + ms * kStgRow + 16 * mjb + mnh;
+            const int64_t bx0 = (int64_t)*reinterpret_cast<const uint64_t *>(col);
+            const int64_t bx1 = (int64_t)*reinterpret_cast<const uint64_t *>(col + 16);
+            v16i acc = {};
+            acc = __builtin_amdgcn_mfma_i32_32x32x16_i8((int64_t)a_hi[0], bx0, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_i32_32x32x16_i8((int64_t)a_hi[1], bx1, acc, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[r] = (int32_t)((uint32_t)acc[r] << 8);
+            acc = __builtin_amdgcn_mfma_i32_32x32x16_i8((int64_t)a_lo[0], bx0, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_i32_32x32x16_i8((int64_t)a_lo[1], bx1, acc, 0, 0, 0);
+            // lane: column (mjb, ms), register r: position 8 (r / 4) + 4 (lane / 32) + r % 4
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+                *reinterpret_cast<int4 *>(&aspec[mjb][ms][8 * g + 4 * (lane >> 5)]) =
+                    make_int4(fold16(acc[4 * g]), fold16(acc[4 * g + 1]), fold16(acc[4 * g + 2]),
+                              fold16(acc[4 * g + 3]));
+            wave_lds_sync();
+            const uint32_t nb = min((uint32_t)kBatch, nblocks - b0);
+            for (uint32_t jb = 0; jb < nb; ++jb)
+                block_core(b0 + jb, aspec[jb], winw, kStgRow, 16 * (int)jb + 16, [] {});
         }
     }
     if (bad) flag(err, RANGE_SYMBOL);
@@ -1948,15 +2053,15 @@ __device__ __forceinline__ void aeq_pol_body(const AeqItem *items, int n, const 
     const int vh = v % WPP;                            // wave within its half
     const int pol = IW == 1 ? (int)((bid >> 3) & 1) : v;
 
-    // rows padded to 33 words: lanes reading the same position of different
-    // rows hit different LDS banks
-    __shared__ int32_t aspec_s[WPP * IW][2][4][33];    // per wave: input spectra by position, by block parity
+    // spectra rows of 36 words: the products' lanes reading one position of the
+    // 4 rows (and 4 positions apart) hit 16 different banks
+    __shared__ __align__(16) int32_t aspec_s[WPP * IW][kBatch][4][kSpecRow];   // per wave: a batch's input spectra
     // per half: [block parity][g*2+d][m*2+S2l], shared by the half's waves;
     // double-buffered so a wave that runs ahead (one barrier per block) never
     // overwrites partials another wave is still reading
     __shared__ int32_t part_s[IW][2][4][33];
     __shared__ uint32_t epsw_s[WPP * IW][8];           // per wave: bytes [S2l][m]
-    __shared__ uint32_t winw_s[WPP * IW][36];          // per wave: bytes [S1][32] + pad
+    __shared__ __align__(16) uint32_t winw_s[WPP * IW][kStgRow];   // per wave: a batch's window bytes [S1][kStgRow]
     AeqSrcGlobal src{&it, gptr(reinterpret_cast<const uint32_t *>(it.a)), it.m};
     HalfSyncWg hs;
     aeq_pol_run<LPT>(it, pol, vh, lane, err, aspec_s[v], part_s[v / WPP], epsw_s[v], winw_s[v], src, hs);
@@ -2022,7 +2127,7 @@ __global__ __launch_bounds__(64 * (HALVES * (LPT / 4) + NP)) __attribute__((amdg
     __shared__ __align__(16) uint32_t arrive_s[HALVES][WPP < 2 ? 2 : WPP];
     __shared__ int32_t hs_s[NP][2][64];
     __shared__ __align__(16) uint32_t edge_s[NP][2][64];
-    __shared__ int32_t aspec_s[NC][2][4][33];
+    __shared__ int32_t aspec_s[NC][2][4][kSpecRow];
     __shared__ int32_t part_s[HALVES][2][4][33];
     __shared__ uint32_t epsw_s[NC][8];
     __shared__ uint32_t winw_s[NC][36];
