@@ -1954,6 +1954,8 @@ __device__ __forceinline__ void aeq_pol_run(const AeqItem &it, int pol, int vh, 
         // one fold, |X| < 2^17.
         uint8_t *const stgb = reinterpret_cast<uint8_t *>(winw);
         if (lane < 16) winw[(lane >> 2) * (kStgRow / 4) + 36 + (lane & 3)] = 0u;   // row tails: bytes 144..159
+        // operand lanes of v_mfma_i32_32x32x16_i8: lane l holds row (A) or column (B)
+        // l % 32 and the 8 K indices 8 (l / 32) + e of its 16-wide K slice
         const int mp = lane & 31, mkb = bitrev5(mp), mnh = 8 * (lane >> 5);
         uint64_t a_hi[2], a_lo[2];
 #pragma unroll
